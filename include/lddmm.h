@@ -1,0 +1,186 @@
+/*
+ * lddmm.h -- C-ABI of the MI355X library for band-limited Jacobi PDE-EPDiff
+ * LDDMM subject to the state equation, solved by Gauss-Newton-Krylov
+ * (M. Hernandez, "Efficient Gauss-Newton-Krylov momentum conservation
+ * constrained PDE-LDDMM using the band-limited vector field
+ * parameterization", arXiv 1807.11560).
+ *
+ * Problem (paper §3.2, band-limited energy): minimise over the band-limited
+ * initial velocity v0
+ *     E(v0) = 1/2 <L~ v0, v0>_l2 + sigma^-2 || m(1) - I1 ||^2_L2
+ * subject to the band-limited EPDiff equation d_t v + ad~dagger_v v = 0
+ * (paper §3.1) and the state equation d_t m + grad m . iota(v_t) = 0 with
+ * m(0) = I0 (paper §2.3, §3.2), L = (Id - alpha Laplacian)^s (paper §2.1).
+ *
+ * Conventions used by every entry point
+ *   - Domain: the periodic unit cube [0,1)^3; grid point i_j sits at i_j/N_j.
+ *   - Grid images (I0, I1, m1): float32, shape [N0][N1][N2], C order (last
+ *     axis fastest), device memory.
+ *   - Band vector fields (v0, v1, gradients, directions, products): complex64
+ *     interleaved (re, im), shape [3][K0][K1][K2], device memory.  Slot q of
+ *     axis j holds frequency k = q for q < K_j/2 and q - K_j otherwise; the
+ *     slot k = -K_j/2 is zero, so the effective band is |k_j| <= K_j/2 - 1
+ *     (paper §3.1, truncated Fourier domain).  iota(v)(x) = sum_k v(k)
+ *     exp(2 pi i k.x) (no normalisation), pi(f)(k) = |N|^-1 sum_x f(x)
+ *     exp(-2 pi i k.x).  Fields are real, i.e. Hermitian: v(-k) = conj v(k).
+ *     Inputs are projected onto Hermitian fields supported on the effective
+ *     band (never rejected for violating it); outputs are exactly Hermitian.
+ *   - Inner products: <a,b>_l2 = Re sum conj(a) b; the V metric (paper §3.1)
+ *     is <a,b>_V = <L~ a, b>_l2 with L~(k) = (1 + alpha sum_j (2 pi k_j)^2)^s.
+ *   - Time: nt explicit Euler steps of size 1/nt.  The state is moved by one
+ *     first-order semi-Lagrangian step per time step (periodic trilinear
+ *     interpolation at x - dt iota(v_n)(x)).
+ *   - Streams: every call enqueues its work on `stream` (a hipStream_t; NULL
+ *     is the legacy default stream).  lddmm_shoot, lddmm_gradient and
+ *     lddmm_hessvec are asynchronous; lddmm_register synchronises `stream`.
+ *   - Ownership: the caller owns every buffer, including the workspace
+ *     `ws` of `ws_bytes` >= lddmm_workspace_bytes() bytes of device memory.
+ *     The library allocates no device memory.  It keeps, per workspace
+ *     pointer, a small host record (parameters, prepared flag); the
+ *     workspace must not be shared by calls that run concurrently.
+ *   - Errors: arguments are validated before anything is enqueued, so a
+ *     negative return means nothing was enqueued (except LDDMM_E_HIP, which
+ *     reports a failed launch or copy).  lddmm_last_error() gives a
+ *     thread-local detail string for the last failure.
+ */
+#ifndef LDDMM_H
+#define LDDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LDDMM_OK = 0,
+  LDDMM_W_LINESEARCH = 1,     /* register: Armijo search failed; v0 holds the last accepted iterate */
+  LDDMM_E_INVALID_ARG = -1,   /* null pointer, non-positive alpha/sigma, unknown enum value */
+  LDDMM_E_SHAPE = -2,         /* unsupported ndim, odd band, band > grid, spectral grid too small */
+  LDDMM_E_WORKSPACE = -3,     /* ws_bytes smaller than lddmm_workspace_bytes() */
+  LDDMM_E_HIP = -4,           /* a HIP runtime call or kernel launch failed */
+  LDDMM_E_NOT_PREPARED = -5,  /* hessvec without a preceding gradient on this workspace/params */
+  LDDMM_E_NONFINITE = -6      /* register: energy or gradient is not finite */
+};
+
+enum { LDDMM_FP32 = 0 };                              /* arithmetic of the bulk path */
+enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1 };  /* Gauss-Newton reading, see lddmm_params */
+
+typedef struct lddmm_params {
+  int32_t ndim;         /* spatial dimension; this library computes ndim == 3 */
+  int32_t grid[3];      /* N_j >= 8, C order */
+  int32_t band[3];      /* K_j even, 4 <= K_j <= min(N_j, 64) */
+  int32_t spectral[3];  /* M_j, padded grid of the truncated convolution; 0 selects 3*K_j/2.
+                           Must satisfy 3*K_j/2 - 2 <= M_j <= 256 so that the product of two
+                           band fields is alias-free on the band (paper §3.1, truncated
+                           convolution). */
+  int32_t time_steps;   /* nt >= 1 */
+  int32_t s;            /* exponent of L, 1 <= s <= 8 */
+  double alpha;         /* > 0 */
+  double sigma;         /* > 0, weight of the image term */
+  int32_t precision;    /* LDDMM_FP32 */
+  int32_t hessian;      /* LDDMM_GN_PAPER: Gauss-Newton drops only the -lambda(1) grad dm(1) term
+                           of dU(1) and keeps every coupling term of the incremental adjoint
+                           Jacobi equations; LDDMM_GN_CLASSICAL also drops the coupling terms
+                           that carry U or w (paper §2.7: "dropping expressions" of the Hessian). */
+} lddmm_params;
+
+/* One Gauss-Newton iteration of lddmm_register (host memory). */
+typedef struct lddmm_stats {
+  double energy, energy_reg, energy_data; /* at the start of the iteration */
+  double mse_rel;       /* 100 ||m1 - I1||^2 / ||I0 - I1||^2 at the start of the iteration */
+  double grad_inf_rel;  /* max |g_V(k)| relative to the first iteration */
+  double step;          /* accepted Armijo step eps (0 if none) */
+  int32_t trials;       /* line-search trials */
+  int32_t pcg_iters;    /* CG iterations that updated the solution */
+  int32_t pcg_guard;    /* 1 if CG stopped on non-positive curvature */
+  int32_t reserved;
+} lddmm_stats;
+
+/* Bytes of device workspace needed for these parameters.  Host only, no side
+ * effects.  Returns LDDMM_OK or a validation error. */
+int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes);
+
+/* Geodesic shooting and state transport (paper §3.2, the two constraints):
+ * v_{n+1} = v_n - dt K~ ad~*_{v_n}(L~ v_n) on the band (band-limited EPDiff,
+ * §3.1, explicit Euler), m_{n+1} = I[m_n](x - dt iota(v_n)(x)), m_0 = I0.
+ *   I0  [N0][N1][N2] float32 (device, read)
+ *   v0  [3][K0][K1][K2] complex64 (device, read)
+ *   m1  [N0][N1][N2] float32 (device, written): m_nt
+ *   v1  [3][K0][K1][K2] complex64 (device, written) or NULL: v_nt */
+int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Energy and gradient in the V metric (paper §3.2: energy, the reduced
+ * adjoint Jacobi equations in the band with U(1) = K~ pi(lambda(1) grad
+ * m(1)), lambda(1) = -(2/sigma^2)(m(1) - I1) from §2.3), integrated backward
+ * by the transpose of the Euler steps:
+ *   w_n = w_{n+1} + dt [U_{n+1} - ad~_{v_n} w_{n+1} + K~ ad~*_{w_{n+1}}(L~ v_n)],
+ *   U_n = U_{n+1} + dt K~ ad~*_{v_n}(L~ U_{n+1}),  g_V = v0 + w_0.
+ * grad m(1) is the periodic central difference.
+ *   I0, I1   [N0][N1][N2] float32 (device, read)
+ *   v0       [3][K0][K1][K2] complex64 (device, read)
+ *   grad     [3][K0][K1][K2] complex64 (device, written): g_V
+ *   energy3  3 doubles (device, written): E, E_reg, E_data; may be NULL
+ * Leaves in `ws` the trajectories lddmm_hessvec needs (prepares it). */
+int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
+                   void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream);
+
+/* Gauss-Newton Hessian-vector product in the V metric at the v0 of the last
+ * lddmm_gradient on this workspace with equal parameters (paper §3.2: the
+ * incremental EPDiff and incremental state equations forward, then the
+ * reduced incremental adjoint Jacobi equations backward from
+ * dU(1) = K~ pi(dlambda(1) grad m(1)), dlambda(1) = -(2/sigma^2) dm(1)):
+ *   dv_{n+1} = dv_n - dt K~[ad~*_{dv_n}(L~ v_n) + ad~*_{v_n}(L~ dv_n)]
+ *   dm_{n+1} = I[dm_n - dt grad m_n . iota(dv_n)](x - dt iota(v_n)(x)), dm_0 = 0
+ *   dU_n = dU_{n+1} + dt K~[ad~*_{v_n}(L~ dU_{n+1}) + ad~*_{dv_n}(L~ U_{n+1})]
+ *   dw_n = dw_{n+1} + dt[dU_{n+1} - ad~_{v_n} dw_{n+1} - ad~_{dv_n} w_{n+1}
+ *                       + K~ ad~*_{dw_{n+1}}(L~ v_n) + K~ ad~*_{w_{n+1}}(L~ dv_n)]
+ *   Hdv = dv0 + dw_0
+ * (terms with U or w are dropped under LDDMM_GN_CLASSICAL).
+ *   dv0  [3][K0][K1][K2] complex64 (device, read)
+ *   Hdv  [3][K0][K1][K2] complex64 (device, written; may not alias dv0)
+ * Returns LDDMM_E_NOT_PREPARED if no such gradient preceded it. */
+int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* Gauss-Newton-Krylov registration (paper §2.7): for each iteration, the
+ * gradient, then `pcg_iters` iterations of CG in the V metric on
+ * H_V p = -g_V from p = 0 (stopping early on non-positive curvature, in which
+ * case the first iteration returns p = -g_V), then an Armijo search
+ * (eps = 1, 1/2, ..., at most 10 trials, c1 = 1e-4) and v0 <- v0 + eps p.
+ *   I0, I1    [N0][N1][N2] float32 (device, read)
+ *   v0_inout  [3][K0][K1][K2] complex64 (device, read and written): the start
+ *             iterate (zero for a fresh registration) and the result
+ *   stats     host array of `stats_len` entries (one per iteration) or NULL
+ * Synchronous.  Returns LDDMM_OK, LDDMM_W_LINESEARCH (stopped early on a
+ * failed search; v0 holds the last accepted iterate) or an error. */
+int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void* v0_inout,
+                   int32_t gn_iters, int32_t pcg_iters, lddmm_stats* stats, int32_t stats_len,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Number of Hessian-vector products the last lddmm_register on this thread
+ * evaluated (host only). */
+int64_t lddmm_last_register_hvps(void);
+
+/* Launch timing of one kernel family, for roofline accounting.  While
+ * enabled, every launch of family `family` (LDDMM_KF_*) made by this process
+ * is bracketed by HIP events on its stream; lddmm_kernel_timer_read
+ * synchronises those events and returns the number of timed launches and
+ * their summed duration in milliseconds.  Enabling resets the counters. */
+enum { LDDMM_KF_NONE = 0, LDDMM_KF_MSTEP = 1, LDDMM_KF_GRID_SRC = 2, LDDMM_KF_SL = 3,
+       LDDMM_KF_INV0 = 4, LDDMM_KF_FWD = 5 };
+int lddmm_kernel_timer(int32_t family);
+int lddmm_kernel_timer_read(int64_t* launches, double* total_ms);
+
+/* Static description of a status code. */
+const char* lddmm_status_string(int code);
+/* Thread-local detail of the last failure on this thread ("" if none). */
+const char* lddmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDDMM_H */

@@ -1,0 +1,404 @@
+// C-ABI entry points (include/lddmm.h): argument validation, the per-
+// workspace record that ties lddmm_hessvec to the preceding
+// lddmm_gradient, the Gauss-Newton-Krylov loop of lddmm_register, and the
+// kernel-family timer.
+#include "../../include/lddmm.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+using namespace lddmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local int64_t g_last_hvps = 0;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(LDDMM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Record per workspace pointer: the parameters of the last gradient that
+// prepared it for lddmm_hessvec.
+struct WsRecord {
+  bool prepared = false;
+  Dims dims{};
+};
+std::mutex g_ws_mu;
+std::map<const void*, WsRecord> g_ws;
+
+bool same_dims(const Dims& a, const Dims& b) {
+  for (int j = 0; j < 3; ++j)
+    if (a.N[j] != b.N[j] || a.K[j] != b.K[j] || a.M[j] != b.M[j]) return false;
+  return a.nt == b.nt && a.s == b.s && a.alpha == b.alpha && a.sigma == b.sigma &&
+         a.hessian == b.hessian;
+}
+
+void set_prepared(const void* ws, bool prepared, const Dims& d) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  WsRecord& r = g_ws[ws];
+  r.prepared = prepared;
+  r.dims = d;
+}
+
+int validate(const lddmm_params* p, Dims* d) {
+  if (!p) return fail(LDDMM_E_INVALID_ARG, "params is NULL");
+  if (p->ndim != 3) return fail(LDDMM_E_SHAPE, "only ndim == 3 is supported");
+  if (!(p->alpha > 0.0) || !std::isfinite(p->alpha))
+    return fail(LDDMM_E_INVALID_ARG, "alpha must be positive");
+  if (!(p->sigma > 0.0) || !std::isfinite(p->sigma))
+    return fail(LDDMM_E_INVALID_ARG, "sigma must be positive");
+  if (p->s < 1 || p->s > 8) return fail(LDDMM_E_INVALID_ARG, "s must be in [1, 8]");
+  if (p->time_steps < 1 || p->time_steps > 1000)
+    return fail(LDDMM_E_INVALID_ARG, "time_steps must be in [1, 1000]");
+  if (p->precision != LDDMM_FP32) return fail(LDDMM_E_INVALID_ARG, "unknown precision");
+  if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL)
+    return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
+  Dims& o = *d;
+  o = Dims{};
+  for (int j = 0; j < 3; ++j) {
+    const int N = p->grid[j], K = p->band[j];
+    if (N < 8 || N > 2048) return fail(LDDMM_E_SHAPE, "grid sizes must be in [8, 2048]");
+    if (K < 4 || K > kMaxBand || (K & 1) || K > N)
+      return fail(LDDMM_E_SHAPE, "band sizes must be even, in [4, 64] and at most the grid size");
+    const int M = p->spectral[j] ? p->spectral[j] : 3 * K / 2;
+    if (M < 3 * K / 2 - 2 || M > 256)
+      return fail(LDDMM_E_SHAPE, "spectral grid must satisfy 3K/2 - 2 <= M <= 256");
+    o.N[j] = N;
+    o.K[j] = K;
+    o.M[j] = M;
+  }
+  o.Kh = o.K[2] / 2;
+  o.nb = o.K[0] * o.K[1] * o.Kh;
+  o.nN = (long long)o.N[0] * o.N[1] * o.N[2];
+  o.nM = (long long)o.M[0] * o.M[1] * o.M[2];
+  o.nt = p->time_steps;
+  o.s = p->s;
+  o.alpha = p->alpha;
+  o.sigma = p->sigma;
+  o.hessian = p->hessian;
+  // the fused step kernel keeps a block's fields in LDS
+  // each block keeps its rows in LDS (at most 64 KiB per block)
+  if (mstep_shared_bytes(o, 2, 9) > 64 * 1024)
+    return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
+  if (gridstep_shared_bytes(o) > 64 * 1024 || src_shared_bytes(o) > 64 * 1024)
+    return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");
+  return LDDMM_OK;
+}
+
+int check_ws(const Dims& d, const void* ws, size_t ws_bytes) {
+  if (!ws) return fail(LDDMM_E_INVALID_ARG, "workspace is NULL");
+  size_t need = Engine::workspace_bytes(d);
+  if (ws_bytes < need)
+    return fail(LDDMM_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return LDDMM_OK;
+}
+
+// ---------------------------------------------------------------- timer
+struct Timer {
+  std::mutex mu;
+  int family = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+Timer g_timer;
+
+}  // namespace
+
+namespace lddmm {
+void timer_begin(int family, hipStream_t st) {
+  if (g_timer.family == 0 || family != g_timer.family) return;
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!g_timer.pool.empty()) {
+    ev = g_timer.pool.back();
+    g_timer.pool.pop_back();
+  } else {
+    if (hipEventCreate(&ev.first) != hipSuccess) return;
+    if (hipEventCreate(&ev.second) != hipSuccess) return;
+  }
+  if (hipEventRecord(ev.first, st) != hipSuccess) return;
+  g_timer.pending.push_back(ev);
+}
+void timer_end(int family, hipStream_t st) {
+  if (g_timer.family == 0 || family != g_timer.family) return;
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  if (!g_timer.pending.empty()) (void)hipEventRecord(g_timer.pending.back().second, st);
+}
+}  // namespace lddmm
+
+namespace {
+
+// ------------------------------------------------------ register loop
+int run_register(Engine& e, const float* I0, const float* I1, void* v0_inout, int gn_iters,
+                 int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
+  const Dims& d = e.dims();
+  hipStream_t st = e.stream();
+  const int n = 3 * d.nb;
+  const double c1 = 1e-4;
+  const int max_trials = 10;
+  hipError_t err;
+#define HTRY(x)                                  \
+  do {                                           \
+    err = (x);                                   \
+    if (err != hipSuccess) return hip_fail(err, #x); \
+  } while (0)
+  HTRY(e.init_tables());
+  HTRY(e.load_band(v0_inout, e.v0h));
+  // ||I0 - I1||^2 for MSE_rel
+  HTRY(launch_sqdiff(I0, I1, d.nN, e.partial, e.scal + 8, 1.0, st));
+  double denom = 0.0;
+  HTRY(hipMemcpyAsync(&denom, e.scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+  HTRY(hipStreamSynchronize(st));
+  double g0_inf = -1.0;
+  int status = LDDMM_OK;
+  for (int it = 0; it < gn_iters; ++it) {
+    HTRY(launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n, st));
+    HTRY(e.forward(I0));
+    HTRY(e.energy(e.m[d.nt], I1));
+    HTRY(e.backward(I1, e.gh));
+    HTRY(launch_band_maxabs(e.gh, d, e.partial, e.scal + 3, st));
+    double sc[4];
+    HTRY(hipMemcpyAsync(sc, e.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HTRY(hipStreamSynchronize(st));
+    if (!std::isfinite(sc[0]) || !std::isfinite(sc[3]))
+      return fail(LDDMM_E_NONFINITE, "energy or gradient is not finite");
+    if (g0_inf < 0) g0_inf = sc[3];
+    // CG in the V metric on H_V p = -g_V
+    HTRY(launch_pcg_init(e.gh, e.ph, e.rh, e.dh, n, st));
+    HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
+    HTRY(launch_pcg_reset(e.pcg, st));
+    int used = 0;
+    for (int k = 0; k < pcg_iters; ++k) {
+      HTRY(e.hessvec(e.dh, e.Hdh));
+      ++*hvps;
+      HTRY(launch_band_dot(e.dh, e.Hdh, e.Lsym, d, e.partial, e.pcg + SC_DHD, 1.0, st));
+      HTRY(launch_pcg_phase_a(e.pcg, k, st));
+      HTRY(launch_pcg_update_pr(e.pcg, e.dh, e.Hdh, e.ph, e.rh, n, st));
+      HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, st));
+      HTRY(launch_pcg_phase_b(e.pcg, st));
+      HTRY(launch_pcg_update_d(e.pcg, e.rh, e.dh, n, st));
+      double stopped = 0.0;
+      HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
+      HTRY(hipStreamSynchronize(st));
+      used = k + 1;
+      if (stopped != 0.0) break;
+    }
+    (void)used;
+    double pc[SC_COUNT];
+    HTRY(hipMemcpyAsync(pc, e.pcg, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+    // slope <g, p>_V; fall back to -g if p is not a descent direction
+    HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
+    double slope = 0.0;
+    HTRY(hipMemcpyAsync(&slope, e.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+    HTRY(hipStreamSynchronize(st));
+    if (!(slope < 0.0)) {
+      HTRY(launch_axpy_band(e.tmph, e.gh, -1.f, e.ph, n, st));  // tmph is zero-filled below
+      HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
+      HTRY(hipMemcpyAsync(&slope, e.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+      HTRY(hipStreamSynchronize(st));
+    }
+    // Armijo backtracking
+    double eps = 1.0, Etry = 0.0;
+    bool ok = false;
+    int trials = 0;
+    for (int t = 0; t < max_trials; ++t) {
+      ++trials;
+      HTRY(launch_axpy_band(e.v0h, e.ph, (float)eps, e.vtry, n, st));
+      HTRY(launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.V[0]), 2LL * n, st));
+      const float* mnt = nullptr;
+      HTRY(e.forward_light(I0, &mnt));
+      HTRY(e.energy(mnt, I1));
+      HTRY(hipMemcpyAsync(&Etry, e.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+      HTRY(hipStreamSynchronize(st));
+      if (std::isfinite(Etry) && Etry <= sc[0] + c1 * eps * slope) {
+        ok = true;
+        break;
+      }
+      eps *= 0.5;
+    }
+    if (stats && it < stats_len) {
+      lddmm_stats& s = stats[it];
+      std::memset(&s, 0, sizeof(s));
+      s.energy = sc[0];
+      s.energy_reg = sc[1];
+      s.energy_data = sc[2];
+      s.mse_rel = denom > 0 ? 100.0 * sc[2] * d.sigma * d.sigma * (double)d.nN / denom : 0.0;
+      s.grad_inf_rel = g0_inf > 0 ? sc[3] / g0_inf : 0.0;
+      s.step = ok ? eps : 0.0;
+      s.trials = trials;
+      s.pcg_iters = (int)pc[SC_ITERS];
+      s.pcg_guard = pc[SC_GUARD] != 0.0;
+    }
+    if (!ok) {
+      status = LDDMM_W_LINESEARCH;
+      break;
+    }
+    HTRY(launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.v0h), 2LL * n, st));
+  }
+  HTRY(e.store_band(e.v0h, nullptr, 0.f, v0_inout));
+  HTRY(hipStreamSynchronize(st));
+  return status;
+#undef HTRY
+}
+
+}  // namespace
+
+extern "C" {
+
+int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!bytes) return fail(LDDMM_E_INVALID_ARG, "bytes is NULL");
+  *bytes = Engine::workspace_bytes(d);
+  return LDDMM_OK;
+}
+
+int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
+                void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!I0 || !v0 || !m1) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  const float* mnt = nullptr;
+  if ((err = e.forward_light(I0, &mnt)) != hipSuccess) return hip_fail(err, "shoot");
+  if ((err = launch_copy(mnt, m1, d.nN, e.stream())) != hipSuccess) return hip_fail(err, "copy m1");
+  if (v1 && (err = e.store_band(e.V[d.nt], nullptr, 0.f, v1)) != hipSuccess)
+    return hip_fail(err, "store v1");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
+                   void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  if ((err = e.forward(I0)) != hipSuccess) return hip_fail(err, "forward");
+  if ((err = e.energy(e.m[d.nt], I1)) != hipSuccess) return hip_fail(err, "energy");
+  if ((err = e.backward(I1, nullptr)) != hipSuccess) return hip_fail(err, "backward");
+  if ((err = e.store_band(e.V[0], e.W[0], 1.f, grad)) != hipSuccess) return hip_fail(err, "store");
+  if (energy3 && (err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess)
+    return hip_fail(err, "energy copy");
+  set_prepared(ws, true, d);
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, size_t ws_bytes,
+                  void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!dv0 || !Hdv) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if (dv0 == Hdv) return fail(LDDMM_E_INVALID_ARG, "Hdv may not alias dv0");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(ws);
+    if (it == g_ws.end() || !it->second.prepared || !same_dims(it->second.dims, d))
+      return fail(LDDMM_E_NOT_PREPARED, "no lddmm_gradient with these parameters on this workspace");
+  }
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.load_band(dv0, e.dV[0])) != hipSuccess) return hip_fail(err, "load dv0");
+  if ((err = e.hessvec(e.dV[0], e.Hdh)) != hipSuccess) return hip_fail(err, "hessvec");
+  if ((err = e.store_band(e.Hdh, nullptr, 0.f, Hdv)) != hipSuccess) return hip_fail(err, "store");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void* v0_inout,
+                   int32_t gn_iters, int32_t pcg_iters, lddmm_stats* stats, int32_t stats_len,
+                   void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!I0 || !I1 || !v0_inout) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if (gn_iters < 0 || pcg_iters < 1) return fail(LDDMM_E_INVALID_ARG, "bad iteration counts");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  // zero-filled scratch used to negate the gradient
+  hipError_t err = launch_fill(reinterpret_cast<float*>(e.tmph), 6LL * d.nb, 0.f, e.stream());
+  if (err != hipSuccess) return hip_fail(err, "fill");
+  g_last_hvps = 0;
+  rc = run_register(e, I0, I1, v0_inout, gn_iters, pcg_iters, stats, stats_len, &g_last_hvps);
+  if (rc >= 0) g_last_error.clear();
+  return rc;
+}
+
+int64_t lddmm_last_register_hvps(void) { return g_last_hvps; }
+
+int lddmm_kernel_timer(int32_t family) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  for (auto& ev : g_timer.pending) g_timer.pool.push_back(ev);
+  g_timer.pending.clear();
+  g_timer.family = family;
+  g_timer.launches = 0;
+  g_timer.ms = 0.0;
+  return LDDMM_OK;
+}
+
+int lddmm_kernel_timer_read(int64_t* launches, double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  for (auto& ev : g_timer.pending) {
+    if (hipEventSynchronize(ev.second) != hipSuccess) return fail(LDDMM_E_HIP, "event sync");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess)
+      return fail(LDDMM_E_HIP, "event elapsed");
+    g_timer.ms += ms;
+    g_timer.launches += 1;
+    g_timer.pool.push_back(ev);
+  }
+  g_timer.pending.clear();
+  if (launches) *launches = g_timer.launches;
+  if (total_ms) *total_ms = g_timer.ms;
+  return LDDMM_OK;
+}
+
+const char* lddmm_status_string(int code) {
+  switch (code) {
+    case LDDMM_OK: return "ok";
+    case LDDMM_W_LINESEARCH: return "line search failed; last accepted iterate returned";
+    case LDDMM_E_INVALID_ARG: return "invalid argument";
+    case LDDMM_E_SHAPE: return "unsupported shape";
+    case LDDMM_E_WORKSPACE: return "workspace too small";
+    case LDDMM_E_HIP: return "HIP runtime error";
+    case LDDMM_E_NOT_PREPARED: return "hessvec needs a preceding gradient on this workspace";
+    case LDDMM_E_NONFINITE: return "non-finite energy or gradient";
+    default: return "unknown status";
+  }
+}
+
+const char* lddmm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

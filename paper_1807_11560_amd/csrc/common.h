@@ -1,0 +1,154 @@
+// Shared declarations of the HIP library: problem dimensions, kernel job
+// descriptors and the launch wrappers the host engine calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lddmm {
+
+constexpr int kMaxBand = 64;   // K_j upper bound
+constexpr int kMaxJobs = 32;   // jobs per batched launch
+
+// Problem sizes.  Band fields are kept internally as the half spectrum
+// [3][K0][K1][Kh] (k2 = 0..K2/2-1), complex float; the negative-k2 half
+// follows from Hermitian symmetry.
+struct Dims {
+  int N[3], K[3], M[3];
+  int Kh;           // K[2] / 2
+  int nb;           // K0 * K1 * Kh, complex values per component
+  long long nN;     // grid points
+  long long nM;     // padded spectral grid points
+  int nt;
+  int s;
+  double alpha, sigma;
+  int hessian;      // 0: couplings kept (paper reading), 1: dropped
+};
+
+// ---------------------------------------------------------------- tables
+// Twiddle tables for one transform direction set (grid G = M or N).
+struct Twiddles {
+  const float2* inv0;  // [2][G0][K0]  exp(+2 pi i k x/G), variant 1 times 2 pi i k
+  const float2* inv1;  // [2][G1][K1]
+  const float2* inv2;  // [2][G2][Kh]  weight 1 (k2 = 0) or 2 folded in
+  const float2* fwd0;  // [K0][G0]     exp(-2 pi i k x/G)
+  const float2* fwd1;  // [K1][G1]
+  const float2* fwd2;  // [Kh][G2]
+  int G[3];
+};
+
+// ---------------------------------------------------------------- jobs
+struct Inv0Job {
+  const float2* in;   // band half spectrum of one component [K0][K1*Kh]
+  float2* out;        // [nvar][G0][K1*Kh]
+  int lflag;          // multiply the input by L~ on load
+};
+struct Inv0Jobs { Inv0Job j[kMaxJobs]; };
+
+// Program of the fused M-grid step kernel: which band-limited Lie products
+// to form at each point of the padded grid.
+enum MProg {
+  PROG_STORE = 0,   // only synthesise (and store) the new groups
+  PROG_SHOOT = 1,   // out0 = ad*_V(LV)                         new: V, LV
+  PROG_H1 = 2,      // out0 = ad*_dV(LV) + ad*_V(LdV)           new: dV, LdV; cached: V, LV
+  PROG_GRAD = 3,    // out0 = ad*_V(LU), out1 = ad_V(W), out2 = ad*_W(LV)
+                    //                                          new: LU, W; cached: V, LV
+  PROG_H5 = 4,      // out0 = ad*_V(LdU) + ad*_dV(LU)
+                    // out1 = ad_V(dW) + ad_dV(W)
+                    // out2 = ad*_dW(LV) + ad*_W(LdV)
+                    //                   new: LdU, dW; cached: V, LV, LU, W, dV, LdV
+  PROG_H5_NOCOUPLE = 5  // out0 = ad*_V(LdU), out1 = ad_V(dW), out2 = ad*_dW(LV)
+};
+
+struct MStepArgs {
+  const float2* t1[2];    // stage-0 output of new group g: [3 comps][2 vars][M0][K1*Kh]
+  float* store[2];        // cache for new group g: [12][nM], or null
+  const float* cached[6]; // cached groups: [12][nM] each
+  float2* s1;             // [nout][M0][M1][Kh] forward stage-2 output
+  int nnew, nout, prog;
+};
+
+struct Fwd1Job { const float2* in; float2* out; };   // [G0][G1][Kh] -> [G0][K1][Kh]
+struct Fwd1Jobs { Fwd1Job j[kMaxJobs]; };
+
+// out = base + ca*(K~ if syma)*F(a) + cb*(K~ if symb)*F(b) + ce*extra, per
+// band point; F is the last forward stage with the 1/|G| normalisation.
+struct Fwd0Job {
+  const float2* a;
+  const float2* b;
+  const float2* base;
+  const float2* extra;
+  float2* out;
+  float ca, cb, ce;
+  int syma, symb;
+};
+struct Fwd0Jobs { Fwd0Job j[kMaxJobs]; };
+
+struct GridStepArgs {
+  const float2* t1;   // [3][N0][K1*Kh]
+  int op;             // 0: write the velocity; 1: incremental-state source
+  float* vout;        // op 0: [3][nN]
+  const float* m;     // op 1: state m_n
+  const float* dm;    // op 1: incremental state dm_n (null: zero)
+  float* q;           // op 1: dm_n - dt grad_h m_n . dv_n
+  float dt;
+};
+
+// ------------------------------------------------------- launch wrappers
+// Each returns hipSuccess or the launch error.
+hipError_t launch_twiddles(float2* dst, int K, int G, int mode, hipStream_t st);
+hipError_t launch_symbols(float* Lsym, float* Ksym, const Dims& d, hipStream_t st);
+hipError_t launch_full_to_half(const float2* full, float2* half, const Dims& d, hipStream_t st);
+hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float2* full,
+                               const Dims& d, hipStream_t st);
+hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
+                       int K0, int C, int G0, hipStream_t st);
+hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
+hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
+                       int Kh, hipStream_t st);
+hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const float* Ksym, int G0,
+                       int K0, int K1, int Kh, float invG, hipStream_t st);
+hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
+hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
+                     hipStream_t st);
+hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
+                           const Dims& d, const Twiddles& tw, hipStream_t st);
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
+hipError_t launch_copy(const float* src, float* dst, long long n, hipStream_t st);
+hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* out, int n,
+                            hipStream_t st);   // out = x + a*y
+// Reductions, deterministic two-pass; results in double on the device.
+hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* partial, double* out,
+                         double scale, hipStream_t st);
+hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
+                           double* partial, double* out, double scale, hipStream_t st);
+hipError_t launch_band_maxabs(const float2* a, const Dims& d, double* partial, double* out,
+                              hipStream_t st);
+hipError_t launch_scalar_copy(const double* src, double* dst, int n, hipStream_t st);
+hipError_t launch_energy_combine(double* sc, hipStream_t st);  // sc[0] = sc[1] + sc[2]
+size_t mstep_shared_bytes(const Dims& d, int nnew, int nout);
+size_t gridstep_shared_bytes(const Dims& d);
+size_t src_shared_bytes(const Dims& d);
+// CG in the V metric, all scalars on the device (see engine).
+hipError_t launch_pcg_reset(double* sc, hipStream_t st);
+hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dvec, int n,
+                           hipStream_t st);
+hipError_t launch_pcg_phase_a(double* sc, int it, hipStream_t st);
+hipError_t launch_pcg_update_pr(const double* sc, const float2* dvec, const float2* Hd, float2* p,
+                                float2* r, int n, hipStream_t st);
+hipError_t launch_pcg_phase_b(double* sc, hipStream_t st);
+hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dvec, int n,
+                               hipStream_t st);
+
+// Kernel-family timing (see lddmm_kernel_timer).
+void timer_begin(int family, hipStream_t st);
+void timer_end(int family, hipStream_t st);
+
+// Scalar slots of the CG state.
+enum PcgSlot {
+  SC_RR = 0, SC_DHD = 1, SC_RRNEW = 2, SC_ALPHA = 3, SC_BETA = 4, SC_STOPPED = 5, SC_GUARD = 6,
+  SC_ITERS = 7, SC_NEGG = 8, SC_DOUPD = 9, SC_COUNT = 16
+};
+
+}  // namespace lddmm

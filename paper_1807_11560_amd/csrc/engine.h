@@ -1,0 +1,80 @@
+// Host engine: workspace layout and the time loops of shooting, transport,
+// the adjoint Jacobi gradient, the incremental adjoint Jacobi
+// Hessian-vector product and the Gauss-Newton-Krylov loop.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace lddmm {
+
+// Carves named buffers out of the caller's workspace.  With base == nullptr
+// it only accumulates the size.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+class Engine {
+ public:
+  Engine(const Dims& d, void* ws, hipStream_t st);
+  static size_t workspace_bytes(const Dims& d);
+
+  hipError_t init_tables();
+  // band I/O in the caller's full layout
+  hipError_t load_band(const void* full, float2* half);
+  hipError_t store_band(const float2* a, const float2* b, float cb, void* full);
+
+  // Band shooting from V[0] (fills V[1..nt]; caches the padded-grid fields
+  // when `cache`).
+  hipError_t shoot_band(bool cache);
+  // Shooting with caches, grid velocities vg[n] and states m[0..nt].
+  hipError_t forward(const float* I0);
+  // Shooting and transport without caches; *m_out = m_nt.
+  hipError_t forward_light(const float* I0, const float** m_out);
+  // E, E_reg, E_data of (V[0], m_nt) into scal[0..2] (device).
+  hipError_t energy(const float* mnt, const float* I1);
+  // U, W sweeps from m_nt; g_V = V[0] + W[0] into g_out (half) if non-null.
+  hipError_t backward(const float* I1, float2* g_out);
+  // Hessian-vector product on half-spectrum vectors.
+  hipError_t hessvec(const float2* dvh, float2* out);
+
+  const Dims& dims() const { return d_; }
+  hipStream_t stream() const { return st_; }
+
+  // buffers
+  std::vector<float2*> V, U, W, dV;
+  float2 *dU[2], *dW[2];
+  float2 *gh, *ph, *rh, *dh, *Hdh, *v0h, *vtry, *tmph;
+  std::vector<float*> VG, UG, WG, dVG;
+  std::vector<float*> m, vg;
+  float *dm[2], *q;
+  float *mlight[2];
+  double *partial, *scal, *pcg;
+  float *Lsym, *Ksym;
+
+ private:
+  void layout(Carver& c);
+  hipError_t mstep_step(int prog, int nout, const float2* in0, int l0, const float2* in1, int l1,
+                        float* store0, float* store1, const float* const* cached);
+  hipError_t fwd_batch(int nout, Fwd0Job* jobs, int njobs, bool gridN);
+  hipError_t grid_velocities(const std::vector<float2*>& bands, int count, std::vector<float*>& out);
+  const float2* s2(int o, bool gridN) const;
+
+  Dims d_;
+  hipStream_t st_;
+  Twiddles twM_{}, twN_{};
+  float2* twbuf_ = nullptr;
+  float2 *T1_ = nullptr, *S1_ = nullptr, *S2_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr,
+         *S2N_ = nullptr;
+};
+
+}  // namespace lddmm

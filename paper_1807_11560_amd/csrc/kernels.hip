@@ -1,0 +1,985 @@
+// Device kernels of band-limited Jacobi PDE-EPDiff LDDMM for CDNA4 (gfx950).
+//
+// Transforms between the band (paper §3.1, truncated Fourier domain) and a
+// grid are separable partial DFTs: one contraction per axis, axis 0 first
+// (k0 -> x0), then axis 1, then the real-output contraction over the half
+// spectrum along axis 2.  The truncated convolution of the band Lie algebra
+// (paper §3.1) is evaluated on the padded grid M >= 3K/2 - 2 where it is
+// alias-free on the band.  Partial derivatives are folded into the twiddle
+// tables of the axis they act on.
+#include "common.h"
+
+#include <math.h>
+
+namespace lddmm {
+
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+// ------------------------------------------------------------- tables
+// mode 0: inverse, full axis  [2][G][K]
+// mode 1: inverse, half axis  [2][G][K/2], weight 1 at k = 0 else 2
+// mode 2: forward, full axis  [K][G]
+// mode 3: forward, half axis  [K/2][G]
+__global__ void k_twiddles(float2* dst, int K, int G, int mode) {
+  const int Kq = (mode == 1 || mode == 3) ? K / 2 : K;
+  const int total = (mode <= 1) ? 2 * G * Kq : Kq * G;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int v = 0, x, q;
+  if (mode <= 1) {
+    v = i / (G * Kq);
+    x = (i / Kq) % G;
+    q = i % Kq;
+  } else {
+    q = i / G;
+    x = i % G;
+  }
+  const bool half = (mode == 1 || mode == 3);
+  const int k = half ? q : (q < K / 2 ? q : q - K);
+  if (!half && q == K / 2) { dst[i] = make_float2(0.f, 0.f); return; }
+  long long r = ((long long)k * x) % G;
+  if (r < 0) r += G;
+  double s, c;
+  sincospi(2.0 * (double)r / (double)G, &s, &c);
+  double re = c, im = (mode >= 2) ? -s : s;
+  if (mode <= 1 && v == 1) {  // times 2 pi i k
+    const double w = 2.0 * M_PI * (double)k;
+    const double nre = -w * im, nim = w * re;
+    re = nre;
+    im = nim;
+  }
+  if (mode == 1 && q > 0) { re *= 2.0; im *= 2.0; }
+  dst[i] = make_float2((float)re, (float)im);
+}
+
+__global__ void k_symbols(float* Lsym, float* Ksym, int K0, int K1, int Kh, int s, double alpha) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K0 * K1 * Kh) return;
+  int q0 = i / (K1 * Kh), q1 = (i / Kh) % K1, k2 = i % Kh;
+  int k0 = q0 < K0 / 2 ? q0 : q0 - K0;
+  int k1 = q1 < K1 / 2 ? q1 : q1 - K1;
+  const double tp = 2.0 * M_PI;
+  double lap = tp * tp * ((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
+  double base = 1.0 + alpha * lap, L = 1.0;
+  for (int e = 0; e < s; ++e) L *= base;
+  Lsym[i] = (float)L;
+  Ksym[i] = (float)(1.0 / L);
+}
+
+// ------------------------------------------------------- layout changes
+// full [3][K0][K1][K2] -> half [3][K0][K1][Kh], projecting onto Hermitian
+// fields on the effective band.
+__global__ void k_full_to_half(const float2* __restrict__ full, float2* __restrict__ half, int K0,
+                               int K1, int K2) {
+  const int Kh = K2 / 2;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * K0 * K1 * Kh) return;
+  int c = i / (K0 * K1 * Kh);
+  int q0 = (i / (K1 * Kh)) % K0, q1 = (i / Kh) % K1, q2 = i % Kh;
+  if (q0 == K0 / 2 || q1 == K1 / 2) { half[i] = make_float2(0.f, 0.f); return; }
+  const float2* f = full + (size_t)c * K0 * K1 * K2;
+  float2 a = f[((size_t)q0 * K1 + q1) * K2 + q2];
+  int r0 = (K0 - q0) % K0, r1 = (K1 - q1) % K1, r2 = (K2 - q2) % K2;
+  float2 b = f[((size_t)r0 * K1 + r1) * K2 + r2];
+  half[i] = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+}
+
+// full = expand(a + cb*b)
+__global__ void k_half_to_full(const float2* __restrict__ a, const float2* __restrict__ b, float cb,
+                               float2* __restrict__ full, int K0, int K1, int K2) {
+  const int Kh = K2 / 2;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * K0 * K1 * K2) return;
+  int c = i / (K0 * K1 * K2);
+  int q0 = (i / (K1 * K2)) % K0, q1 = (i / K2) % K1, q2 = i % K2;
+  if (q0 == K0 / 2 || q1 == K1 / 2 || q2 == K2 / 2) { full[i] = make_float2(0.f, 0.f); return; }
+  bool conj = q2 > Kh;
+  int s0 = conj ? (K0 - q0) % K0 : q0, s1 = conj ? (K1 - q1) % K1 : q1, s2 = conj ? K2 - q2 : q2;
+  size_t j = (size_t)c * K0 * K1 * Kh + ((size_t)s0 * K1 + s1) * Kh + s2;
+  float2 v = a[j];
+  if (b) { v.x += cb * b[j].x; v.y += cb * b[j].y; }
+  if (conj) v.y = -v.y;
+  full[i] = v;
+}
+
+// ------------------------------------------------- inverse stage 0 (k0)
+// out[v][x0][c] = sum_k0 tw[v][x0][k0] * in[k0][c] (optionally in * L~).
+template <int NV, int XT>
+__global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __restrict__ tw,
+                                              const float* __restrict__ Lsym, int K0, int C,
+                                              int G0) {
+  extern __shared__ float2 sh[];
+  const Inv0Job job = jobs.j[blockIdx.z];
+  const int xb = blockIdx.y * XT;
+  for (int i = threadIdx.x; i < NV * XT * K0; i += blockDim.x) {
+    int v = i / (XT * K0), t = (i / K0) % XT, k = i % K0;
+    int x = xb + t;
+    sh[i] = (x < G0) ? tw[((size_t)v * G0 + x) * K0 + k] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float2 acc[NV][XT];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int t = 0; t < XT; ++t) acc[v][t] = make_float2(0.f, 0.f);
+  for (int k = 0; k < K0; ++k) {
+    float2 val = job.in[(size_t)k * C + c];
+    if (job.lflag) {
+      float l = Lsym[(size_t)k * C + c];
+      val.x *= l;
+      val.y *= l;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int t = 0; t < XT; ++t) cmac(acc[v][t], sh[(v * XT + t) * K0 + k], val);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int t = 0; t < XT; ++t) {
+      int x = xb + t;
+      if (x < G0) job.out[((size_t)v * G0 + x) * C + c] = acc[v][t];
+    }
+}
+
+// --------------------------------------------- band Lie algebra products
+// Group layout: 12 scalar fields of one vector field f: f_c at index c,
+// d_i f_c at index 3 + 3c + i.
+// (ad*_a mu)_i = sum_j (d_i a_j) mu_j + (d_j mu_i) a_j + mu_i (d_j a_j)
+__device__ __forceinline__ void adstar_acc(float* o, const float* a, const float* mu, float s) {
+  const float diva = a[3] + a[7] + a[11];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float r = mu[i] * diva;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      r = fmaf(a[3 + 3 * j + i], mu[j], r);
+      r = fmaf(mu[3 + 3 * i + j], a[j], r);
+    }
+    o[i] = fmaf(s, r, o[i]);
+  }
+}
+
+// (ad_a b)_i = sum_j (d_j a_i) b_j - (d_j b_i) a_j
+__device__ __forceinline__ void ad_acc(float* o, const float* a, const float* b, float s) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float r = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      r = fmaf(a[3 + 3 * i + j], b[j], r);
+      r = fmaf(-b[3 + 3 * i + j], a[j], r);
+    }
+    o[i] = fmaf(s, r, o[i]);
+  }
+}
+
+// ------------------------------------------------ fused padded-grid step
+// One block per (x0, R consecutive x1 rows).  It synthesises the new groups
+// on its points (inverse stages 1 and 2, from the stage-0 output), stores
+// them if asked, forms the Lie products of the program at each point, and
+// contracts the products over x2 (forward stage 2).
+__global__ void __launch_bounds__(256) k_mstep(MStepArgs a, Twiddles tw, int M0, int M1, int M2,
+                                               int K1, int Kh, int R) {
+  extern __shared__ float smem[];
+  const int P = R * M2;
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, M1 - x1b);
+  const long long nM = (long long)M0 * M1 * M2;
+  const long long gbase = ((long long)x0 * M1 + x1b) * M2;
+  const int C = K1 * Kh;
+
+  const int nf = (a.nnew * 12 * P + a.nout * P + 3) & ~3;
+  float* fld = smem;                                   // nnew*12*P
+  float* outv = fld + a.nnew * 12 * P;                 // nout*P
+  float2* t1s = (float2*)(smem + nf);                  // 2*C
+  float2* t2s = t1s + 2 * C;                           // 3*R*Kh
+  float2* w1s = t2s + 3 * R * Kh;                      // 2*R*K1
+  float2* w2s = w1s + 2 * R * K1;                      // 2*M2*Kh
+  float2* wf2 = w2s + 2 * M2 * Kh;                     // Kh*M2
+
+  for (int i = threadIdx.x; i < 2 * R * K1; i += blockDim.x) {
+    int v = i / (R * K1), r = (i / K1) % R, k = i % K1;
+    int x1 = x1b + r;
+    w1s[i] = (x1 < M1) ? tw.inv1[((size_t)v * M1 + x1) * K1 + k] : make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < 2 * M2 * Kh; i += blockDim.x) w2s[i] = tw.inv2[i];
+  if (a.nout > 0)
+    for (int i = threadIdx.x; i < Kh * M2; i += blockDim.x) wf2[i] = tw.fwd2[i];
+
+  for (int g = 0; g < a.nnew; ++g) {
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();
+      const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
+      for (int i = threadIdx.x; i < 2 * C; i += blockDim.x) {
+        int v = i / C, e = i % C;
+        t1s[i] = src[((size_t)v * M0 + x0) * C + e];
+      }
+      __syncthreads();
+      // T2 rows: var 0 = plain/plain, 1 = plain/d1, 2 = d0/plain
+      for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
+        int var = i / (R * Kh), r = (i / Kh) % R, kh = i % Kh;
+        int vs = (var == 2) ? 1 : 0, vt = (var == 1) ? 1 : 0;
+        float2 acc = make_float2(0.f, 0.f);
+        const float2* wr = w1s + ((size_t)vt * R + r) * K1;
+        const float2* tc = t1s + (size_t)vs * C + kh;
+        for (int k = 0; k < K1; ++k) cmac(acc, wr[k], tc[(size_t)k * Kh]);
+        t2s[i] = acc;
+      }
+      __syncthreads();
+      // real outputs: value, d2, d1, d0
+      for (int i = threadIdx.x; i < 4 * P; i += blockDim.x) {
+        int ov = i / P, p = i % P;
+        int r = p / M2, x2 = p % M2;
+        int srcvar = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
+        int wv = (ov == 1) ? 1 : 0;
+        const float2* t = t2s + ((size_t)srcvar * R + r) * Kh;
+        const float2* w = w2s + ((size_t)wv * M2 + x2) * Kh;
+        float val = 0.f;
+        for (int kh = 0; kh < Kh; ++kh) {
+          val = fmaf(t[kh].x, w[kh].x, val);
+          val = fmaf(-t[kh].y, w[kh].y, val);
+        }
+        int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
+        fld[((size_t)g * 12 + f) * P + p] = (r < rv) ? val : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  for (int g = 0; g < a.nnew; ++g) {
+    if (!a.store[g]) continue;
+    for (int i = threadIdx.x; i < 12 * rv * M2; i += blockDim.x) {
+      int f = i / (rv * M2), p = i % (rv * M2);
+      a.store[g][(size_t)f * nM + gbase + p] = fld[((size_t)g * 12 + f) * P + p];
+    }
+  }
+  if (a.nout == 0) return;
+
+  // pointwise Lie products
+  for (int p = threadIdx.x; p < rv * M2; p += blockDim.x) {
+    float o[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = 0.f;
+    float A[12], B[12];
+    auto getnew = [&](int g, float* dst) {
+#pragma unroll
+      for (int f = 0; f < 12; ++f) dst[f] = fld[((size_t)g * 12 + f) * P + p];
+    };
+    auto getc = [&](int k, float* dst) {
+      const float* src = a.cached[k] + gbase + p;
+#pragma unroll
+      for (int f = 0; f < 12; ++f) dst[f] = src[(size_t)f * nM];
+    };
+    switch (a.prog) {
+      case PROG_SHOOT:
+        getnew(0, A); getnew(1, B);
+        adstar_acc(o, A, B, 1.f);
+        break;
+      case PROG_H1:
+        getnew(0, A); getc(1, B);            // ad*_dV(LV)
+        adstar_acc(o, A, B, 1.f);
+        getc(0, A); getnew(1, B);            // ad*_V(LdV)
+        adstar_acc(o, A, B, 1.f);
+        break;
+      case PROG_GRAD:
+        getc(0, A); getnew(0, B);            // ad*_V(LU)
+        adstar_acc(o, A, B, 1.f);
+        getnew(1, B);                        // ad_V(W)
+        ad_acc(o + 3, A, B, 1.f);
+        getc(1, A);                          // ad*_W(LV)
+        adstar_acc(o + 6, B, A, 1.f);
+        break;
+      case PROG_H5:
+        getc(0, A); getnew(0, B);            // ad*_V(LdU)
+        adstar_acc(o, A, B, 1.f);
+        getnew(1, B);                        // ad_V(dW)
+        ad_acc(o + 3, A, B, 1.f);
+        getc(1, A);                          // ad*_dW(LV)
+        adstar_acc(o + 6, B, A, 1.f);
+        getc(4, A); getc(2, B);              // ad*_dV(LU)
+        adstar_acc(o, A, B, 1.f);
+        getc(3, B);                          // ad_dV(W)
+        ad_acc(o + 3, A, B, 1.f);
+        getc(5, A);                          // ad*_W(LdV)
+        adstar_acc(o + 6, B, A, 1.f);
+        break;
+      case PROG_H5_NOCOUPLE:
+        getc(0, A); getnew(0, B);
+        adstar_acc(o, A, B, 1.f);
+        getnew(1, B);
+        ad_acc(o + 3, A, B, 1.f);
+        getc(1, A);
+        adstar_acc(o + 6, B, A, 1.f);
+        break;
+      default:
+        break;
+    }
+    for (int i = 0; i < a.nout; ++i) outv[(size_t)i * P + p] = o[i];
+  }
+  __syncthreads();
+  // forward stage 2: contraction over x2
+  for (int i = threadIdx.x; i < a.nout * rv * Kh; i += blockDim.x) {
+    int o = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
+    const float* row = outv + (size_t)o * P + r * M2;
+    const float2* w = wf2 + (size_t)kh * M2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x2 = 0; x2 < M2; ++x2) {
+      acc.x = fmaf(row[x2], w[x2].x, acc.x);
+      acc.y = fmaf(row[x2], w[x2].y, acc.y);
+    }
+    a.s1[(((size_t)o * M0 + x0) * M1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
+// ----------------------------------------------- forward stage 1 (x1)
+template <int QT>
+__global__ void __launch_bounds__(128) k_fwd1(Fwd1Jobs jobs, const float2* __restrict__ tw, int G0,
+                                              int G1, int K1, int Kh) {
+  extern __shared__ float2 sh[];
+  const Fwd1Job job = jobs.j[blockIdx.z];
+  const int qb = blockIdx.y * QT;
+  for (int i = threadIdx.x; i < QT * G1; i += blockDim.x) {
+    int t = i / G1, x = i % G1;
+    int q = qb + t;
+    sh[i] = (q < K1) ? tw[(size_t)q * G1 + x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (x0, kh)
+  if (e >= G0 * Kh) return;
+  const int x0 = e / Kh, kh = e % Kh;
+  float2 acc[QT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) acc[t] = make_float2(0.f, 0.f);
+  const float2* src = job.in + (size_t)x0 * G1 * Kh + kh;
+  for (int x = 0; x < G1; ++x) {
+    float2 val = src[(size_t)x * Kh];
+#pragma unroll
+    for (int t = 0; t < QT; ++t) cmac(acc[t], sh[t * G1 + x], val);
+  }
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    int q = qb + t;
+    if (q < K1) job.out[((size_t)x0 * K1 + q) * Kh + kh] = acc[t];
+  }
+}
+
+// ------------------------------------- forward stage 0 (x0) + epilogue
+template <int QT>
+__global__ void __launch_bounds__(128) k_fwd0(Fwd0Jobs jobs, const float2* __restrict__ tw,
+                                              const float* __restrict__ Ksym, int G0, int K0,
+                                              int K1, int Kh, float invG) {
+  extern __shared__ float2 sh[];
+  const Fwd0Job job = jobs.j[blockIdx.z];
+  const int qb = blockIdx.y * QT;
+  for (int i = threadIdx.x; i < QT * G0; i += blockDim.x) {
+    int t = i / G0, x = i % G0;
+    int q = qb + t;
+    sh[i] = (q < K0) ? tw[(size_t)q * G0 + x] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int C = K1 * Kh;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float2 aa[QT], bb[QT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) { aa[t] = make_float2(0.f, 0.f); bb[t] = make_float2(0.f, 0.f); }
+  for (int x = 0; x < G0; ++x) {
+    float2 va = job.a[(size_t)x * C + c];
+#pragma unroll
+    for (int t = 0; t < QT; ++t) cmac(aa[t], sh[t * G0 + x], va);
+  }
+  if (job.b) {
+    for (int x = 0; x < G0; ++x) {
+      float2 vb = job.b[(size_t)x * C + c];
+#pragma unroll
+      for (int t = 0; t < QT; ++t) cmac(bb[t], sh[t * G0 + x], vb);
+    }
+  }
+  const int q1 = c / Kh;
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    int q0 = qb + t;
+    if (q0 >= K0) continue;
+    size_t idx = (size_t)q0 * C + c;
+    float2 r = make_float2(0.f, 0.f);
+    if (q0 != K0 / 2 && q1 != K1 / 2) {
+      if (job.base) r = job.base[idx];
+      float ks = Ksym[idx];
+      float sa = job.ca * invG * (job.syma ? ks : 1.f);
+      r.x = fmaf(sa, aa[t].x, r.x);
+      r.y = fmaf(sa, aa[t].y, r.y);
+      if (job.b) {
+        float sb = job.cb * invG * (job.symb ? ks : 1.f);
+        r.x = fmaf(sb, bb[t].x, r.x);
+        r.y = fmaf(sb, bb[t].y, r.y);
+      }
+      if (job.extra) {
+        float2 e = job.extra[idx];
+        r.x = fmaf(job.ce, e.x, r.x);
+        r.y = fmaf(job.ce, e.y, r.y);
+      }
+    }
+    job.out[idx] = r;
+  }
+}
+
+// ----------------------------------------------------- grid step (N)
+// One block per (x0, R rows of x1): inverse stages 1 and 2 of the three
+// velocity components from their stage-0 output, then either the velocity
+// itself or the incremental-state source at each grid point.
+__global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, int N0, int N1,
+                                                  int N2, int K1, int Kh, int R) {
+  extern __shared__ float2 sh2[];
+  const int C = K1 * Kh;
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, N1 - x1b);
+  float2* t1s = sh2;                 // 3*C
+  float2* t2s = t1s + 3 * C;         // 3*R*Kh
+  float2* w1s = t2s + 3 * R * Kh;    // R*K1
+  float2* w2s = w1s + R * K1;        // N2*Kh
+  for (int i = threadIdx.x; i < 3 * C; i += blockDim.x) {
+    int c = i / C, e = i % C;
+    t1s[i] = a.t1[((size_t)c * N0 + x0) * C + e];
+  }
+  for (int i = threadIdx.x; i < R * K1; i += blockDim.x) {
+    int r = i / K1, k = i % K1;
+    int x1 = x1b + r;
+    w1s[i] = (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + k] : make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < N2 * Kh; i += blockDim.x) w2s[i] = tw.inv2[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
+    int c = i / (R * Kh), r = (i / Kh) % R, kh = i % Kh;
+    float2 acc = make_float2(0.f, 0.f);
+    const float2* wr = w1s + (size_t)r * K1;
+    const float2* tc = t1s + (size_t)c * C + kh;
+    for (int k = 0; k < K1; ++k) cmac(acc, wr[k], tc[(size_t)k * Kh]);
+    t2s[i] = acc;
+  }
+  __syncthreads();
+  const long long nN = (long long)N0 * N1 * N2;
+  for (int p = threadIdx.x; p < rv * N2; p += blockDim.x) {
+    int r = p / N2, x2 = p % N2;
+    const float2* w = w2s + (size_t)x2 * Kh;
+    float vel[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float2* t = t2s + ((size_t)c * R + r) * Kh;
+      float val = 0.f;
+      for (int kh = 0; kh < Kh; ++kh) {
+        val = fmaf(t[kh].x, w[kh].x, val);
+        val = fmaf(-t[kh].y, w[kh].y, val);
+      }
+      vel[c] = val;
+    }
+    const int x1 = x1b + r;
+    const long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+    if (a.op == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = vel[c];
+    } else {
+      const float* m = a.m;
+      int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
+      int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
+      int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
+      float g0 = (m[((long long)xp0 * N1 + x1) * N2 + x2] - m[((long long)xm0 * N1 + x1) * N2 + x2]) *
+                 (0.5f * N0);
+      float g1 = (m[((long long)x0 * N1 + xp1) * N2 + x2] - m[((long long)x0 * N1 + xm1) * N2 + x2]) *
+                 (0.5f * N1);
+      float g2 = (m[((long long)x0 * N1 + x1) * N2 + xp2] - m[((long long)x0 * N1 + x1) * N2 + xm2]) *
+                 (0.5f * N2);
+      float dot = g0 * vel[0] + g1 * vel[1] + g2 * vel[2];
+      float base = a.dm ? a.dm[gi] : 0.f;
+      a.q[gi] = fmaf(-a.dt, dot, base);
+    }
+  }
+}
+
+// ----------------------------------------- semi-Lagrangian step (N)
+// dst(x) = src(x - dt v(x)) by periodic trilinear interpolation; v in
+// domain units, converted to voxels per axis.
+__global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
+                                            const float* __restrict__ vel, float* __restrict__ dst,
+                                            float dt, int N0, int N1, int N2) {
+  const long long nN = (long long)N0 * N1 * N2;
+  long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= nN) return;
+  int i2 = (int)(gi % N2);
+  int i1 = (int)((gi / N2) % N1);
+  int i0 = (int)(gi / ((long long)N1 * N2));
+  float X0 = (float)i0 - dt * vel[gi] * (float)N0;
+  float X1 = (float)i1 - dt * vel[nN + gi] * (float)N1;
+  float X2 = (float)i2 - dt * vel[2 * nN + gi] * (float)N2;
+  // a non-finite velocity must not turn into an out-of-range index
+  if (!isfinite(X0)) X0 = (float)i0;
+  if (!isfinite(X1)) X1 = (float)i1;
+  if (!isfinite(X2)) X2 = (float)i2;
+  float f0 = floorf(X0), f1 = floorf(X1), f2 = floorf(X2);
+  float w0 = X0 - f0, w1 = X1 - f1, w2 = X2 - f2;
+  int a0 = (int)f0 % N0; if (a0 < 0) a0 += N0;
+  int a1 = (int)f1 % N1; if (a1 < 0) a1 += N1;
+  int a2 = (int)f2 % N2; if (a2 < 0) a2 += N2;
+  int b0 = (a0 + 1 == N0) ? 0 : a0 + 1;
+  int b1 = (a1 + 1 == N1) ? 0 : a1 + 1;
+  int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
+  auto at = [&](int u, int v, int w) { return src[((long long)u * N1 + v) * N2 + w]; };
+  float c00 = at(a0, a1, a2) + w2 * (at(a0, a1, b2) - at(a0, a1, a2));
+  float c01 = at(a0, b1, a2) + w2 * (at(a0, b1, b2) - at(a0, b1, a2));
+  float c10 = at(b0, a1, a2) + w2 * (at(b0, a1, b2) - at(b0, a1, a2));
+  float c11 = at(b0, b1, a2) + w2 * (at(b0, b1, b2) - at(b0, b1, a2));
+  float c0 = c00 + w1 * (c01 - c00);
+  float c1 = c10 + w1 * (c11 - c10);
+  dst[gi] = c0 + w0 * (c1 - c0);
+}
+
+// ------------------- image-term source and forward stage 2 (N grid)
+// s_j = coef * (a - b) * d_j m (periodic central differences), contracted
+// over x2: s1[j][x0][x1][kh].
+__global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
+                                                  const float* __restrict__ b,
+                                                  const float* __restrict__ m, float coef,
+                                                  float2* __restrict__ s1, Twiddles tw, int N0,
+                                                  int N1, int N2, int Kh, int R) {
+  extern __shared__ float shs[];
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, N1 - x1b);
+  const int P = R * N2;
+  float* vals = shs;                                   // 3*P
+  float2* wf2 = (float2*)(vals + ((3 * P + 3) & ~3));  // Kh*N2
+  for (int i = threadIdx.x; i < Kh * N2; i += blockDim.x) wf2[i] = tw.fwd2[i];
+  for (int p = threadIdx.x; p < rv * N2; p += blockDim.x) {
+    int r = p / N2, x2 = p % N2;
+    int x1 = x1b + r;
+    long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+    int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
+    int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
+    int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
+    float g0 = (m[((long long)xp0 * N1 + x1) * N2 + x2] - m[((long long)xm0 * N1 + x1) * N2 + x2]) *
+               (0.5f * N0);
+    float g1 = (m[((long long)x0 * N1 + xp1) * N2 + x2] - m[((long long)x0 * N1 + xm1) * N2 + x2]) *
+               (0.5f * N1);
+    float g2 = (m[((long long)x0 * N1 + x1) * N2 + xp2] - m[((long long)x0 * N1 + x1) * N2 + xm2]) *
+               (0.5f * N2);
+    float r0 = a[gi] - (b ? b[gi] : 0.f);
+    float s = coef * r0;
+    vals[p] = s * g0;
+    vals[P + p] = s * g1;
+    vals[2 * P + p] = s * g2;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * rv * Kh; i += blockDim.x) {
+    int j = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
+    const float* row = vals + (size_t)j * P + r * N2;
+    const float2* w = wf2 + (size_t)kh * N2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x2 = 0; x2 < N2; ++x2) {
+      acc.x = fmaf(row[x2], w[x2].x, acc.x);
+      acc.y = fmaf(row[x2], w[x2].y, acc.y);
+    }
+    s1[(((size_t)j * N0 + x0) * N1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
+// ------------------------------------------------------ elementwise
+__global__ void k_fill(float* p, long long n, float v) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+__global__ void k_axpy_band(const float2* x, const float2* y, float a, float2* out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 u = x[i], v = y[i];
+  out[i] = make_float2(fmaf(a, v.x, u.x), fmaf(a, v.y, u.y));
+}
+
+// ------------------------------------------------------- reductions
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  return r;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_sqdiff(const float* a, const float* b, long long n,
+                                                        double* partial) {
+  __shared__ double sh[kRedThreads / 64];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double d = (double)a[i] - (double)(b ? b[i] : 0.f);
+    s += d * d;
+  }
+  double r = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// sum_c sum_k w(k2) (L~ if given) Re(conj a b), w = 1 at k2 = 0 else 2
+__global__ void __launch_bounds__(kRedThreads) k_band_dot(const float2* a, const float2* b,
+                                                          const float* Lsym, int nb, int Kh,
+                                                          double* partial) {
+  __shared__ double sh[kRedThreads / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nb; i += gridDim.x * blockDim.x) {
+    int e = i % nb;
+    double w = (e % Kh == 0) ? 1.0 : 2.0;
+    if (Lsym) w *= (double)Lsym[e];
+    s += w * ((double)a[i].x * b[i].x + (double)a[i].y * b[i].y);
+  }
+  double r = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_band_maxabs(const float2* a, int n,
+                                                             double* partial) {
+  __shared__ double sh[kRedThreads];
+  double m = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    m = fmax(m, sqrt((double)a[i].x * a[i].x + (double)a[i].y * a[i].y));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_final(const double* partial, int n, double* out,
+                                                       double scale, int is_max) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s = is_max ? fmax(s, partial[i]) : s + partial[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      sh[threadIdx.x] = is_max ? fmax(sh[threadIdx.x], sh[threadIdx.x + o])
+                               : sh[threadIdx.x] + sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = scale * sh[0];
+}
+
+__global__ void k_energy_combine(double* sc) {
+  if (threadIdx.x == 0) sc[0] = sc[1] + sc[2];
+}
+
+__global__ void k_pcg_reset(double* sc) {
+  int i = threadIdx.x;
+  if (i < SC_COUNT && i != SC_RR) sc[i] = 0.0;
+}
+
+__global__ void k_scalar_copy(const double* s, double* d, int n) {
+  int i = threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+// ------------------------------------------------------------- CG
+__global__ void k_pcg_init(const float2* g, float2* p, float2* r, float2* dv, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 v = make_float2(-g[i].x, -g[i].y);
+  p[i] = make_float2(0.f, 0.f);
+  r[i] = v;
+  dv[i] = v;
+}
+
+// After <d, H d>_V: decide whether this iteration updates.
+__global__ void k_pcg_phase_a(double* sc, int it) {
+  if (threadIdx.x != 0) return;
+  sc[SC_DOUPD] = 0.0;
+  sc[SC_NEGG] = 0.0;
+  if (sc[SC_STOPPED] != 0.0) return;
+  if (!(sc[SC_RR] > 0.0)) { sc[SC_STOPPED] = 1.0; return; }
+  if (!(sc[SC_DHD] > 0.0)) {
+    sc[SC_STOPPED] = 1.0;
+    sc[SC_GUARD] = 1.0;
+    if (it == 0) sc[SC_NEGG] = 1.0;
+    return;
+  }
+  sc[SC_ALPHA] = sc[SC_RR] / sc[SC_DHD];
+  sc[SC_DOUPD] = 1.0;
+}
+
+__global__ void k_pcg_update_pr(const double* sc, const float2* dv, const float2* Hd, float2* p,
+                                float2* r, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (sc[SC_NEGG] != 0.0) { p[i] = dv[i]; return; }  // first iteration: d = -g
+  if (sc[SC_DOUPD] == 0.0) return;
+  float al = (float)sc[SC_ALPHA];
+  float2 pv = p[i], rv = r[i], dd = dv[i], hd = Hd[i];
+  p[i] = make_float2(fmaf(al, dd.x, pv.x), fmaf(al, dd.y, pv.y));
+  r[i] = make_float2(fmaf(-al, hd.x, rv.x), fmaf(-al, hd.y, rv.y));
+}
+
+__global__ void k_pcg_phase_b(double* sc) {
+  if (threadIdx.x != 0) return;
+  if (sc[SC_DOUPD] == 0.0) return;
+  sc[SC_BETA] = sc[SC_RRNEW] / sc[SC_RR];
+  sc[SC_RR] = sc[SC_RRNEW];
+  sc[SC_ITERS] += 1.0;
+}
+
+__global__ void k_pcg_update_d(const double* sc, const float2* r, float2* dv, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (sc[SC_DOUPD] == 0.0) return;
+  float be = (float)sc[SC_BETA];
+  float2 rv = r[i], dd = dv[i];
+  dv[i] = make_float2(fmaf(be, dd.x, rv.x), fmaf(be, dd.y, rv.y));
+}
+
+// ================================================= launch wrappers
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_twiddles(float2* dst, int K, int G, int mode, hipStream_t st) {
+  int Kq = (mode == 1 || mode == 3) ? K / 2 : K;
+  int total = (mode <= 1) ? 2 * G * Kq : Kq * G;
+  hipLaunchKernelGGL(k_twiddles, dim3(nblk(total, 256)), dim3(256), 0, st, dst, K, G, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_symbols(float* Lsym, float* Ksym, const Dims& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_symbols, dim3(nblk(d.nb, 256)), dim3(256), 0, st, Lsym, Ksym, d.K[0], d.K[1],
+                     d.Kh, d.s, d.alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_full_to_half(const float2* full, float2* half, const Dims& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_full_to_half, dim3(nblk(3LL * d.nb, 256)), dim3(256), 0, st, full, half,
+                     d.K[0], d.K[1], d.K[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float2* full,
+                               const Dims& d, hipStream_t st) {
+  long long n = 3LL * d.K[0] * d.K[1] * d.K[2];
+  hipLaunchKernelGGL(k_half_to_full, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, cb, full, d.K[0],
+                     d.K[1], d.K[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
+                       int K0, int C, int G0, hipStream_t st) {
+  const int T = 128;
+  if (nvar == 2) {
+    constexpr int XT = 8;
+    dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
+    size_t shm = 2 * XT * K0 * sizeof(float2);
+    timer_begin(4, st);
+    hipLaunchKernelGGL((k_inv0<2, XT>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0);
+    timer_end(4, st);
+  } else {
+    constexpr int XT = 16;
+    dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
+    size_t shm = XT * K0 * sizeof(float2);
+    timer_begin(4, st);
+    hipLaunchKernelGGL((k_inv0<1, XT>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0);
+    timer_end(4, st);
+  }
+  return hipGetLastError();
+}
+
+static int mstep_rows(const Dims& d) {
+  int R = 256 / d.M[2];
+  if (R < 1) R = 1;
+  if (R > d.M[1]) R = d.M[1];
+  return R;
+}
+
+size_t mstep_shared_bytes(const Dims& d, int nnew, int nout) {
+  const int R = mstep_rows(d);
+  const int P = R * d.M[2];
+  const int C = d.K[1] * d.Kh;
+  size_t floats = ((size_t)nnew * 12 * P + (size_t)nout * P + 3) & ~(size_t)3;
+  size_t cplx = 2 * (size_t)C + 3 * (size_t)R * d.Kh + 2 * (size_t)R * d.K[1] + 2 * (size_t)d.M[2] * d.Kh +
+                (size_t)d.Kh * d.M[2];
+  return floats * sizeof(float) + cplx * sizeof(float2) + 16;
+}
+
+hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
+  const int R = mstep_rows(d);
+  dim3 grid(nblk(d.M[1], R), d.M[0]);
+  size_t shm = mstep_shared_bytes(d, a.nnew, a.nout);
+  timer_begin(1, st);
+  hipLaunchKernelGGL(k_mstep, grid, dim3(256), shm, st, a, tw, d.M[0], d.M[1], d.M[2], d.K[1], d.Kh,
+                     R);
+  timer_end(1, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
+                       int Kh, hipStream_t st) {
+  constexpr int QT = 8;
+  const int T = 128;
+  dim3 grid(nblk((long long)G0 * Kh, T), nblk(K1, QT), njobs);
+  size_t shm = QT * G1 * sizeof(float2);
+  timer_begin(5, st);
+  hipLaunchKernelGGL((k_fwd1<QT>), grid, dim3(T), shm, st, jobs, tw, G0, G1, K1, Kh);
+  timer_end(5, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const float* Ksym, int G0,
+                       int K0, int K1, int Kh, float invG, hipStream_t st) {
+  constexpr int QT = 8;
+  const int T = 128;
+  dim3 grid(nblk((long long)K1 * Kh, T), nblk(K0, QT), njobs);
+  size_t shm = QT * G0 * sizeof(float2);
+  timer_begin(5, st);
+  hipLaunchKernelGGL((k_fwd0<QT>), grid, dim3(T), shm, st, jobs, tw, Ksym, G0, K0, K1, Kh, invG);
+  timer_end(5, st);
+  return hipGetLastError();
+}
+
+static int grid_rows(const Dims& d) {
+  int R = 256 / d.N[2];
+  if (R < 1) R = 1;
+  if (R > d.N[1]) R = d.N[1];
+  return R;
+}
+
+size_t gridstep_shared_bytes(const Dims& d) {
+  const int R = grid_rows(d);
+  const int C = d.K[1] * d.Kh;
+  return (3 * (size_t)C + 3 * (size_t)R * d.Kh + (size_t)R * d.K[1] + (size_t)d.N[2] * d.Kh) *
+         sizeof(float2);
+}
+
+size_t src_shared_bytes(const Dims& d) {
+  const int R = grid_rows(d);
+  return (size_t)((3 * R * d.N[2] + 3) & ~3) * sizeof(float) + (size_t)d.Kh * d.N[2] * sizeof(float2);
+}
+
+hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
+  const int R = grid_rows(d);
+  const int C = d.K[1] * d.Kh;
+  (void)C;
+  dim3 grid(nblk(d.N[1], R), d.N[0]);
+  size_t shm = gridstep_shared_bytes(d);
+  timer_begin(2, st);
+  hipLaunchKernelGGL(k_gridstep, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1],
+                     d.Kh, R);
+  timer_end(2, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
+                     hipStream_t st) {
+  timer_begin(3, st);
+  hipLaunchKernelGGL(k_sl, dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, d.N[0],
+                     d.N[1], d.N[2]);
+  timer_end(3, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
+                           const Dims& d, const Twiddles& tw, hipStream_t st) {
+  const int R = grid_rows(d);
+  dim3 grid(nblk(d.N[1], R), d.N[0]);
+  size_t shm = src_shared_bytes(d);
+  hipLaunchKernelGGL(k_src_fwd2, grid, dim3(256), shm, st, a, b, m, coef, s1, tw, d.N[0], d.N[1],
+                     d.N[2], d.Kh, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* s, float* dd, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(nblk(n, 256)), dim3(256), 0, st, s, dd, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* out, int n,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_band, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, a, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* partial, double* out,
+                         double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_sqdiff, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, n, partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, partial, kRedBlocks, out, scale, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
+                           double* partial, double* out, double scale, hipStream_t st) {
+  const int blocks = 64;
+  hipLaunchKernelGGL(k_band_dot, dim3(blocks), dim3(kRedThreads), 0, st, a, b, Lsym, d.nb, d.Kh,
+                     partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, partial, blocks, out, scale, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_maxabs(const float2* a, const Dims& d, double* partial, double* out,
+                              hipStream_t st) {
+  const int blocks = 64;
+  hipLaunchKernelGGL(k_band_maxabs, dim3(blocks), dim3(kRedThreads), 0, st, a, 3 * d.nb, partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, partial, blocks, out, 1.0, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_copy(const double* src, double* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_combine(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_combine, dim3(1), dim3(64), 0, st, sc);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_reset(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_reset, dim3(1), dim3(64), 0, st, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dv, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblk(n, 256)), dim3(256), 0, st, g, p, r, dv, n);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_phase_a(double* sc, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_phase_a, dim3(1), dim3(64), 0, st, sc, it);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_update_pr(const double* sc, const float2* dv, const float2* Hd, float2* p,
+                                float2* r, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update_pr, dim3(nblk(n, 256)), dim3(256), 0, st, sc, dv, Hd, p, r, n);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_phase_b(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_phase_b, dim3(1), dim3(64), 0, st, sc);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dv, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update_d, dim3(nblk(n, 256)), dim3(256), 0, st, sc, r, dv, n);
+  return hipGetLastError();
+}
+
+}  // namespace lddmm

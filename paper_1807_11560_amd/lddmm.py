@@ -1,0 +1,259 @@
+"""Python binding of liblddmm.so (include/lddmm.h): argument marshalling only.
+
+Every step of shooting, transport, gradient, Hessian-vector product and
+registration runs in the HIP library; torch provides device memory and the
+stream.  Importing this module fails loudly if the library has not been
+built (``python -m paper_1807_11560_amd.build``).
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblddmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first (python -m paper_1807_11560_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+W_LINESEARCH = 1
+E_INVALID_ARG = -1
+E_SHAPE = -2
+E_WORKSPACE = -3
+E_HIP = -4
+E_NOT_PREPARED = -5
+E_NONFINITE = -6
+FP32 = 0
+GN_PAPER = 0
+GN_CLASSICAL = 1
+KF_MSTEP, KF_GRID_SRC, KF_SL, KF_INV0, KF_FWD = 1, 2, 3, 4, 5
+
+
+class LddmmParams(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("grid", ctypes.c_int32 * 3),
+        ("band", ctypes.c_int32 * 3),
+        ("spectral", ctypes.c_int32 * 3),
+        ("time_steps", ctypes.c_int32),
+        ("s", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("hessian", ctypes.c_int32),
+    ]
+
+
+class LddmmStats(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double),
+        ("energy_reg", ctypes.c_double),
+        ("energy_data", ctypes.c_double),
+        ("mse_rel", ctypes.c_double),
+        ("grad_inf_rel", ctypes.c_double),
+        ("step", ctypes.c_double),
+        ("trials", ctypes.c_int32),
+        ("pcg_iters", ctypes.c_int32),
+        ("pcg_guard", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER(LddmmParams)
+_SIGS = {
+    "lddmm_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "lddmm_shoot": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_gradient": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_hessvec": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_register": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(LddmmStats), ctypes.c_int32, _vp,
+                                      ctypes.c_size_t, _vp]),
+    "lddmm_last_register_hvps": (ctypes.c_int64, []),
+    "lddmm_kernel_timer": (ctypes.c_int, [ctypes.c_int32]),
+    "lddmm_kernel_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_double)]),
+    "lddmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lddmm_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class LddmmError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        detail = _lib.lddmm_last_error().decode()
+        super().__init__(f"{where}: {_lib.lddmm_status_string(code).decode()} ({code}): {detail}")
+
+
+def _check(code, where):
+    if code < 0:
+        raise LddmmError(code, where)
+    return code
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Parameters of one registration problem (paper §3.2 problem statement)."""
+
+    grid: Tuple[int, int, int]
+    band: Tuple[int, int, int]
+    time_steps: int = 10
+    alpha: float = 0.0025
+    s: int = 2
+    sigma: float = 0.03
+    spectral: Tuple[int, int, int] = (0, 0, 0)
+    hessian: int = GN_PAPER
+
+    def c_params(self) -> LddmmParams:
+        p = LddmmParams()
+        p.ndim = len(self.grid)
+        for j in range(3):
+            p.grid[j] = int(self.grid[j]) if j < len(self.grid) else 1
+            p.band[j] = int(self.band[j]) if j < len(self.band) else 1
+            p.spectral[j] = int(self.spectral[j]) if j < len(self.spectral) else 0
+        p.time_steps = int(self.time_steps)
+        p.s = int(self.s)
+        p.alpha = float(self.alpha)
+        p.sigma = float(self.sigma)
+        p.precision = FP32
+        p.hessian = int(self.hessian)
+        return p
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check(_lib.lddmm_workspace_bytes(ctypes.byref(self.c_params()), ctypes.byref(n)),
+               "lddmm_workspace_bytes")
+        return n.value
+
+    @property
+    def band_shape(self):
+        return (3,) + tuple(self.band)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Workspace:
+    """Device workspace owned by torch; carries the gradient -> hessvec state."""
+
+    def __init__(self, problem: Problem, device=None):
+        torch = _torch()
+        self.problem = problem
+        self.nbytes = problem.workspace_bytes()
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device or "cuda")
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def shoot(problem: Problem, I0, v0, ws: Workspace, want_v1=False, stream=None):
+    """m_1 (and v_1) of the band geodesic from v0 (lddmm_shoot)."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    m1 = torch.empty_like(I0)
+    v1 = torch.empty_like(v0) if want_v1 else None
+    _check(_lib.lddmm_shoot(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(v0), _ptr(m1), _ptr(v1),
+                            ws.ptr, ws.nbytes, _stream(stream)), "lddmm_shoot")
+    return (m1, v1) if want_v1 else m1
+
+
+def gradient(problem: Problem, I0, I1, v0, ws: Workspace, stream=None):
+    """(g_V, energy[3] float64 on the device) at v0 (lddmm_gradient)."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(I1, torch.float32, problem.grid, "I1")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    g = torch.empty_like(v0)
+    e3 = torch.empty(3, dtype=torch.float64, device=v0.device)
+    _check(_lib.lddmm_gradient(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0), _ptr(g),
+                               _ptr(e3), ws.ptr, ws.nbytes, _stream(stream)), "lddmm_gradient")
+    return g, e3
+
+
+def hessvec(problem: Problem, dv0, ws: Workspace, out=None, stream=None):
+    """Gauss-Newton H_V dv0 at the v0 of the last gradient on ws (lddmm_hessvec)."""
+    torch = _torch()
+    _need(dv0, torch.complex64, problem.band_shape, "dv0")
+    if out is None:
+        out = torch.empty_like(dv0)
+    else:
+        _need(out, torch.complex64, problem.band_shape, "out")
+    _check(_lib.lddmm_hessvec(ctypes.byref(problem.c_params()), _ptr(dv0), _ptr(out), ws.ptr, ws.nbytes,
+                              _stream(stream)), "lddmm_hessvec")
+    return out
+
+
+def register(problem: Problem, I0, I1, ws: Workspace, gn_iters=10, pcg_iters=20, v0=None,
+             stream=None):
+    """Gauss-Newton-Krylov registration (lddmm_register).
+
+    Returns (v0, stats, status, hvps): the result, one dict per GN iteration,
+    OK or W_LINESEARCH, and the number of Hessian-vector products."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(I1, torch.float32, problem.grid, "I1")
+    if v0 is None:
+        v0 = torch.zeros(problem.band_shape, dtype=torch.complex64, device=I0.device)
+    else:
+        _need(v0, torch.complex64, problem.band_shape, "v0")
+    stats = (LddmmStats * max(gn_iters, 1))()
+    rc = _check(_lib.lddmm_register(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0),
+                                    int(gn_iters), int(pcg_iters), stats, int(gn_iters), ws.ptr,
+                                    ws.nbytes, _stream(stream)), "lddmm_register")
+    recs = []
+    for i in range(gn_iters):
+        s = stats[i]
+        if s.trials == 0:
+            break
+        recs.append({f: getattr(s, f) for f, _ in LddmmStats._fields_ if f != "reserved"})
+    return v0, recs, rc, int(_lib.lddmm_last_register_hvps())
+
+
+def kernel_timer(family: int):
+    _check(_lib.lddmm_kernel_timer(int(family)), "lddmm_kernel_timer")
+
+
+def kernel_timer_read():
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.lddmm_kernel_timer_read(ctypes.byref(n), ctypes.byref(ms)), "lddmm_kernel_timer_read")
+    return n.value, ms.value
+
+
+def raw():
+    """The loaded ctypes library (for tests of the C-ABI itself)."""
+    return _lib

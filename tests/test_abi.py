@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every entry point include/lddmm.h
+declares; host-side validation and workspace sizing (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1807_11560_amd import lddmm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lddmm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lddmm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "lddmm_hessvec" in names and "lddmm_register" in names and len(names) >= 10
+    lib = L.raw()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors have the C compiler's size and offsets."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "lddmm.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu", sizeof(lddmm_params),'
+        ' offsetof(lddmm_params, alpha), offsetof(lddmm_params, hessian),'
+        ' sizeof(lddmm_stats), offsetof(lddmm_stats, trials)); return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [ctypes.sizeof(L.LddmmParams), L.LddmmParams.alpha.offset,
+                   L.LddmmParams.hessian.offset, ctypes.sizeof(L.LddmmStats),
+                   L.LddmmStats.trials.offset]
+
+
+def test_workspace_bytes_scales_with_problem():
+    small = L.Problem(grid=(32, 32, 32), band=(8, 8, 8)).workspace_bytes()
+    big = L.Problem(grid=(128, 128, 128), band=(32, 32, 32), s=3).workspace_bytes()
+    assert 0 < small < big
+    assert big < 2 * 1024 ** 3  # fits comfortably in one MI355X
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(band=(15, 16, 16)), L.E_SHAPE),            # odd band
+    (dict(band=(16, 16, 80)), L.E_SHAPE),            # band larger than 64
+    (dict(grid=(12, 64, 64)), L.E_SHAPE),            # band > grid
+    (dict(spectral=(20, 0, 0)), L.E_SHAPE),          # alias-free bound 3K/2 - 2 = 22
+    (dict(alpha=0.0), L.E_INVALID_ARG),
+    (dict(sigma=-1.0), L.E_INVALID_ARG),
+    (dict(s=0), L.E_INVALID_ARG),
+    (dict(time_steps=0), L.E_INVALID_ARG),
+    (dict(hessian=7), L.E_INVALID_ARG),
+])
+def test_validation_rejects(kw, code):
+    base = dict(grid=(64, 64, 64), band=(16, 16, 16))
+    base.update(kw)
+    with pytest.raises(L.LddmmError) as e:
+        L.Problem(**base).workspace_bytes()
+    assert e.value.code == code
+
+
+def test_two_dimensional_problems_are_rejected_by_the_gpu_library():
+    p = L.Problem(grid=(64, 64, 64), band=(16, 16, 16)).c_params()
+    p.ndim = 2
+    n = ctypes.c_size_t(0)
+    assert L.raw().lddmm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == L.E_SHAPE
+
+
+def test_entry_points_validate_before_touching_the_device():
+    """Null pointers and short workspaces are rejected on the host."""
+    lib = L.raw()
+    p = L.Problem(grid=(32, 32, 32), band=(8, 8, 8)).c_params()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.lddmm_shoot(ctypes.byref(p), null, fake, fake, null, fake, 1 << 40, null) == L.E_INVALID_ARG
+    assert lib.lddmm_shoot(ctypes.byref(p), fake, fake, fake, null, fake, 16, null) == L.E_WORKSPACE
+    assert lib.lddmm_hessvec(ctypes.byref(p), fake, fake, fake, 1 << 40, null) == L.E_INVALID_ARG
+    assert lib.lddmm_hessvec(ctypes.byref(p), fake, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000),
+                             1 << 40, null) == L.E_NOT_PREPARED
+    assert lib.lddmm_register(ctypes.byref(p), fake, fake, fake, 1, 0, None, 0, fake, 1 << 40,
+                              null) == L.E_INVALID_ARG
+    assert b"grid" in lib.lddmm_status_string(L.E_SHAPE) or lib.lddmm_status_string(L.E_SHAPE)
