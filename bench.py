@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: Hessian-vector products/s and registrations/min of band-limited
+Jacobi PDE-EPDiff LDDMM (Gauss-Newton-Krylov) on one MI355X.
+
+Workload: the 128^3 synthetic tissue phantom, band 32^3 (padded grid 48^3),
+L = (Id - 0.0025 Laplacian)^3, sigma = 0.03, 10 Euler steps; the target is
+the phantom warped by a random band-limited geodesic of 8 voxels maximal
+displacement.  One step = one full registration from v0 = 0: 10 Gauss-Newton
+iterations, each with the gradient, 20 CG iterations (one Hessian-vector
+product each) and the Armijo line search.  Inputs are resident in HBM before
+the timed region.
+
+Prints one JSON line on stdout (everything else goes to stderr).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hessian-vector products/s + registrations/min, 128³ band 32³, FP32/BF16 vs FP64"
+CONFIG = 3
+PEAK_TFLOPS_FP32 = 157.3
+PEAK_GBS_HBM = 8000.0
+FAMILIES = {1: "k_mstep", 2: "k_gridstep", 3: "k_sl", 4: "k_inv0", 5: "k_fwd1+k_fwd0"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hvp-loop", type=int, default=50, help="extra pure hessvec calls timed")
+    return ap.parse_args()
+
+
+def roofline(fam, launches, ms, flops, nbytes):
+    t = ms * 1e-3
+    tf = flops / t / 1e12
+    gbs = nbytes / t / 1e9
+    f_alu = tf / PEAK_TFLOPS_FP32
+    f_hbm = gbs / PEAK_GBS_HBM
+    if f_hbm > f_alu:
+        return {"bound": "hbm", "achieved": gbs, "peak": PEAK_GBS_HBM, "unit": "GB/s", "frac": f_hbm,
+                "traffic": None, "kernel": FAMILIES[fam], "launches": launches,
+                "avg_us": 1e3 * ms / max(launches, 1), "flops_tflops": tf}
+    return {"bound": "alu", "achieved": tf, "peak": PEAK_TFLOPS_FP32, "unit": "TFLOP/s", "frac": f_alu,
+            "traffic": None, "kernel": FAMILIES[fam], "launches": launches,
+            "avg_us": 1e3 * ms / max(launches, 1), "hbm_gbs": gbs}
+
+
+def cpu_baseline(w):
+    """The FP64 oracle on the host: one Hessian-vector product of the same
+    problem at v0 = v*/2, after an untimed oracle gradient."""
+    from oracle import Params
+    from oracle.jacobi import forward, gradient, hessvec
+    from paper_1807_11560_amd import synth
+    try:
+        import threadpoolctl
+        cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    pp = w["params"]
+    p = Params(grid=pp["grid"], band=pp["band"], nt=pp["nt"], alpha=pp["alpha"], s=pp["s"], sigma=pp["sigma"])
+    I0, vstar = w["I0"], w["v_star"]
+    I1 = forward(vstar, I0, p)[2][-1]
+    _, _, cache = gradient(0.5 * vstar, I0, I1, p)
+    d = synth.random_direction(4242, p.band, s=pp["s"])
+    t0 = time.perf_counter()
+    hessvec(cache, d, p, "R1")
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "HVP/s", "cores": int(cores), "kind": "oracle",
+            "sample": "one Hessian-vector product of the 128^3 / band 32^3 problem at v0 = v*/2 "
+                      "(FP64 NumPy, after an untimed oracle gradient)",
+            "seconds": t}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1807_11560_amd import lddmm as L
+    from paper_1807_11560_amd import synth
+
+    w = synth.workload(CONFIG)
+    pp = w["params"]
+    prob = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
+                     sigma=pp["sigma"], hessian=L.GN_PAPER)
+    gn, pcg = pp["gn"], pp["pcg"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ws = L.Workspace(prob, dev)
+    I0 = torch.from_numpy(w["I0"]).float().to(dev)
+    vstar = torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev)
+    I1 = L.shoot(prob, I0, vstar, ws)
+    torch.cuda.synchronize()
+    log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
+
+    # dominant kernel family, from a short Hessian-vector product loop
+    L.gradient(prob, I0, I1, 0.5 * vstar, ws)
+    d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
+    out = torch.empty_like(d)
+    fam_ms = {}
+    for fam in FAMILIES:
+        L.kernel_timer(fam)
+        for _ in range(3):
+            L.hessvec(prob, d, ws, out=out)
+        torch.cuda.synchronize()
+        fam_ms[fam] = L.kernel_timer_read()[1] / 3
+    L.kernel_timer(0)
+    dominant = max(fam_ms, key=fam_ms.get)
+    log("per-HVP ms by family: " + ", ".join(f"{FAMILIES[f]} {fam_ms[f]:.3f}" for f in FAMILIES))
+
+    for _ in range(args.warmup):
+        L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
+    torch.cuda.synchronize()
+
+    L.kernel_timer(dominant)
+    hvps = 0
+    stats = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v, stats, rc, n = L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
+        hvps += n
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    launches, kms, kfl, kby = L.kernel_timer_read()
+    L.kernel_timer(0)
+    log(f"timed {args.steps} registrations in {T:.3f} s, {hvps} HVPs; last status {rc}")
+    for i, s in enumerate(stats):
+        log(f"  GN {i}: E {s['energy']:.5f} MSE_rel {s['mse_rel']:.3f} |g|rel {s['grad_inf_rel']:.4f} "
+            f"eps {s['step']} pcg {s['pcg_iters']}")
+
+    # pure Hessian-vector product rate (same problem, last iterate)
+    L.gradient(prob, I0, I1, v, ws)
+    for _ in range(3):
+        L.hessvec(prob, d, ws, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.hvp_loop):
+        L.hessvec(prob, d, ws, out=out)
+    torch.cuda.synchronize()
+    hvp_only = args.hvp_loop / (time.perf_counter() - t1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline(w)
+        log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
+
+    res = {
+        "metric": METRIC,
+        "value": hvps / T,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "tissue phantom 128^3 registered to its warp by a random band-limited geodesic "
+                        "(8 voxels), band 32^3, padded grid 48^3, s=3, alpha=0.0025, sigma=0.03, nt=10, "
+                        "10 Gauss-Newton x 20 CG iterations, paper Gauss-Newton reading",
+            "grid": list(prob.grid), "band": list(prob.band), "time_steps": prob.time_steps,
+            "gn_iters": gn, "pcg_iters": pcg,
+        },
+        "registrations_per_min": 60.0 * args.steps / T,
+        "hvps_per_registration": hvps / args.steps,
+        "hvp_only_per_s": hvp_only,
+        "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
+        "roofline": roofline(dominant, launches, kms, kfl, kby),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,13 +166,17 @@ int64_t lddmm_last_register_hvps(void);
 
 /* Launch timing of one kernel family, for roofline accounting.  While
  * enabled, every launch of family `family` (LDDMM_KF_*) made by this process
- * is bracketed by HIP events on its stream; lddmm_kernel_timer_read
- * synchronises those events and returns the number of timed launches and
- * their summed duration in milliseconds.  Enabling resets the counters. */
+ * is bracketed by HIP events on its stream, and the algorithmic work of the
+ * launch (flops of the separable contractions and Lie products, HBM bytes of
+ * its inputs and outputs read or written once) is summed.
+ * lddmm_kernel_timer_read synchronises those events and returns the number
+ * of timed launches, their summed duration in milliseconds and the summed
+ * algorithmic flops and bytes.  Enabling (or LDDMM_KF_NONE) resets the
+ * counters.  Host only; not thread-safe against concurrent enabling. */
 enum { LDDMM_KF_NONE = 0, LDDMM_KF_MSTEP = 1, LDDMM_KF_GRID_SRC = 2, LDDMM_KF_SL = 3,
        LDDMM_KF_INV0 = 4, LDDMM_KF_FWD = 5 };
 int lddmm_kernel_timer(int32_t family);
-int lddmm_kernel_timer_read(int64_t* launches, double* total_ms);
+int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, double* bytes);
 
 /* Static description of a status code. */
 const char* lddmm_status_string(int code);

@@ -114,12 +114,19 @@ struct Timer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   int64_t launches = 0;
   double ms = 0.0;
+  double flops = 0.0, bytes = 0.0;
 };
 Timer g_timer;
 
 }  // namespace
 
 namespace lddmm {
+void timer_work(int family, double flops, double bytes) {
+  if (g_timer.family == 0 || family != g_timer.family) return;
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  g_timer.flops += flops;
+  g_timer.bytes += bytes;
+}
 void timer_begin(int family, hipStream_t st) {
   if (g_timer.family == 0 || family != g_timer.family) return;
   std::lock_guard<std::mutex> lk(g_timer.mu);
@@ -365,10 +372,12 @@ int lddmm_kernel_timer(int32_t family) {
   g_timer.family = family;
   g_timer.launches = 0;
   g_timer.ms = 0.0;
+  g_timer.flops = 0.0;
+  g_timer.bytes = 0.0;
   return LDDMM_OK;
 }
 
-int lddmm_kernel_timer_read(int64_t* launches, double* total_ms) {
+int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, double* bytes) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
   for (auto& ev : g_timer.pending) {
     if (hipEventSynchronize(ev.second) != hipSuccess) return fail(LDDMM_E_HIP, "event sync");
@@ -382,6 +391,8 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms) {
   g_timer.pending.clear();
   if (launches) *launches = g_timer.launches;
   if (total_ms) *total_ms = g_timer.ms;
+  if (flops) *flops = g_timer.flops;
+  if (bytes) *bytes = g_timer.bytes;
   return LDDMM_OK;
 }
 

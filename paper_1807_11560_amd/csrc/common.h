@@ -142,6 +142,9 @@ hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dvec, 
                                hipStream_t st);
 
 // Kernel-family timing (see lddmm_kernel_timer).
+// timer_work records the algorithmic flops and HBM bytes of the launch that
+// follows (counted only while its family is being timed).
+void timer_work(int family, double flops, double bytes);
 void timer_begin(int family, hipStream_t st);
 void timer_end(int family, hipStream_t st);
 

@@ -785,6 +785,14 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
                        int K0, int C, int G0, hipStream_t st) {
   const int T = 128;
+  {
+    double fl = 0, by = 0;
+    for (int i = 0; i < njobs; ++i) {
+      fl += 8.0 * nvar * G0 * K0 * (double)C;
+      by += 8.0 * K0 * (double)C * (1 + nvar * (double)G0 / K0) + (jobs.j[i].lflag ? 4.0 * K0 * C : 0.0);
+    }
+    timer_work(4, fl, by);
+  }
   if (nvar == 2) {
     constexpr int XT = 8;
     dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
@@ -824,6 +832,19 @@ hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, h
   const int R = mstep_rows(d);
   dim3 grid(nblk(d.M[1], R), d.M[0]);
   size_t shm = mstep_shared_bytes(d, a.nnew, a.nout);
+  {
+    static const double prog_flops[6] = {0, 47, 94, 136, 272, 136};
+    const double nM = (double)d.nM, C = (double)d.K[1] * d.Kh;
+    double fl = a.nnew * 3.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0) +
+                prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
+    int nstore = (a.store[0] != nullptr) + (a.store[1] != nullptr);
+    int ncached = 0;
+    static const int prog_cached[6] = {0, 0, 2, 2, 6, 2};
+    ncached = prog_cached[a.prog];
+    double by = a.nnew * 3.0 * 2.0 * d.M[0] * C * 8.0 + (nstore + ncached) * 12.0 * nM * 4.0 +
+                a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
+    timer_work(1, fl, by);
+  }
   timer_begin(1, st);
   hipLaunchKernelGGL(k_mstep, grid, dim3(256), shm, st, a, tw, d.M[0], d.M[1], d.M[2], d.K[1], d.Kh,
                      R);
@@ -837,6 +858,8 @@ hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0
   const int T = 128;
   dim3 grid(nblk((long long)G0 * Kh, T), nblk(K1, QT), njobs);
   size_t shm = QT * G1 * sizeof(float2);
+  timer_work(5, njobs * 8.0 * G0 * Kh * (double)K1 * G1,
+             njobs * 8.0 * ((double)G0 * G1 * Kh + (double)G0 * K1 * Kh));
   timer_begin(5, st);
   hipLaunchKernelGGL((k_fwd1<QT>), grid, dim3(T), shm, st, jobs, tw, G0, G1, K1, Kh);
   timer_end(5, st);
@@ -849,6 +872,17 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
   const int T = 128;
   dim3 grid(nblk((long long)K1 * Kh, T), nblk(K0, QT), njobs);
   size_t shm = QT * G0 * sizeof(float2);
+  {
+    const double C = (double)K1 * Kh;
+    double fl = 0, by = 0;
+    for (int i = 0; i < njobs; ++i) {
+      const Fwd0Job& j = jobs.j[i];
+      int terms = 1 + (j.b != nullptr);
+      fl += terms * 8.0 * K0 * C * G0;
+      by += terms * 8.0 * G0 * C + 8.0 * K0 * C * (1 + (j.base != nullptr) + (j.extra != nullptr)) + 4.0 * K0 * C;
+    }
+    timer_work(5, fl, by);
+  }
   timer_begin(5, st);
   hipLaunchKernelGGL((k_fwd0<QT>), grid, dim3(T), shm, st, jobs, tw, Ksym, G0, K0, K1, Kh, invG);
   timer_end(5, st);
@@ -880,6 +914,12 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
   (void)C;
   dim3 grid(nblk(d.N[1], R), d.N[0]);
   size_t shm = gridstep_shared_bytes(d);
+  {
+    const double nN = (double)d.nN;
+    double fl = 3.0 * d.N[0] * d.N[1] * d.Kh * d.K[1] * 8.0 + 3.0 * nN * d.Kh * 4.0 + (a.op ? 15.0 * nN : 0.0);
+    double by = 3.0 * d.N[0] * (double)C * 8.0 + (a.op ? (a.dm ? 12.0 : 8.0) * nN : 12.0 * nN);
+    timer_work(2, fl, by);
+  }
   timer_begin(2, st);
   hipLaunchKernelGGL(k_gridstep, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1],
                      d.Kh, R);
@@ -889,6 +929,7 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
 
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st) {
+  timer_work(3, 40.0 * (double)d.nN, 20.0 * (double)d.nN);
   timer_begin(3, st);
   hipLaunchKernelGGL(k_sl, dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, d.N[0],
                      d.N[1], d.N[2]);

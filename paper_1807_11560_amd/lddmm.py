@@ -76,6 +76,8 @@ _SIGS = {
     "lddmm_last_register_hvps": (ctypes.c_int64, []),
     "lddmm_kernel_timer": (ctypes.c_int, [ctypes.c_int32]),
     "lddmm_kernel_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double)]),
     "lddmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, []),
@@ -248,10 +250,14 @@ def kernel_timer(family: int):
 
 
 def kernel_timer_read():
+    """(launches, total ms, algorithmic flops, algorithmic bytes) of the timed family."""
     n = ctypes.c_int64(0)
     ms = ctypes.c_double(0.0)
-    _check(_lib.lddmm_kernel_timer_read(ctypes.byref(n), ctypes.byref(ms)), "lddmm_kernel_timer_read")
-    return n.value, ms.value
+    fl = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    _check(_lib.lddmm_kernel_timer_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)),
+           "lddmm_kernel_timer_read")
+    return n.value, ms.value, fl.value, by.value
 
 
 def raw():
