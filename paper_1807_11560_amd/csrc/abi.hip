@@ -80,6 +80,7 @@ int validate(const lddmm_params* p, Dims* d) {
     o.K[j] = K;
     o.M[j] = M;
   }
+  if (o.N[2] > 256) return fail(LDDMM_E_SHAPE, "the last grid axis must be at most 256");
   o.Kh = o.K[2] / 2;
   o.nb = o.K[0] * o.K[1] * o.Kh;
   o.nN = (long long)o.N[0] * o.N[1] * o.N[2];
@@ -91,7 +92,7 @@ int validate(const lddmm_params* p, Dims* d) {
   o.hessian = p->hessian;
   // the fused step kernel keeps a block's fields in LDS
   // each block keeps its rows in LDS (at most 64 KiB per block)
-  if (mstep_shared_bytes(o, 2, 9) > 64 * 1024)
+  if (mstep_shared_bytes(o, 2, 9) > 64 * 1024 || colstep_shared_bytes(o) > 64 * 1024)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
   if (gridstep_shared_bytes(o) > 64 * 1024 || src_shared_bytes(o) > 64 * 1024)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");

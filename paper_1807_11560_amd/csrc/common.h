@@ -65,9 +65,28 @@ struct MStepArgs {
   const float2* t1[2];    // stage-0 output of new group g: [3 comps][2 vars][M0][K1*Kh]
   float* store[2];        // cache for new group g: [12][nM], or null
   const float* cached[6]; // cached groups: [12][nM] each
-  float2* s1;             // [nout][M0][M1][Kh] forward stage-2 output
+  float2* s1;             // [nout][Kh][M0][M1] forward stage-2 output
   int nnew, nout, prog;
 };
+
+// Band-side step of one output component (k_colstep): forward stages 1 and
+// 0 of one or two product fields s1 ([Kh][M0][M1] each), the update
+// out = base + ca*(K~ if syma)*F(a) + cb*(K~ if symb)*F(b) + ce*extra, and
+// the inverse stage 0 of out (of L~ out where t1l) into up to two stage-0
+// buffers [2 vars][M0][K1*Kh] for the next step.
+struct ColJob {
+  const float2* a;
+  const float2* b;
+  const float2* base;
+  const float2* extra;
+  float2* out;
+  float2* t1[2];
+  float ca, cb, ce;
+  int syma, symb;
+  int t1l[2];
+  int nt1;
+};
+struct ColJobs { ColJob j[8]; };
 
 struct Fwd1Job { const float2* in; float2* out; };   // [G0][G1][Kh] -> [G0][K1][Kh]
 struct Fwd1Jobs { Fwd1Job j[kMaxJobs]; };
@@ -105,6 +124,9 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
                        int K0, int C, int G0, hipStream_t st);
 hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
+hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
+                          const float* Lsym, const float* Ksym, hipStream_t st);
+size_t colstep_shared_bytes(const Dims& d);
 hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
                        int Kh, hipStream_t st);
 hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const float* Ksym, int G0,

@@ -63,18 +63,22 @@ class Engine {
 
  private:
   void layout(Carver& c);
-  hipError_t mstep_step(int prog, int nout, const float2* in0, int l0, const float2* in1, int l1,
-                        float* store0, float* store1, const float* const* cached);
-  hipError_t fwd_batch(int nout, Fwd0Job* jobs, int njobs, bool gridN);
+  float2* t1(int g, int c) const;
+  const float2* s1(int o) const;
+  const float2* s2n(int o) const;
+  hipError_t inv0_groups(const float2* in0, int l0, const float2* in1, int l1);
+  hipError_t mstep(int prog, int nout, float* store0, float* store1, const float* const* cached);
+  ColJob col_job(int c, int oa, float ca, int syma, int ob, float cb, int symb, const float2* base,
+                 const float2* extra, float ce, float2* out, int g0, int l0, int g1, int l1) const;
+  hipError_t colstep(const ColJob* jobs, int n);
+  hipError_t fwd_grid(Fwd0Job* jobs, int njobs);
   hipError_t grid_velocities(const std::vector<float2*>& bands, int count, std::vector<float*>& out);
-  const float2* s2(int o, bool gridN) const;
 
   Dims d_;
   hipStream_t st_;
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;
-  float2 *T1_ = nullptr, *S1_ = nullptr, *S2_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr,
-         *S2N_ = nullptr;
+  float2 *T1_ = nullptr, *S1_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
 };
 
 }  // namespace lddmm

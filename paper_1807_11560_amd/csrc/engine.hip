@@ -1,11 +1,12 @@
 // Host engine of band-limited Jacobi PDE-EPDiff LDDMM (paper §3.2).
 //
-// Per Euler step on the padded grid the engine issues four launches:
-// stage 0 of the inverse transforms of the new fields (k_inv0), the fused
-// step kernel (inverse stages 1-2, Lie products, forward stage 2; k_mstep),
-// and forward stages 1 and 0 with the band update as epilogue (k_fwd1,
-// k_fwd0).  Fields of the trajectory that later sweeps reuse are cached on
-// the padded grid when they are first synthesised.
+// Per Euler step on the padded grid the engine issues two launches: the
+// fused step kernel (inverse stages 1-2 of the new fields, their Lie
+// products, forward stage 2; k_mstep) and the column kernel (forward stages
+// 1-0, the band update, and stage 0 of the next step's inverse transforms;
+// k_colstep).  The first step of a sweep gets its stage 0 from k_inv0.
+// Fields of the trajectory that later sweeps reuse are cached on the padded
+// grid when they are first synthesised.
 #include "engine.h"
 
 #include <algorithm>
@@ -62,7 +63,6 @@ void Engine::layout(Carver& c) {
   const size_t C = (size_t)d.K[1] * d.Kh;
   T1_ = c.take<float2>(2 * 3 * 2 * (size_t)d.M[0] * C);
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
-  S2_ = c.take<float2>(9 * (size_t)d.M[0] * C);
   const int chunk = std::min(nt, kGridChunk);
   T1N_ = c.take<float2>((size_t)chunk * 3 * d.N[0] * C);
   S1N_ = c.take<float2>(3 * (size_t)d.N[0] * d.N[1] * d.Kh);
@@ -116,60 +116,92 @@ hipError_t Engine::store_band(const float2* a, const float2* b, float cb, void* 
   return launch_half_to_full(a, b, cb, static_cast<float2*>(full), d_, st_);
 }
 
-// Stage 0 for the new groups, then the fused step kernel.
-hipError_t Engine::mstep_step(int prog, int nout, const float2* in0, int l0, const float2* in1,
-                              int l1, float* store0, float* store1, const float* const* cached) {
+float2* Engine::t1(int g, int c) const {
+  return T1_ + (size_t)(g * 3 + c) * 2 * d_.M[0] * d_.K[1] * d_.Kh;
+}
+
+const float2* Engine::s1(int o) const { return S1_ + (size_t)o * d_.Kh * d_.M[0] * d_.M[1]; }
+
+// Inverse stage 0 of the new groups of a step (at the start of a sweep;
+// later steps get it from the column kernel of the previous step).
+hipError_t Engine::inv0_groups(const float2* in0, int l0, const float2* in1, int l1) {
   const int C = d_.K[1] * d_.Kh;
-  const size_t t1comp = 2 * (size_t)d_.M[0] * C;
   Inv0Jobs jobs{};
   int nj = 0;
   const float2* ins[2] = {in0, in1};
   const int lf[2] = {l0, l1};
-  const int nnew = in1 ? 2 : 1;
-  for (int g = 0; g < nnew; ++g)
+  for (int g = 0; g < 2; ++g)
     for (int c = 0; c < 3; ++c) {
       jobs.j[nj].in = ins[g] + (size_t)c * d_.nb;
-      jobs.j[nj].out = T1_ + (size_t)(g * 3 + c) * t1comp;
+      jobs.j[nj].out = t1(g, c);
       jobs.j[nj].lflag = lf[g];
       ++nj;
     }
-  TRY(launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], st_));
+  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], st_);
+}
+
+hipError_t Engine::mstep(int prog, int nout, float* store0, float* store1, const float* const* cached) {
   MStepArgs a{};
-  for (int g = 0; g < nnew; ++g) a.t1[g] = T1_ + (size_t)g * 3 * t1comp;
+  a.t1[0] = t1(0, 0);
+  a.t1[1] = t1(1, 0);
   a.store[0] = store0;
   a.store[1] = store1;
   for (int k = 0; k < 6; ++k) a.cached[k] = cached ? cached[k] : nullptr;
   a.s1 = S1_;
-  a.nnew = nnew;
+  a.nnew = 2;
   a.nout = nout;
   a.prog = prog;
   return launch_mstep(a, d_, twM_, st_);
 }
 
-// Forward stages 1 and 0 of `nout` padded-grid fields (or of the three
-// grid fields when gridN) with the given band epilogues.
-hipError_t Engine::fwd_batch(int nout, Fwd0Job* jobs, int njobs, bool gridN) {
-  const int C = d_.K[1] * d_.Kh;
-  const int* G = gridN ? d_.N : d_.M;
-  float2* S1 = gridN ? S1N_ : S1_;
-  float2* S2 = gridN ? S2N_ : S2_;
-  const Twiddles& tw = gridN ? twN_ : twM_;
-  Fwd1Jobs j1{};
-  for (int o = 0; o < nout; ++o) {
-    j1.j[o].in = S1 + (size_t)o * G[0] * G[1] * d_.Kh;
-    j1.j[o].out = S2 + (size_t)o * G[0] * C;
+// One column job: out_c = base + ca S F(s1[oa]) (+ cb S F(s1[ob])) + ce extra;
+// next-step stage 0 into group g0 (L flag l0) and optionally g1 (l1).
+ColJob Engine::col_job(int c, int oa, float ca, int syma, int ob, float cb, int symb,
+                       const float2* base, const float2* extra, float ce, float2* out, int g0, int l0,
+                       int g1, int l1) const {
+  ColJob j{};
+  j.a = s1(oa);
+  j.ca = ca;
+  j.syma = syma;
+  if (ob >= 0) {
+    j.b = s1(ob);
+    j.cb = cb;
+    j.symb = symb;
   }
-  TRY(launch_fwd1(j1, nout, tw.fwd1, G[0], G[1], d_.K[1], d_.Kh, st_));
+  j.base = base ? base + (size_t)c * d_.nb : nullptr;
+  j.extra = extra ? extra + (size_t)c * d_.nb : nullptr;
+  j.ce = ce;
+  j.out = out + (size_t)c * d_.nb;
+  j.nt1 = 0;
+  if (g0 >= 0) { j.t1[j.nt1] = t1(g0, c); j.t1l[j.nt1] = l0; ++j.nt1; }
+  if (g1 >= 0) { j.t1[j.nt1] = t1(g1, c); j.t1l[j.nt1] = l1; ++j.nt1; }
+  return j;
+}
+
+hipError_t Engine::colstep(const ColJob* jobs, int n) {
+  ColJobs js{};
+  for (int i = 0; i < n; ++i) js.j[i] = jobs[i];
+  return launch_colstep(js, n, d_, twM_, Lsym, Ksym, st_);
+}
+
+// Forward stages 1 and 0 of the three grid fields in S1N with the given
+// band epilogues.
+hipError_t Engine::fwd_grid(Fwd0Job* jobs, int njobs) {
+  const int C = d_.K[1] * d_.Kh;
+  const int* G = d_.N;
+  Fwd1Jobs j1{};
+  for (int o = 0; o < 3; ++o) {
+    j1.j[o].in = S1N_ + (size_t)o * G[0] * G[1] * d_.Kh;
+    j1.j[o].out = S2N_ + (size_t)o * G[0] * C;
+  }
+  TRY(launch_fwd1(j1, 3, twN_.fwd1, G[0], G[1], d_.K[1], d_.Kh, st_));
   Fwd0Jobs j0{};
   for (int k = 0; k < njobs; ++k) j0.j[k] = jobs[k];
   const float invG = (float)(1.0 / ((double)G[0] * G[1] * G[2]));
-  return launch_fwd0(j0, njobs, tw.fwd0, Ksym, G[0], d_.K[0], d_.K[1], d_.Kh, invG, st_);
+  return launch_fwd0(j0, njobs, twN_.fwd0, Ksym, G[0], d_.K[0], d_.K[1], d_.Kh, invG, st_);
 }
 
-const float2* Engine::s2(int o, bool gridN) const {
-  const int C = d_.K[1] * d_.Kh;
-  return (gridN ? S2N_ : S2_) + (size_t)o * (gridN ? d_.N[0] : d_.M[0]) * C;
-}
+const float2* Engine::s2n(int o) const { return S2N_ + (size_t)o * d_.N[0] * d_.K[1] * d_.Kh; }
 
 // Band fields -> grid velocities vg[n] for the first `count` entries.
 hipError_t Engine::grid_velocities(const std::vector<float2*>& bands, int count,
@@ -201,20 +233,17 @@ hipError_t Engine::grid_velocities(const std::vector<float2*>& bands, int count,
 
 hipError_t Engine::shoot_band(bool cache) {
   const float dt = 1.0f / d_.nt;
+  TRY(inv0_groups(V[0], 0, V[0], 1));
   for (int n = 0; n < d_.nt; ++n) {
     float* st0 = cache ? VG[n] : nullptr;
     float* st1 = cache ? VG[n] + 12 * (size_t)d_.nM : nullptr;
-    TRY(mstep_step(PROG_SHOOT, 3, V[n], 0, V[n], 1, st0, st1, nullptr));
-    Fwd0Job jobs[3];
-    for (int c = 0; c < 3; ++c) {
-      jobs[c] = Fwd0Job{};
-      jobs[c].a = s2(c, false);
-      jobs[c].ca = -dt;
-      jobs[c].syma = 1;
-      jobs[c].base = V[n] + (size_t)c * d_.nb;
-      jobs[c].out = V[n + 1] + (size_t)c * d_.nb;
-    }
-    TRY(fwd_batch(3, jobs, 3, false));
+    TRY(mstep(PROG_SHOOT, 3, st0, st1, nullptr));
+    const bool next = n + 1 < d_.nt;
+    ColJob jobs[3];
+    for (int c = 0; c < 3; ++c)
+      jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, V[n], nullptr, 0.f, V[n + 1], next ? 0 : -1, 0,
+                        next ? 1 : -1, 1);
+    TRY(colstep(jobs, 3));
   }
   return hipSuccess;
 }
@@ -258,41 +287,30 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
   const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
   // U_nt = K~ pi(lambda_1 grad_h m_nt), lambda_1 = -(2/sigma^2)(m_nt - I1)
   TRY(launch_src_fwd2(m[nt], I1, m[nt], coef, S1N_, d_, twN_, st_));
-  Fwd0Job jobs[9];
+  Fwd0Job fj[3];
   for (int c = 0; c < 3; ++c) {
-    jobs[c] = Fwd0Job{};
-    jobs[c].a = s2(c, true);
-    jobs[c].ca = 1.f;
-    jobs[c].syma = 1;
-    jobs[c].out = U[nt] + (size_t)c * d_.nb;
+    fj[c] = Fwd0Job{};
+    fj[c].a = s2n(c);
+    fj[c].ca = 1.f;
+    fj[c].syma = 1;
+    fj[c].out = U[nt] + (size_t)c * d_.nb;
   }
-  TRY(fwd_batch(3, jobs, 3, true));
+  TRY(fwd_grid(fj, 3));
   TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
+  TRY(inv0_groups(U[nt], 1, W[nt], 0));
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * (size_t)d_.nM, nullptr, nullptr, nullptr, nullptr};
-    TRY(mstep_step(PROG_GRAD, 9, U[n + 1], 1, W[n + 1], 0, UG[n], WG[n], cached));
+    TRY(mstep(PROG_GRAD, 9, UG[n], WG[n], cached));
+    const bool next = n > 0;
+    ColJob jobs[6];
     for (int c = 0; c < 3; ++c) {
-      Fwd0Job& ju = jobs[c];
-      ju = Fwd0Job{};
-      ju.a = s2(c, false);
-      ju.ca = dt;
-      ju.syma = 1;
-      ju.base = U[n + 1] + (size_t)c * d_.nb;
-      ju.out = U[n] + (size_t)c * d_.nb;
-      Fwd0Job& jw = jobs[3 + c];
-      jw = Fwd0Job{};
-      jw.a = s2(3 + c, false);
-      jw.ca = -dt;
-      jw.syma = 0;
-      jw.b = s2(6 + c, false);
-      jw.cb = dt;
-      jw.symb = 1;
-      jw.base = W[n + 1] + (size_t)c * d_.nb;
-      jw.extra = U[n + 1] + (size_t)c * d_.nb;
-      jw.ce = dt;
-      jw.out = W[n] + (size_t)c * d_.nb;
+      // U_n = U_{n+1} + dt K~ F(ad*_V LU)
+      jobs[c] = col_job(c, c, dt, 1, -1, 0.f, 0, U[n + 1], nullptr, 0.f, U[n], next ? 0 : -1, 1, -1, 0);
+      // W_n = W_{n+1} - dt F(ad_V W) + dt K~ F(ad*_W LV) + dt U_{n+1}
+      jobs[3 + c] = col_job(c, 3 + c, -dt, 0, 6 + c, dt, 1, W[n + 1], U[n + 1], dt, W[n],
+                            next ? 1 : -1, 0, -1, 0);
     }
-    TRY(fwd_batch(9, jobs, 6, false));
+    TRY(colstep(jobs, 6));
   }
   if (g_out) TRY(launch_axpy_band(V[0], W[0], 1.f, g_out, 3 * d_.nb, st_));
   return hipSuccess;
@@ -306,30 +324,25 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
                                     6LL * d_.nb, st_));
   // incremental EPDiff forward
+  TRY(inv0_groups(dV[0], 0, dV[0], 1));
   for (int n = 0; n < nt; ++n) {
     const bool last = n == nt - 1;
     if (last && !coupled) break;
     const float* cached[6] = {VG[n], VG[n] + 12 * nM, nullptr, nullptr, nullptr, nullptr};
     float* st0 = coupled ? dVG[n] : nullptr;
     float* st1 = coupled ? dVG[n] + 12 * nM : nullptr;
-    TRY(mstep_step(last ? PROG_STORE : PROG_H1, last ? 0 : 3, dV[n], 0, dV[n], 1, st0, st1, cached));
+    TRY(mstep(last ? PROG_STORE : PROG_H1, last ? 0 : 3, st0, st1, cached));
     if (!last) {
-      Fwd0Job jobs[3];
-      for (int c = 0; c < 3; ++c) {
-        jobs[c] = Fwd0Job{};
-        jobs[c].a = s2(c, false);
-        jobs[c].ca = -dt;
-        jobs[c].syma = 1;
-        jobs[c].base = dV[n] + (size_t)c * d_.nb;
-        jobs[c].out = dV[n + 1] + (size_t)c * d_.nb;
-      }
-      TRY(fwd_batch(3, jobs, 3, false));
+      ColJob jobs[3];
+      for (int c = 0; c < 3; ++c)
+        jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1);
+      TRY(colstep(jobs, 3));
     }
   }
   // incremental state transport
   {
     const int C = d_.K[1] * d_.Kh;
-    const size_t t1 = (size_t)d_.N[0] * C;
+    const size_t t1n = (size_t)d_.N[0] * C;
     const float* dmcur = nullptr;
     for (int s0 = 0; s0 < nt; s0 += kGridChunk) {
       const int ns = std::min(kGridChunk, nt - s0);
@@ -338,7 +351,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
       for (int s = 0; s < ns; ++s)
         for (int c = 0; c < 3; ++c) {
           jobs.j[nj].in = dV[s0 + s] + (size_t)c * d_.nb;
-          jobs.j[nj].out = T1N_ + (size_t)(s * 3 + c) * t1;
+          jobs.j[nj].out = T1N_ + (size_t)(s * 3 + c) * t1n;
           jobs.j[nj].lflag = 0;
           ++nj;
         }
@@ -346,7 +359,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
       for (int s = 0; s < ns; ++s) {
         const int n = s0 + s;
         GridStepArgs a{};
-        a.t1 = T1N_ + (size_t)s * 3 * t1;
+        a.t1 = T1N_ + (size_t)s * 3 * t1n;
         a.op = 1;
         a.m = m[n];
         a.dm = dmcur;
@@ -361,46 +374,31 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
     // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt
     const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
     TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, st_));
-    Fwd0Job jobs[3];
+    Fwd0Job fj[3];
     for (int c = 0; c < 3; ++c) {
-      jobs[c] = Fwd0Job{};
-      jobs[c].a = s2(c, true);
-      jobs[c].ca = 1.f;
-      jobs[c].syma = 1;
-      jobs[c].out = dU[0] + (size_t)c * d_.nb;
+      fj[c] = Fwd0Job{};
+      fj[c].a = s2n(c);
+      fj[c].ca = 1.f;
+      fj[c].syma = 1;
+      fj[c].out = dU[0] + (size_t)c * d_.nb;
     }
-    TRY(fwd_batch(3, jobs, 3, true));
+    TRY(fwd_grid(fj, 3));
   }
   // incremental adjoint Jacobi sweep backward
   TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
+  TRY(inv0_groups(dU[0], 1, dW[0], 0));
   int cur = 0;
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * nM, UG[n], WG[n], dVG[n], dVG[n] + 12 * nM};
-    TRY(mstep_step(coupled ? PROG_H5 : PROG_H5_NOCOUPLE, 9, dU[cur], 1, dW[cur], 0, nullptr, nullptr,
-                   cached));
-    Fwd0Job jobs[6];
+    TRY(mstep(coupled ? PROG_H5 : PROG_H5_NOCOUPLE, 9, nullptr, nullptr, cached));
+    const bool next = n > 0;
+    ColJob jobs[6];
     for (int c = 0; c < 3; ++c) {
-      Fwd0Job& ju = jobs[c];
-      ju = Fwd0Job{};
-      ju.a = s2(c, false);
-      ju.ca = dt;
-      ju.syma = 1;
-      ju.base = dU[cur] + (size_t)c * d_.nb;
-      ju.out = dU[1 - cur] + (size_t)c * d_.nb;
-      Fwd0Job& jw = jobs[3 + c];
-      jw = Fwd0Job{};
-      jw.a = s2(3 + c, false);
-      jw.ca = -dt;
-      jw.syma = 0;
-      jw.b = s2(6 + c, false);
-      jw.cb = dt;
-      jw.symb = 1;
-      jw.base = dW[cur] + (size_t)c * d_.nb;
-      jw.extra = dU[cur] + (size_t)c * d_.nb;
-      jw.ce = dt;
-      jw.out = dW[1 - cur] + (size_t)c * d_.nb;
+      jobs[c] = col_job(c, c, dt, 1, -1, 0.f, 0, dU[cur], nullptr, 0.f, dU[1 - cur], next ? 0 : -1, 1, -1, 0);
+      jobs[3 + c] = col_job(c, 3 + c, -dt, 0, 6 + c, dt, 1, dW[cur], dU[cur], dt, dW[1 - cur],
+                            next ? 1 : -1, 0, -1, 0);
     }
-    TRY(fwd_batch(9, jobs, 6, false));
+    TRY(colstep(jobs, 6));
     cur = 1 - cur;
   }
   return launch_axpy_band(dV[0], dW[cur], 1.f, out, 3 * d_.nb, st_);

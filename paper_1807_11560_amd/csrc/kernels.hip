@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace lddmm {
 
 __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
@@ -183,40 +185,54 @@ __device__ __forceinline__ void ad_acc(float* o, const float* a, const float* b,
 }
 
 // ------------------------------------------------ fused padded-grid step
-// One block per (x0, R consecutive x1 rows).  It synthesises the new groups
-// on its points (inverse stages 1 and 2, from the stage-0 output), stores
-// them if asked, forms the Lie products of the program at each point, and
-// contracts the products over x2 (forward stage 2).
-__global__ void __launch_bounds__(256) k_mstep(MStepArgs a, Twiddles tw, int M0, int M1, int M2,
-                                               int K1, int Kh, int R) {
+// One block per (x0, R consecutive x1 rows), R*16 threads: thread (r, lane)
+// owns the points x2 = lane + 16 j (j < JN) of row x1 = x1b + r.  For each
+// new group it runs the inverse stages 1 (k1 -> x1, from the stage-0 output)
+// and 2 (half spectrum k2 -> real x2) for the value and the three partial
+// derivatives, keeping the 12 fields of each group in registers; stores them
+// if asked; forms the Lie products of the program; and contracts the
+// products over x2 (forward stage 2) into s1[o][kh][x0][x1].
+constexpr int kStepRows = 8;
+
+template <int JN, int R>
+__global__ void __launch_bounds__(R * 16) k_mstep(MStepArgs a, Twiddles tw, int M0, int M1, int M2,
+                                                   int K1, int Kh) {
   extern __shared__ float smem[];
-  const int P = R * M2;
+  const int C = K1 * Kh;
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
-  const int rv = min(R, M1 - x1b);
+  const int r = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int x1 = x1b + r;
+  const bool rowok = x1 < M1;
   const long long nM = (long long)M0 * M1 * M2;
-  const long long gbase = ((long long)x0 * M1 + x1b) * M2;
-  const int C = K1 * Kh;
+  const long long rowbase = ((long long)x0 * M1 + x1) * M2;
 
-  const int nf = (a.nnew * 12 * P + a.nout * P + 3) & ~3;
-  float* fld = smem;                                   // nnew*12*P
-  float* outv = fld + a.nnew * 12 * P;                 // nout*P
-  float2* t1s = (float2*)(smem + nf);                  // 2*C
-  float2* t2s = t1s + 2 * C;                           // 3*R*Kh
-  float2* w1s = t2s + 3 * R * Kh;                      // 2*R*K1
-  float2* w2s = w1s + 2 * R * K1;                      // 2*M2*Kh
-  float2* wf2 = w2s + 2 * M2 * Kh;                     // Kh*M2
+  float2* wfx = (float2*)smem;                 // [M2][Kh]
+  float2* t1s = wfx + M2 * Kh;                 // [2][C]
+  float2* t2s = t1s + 2 * C;                   // [3][R][Kh]
+  float2* w1s = t2s + 3 * R * Kh;              // [2][R][K1]
+  float2* w2t = w1s + 2 * R * K1;              // [2][Kh][M2]
+  float* outv = (float*)t1s;                   // [nout][R][M2], after the inverse part
 
-  for (int i = threadIdx.x; i < 2 * R * K1; i += blockDim.x) {
-    int v = i / (R * K1), r = (i / K1) % R, k = i % K1;
-    int x1 = x1b + r;
-    w1s[i] = (x1 < M1) ? tw.inv1[((size_t)v * M1 + x1) * K1 + k] : make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < M2 * Kh; i += blockDim.x) {
+    int x2 = i / Kh, kh = i % Kh;
+    wfx[i] = tw.fwd2[(size_t)kh * M2 + x2];
   }
-  for (int i = threadIdx.x; i < 2 * M2 * Kh; i += blockDim.x) w2s[i] = tw.inv2[i];
-  if (a.nout > 0)
-    for (int i = threadIdx.x; i < Kh * M2; i += blockDim.x) wf2[i] = tw.fwd2[i];
+  for (int i = threadIdx.x; i < 2 * R * K1; i += blockDim.x) {
+    int v = i / (R * K1), rr = (i / K1) % R, k = i % K1;
+    int xx = x1b + rr;
+    w1s[i] = (xx < M1) ? tw.inv1[((size_t)v * M1 + xx) * K1 + k] : make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < 2 * Kh * M2; i += blockDim.x) {
+    int v = i / (Kh * M2), kh = (i / M2) % Kh, x2 = i % M2;
+    w2t[i] = tw.inv2[((size_t)v * M2 + x2) * Kh + kh];
+  }
 
-  for (int g = 0; g < a.nnew; ++g) {
+  float F[2][12][JN];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (g >= a.nnew) break;
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       __syncthreads();
       const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
@@ -227,116 +243,241 @@ __global__ void __launch_bounds__(256) k_mstep(MStepArgs a, Twiddles tw, int M0,
       __syncthreads();
       // T2 rows: var 0 = plain/plain, 1 = plain/d1, 2 = d0/plain
       for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
-        int var = i / (R * Kh), r = (i / Kh) % R, kh = i % Kh;
+        int var = i / (R * Kh), rr = (i / Kh) % R, kh = i % Kh;
         int vs = (var == 2) ? 1 : 0, vt = (var == 1) ? 1 : 0;
         float2 acc = make_float2(0.f, 0.f);
-        const float2* wr = w1s + ((size_t)vt * R + r) * K1;
+        const float2* wr = w1s + ((size_t)vt * R + rr) * K1;
         const float2* tc = t1s + (size_t)vs * C + kh;
         for (int k = 0; k < K1; ++k) cmac(acc, wr[k], tc[(size_t)k * Kh]);
         t2s[i] = acc;
       }
       __syncthreads();
-      // real outputs: value, d2, d1, d0
-      for (int i = threadIdx.x; i < 4 * P; i += blockDim.x) {
-        int ov = i / P, p = i % P;
-        int r = p / M2, x2 = p % M2;
-        int srcvar = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
-        int wv = (ov == 1) ? 1 : 0;
-        const float2* t = t2s + ((size_t)srcvar * R + r) * Kh;
-        const float2* w = w2s + ((size_t)wv * M2 + x2) * Kh;
-        float val = 0.f;
-        for (int kh = 0; kh < Kh; ++kh) {
-          val = fmaf(t[kh].x, w[kh].x, val);
-          val = fmaf(-t[kh].y, w[kh].y, val);
+      float val[JN], d0[JN], d1[JN], d2[JN];
+#pragma unroll
+      for (int j = 0; j < JN; ++j) val[j] = d0[j] = d1[j] = d2[j] = 0.f;
+      for (int kh = 0; kh < Kh; ++kh) {
+        const float2 tpp = t2s[(0 * R + r) * Kh + kh];
+        const float2 tp1 = t2s[(1 * R + r) * Kh + kh];
+        const float2 t0p = t2s[(2 * R + r) * Kh + kh];
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+          int x2 = lane + 16 * j;
+          if (x2 >= M2) continue;
+          const float2 w0 = w2t[(size_t)kh * M2 + x2];
+          const float2 w1 = w2t[((size_t)Kh + kh) * M2 + x2];
+          val[j] = fmaf(tpp.x, w0.x, fmaf(-tpp.y, w0.y, val[j]));
+          d2[j] = fmaf(tpp.x, w1.x, fmaf(-tpp.y, w1.y, d2[j]));
+          d1[j] = fmaf(tp1.x, w0.x, fmaf(-tp1.y, w0.y, d1[j]));
+          d0[j] = fmaf(t0p.x, w0.x, fmaf(-t0p.y, w0.y, d0[j]));
         }
-        int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
-        fld[((size_t)g * 12 + f) * P + p] = (r < rv) ? val : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        F[g][c][j] = val[j];
+        F[g][3 + 3 * c + 0][j] = d0[j];
+        F[g][3 + 3 * c + 1][j] = d1[j];
+        F[g][3 + 3 * c + 2][j] = d2[j];
       }
     }
   }
-  __syncthreads();
-  for (int g = 0; g < a.nnew; ++g) {
-    if (!a.store[g]) continue;
-    for (int i = threadIdx.x; i < 12 * rv * M2; i += blockDim.x) {
-      int f = i / (rv * M2), p = i % (rv * M2);
-      a.store[g][(size_t)f * nM + gbase + p] = fld[((size_t)g * 12 + f) * P + p];
-    }
+  // cache the new groups
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (g >= a.nnew || !a.store[g] || !rowok) continue;
+#pragma unroll
+    for (int f = 0; f < 12; ++f)
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        int x2 = lane + 16 * j;
+        if (x2 < M2) a.store[g][(size_t)f * nM + rowbase + x2] = F[g][f][j];
+      }
   }
   if (a.nout == 0) return;
+  __syncthreads();  // the inverse part's LDS is reused for the products
 
   // pointwise Lie products
-  for (int p = threadIdx.x; p < rv * M2; p += blockDim.x) {
+#pragma unroll
+  for (int j = 0; j < JN; ++j) {
+    const int x2 = lane + 16 * j;
+    const bool ok = rowok && x2 < M2;
     float o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = 0.f;
-    float A[12], B[12];
-    auto getnew = [&](int g, float* dst) {
+    if (ok) {
+      float A[12], B[12];
+      const long long gp = rowbase + x2;
+      auto getnew = [&](int g, float* dst) {
 #pragma unroll
-      for (int f = 0; f < 12; ++f) dst[f] = fld[((size_t)g * 12 + f) * P + p];
-    };
-    auto getc = [&](int k, float* dst) {
-      const float* src = a.cached[k] + gbase + p;
+        for (int f = 0; f < 12; ++f) dst[f] = (g == 0) ? F[0][f][j] : F[1][f][j];
+      };
+      auto getc = [&](int k, float* dst) {
+        const float* src = a.cached[k] + gp;
 #pragma unroll
-      for (int f = 0; f < 12; ++f) dst[f] = src[(size_t)f * nM];
-    };
-    switch (a.prog) {
-      case PROG_SHOOT:
-        getnew(0, A); getnew(1, B);
-        adstar_acc(o, A, B, 1.f);
-        break;
-      case PROG_H1:
-        getnew(0, A); getc(1, B);            // ad*_dV(LV)
-        adstar_acc(o, A, B, 1.f);
-        getc(0, A); getnew(1, B);            // ad*_V(LdV)
-        adstar_acc(o, A, B, 1.f);
-        break;
-      case PROG_GRAD:
-        getc(0, A); getnew(0, B);            // ad*_V(LU)
-        adstar_acc(o, A, B, 1.f);
-        getnew(1, B);                        // ad_V(W)
-        ad_acc(o + 3, A, B, 1.f);
-        getc(1, A);                          // ad*_W(LV)
-        adstar_acc(o + 6, B, A, 1.f);
-        break;
-      case PROG_H5:
-        getc(0, A); getnew(0, B);            // ad*_V(LdU)
-        adstar_acc(o, A, B, 1.f);
-        getnew(1, B);                        // ad_V(dW)
-        ad_acc(o + 3, A, B, 1.f);
-        getc(1, A);                          // ad*_dW(LV)
-        adstar_acc(o + 6, B, A, 1.f);
-        getc(4, A); getc(2, B);              // ad*_dV(LU)
-        adstar_acc(o, A, B, 1.f);
-        getc(3, B);                          // ad_dV(W)
-        ad_acc(o + 3, A, B, 1.f);
-        getc(5, A);                          // ad*_W(LdV)
-        adstar_acc(o + 6, B, A, 1.f);
-        break;
-      case PROG_H5_NOCOUPLE:
-        getc(0, A); getnew(0, B);
-        adstar_acc(o, A, B, 1.f);
-        getnew(1, B);
-        ad_acc(o + 3, A, B, 1.f);
-        getc(1, A);
-        adstar_acc(o + 6, B, A, 1.f);
-        break;
-      default:
-        break;
+        for (int f = 0; f < 12; ++f) dst[f] = src[(size_t)f * nM];
+      };
+      switch (a.prog) {
+        case PROG_SHOOT:
+          getnew(0, A); getnew(1, B);
+          adstar_acc(o, A, B, 1.f);
+          break;
+        case PROG_H1:
+          getnew(0, A); getc(1, B);            // ad*_dV(LV)
+          adstar_acc(o, A, B, 1.f);
+          getc(0, A); getnew(1, B);            // ad*_V(LdV)
+          adstar_acc(o, A, B, 1.f);
+          break;
+        case PROG_GRAD:
+          getc(0, A); getnew(0, B);            // ad*_V(LU)
+          adstar_acc(o, A, B, 1.f);
+          getnew(1, B);                        // ad_V(W)
+          ad_acc(o + 3, A, B, 1.f);
+          getc(1, A);                          // ad*_W(LV)
+          adstar_acc(o + 6, B, A, 1.f);
+          break;
+        case PROG_H5:
+          getc(0, A); getnew(0, B);            // ad*_V(LdU)
+          adstar_acc(o, A, B, 1.f);
+          getnew(1, B);                        // ad_V(dW)
+          ad_acc(o + 3, A, B, 1.f);
+          getc(1, A);                          // ad*_dW(LV)
+          adstar_acc(o + 6, B, A, 1.f);
+          getc(4, A); getc(2, B);              // ad*_dV(LU)
+          adstar_acc(o, A, B, 1.f);
+          getc(3, B);                          // ad_dV(W)
+          ad_acc(o + 3, A, B, 1.f);
+          getc(5, A);                          // ad*_W(LdV)
+          adstar_acc(o + 6, B, A, 1.f);
+          break;
+        case PROG_H5_NOCOUPLE:
+          getc(0, A); getnew(0, B);
+          adstar_acc(o, A, B, 1.f);
+          getnew(1, B);
+          ad_acc(o + 3, A, B, 1.f);
+          getc(1, A);
+          adstar_acc(o + 6, B, A, 1.f);
+          break;
+        default:
+          break;
+      }
     }
-    for (int i = 0; i < a.nout; ++i) outv[(size_t)i * P + p] = o[i];
+    if (x2 < M2)
+      for (int i = 0; i < a.nout; ++i) outv[((size_t)i * R + r) * M2 + x2] = o[i];
   }
   __syncthreads();
-  // forward stage 2: contraction over x2
-  for (int i = threadIdx.x; i < a.nout * rv * Kh; i += blockDim.x) {
-    int o = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
-    const float* row = outv + (size_t)o * P + r * M2;
-    const float2* w = wf2 + (size_t)kh * M2;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int x2 = 0; x2 < M2; ++x2) {
-      acc.x = fmaf(row[x2], w[x2].x, acc.x);
-      acc.y = fmaf(row[x2], w[x2].y, acc.y);
+  // forward stage 2: contraction over x2, thread (r, kh)
+  if (!rowok) return;
+  for (int kh = lane; kh < Kh; kh += 16) {
+    for (int o = 0; o < a.nout; ++o) {
+      const float* row = outv + ((size_t)o * R + r) * M2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int x2 = 0; x2 < M2; ++x2) {
+        const float2 w = wfx[(size_t)x2 * Kh + kh];
+        acc.x = fmaf(row[x2], w.x, acc.x);
+        acc.y = fmaf(row[x2], w.y, acc.y);
+      }
+      a.s1[(((size_t)o * Kh + kh) * M0 + x0) * M1 + x1] = acc;
     }
-    a.s1[(((size_t)o * M0 + x0) * M1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
+// --------------------------------------- column step on the band side
+// One block per (job, kh, group of KG k1 values): forward stage 1 (x1 -> k1)
+// and stage 0 (x0 -> k0) of the job's one or two product fields at this kh,
+// the band update out = base + ca S_a F(a) + cb S_b F(b) + ce extra (S = K~
+// or 1), and the next step's inverse stage 0 (k0 -> x0, value and d0
+// variants, optionally of L~ out) for the same columns.
+template <int KG>
+__global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, const float* __restrict__ Lsym,
+                                                 const float* __restrict__ Ksym, int M0, int M1,
+                                                 int K0, int K1, int Kh, float invG) {
+  extern __shared__ float2 shc[];
+  const ColJob job = jobs.j[blockIdx.z];
+  const int kh = blockIdx.y;
+  const int kb = blockIdx.x * KG;
+  const int C = K1 * Kh;
+  const int nterm = job.b ? 2 : 1;
+  // region X: S1 slices (and later the inverse twiddles); region Y: the rest
+  const int xsz = max(2 * M0 * M1, 2 * M0 * K0);
+  float2* sx = shc;                       // [nterm][M0][M1]
+  float2* w0s = shc;                      // [2][M0][K0] (phase 3)
+  float2* wf1 = shc + xsz;                // [KG][M1]
+  float2* s2 = wf1 + KG * M1;             // [2][M0][KG]
+  float2* wf0 = s2 + 2 * M0 * KG;         // [K0][M0]
+  float2* bnd = wf0 + K0 * M0;            // [2][K0][KG]  (out, L~ out)
+
+  for (int t = 0; t < nterm; ++t) {
+    const float2* src = (t == 0 ? job.a : job.b) + (size_t)kh * M0 * M1;
+    for (int i = threadIdx.x; i < M0 * M1; i += blockDim.x) sx[(size_t)t * M0 * M1 + i] = src[i];
+  }
+  for (int i = threadIdx.x; i < KG * M1; i += blockDim.x) {
+    int kk = i / M1, x = i % M1;
+    int k1 = kb + kk;
+    wf1[i] = (k1 < K1) ? tw.fwd1[(size_t)k1 * M1 + x] : make_float2(0.f, 0.f);
+  }
+  for (int i = threadIdx.x; i < K0 * M0; i += blockDim.x) wf0[i] = tw.fwd0[i];
+  __syncthreads();
+  // stage 1': s2[t][x0][kk] = sum_x1 wf1[kk][x1] S[t][x0][x1]
+  for (int i = threadIdx.x; i < nterm * M0 * KG; i += blockDim.x) {
+    int t = i / (M0 * KG), x0 = (i / KG) % M0, kk = i % KG;
+    const float2* row = sx + ((size_t)t * M0 + x0) * M1;
+    const float2* w = wf1 + (size_t)kk * M1;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x = 0; x < M1; ++x) cmac(acc, w[x], row[x]);
+    s2[i] = acc;
+  }
+  __syncthreads();
+  // stage 0' + band update
+  for (int i = threadIdx.x; i < K0 * KG; i += blockDim.x) {
+    int k0 = i / KG, kk = i % KG;
+    int k1 = kb + kk;
+    float2 res = make_float2(0.f, 0.f);
+    if (k1 < K1 && k0 != K0 / 2 && k1 != K1 / 2) {
+      const size_t idx = ((size_t)k0 * K1 + k1) * Kh + kh;
+      float2 fa = make_float2(0.f, 0.f), fb = make_float2(0.f, 0.f);
+      const float2* w = wf0 + (size_t)k0 * M0;
+      for (int x0 = 0; x0 < M0; ++x0) cmac(fa, w[x0], s2[(size_t)x0 * KG + kk]);
+      if (nterm == 2)
+        for (int x0 = 0; x0 < M0; ++x0) cmac(fb, w[x0], s2[((size_t)M0 + x0) * KG + kk]);
+      if (job.base) res = job.base[idx];
+      const float ks = Ksym[idx];
+      const float sa = job.ca * invG * (job.syma ? ks : 1.f);
+      res.x = fmaf(sa, fa.x, res.x);
+      res.y = fmaf(sa, fa.y, res.y);
+      if (nterm == 2) {
+        const float sb = job.cb * invG * (job.symb ? ks : 1.f);
+        res.x = fmaf(sb, fb.x, res.x);
+        res.y = fmaf(sb, fb.y, res.y);
+      }
+      if (job.extra) {
+        const float2 e = job.extra[idx];
+        res.x = fmaf(job.ce, e.x, res.x);
+        res.y = fmaf(job.ce, e.y, res.y);
+      }
+    }
+    if (k1 < K1) job.out[((size_t)k0 * K1 + k1) * Kh + kh] = res;
+    bnd[i] = res;
+    float l = (k1 < K1) ? Lsym[((size_t)k0 * K1 + k1) * Kh + kh] : 0.f;
+    bnd[K0 * KG + i] = make_float2(l * res.x, l * res.y);
+  }
+  if (job.nt1 == 0) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * M0 * K0; i += blockDim.x) w0s[i] = tw.inv0[i];
+  __syncthreads();
+  // next inverse stage 0: t1[v][x0][k1][kh] = sum_k0 w0[v][x0][k0] b[k0]
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (u >= job.nt1) break;
+    const float2* bsrc = bnd + ((u == 0 ? job.t1l[0] : job.t1l[1]) ? K0 * KG : 0);
+    float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
+    for (int i = threadIdx.x; i < 2 * M0 * KG; i += blockDim.x) {
+      int v = i / (M0 * KG), x0 = (i / KG) % M0, kk = i % KG;
+      int k1 = kb + kk;
+      if (k1 >= K1) continue;
+      const float2* w = w0s + ((size_t)v * M0 + x0) * K0;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int k0 = 0; k0 < K0; ++k0) cmac(acc, w[k0], bsrc[(size_t)k0 * KG + kk]);
+      dst[((size_t)v * M0 + x0) * C + (size_t)k1 * Kh + kh] = acc;
+    }
   }
 }
 
@@ -433,20 +574,38 @@ __global__ void __launch_bounds__(128) k_fwd0(Fwd0Jobs jobs, const float2* __res
 }
 
 // ----------------------------------------------------- grid step (N)
-// One block per (x0, R rows of x1): inverse stages 1 and 2 of the three
-// velocity components from their stage-0 output, then either the velocity
-// itself or the incremental-state source at each grid point.
+// One block per (x0, 16 consecutive x1 rows), 256 threads = 16 rows x 16
+// lanes: inverse stage 1 of the three velocity components from their
+// stage-0 output, then stage 2 register-blocked (lane l owns x2 = l + 16 j),
+// then either the velocity itself or the incremental-state source.
+constexpr int kGridRows = 16;
+
+__device__ __forceinline__ float central_diff(const float* __restrict__ m, int x0, int x1, int x2,
+                                              int N0, int N1, int N2, int axis) {
+  if (axis == 0) {
+    int p = (x0 + 1 == N0) ? 0 : x0 + 1, q = (x0 == 0) ? N0 - 1 : x0 - 1;
+    return (m[((long long)p * N1 + x1) * N2 + x2] - m[((long long)q * N1 + x1) * N2 + x2]) * (0.5f * N0);
+  }
+  if (axis == 1) {
+    int p = (x1 + 1 == N1) ? 0 : x1 + 1, q = (x1 == 0) ? N1 - 1 : x1 - 1;
+    return (m[((long long)x0 * N1 + p) * N2 + x2] - m[((long long)x0 * N1 + q) * N2 + x2]) * (0.5f * N1);
+  }
+  int p = (x2 + 1 == N2) ? 0 : x2 + 1, q = (x2 == 0) ? N2 - 1 : x2 - 1;
+  return (m[((long long)x0 * N1 + x1) * N2 + p] - m[((long long)x0 * N1 + x1) * N2 + q]) * (0.5f * N2);
+}
+
+template <int JN>
 __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, int N0, int N1,
-                                                  int N2, int K1, int Kh, int R) {
+                                                  int N2, int K1, int Kh) {
   extern __shared__ float2 sh2[];
+  constexpr int R = kGridRows;
   const int C = K1 * Kh;
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
-  const int rv = min(R, N1 - x1b);
-  float2* t1s = sh2;                 // 3*C
-  float2* t2s = t1s + 3 * C;         // 3*R*Kh
-  float2* w1s = t2s + 3 * R * Kh;    // R*K1
-  float2* w2s = w1s + R * K1;        // N2*Kh
+  float2* t1s = sh2;                 // [3][K1][Kh]
+  float2* t2s = t1s + 3 * C;         // [3][R][Kh]
+  float2* w1s = t2s + 3 * R * Kh;    // [R][K1]
+  float2* w2t = w1s + R * K1;        // [Kh][N2]
   for (int i = threadIdx.x; i < 3 * C; i += blockDim.x) {
     int c = i / C, e = i % C;
     t1s[i] = a.t1[((size_t)c * N0 + x0) * C + e];
@@ -456,7 +615,10 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, i
     int x1 = x1b + r;
     w1s[i] = (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + k] : make_float2(0.f, 0.f);
   }
-  for (int i = threadIdx.x; i < N2 * Kh; i += blockDim.x) w2s[i] = tw.inv2[i];
+  for (int i = threadIdx.x; i < N2 * Kh; i += blockDim.x) {
+    int kh = i / N2, x2 = i % N2;
+    w2t[i] = tw.inv2[(size_t)x2 * Kh + kh];
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
     int c = i / (R * Kh), r = (i / Kh) % R, kh = i % Kh;
@@ -467,38 +629,44 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, i
     t2s[i] = acc;
   }
   __syncthreads();
-  const long long nN = (long long)N0 * N1 * N2;
-  for (int p = threadIdx.x; p < rv * N2; p += blockDim.x) {
-    int r = p / N2, x2 = p % N2;
-    const float2* w = w2s + (size_t)x2 * Kh;
-    float vel[3];
+  const int r = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int x1 = x1b + r;
+  float acc[3][JN];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float2* t = t2s + ((size_t)c * R + r) * Kh;
-      float val = 0.f;
-      for (int kh = 0; kh < Kh; ++kh) {
-        val = fmaf(t[kh].x, w[kh].x, val);
-        val = fmaf(-t[kh].y, w[kh].y, val);
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) acc[c][j] = 0.f;
+  for (int kh = 0; kh < Kh; ++kh) {
+    float2 t[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] = t2s[((size_t)c * R + r) * Kh + kh];
+    const float2* w = w2t + (size_t)kh * N2;
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      int x2 = lane + 16 * j;
+      float2 ww = (x2 < N2) ? w[x2] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[c][j] = fmaf(t[c].x, ww.x, acc[c][j]);
+        acc[c][j] = fmaf(-t[c].y, ww.y, acc[c][j]);
       }
-      vel[c] = val;
     }
-    const int x1 = x1b + r;
+  }
+  if (x1 >= N1) return;
+  const long long nN = (long long)N0 * N1 * N2;
+#pragma unroll
+  for (int j = 0; j < JN; ++j) {
+    const int x2 = lane + 16 * j;
+    if (x2 >= N2) continue;
     const long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
     if (a.op == 0) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = vel[c];
+      for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = acc[c][j];
     } else {
-      const float* m = a.m;
-      int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
-      int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
-      int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
-      float g0 = (m[((long long)xp0 * N1 + x1) * N2 + x2] - m[((long long)xm0 * N1 + x1) * N2 + x2]) *
-                 (0.5f * N0);
-      float g1 = (m[((long long)x0 * N1 + xp1) * N2 + x2] - m[((long long)x0 * N1 + xm1) * N2 + x2]) *
-                 (0.5f * N1);
-      float g2 = (m[((long long)x0 * N1 + x1) * N2 + xp2] - m[((long long)x0 * N1 + x1) * N2 + xm2]) *
-                 (0.5f * N2);
-      float dot = g0 * vel[0] + g1 * vel[1] + g2 * vel[2];
+      float g0 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 0);
+      float g1 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 1);
+      float g2 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 2);
+      float dot = g0 * acc[0][j] + g1 * acc[1][j] + g2 * acc[2][j];
       float base = a.dm ? a.dm[gi] : 0.f;
       a.q[gi] = fmaf(-a.dt, dot, base);
     }
@@ -543,49 +711,49 @@ __global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
 }
 
 // ------------------- image-term source and forward stage 2 (N grid)
-// s_j = coef * (a - b) * d_j m (periodic central differences), contracted
-// over x2: s1[j][x0][x1][kh].
+// s_j = coef * (a - b) * d_j m (periodic central differences) at the points
+// of 16 x1 rows of plane x0, contracted over x2: s1[j][x0][x1][kh].
 __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
                                                   const float* __restrict__ b,
                                                   const float* __restrict__ m, float coef,
                                                   float2* __restrict__ s1, Twiddles tw, int N0,
-                                                  int N1, int N2, int Kh, int R) {
+                                                  int N1, int N2, int Kh) {
   extern __shared__ float shs[];
+  constexpr int R = kGridRows;
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
   const int rv = min(R, N1 - x1b);
   const int P = R * N2;
-  float* vals = shs;                                   // 3*P
-  float2* wf2 = (float2*)(vals + ((3 * P + 3) & ~3));  // Kh*N2
-  for (int i = threadIdx.x; i < Kh * N2; i += blockDim.x) wf2[i] = tw.fwd2[i];
-  for (int p = threadIdx.x; p < rv * N2; p += blockDim.x) {
+  float* vals = shs;                                   // [3][R][N2]
+  float2* wfx = (float2*)(vals + ((3 * P + 3) & ~3));  // [N2][Kh]
+  for (int i = threadIdx.x; i < Kh * N2; i += blockDim.x) {
+    int x2 = i / Kh, kh = i % Kh;
+    wfx[i] = tw.fwd2[(size_t)kh * N2 + x2];
+  }
+  for (int p = threadIdx.x; p < R * N2; p += blockDim.x) {
     int r = p / N2, x2 = p % N2;
     int x1 = x1b + r;
-    long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
-    int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
-    int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
-    int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
-    float g0 = (m[((long long)xp0 * N1 + x1) * N2 + x2] - m[((long long)xm0 * N1 + x1) * N2 + x2]) *
-               (0.5f * N0);
-    float g1 = (m[((long long)x0 * N1 + xp1) * N2 + x2] - m[((long long)x0 * N1 + xm1) * N2 + x2]) *
-               (0.5f * N1);
-    float g2 = (m[((long long)x0 * N1 + x1) * N2 + xp2] - m[((long long)x0 * N1 + x1) * N2 + xm2]) *
-               (0.5f * N2);
-    float r0 = a[gi] - (b ? b[gi] : 0.f);
-    float s = coef * r0;
-    vals[p] = s * g0;
-    vals[P + p] = s * g1;
-    vals[2 * P + p] = s * g2;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (r < rv) {
+      long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+      float s = coef * (a[gi] - (b ? b[gi] : 0.f));
+      v0 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 0);
+      v1 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 1);
+      v2 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 2);
+    }
+    vals[p] = v0;
+    vals[P + p] = v1;
+    vals[2 * P + p] = v2;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * rv * Kh; i += blockDim.x) {
     int j = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
     const float* row = vals + (size_t)j * P + r * N2;
-    const float2* w = wf2 + (size_t)kh * N2;
     float2 acc = make_float2(0.f, 0.f);
     for (int x2 = 0; x2 < N2; ++x2) {
-      acc.x = fmaf(row[x2], w[x2].x, acc.x);
-      acc.y = fmaf(row[x2], w[x2].y, acc.y);
+      float2 w = wfx[(size_t)x2 * Kh + kh];
+      acc.x = fmaf(row[x2], w.x, acc.x);
+      acc.y = fmaf(row[x2], w.y, acc.y);
     }
     s1[(((size_t)j * N0 + x0) * N1 + x1b + r) * Kh + kh] = acc;
   }
@@ -811,44 +979,76 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
   return hipGetLastError();
 }
 
-static int mstep_rows(const Dims& d) {
-  int R = 256 / d.M[2];
-  if (R < 1) R = 1;
-  if (R > d.M[1]) R = d.M[1];
-  return R;
-}
-
 size_t mstep_shared_bytes(const Dims& d, int nnew, int nout) {
-  const int R = mstep_rows(d);
-  const int P = R * d.M[2];
+  (void)nnew;
+  const int R = kStepRows;
   const int C = d.K[1] * d.Kh;
-  size_t floats = ((size_t)nnew * 12 * P + (size_t)nout * P + 3) & ~(size_t)3;
-  size_t cplx = 2 * (size_t)C + 3 * (size_t)R * d.Kh + 2 * (size_t)R * d.K[1] + 2 * (size_t)d.M[2] * d.Kh +
-                (size_t)d.Kh * d.M[2];
-  return floats * sizeof(float) + cplx * sizeof(float2) + 16;
+  size_t inv = 2 * (size_t)C + 3 * (size_t)R * d.Kh + 2 * (size_t)R * d.K[1] + 2 * (size_t)d.Kh * d.M[2];
+  size_t prod = ((size_t)nout * R * d.M[2] + 1) / 2;
+  return ((size_t)d.M[2] * d.Kh + (inv > prod ? inv : prod)) * sizeof(float2);
 }
 
 hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
-  const int R = mstep_rows(d);
+  const int R = kStepRows;
   dim3 grid(nblk(d.M[1], R), d.M[0]);
   size_t shm = mstep_shared_bytes(d, a.nnew, a.nout);
   {
     static const double prog_flops[6] = {0, 47, 94, 136, 272, 136};
+    static const int prog_cached[6] = {0, 0, 2, 2, 6, 2};
     const double nM = (double)d.nM, C = (double)d.K[1] * d.Kh;
     double fl = a.nnew * 3.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0) +
                 prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
     int nstore = (a.store[0] != nullptr) + (a.store[1] != nullptr);
-    int ncached = 0;
-    static const int prog_cached[6] = {0, 0, 2, 2, 6, 2};
-    ncached = prog_cached[a.prog];
-    double by = a.nnew * 3.0 * 2.0 * d.M[0] * C * 8.0 + (nstore + ncached) * 12.0 * nM * 4.0 +
+    double by = a.nnew * 3.0 * 2.0 * d.M[0] * C * 8.0 + (nstore + prog_cached[a.prog]) * 12.0 * nM * 4.0 +
                 a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
     timer_work(1, fl, by);
   }
   timer_begin(1, st);
-  hipLaunchKernelGGL(k_mstep, grid, dim3(256), shm, st, a, tw, d.M[0], d.M[1], d.M[2], d.K[1], d.Kh,
-                     R);
+  const int jn = (d.M[2] + 15) / 16;
+#define MSTEP_CASE(J)                                                                          \
+  hipLaunchKernelGGL((k_mstep<J, kStepRows>), grid, dim3(R * 16), shm, st, a, tw, d.M[0], d.M[1], \
+                     d.M[2], d.K[1], d.Kh)
+  if (jn <= 1) MSTEP_CASE(1);
+  else if (jn <= 2) MSTEP_CASE(2);
+  else if (jn <= 3) MSTEP_CASE(3);
+  else if (jn <= 4) MSTEP_CASE(4);
+  else if (jn <= 6) MSTEP_CASE(6);
+  else MSTEP_CASE(8);
+#undef MSTEP_CASE
   timer_end(1, st);
+  return hipGetLastError();
+}
+
+constexpr int kColGroup = 8;
+
+size_t colstep_shared_bytes(const Dims& d) {
+  const int M0 = d.M[0], M1 = d.M[1], K0 = d.K[0];
+  size_t xsz = (size_t)std::max(2 * M0 * M1, 2 * M0 * K0);
+  return (xsz + (size_t)kColGroup * M1 + 2 * (size_t)M0 * kColGroup + (size_t)K0 * M0 +
+          2 * (size_t)K0 * kColGroup) * sizeof(float2);
+}
+
+hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
+                          const float* Lsym, const float* Ksym, hipStream_t st) {
+  dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
+  size_t shm = colstep_shared_bytes(d);
+  {
+    const double M0 = d.M[0], M1 = d.M[1], K0 = d.K[0], K1 = d.K[1], Kh = d.Kh;
+    double fl = 0, by = 0;
+    for (int i = 0; i < njobs; ++i) {
+      const ColJob& j = jobs.j[i];
+      int terms = 1 + (j.b != nullptr);
+      fl += terms * (M0 * M1 * K1 + K0 * K1 * M0) * Kh * 8.0 + j.nt1 * 2.0 * M0 * K0 * K1 * Kh * 8.0;
+      by += terms * M0 * M1 * Kh * 8.0 + K0 * K1 * Kh * 8.0 * (2 + (j.base != nullptr) + (j.extra != nullptr)) +
+            j.nt1 * 2.0 * M0 * K1 * Kh * 8.0;
+    }
+    timer_work(5, fl, by);
+  }
+  const float invG = (float)(1.0 / ((double)d.M[0] * d.M[1] * d.M[2]));
+  timer_begin(5, st);
+  hipLaunchKernelGGL((k_colstep<kColGroup>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, d.M[0],
+                     d.M[1], d.K[0], d.K[1], d.Kh, invG);
+  timer_end(5, st);
   return hipGetLastError();
 }
 
@@ -889,30 +1089,20 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
   return hipGetLastError();
 }
 
-static int grid_rows(const Dims& d) {
-  int R = 256 / d.N[2];
-  if (R < 1) R = 1;
-  if (R > d.N[1]) R = d.N[1];
-  return R;
-}
-
 size_t gridstep_shared_bytes(const Dims& d) {
-  const int R = grid_rows(d);
   const int C = d.K[1] * d.Kh;
-  return (3 * (size_t)C + 3 * (size_t)R * d.Kh + (size_t)R * d.K[1] + (size_t)d.N[2] * d.Kh) *
-         sizeof(float2);
+  return (3 * (size_t)C + 3 * (size_t)kGridRows * d.Kh + (size_t)kGridRows * d.K[1] +
+          (size_t)d.N[2] * d.Kh) * sizeof(float2);
 }
 
 size_t src_shared_bytes(const Dims& d) {
-  const int R = grid_rows(d);
-  return (size_t)((3 * R * d.N[2] + 3) & ~3) * sizeof(float) + (size_t)d.Kh * d.N[2] * sizeof(float2);
+  return (size_t)((3 * kGridRows * d.N[2] + 3) & ~3) * sizeof(float) +
+         (size_t)d.Kh * d.N[2] * sizeof(float2);
 }
 
 hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
-  const int R = grid_rows(d);
   const int C = d.K[1] * d.Kh;
-  (void)C;
-  dim3 grid(nblk(d.N[1], R), d.N[0]);
+  dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
   size_t shm = gridstep_shared_bytes(d);
   {
     const double nN = (double)d.nN;
@@ -921,8 +1111,15 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
     timer_work(2, fl, by);
   }
   timer_begin(2, st);
-  hipLaunchKernelGGL(k_gridstep, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1],
-                     d.Kh, R);
+  const int jn = (d.N[2] + 15) / 16;
+  if (jn <= 2)
+    hipLaunchKernelGGL(k_gridstep<2>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
+  else if (jn <= 4)
+    hipLaunchKernelGGL(k_gridstep<4>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
+  else if (jn <= 8)
+    hipLaunchKernelGGL(k_gridstep<8>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
+  else
+    hipLaunchKernelGGL(k_gridstep<16>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
   timer_end(2, st);
   return hipGetLastError();
 }
@@ -939,11 +1136,10 @@ hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, c
 
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st) {
-  const int R = grid_rows(d);
-  dim3 grid(nblk(d.N[1], R), d.N[0]);
+  dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
   size_t shm = src_shared_bytes(d);
   hipLaunchKernelGGL(k_src_fwd2, grid, dim3(256), shm, st, a, b, m, coef, s1, tw, d.N[0], d.N[1],
-                     d.N[2], d.Kh, R);
+                     d.N[2], d.Kh);
   return hipGetLastError();
 }
 
