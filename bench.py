@@ -28,7 +28,7 @@ METRIC = "Hessian-vector products/s + registrations/min, 128³ band 32³, FP32/B
 CONFIG = 3
 PEAK_TFLOPS_FP32 = 157.3
 PEAK_GBS_HBM = 8000.0
-FAMILIES = {1: "k_mstep", 2: "k_gridstep", 3: "k_sl", 4: "k_inv0", 5: "k_fwd1+k_fwd0"}
+FAMILIES = {1: "k_synth", 2: "k_gridstep", 3: "k_sl", 4: "k_inv0", 5: "k_colstep", 6: "k_prods"}
 
 
 def log(*a):

@@ -173,8 +173,15 @@ int64_t lddmm_last_register_hvps(void);
  * of timed launches, their summed duration in milliseconds and the summed
  * algorithmic flops and bytes.  Enabling (or LDDMM_KF_NONE) resets the
  * counters.  Host only; not thread-safe against concurrent enabling. */
-enum { LDDMM_KF_NONE = 0, LDDMM_KF_MSTEP = 1, LDDMM_KF_GRID_SRC = 2, LDDMM_KF_SL = 3,
-       LDDMM_KF_INV0 = 4, LDDMM_KF_FWD = 5 };
+enum {
+  LDDMM_KF_NONE = 0,
+  LDDMM_KF_SYNTH = 1,   /* padded-grid synthesis of new fields (MFMA inverse stages 1-2) */
+  LDDMM_KF_GRID = 2,    /* grid velocity / incremental-state source (inverse stages 1-2 on the grid) */
+  LDDMM_KF_SL = 3,      /* semi-Lagrangian transport step */
+  LDDMM_KF_INV0 = 4,    /* inverse stage 0 at the start of a sweep and for the grid velocities */
+  LDDMM_KF_COLUMN = 5,  /* forward stages 1-0, band update, next inverse stage 0 */
+  LDDMM_KF_PRODS = 6    /* Lie products and forward stage 2 on the padded grid */
+};
 int lddmm_kernel_timer(int32_t family);
 int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, double* bytes);
 

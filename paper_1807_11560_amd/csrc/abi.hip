@@ -92,7 +92,8 @@ int validate(const lddmm_params* p, Dims* d) {
   o.hessian = p->hessian;
   // the fused step kernel keeps a block's fields in LDS
   // each block keeps its rows in LDS (at most 64 KiB per block)
-  if (mstep_shared_bytes(o, 2, 9) > 64 * 1024 || colstep_shared_bytes(o) > 64 * 1024)
+  if (synth_shared_bytes(o) > 64 * 1024 || prods_shared_bytes(o, 9) > 64 * 1024 ||
+      colstep_shared_bytes(o) > 64 * 1024)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
   if (gridstep_shared_bytes(o) > 64 * 1024 || src_shared_bytes(o) > 64 * 1024)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");

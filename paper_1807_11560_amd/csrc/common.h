@@ -46,8 +46,8 @@ struct Inv0Job {
 };
 struct Inv0Jobs { Inv0Job j[kMaxJobs]; };
 
-// Program of the fused M-grid step kernel: which band-limited Lie products
-// to form at each point of the padded grid.
+// Program of the padded-grid products kernel: which band-limited Lie
+// products to form at each point.
 enum MProg {
   PROG_STORE = 0,   // only synthesise (and store) the new groups
   PROG_SHOOT = 1,   // out0 = ad*_V(LV)                         new: V, LV
@@ -59,14 +59,16 @@ enum MProg {
                     // out2 = ad*_dW(LV) + ad*_W(LdV)
                     //                   new: LdU, dW; cached: V, LV, LU, W, dV, LdV
   PROG_H5_NOCOUPLE = 5  // out0 = ad*_V(LdU), out1 = ad_V(dW), out2 = ad*_dW(LV)
+  // k_prods group order: SHOOT (V, LV); H1 (dV, LdV, V, LV); GRAD (LU, W, V, LV);
+  // H5 (LdU, dW, V, LV, LU, W, dV, LdV); H5_NOCOUPLE (LdU, dW, V, LV)
 };
 
-struct MStepArgs {
-  const float2* t1[2];    // stage-0 output of new group g: [3 comps][2 vars][M0][K1*Kh]
-  float* store[2];        // cache for new group g: [12][nM], or null
-  const float* cached[6]; // cached groups: [12][nM] each
-  float2* s1;             // [nout][Kh][M0][M1] forward stage-2 output
-  int nnew, nout, prog;
+// Lie products on the padded grid (k_prods): group pointers [12][nM] in
+// the order the program names them (see MProg).
+struct ProdArgs {
+  const float* g[8];
+  float2* s1;  // [nout][Kh][M0][M1]
+  int nout, prog;
 };
 
 // Band-side step of one output component (k_colstep): forward stages 1 and
@@ -123,7 +125,13 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
                                const Dims& d, hipStream_t st);
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
                        int K0, int C, int G0, hipStream_t st);
-hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
+hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st);
+size_t synth_table_floats(const Dims& d);
+size_t synth_shared_bytes(const Dims& d);
+hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, float* dst1,
+                        const float* tables, const Dims& d, hipStream_t st);
+size_t prods_shared_bytes(const Dims& d, int nout);
+hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
                           const float* Lsym, const float* Ksym, hipStream_t st);
 size_t colstep_shared_bytes(const Dims& d);
@@ -149,7 +157,6 @@ hipError_t launch_band_maxabs(const float2* a, const Dims& d, double* partial, d
                               hipStream_t st);
 hipError_t launch_scalar_copy(const double* src, double* dst, int n, hipStream_t st);
 hipError_t launch_energy_combine(double* sc, hipStream_t st);  // sc[0] = sc[1] + sc[2]
-size_t mstep_shared_bytes(const Dims& d, int nnew, int nout);
 size_t gridstep_shared_bytes(const Dims& d);
 size_t src_shared_bytes(const Dims& d);
 // CG in the V metric, all scalars on the device (see engine).

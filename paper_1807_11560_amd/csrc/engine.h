@@ -79,6 +79,8 @@ class Engine {
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;
   float2 *T1_ = nullptr, *S1_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
+  float* NG_ = nullptr;         // scratch for new groups that are not cached
+  float* synth_tab_ = nullptr;  // MFMA-form stage-1/2 twiddles of the padded grid
 };
 
 }  // namespace lddmm

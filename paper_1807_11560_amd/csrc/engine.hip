@@ -1,10 +1,10 @@
 // Host engine of band-limited Jacobi PDE-EPDiff LDDMM (paper §3.2).
 //
-// Per Euler step on the padded grid the engine issues two launches: the
-// fused step kernel (inverse stages 1-2 of the new fields, their Lie
-// products, forward stage 2; k_mstep) and the column kernel (forward stages
-// 1-0, the band update, and stage 0 of the next step's inverse transforms;
-// k_colstep).  The first step of a sweep gets its stage 0 from k_inv0.
+// Per Euler step on the padded grid the engine issues three launches: the
+// MFMA synthesis of the new fields (inverse stages 1-2; k_synth), their Lie
+// products with forward stage 2 (k_prods) and the column kernel (forward
+// stages 1-0, the band update, and stage 0 of the next step's inverse
+// transforms; k_colstep).  The first step of a sweep gets its stage 0 from k_inv0.
 // Fields of the trajectory that later sweeps reuse are cached on the padded
 // grid when they are first synthesised.
 #include "engine.h"
@@ -62,6 +62,8 @@ void Engine::layout(Carver& c) {
   twbuf_ = c.take<float2>(twiddle_count(d.M, d) + twiddle_count(d.N, d));
   const size_t C = (size_t)d.K[1] * d.Kh;
   T1_ = c.take<float2>(2 * 3 * 2 * (size_t)d.M[0] * C);
+  NG_ = c.take<float>(24 * (size_t)d.nM);
+  synth_tab_ = c.take<float>(synth_table_floats(d));
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
   const int chunk = std::min(nt, kGridChunk);
   T1N_ = c.take<float2>((size_t)chunk * 3 * d.N[0] * C);
@@ -105,6 +107,7 @@ hipError_t Engine::init_tables() {
     TRY(launch_twiddles(const_cast<float2*>(tw.fwd1), d_.K[1], G[1], 2, st_));
     TRY(launch_twiddles(const_cast<float2*>(tw.fwd2), d_.K[2], G[2], 3, st_));
   }
+  TRY(launch_synth_tables(twM_, synth_tab_, d_, st_));
   return launch_symbols(Lsym, Ksym, d_, st_);
 }
 
@@ -140,18 +143,23 @@ hipError_t Engine::inv0_groups(const float2* in0, int l0, const float2* in1, int
   return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], st_);
 }
 
+// Synthesis of the two new groups (into the cache when given, else into
+// scratch), then the Lie products of the program (when nout > 0).
 hipError_t Engine::mstep(int prog, int nout, float* store0, float* store1, const float* const* cached) {
-  MStepArgs a{};
-  a.t1[0] = t1(0, 0);
-  a.t1[1] = t1(1, 0);
-  a.store[0] = store0;
-  a.store[1] = store1;
-  for (int k = 0; k < 6; ++k) a.cached[k] = cached ? cached[k] : nullptr;
+  const size_t nM = (size_t)d_.nM;
+  float* g0 = store0 ? store0 : NG_;
+  float* g1 = store1 ? store1 : NG_ + 12 * nM;
+  TRY(launch_synth(t1(0, 0), t1(1, 0), g0, g1, synth_tab_, d_, st_));
+  if (nout == 0) return hipSuccess;
+  ProdArgs a{};
+  a.g[0] = g0;
+  a.g[1] = g1;
+  if (cached)
+    for (int k = 0; k < 6; ++k) a.g[2 + k] = cached[k];
   a.s1 = S1_;
-  a.nnew = 2;
   a.nout = nout;
   a.prog = prog;
-  return launch_mstep(a, d_, twM_, st_);
+  return launch_prods(a, d_, twM_, st_);
 }
 
 // One column job: out_c = base + ca S F(s1[oa]) (+ cb S F(s1[ob])) + ce extra;

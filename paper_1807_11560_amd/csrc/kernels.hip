@@ -22,6 +22,66 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(a.y, b.x, acc.y);
 }
 
+// Fills n elements with kBatch loads in flight per thread before their
+// stores (a load-then-store loop would wait one memory latency per element):
+// load(i) gives the value of flat index i, store(i, v) puts it.
+constexpr int kBatch = 8;
+template <class T, class Load, class Store>
+__device__ __forceinline__ void batched_fill(int n, Load load, Store store) {
+  const int stride = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += stride * kBatch) {
+    T v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = i0 + u * stride;
+      if (i < n) v[u] = load(i);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = i0 + u * stride;
+      if (i < n) store(i, v[u]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- shapes
+// Sizes seen by a kernel: compile-time for the shapes this library is tuned
+// for (index arithmetic then folds into constants), runtime otherwise.
+struct BandDyn {
+  int k0, k1, kh, m0, m1, m2;
+  __device__ __forceinline__ int K0() const { return k0; }
+  __device__ __forceinline__ int K1() const { return k1; }
+  __device__ __forceinline__ int Kh() const { return kh; }
+  __device__ __forceinline__ int M0() const { return m0; }
+  __device__ __forceinline__ int M1() const { return m1; }
+  __device__ __forceinline__ int M2() const { return m2; }
+};
+template <int K, int M>
+struct BandIso {
+  __device__ static constexpr int K0() { return K; }
+  __device__ static constexpr int K1() { return K; }
+  __device__ static constexpr int Kh() { return K / 2; }
+  __device__ static constexpr int M0() { return M; }
+  __device__ static constexpr int M1() { return M; }
+  __device__ static constexpr int M2() { return M; }
+};
+struct GridDyn {
+  int n0, n1, n2, k1, kh;
+  __device__ __forceinline__ int N0() const { return n0; }
+  __device__ __forceinline__ int N1() const { return n1; }
+  __device__ __forceinline__ int N2() const { return n2; }
+  __device__ __forceinline__ int K1() const { return k1; }
+  __device__ __forceinline__ int Kh() const { return kh; }
+};
+template <int N, int K>
+struct GridIso {
+  __device__ static constexpr int N0() { return N; }
+  __device__ static constexpr int N1() { return N; }
+  __device__ static constexpr int N2() { return N; }
+  __device__ static constexpr int K1() { return K; }
+  __device__ static constexpr int Kh() { return K / 2; }
+};
+
 // ------------------------------------------------------------- tables
 // mode 0: inverse, full axis  [2][G][K]
 // mode 1: inverse, half axis  [2][G][K/2], weight 1 at k = 0 else 2
@@ -118,11 +178,11 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
   extern __shared__ float2 sh[];
   const Inv0Job job = jobs.j[blockIdx.z];
   const int xb = blockIdx.y * XT;
-  for (int i = threadIdx.x; i < NV * XT * K0; i += blockDim.x) {
+  batched_fill<float2>(NV * XT * K0, [&](int i) {
     int v = i / (XT * K0), t = (i / K0) % XT, k = i % K0;
     int x = xb + t;
-    sh[i] = (x < G0) ? tw[((size_t)v * G0 + x) * K0 + k] : make_float2(0.f, 0.f);
-  }
+    return (x < G0) ? tw[((size_t)v * G0 + x) * K0 + k] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { sh[i] = v; });
   __syncthreads();
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
@@ -184,199 +244,235 @@ __device__ __forceinline__ void ad_acc(float* o, const float* a, const float* b,
   }
 }
 
-// ------------------------------------------------ fused padded-grid step
-// One block per (x0, R consecutive x1 rows), R*16 threads: thread (r, lane)
-// owns the points x2 = lane + 16 j (j < JN) of row x1 = x1b + r.  For each
-// new group it runs the inverse stages 1 (k1 -> x1, from the stage-0 output)
-// and 2 (half spectrum k2 -> real x2) for the value and the three partial
-// derivatives, keeping the 12 fields of each group in registers; stores them
-// if asked; forms the Lie products of the program; and contracts the
-// products over x2 (forward stage 2) into s1[o][kh][x0][x1].
-constexpr int kStepRows = 8;
+// ------------------------------------------- MFMA synthesis on the padded grid
+// One block per (x0 plane, new field (g, c)), four waves.  The inverse
+// stages 1 (k1 -> x1, complex) and 2 (half spectrum k2 -> real x2) are two
+// real GEMMs on the matrix cores (v_mfma_f32_16x16x4f32, FP32 in, FP32
+// accumulate):
+//   T2 = [W1r | -W1i] [[T1r, T1i], [T1i, -T1r]]        rows x1, cols (kh re | kh im)
+//   f  = [T2r | T2i] [[w2r], [-w2i]]                   rows x1, cols x2
+// for the variants value, d/dx2 (pp with the derivative stage-2 table), d/dx1
+// (stage-1 derivative table) and d/dx0 (stage-0 derivative input).  The
+// four results go to the group's [12][nM] field array.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int JN, int R>
-__global__ void __launch_bounds__(R * 16) k_mstep(MStepArgs a, Twiddles tw, int M0, int M1, int M2,
-                                                   int K1, int Kh) {
-  extern __shared__ float smem[];
+struct SynthArgs {
+  const float2* t1[2];  // stage-0 output of group g: [3][2][M0][K1*Kh]
+  float* dst[2];        // fields of group g: [12][nM]
+  const float* w1a;     // [2][M1p][2K1]    real block form of the stage-1 twiddles
+  const float* w2b;     // [2][2Khp][M2p]   real block form of the stage-2 twiddles
+};
+
+template <class S>
+__global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
+  extern __shared__ float sms[];
+  const int M0 = sh.M0(), M1 = sh.M1(), M2 = sh.M2(), K1 = sh.K1(), Kh = sh.Kh();
+  const int M1p = (M1 + 15) & ~15, M2p = (M2 + 15) & ~15, Khp = (Kh + 7) & ~7;
+  const int x0 = blockIdx.x;
+  const int g = blockIdx.y / 3, c = blockIdx.y % 3;
   const int C = K1 * Kh;
-  const int x0 = blockIdx.y;
-  const int x1b = blockIdx.x * R;
-  const int r = threadIdx.x >> 4, lane = threadIdx.x & 15;
-  const int x1 = x1b + r;
-  const bool rowok = x1 < M1;
+  const int K2r = 2 * K1;    // GEMM1 depth
+  const int N1 = 2 * Khp;    // GEMM1 width = GEMM2 depth
+  const int lda1 = K2r + 1;  // padded LDS strides
+  const int ldt2 = N1 + 1;
+  float* w1s = sms;                          // [2][M1p][lda1]
+  float* bt1 = w1s + 2 * M1p * lda1;         // [2][K2r][N1]
+  float* t2s = bt1 + 2 * K2r * N1;           // [3][M1p][ldt2]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+
+  batched_fill<float>(2 * M1p * K2r, [&](int i) { return a.w1a[i]; }, [&](int i, float v) {
+    int vv = i / (M1p * K2r), row = (i / K2r) % M1p, k = i % K2r;
+    w1s[((size_t)vv * M1p + row) * lda1 + k] = v;
+  });
+  const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
+  batched_fill<float2>(2 * K1 * Khp, [&](int i) {
+    int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+    return (kh < Kh) ? src[((size_t)vs * M0 + x0) * C + (size_t)k1 * Kh + kh] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 t) {
+    int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+    float* b = bt1 + (size_t)vs * K2r * N1;
+    b[(size_t)k1 * N1 + kh] = t.x;
+    b[(size_t)k1 * N1 + Khp + kh] = t.y;
+    b[(size_t)(K1 + k1) * N1 + kh] = t.y;
+    b[(size_t)(K1 + k1) * N1 + Khp + kh] = -t.x;
+  });
+  __syncthreads();
+  // GEMM1: var 0 = pp (plain stage 0, plain stage 1), 1 = p1 (d1), 2 = 0p (d0 input).
+  // Operands are fetched eight k-steps ahead of the matrix instructions.
+  const int ti1 = M1p / 16, tj1 = N1 / 16;
+  for (int job = wave; job < 3 * ti1 * tj1; job += 4) {
+    const int var = job / (ti1 * tj1), ti = (job / tj1) % ti1, tj = job % tj1;
+    const int vs = (var == 2), vt = (var == 1);
+    const float* A = w1s + ((size_t)vt * M1p + ti * 16 + li) * lda1 + lk;
+    const float* B = bt1 + (size_t)vs * K2r * N1 + (size_t)lk * N1 + tj * 16 + li;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K2r / 4; k0 += 8) {
+      float av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ks = k0 + u;
+        av[u] = (ks < K2r / 4) ? A[4 * ks] : 0.f;
+        bv[u] = (ks < K2r / 4) ? B[(size_t)4 * ks * N1] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
+    }
+    float* T = t2s + ((size_t)var * M1p + ti * 16 + 4 * lk) * ldt2 + tj * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(size_t)r * ldt2] = acc[r];
+  }
+  __syncthreads();
+  // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p)
+  const int ti2 = M1p / 16, tj2 = M2p / 16;
   const long long nM = (long long)M0 * M1 * M2;
-  const long long rowbase = ((long long)x0 * M1 + x1) * M2;
-
-  float2* wfx = (float2*)smem;                 // [M2][Kh]
-  float2* t1s = wfx + M2 * Kh;                 // [2][C]
-  float2* t2s = t1s + 2 * C;                   // [3][R][Kh]
-  float2* w1s = t2s + 3 * R * Kh;              // [2][R][K1]
-  float2* w2t = w1s + 2 * R * K1;              // [2][Kh][M2]
-  float* outv = (float*)t1s;                   // [nout][R][M2], after the inverse part
-
-  for (int i = threadIdx.x; i < M2 * Kh; i += blockDim.x) {
-    int x2 = i / Kh, kh = i % Kh;
-    wfx[i] = tw.fwd2[(size_t)kh * M2 + x2];
-  }
-  for (int i = threadIdx.x; i < 2 * R * K1; i += blockDim.x) {
-    int v = i / (R * K1), rr = (i / K1) % R, k = i % K1;
-    int xx = x1b + rr;
-    w1s[i] = (xx < M1) ? tw.inv1[((size_t)v * M1 + xx) * K1 + k] : make_float2(0.f, 0.f);
-  }
-  for (int i = threadIdx.x; i < 2 * Kh * M2; i += blockDim.x) {
-    int v = i / (Kh * M2), kh = (i / M2) % Kh, x2 = i % M2;
-    w2t[i] = tw.inv2[((size_t)v * M2 + x2) * Kh + kh];
-  }
-
-  float F[2][12][JN];
+  float* out = a.dst[g];
+  for (int job = wave; job < 4 * ti2 * tj2; job += 4) {
+    const int ov = job / (ti2 * tj2), ti = (job / tj2) % ti2, tj = job % tj2;
+    const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
+    const int wv = (ov == 1);
+    const float* A = t2s + ((size_t)srcv * M1p + ti * 16 + li) * ldt2 + lk;
+    const float* B = a.w2b + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < N1 / 4; k0 += 8) {
+      float av[8], bv[8];
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    if (g >= a.nnew) break;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      __syncthreads();
-      const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
-      for (int i = threadIdx.x; i < 2 * C; i += blockDim.x) {
-        int v = i / C, e = i % C;
-        t1s[i] = src[((size_t)v * M0 + x0) * C + e];
-      }
-      __syncthreads();
-      // T2 rows: var 0 = plain/plain, 1 = plain/d1, 2 = d0/plain
-      for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
-        int var = i / (R * Kh), rr = (i / Kh) % R, kh = i % Kh;
-        int vs = (var == 2) ? 1 : 0, vt = (var == 1) ? 1 : 0;
-        float2 acc = make_float2(0.f, 0.f);
-        const float2* wr = w1s + ((size_t)vt * R + rr) * K1;
-        const float2* tc = t1s + (size_t)vs * C + kh;
-        for (int k = 0; k < K1; ++k) cmac(acc, wr[k], tc[(size_t)k * Kh]);
-        t2s[i] = acc;
-      }
-      __syncthreads();
-      float val[JN], d0[JN], d1[JN], d2[JN];
-#pragma unroll
-      for (int j = 0; j < JN; ++j) val[j] = d0[j] = d1[j] = d2[j] = 0.f;
-      for (int kh = 0; kh < Kh; ++kh) {
-        const float2 tpp = t2s[(0 * R + r) * Kh + kh];
-        const float2 tp1 = t2s[(1 * R + r) * Kh + kh];
-        const float2 t0p = t2s[(2 * R + r) * Kh + kh];
-#pragma unroll
-        for (int j = 0; j < JN; ++j) {
-          int x2 = lane + 16 * j;
-          if (x2 >= M2) continue;
-          const float2 w0 = w2t[(size_t)kh * M2 + x2];
-          const float2 w1 = w2t[((size_t)Kh + kh) * M2 + x2];
-          val[j] = fmaf(tpp.x, w0.x, fmaf(-tpp.y, w0.y, val[j]));
-          d2[j] = fmaf(tpp.x, w1.x, fmaf(-tpp.y, w1.y, d2[j]));
-          d1[j] = fmaf(tp1.x, w0.x, fmaf(-tp1.y, w0.y, d1[j]));
-          d0[j] = fmaf(t0p.x, w0.x, fmaf(-t0p.y, w0.y, d0[j]));
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int ks = k0 + u;
+        bv[u] = (ks < N1 / 4) ? B[(size_t)4 * ks * M2p] : 0.f;
+        av[u] = (ks < N1 / 4) ? A[4 * ks] : 0.f;
       }
 #pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        F[g][c][j] = val[j];
-        F[g][3 + 3 * c + 0][j] = d0[j];
-        F[g][3 + 3 * c + 1][j] = d1[j];
-        F[g][3 + 3 * c + 2][j] = d2[j];
-      }
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
+    }
+    const int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
+    const int x2 = tj * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x1 = ti * 16 + 4 * lk + r;
+      if (x1 < M1 && x2 < M2) out[(size_t)f * nM + ((long long)x0 * M1 + x1) * M2 + x2] = acc[r];
     }
   }
-  // cache the new groups
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    if (g >= a.nnew || !a.store[g] || !rowok) continue;
-#pragma unroll
-    for (int f = 0; f < 12; ++f)
-#pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        int x2 = lane + 16 * j;
-        if (x2 < M2) a.store[g][(size_t)f * nM + rowbase + x2] = F[g][f][j];
-      }
-  }
-  if (a.nout == 0) return;
-  __syncthreads();  // the inverse part's LDS is reused for the products
+}
 
-  // pointwise Lie products
-#pragma unroll
-  for (int j = 0; j < JN; ++j) {
-    const int x2 = lane + 16 * j;
-    const bool ok = rowok && x2 < M2;
+// MFMA-friendly real forms of the stage-1 and stage-2 inverse twiddles.
+__global__ void k_synth_tables(const float2* inv1, const float2* inv2, float* w1a, float* w2b, int M1,
+                               int M2, int K1, int Kh, int M1p, int M2p, int Khp) {
+  const int n1 = 2 * M1p * 2 * K1;
+  const int n2 = 2 * 2 * Khp * M2p;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n1) {
+    int v = i / (M1p * 2 * K1), row = (i / (2 * K1)) % M1p, k = i % (2 * K1);
+    float val = 0.f;
+    if (row < M1) {
+      float2 w = inv1[((size_t)v * M1 + row) * K1 + (k < K1 ? k : k - K1)];
+      val = (k < K1) ? w.x : -w.y;
+    }
+    w1a[i] = val;
+  } else if (i < n1 + n2) {
+    int e = i - n1;
+    int v = e / (2 * Khp * M2p), j = (e / M2p) % (2 * Khp), x2 = e % M2p;
+    int kh = (j < Khp) ? j : j - Khp;
+    float val = 0.f;
+    if (x2 < M2 && kh < Kh) {
+      float2 w = inv2[((size_t)v * M2 + x2) * Kh + kh];
+      val = (j < Khp) ? w.x : -w.y;
+    }
+    w2b[e] = val;
+  }
+}
+
+// ------------------------------------------------ Lie products on the padded grid
+// One block per (x0, R rows), one thread per point (R*M2 threads).  Reads
+// the new and cached groups, forms the products of the program and
+// contracts them over x2 (forward stage 2) into s1[o][kh][x0][x1].
+template <class S>
+__global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
+  extern __shared__ float smp[];
+  const int M0 = sh.M0(), M1 = sh.M1(), M2 = sh.M2(), Kh = sh.Kh();
+  const int R = (256 / M2 < 1) ? 1 : (256 / M2 > M1 ? M1 : 256 / M2);
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, M1 - x1b);
+  const int P = R * M2;
+  const long long nM = (long long)M0 * M1 * M2;
+  float2* wfx = (float2*)smp;                  // [M2][Kh]
+  float* outv = (float*)(wfx + M2 * Kh);       // [nout][R][M2]
+  batched_fill<float2>(M2 * Kh, [&](int i) {
+    int x2 = i / Kh, kh = i % Kh;
+    return tw.fwd2[(size_t)kh * M2 + x2];
+  }, [&](int i, float2 v) { wfx[i] = v; });
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const int r = p / M2;
     float o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = 0.f;
-    if (ok) {
+    if (r < rv) {
       float A[12], B[12];
-      const long long gp = rowbase + x2;
-      auto getnew = [&](int g, float* dst) {
+      const long long gp = ((long long)x0 * M1 + x1b) * M2 + p;
+      auto get = [&](const float* base, float* dst) {
 #pragma unroll
-        for (int f = 0; f < 12; ++f) dst[f] = (g == 0) ? F[0][f][j] : F[1][f][j];
-      };
-      auto getc = [&](int k, float* dst) {
-        const float* src = a.cached[k] + gp;
-#pragma unroll
-        for (int f = 0; f < 12; ++f) dst[f] = src[(size_t)f * nM];
+        for (int f = 0; f < 12; ++f) dst[f] = base[(size_t)f * nM + gp];
       };
       switch (a.prog) {
         case PROG_SHOOT:
-          getnew(0, A); getnew(1, B);
+          get(a.g[0], A); get(a.g[1], B);
           adstar_acc(o, A, B, 1.f);
           break;
-        case PROG_H1:
-          getnew(0, A); getc(1, B);            // ad*_dV(LV)
+        case PROG_H1:  // g: dV, LdV, V, LV
+          get(a.g[0], A); get(a.g[3], B);      // ad*_dV(LV)
           adstar_acc(o, A, B, 1.f);
-          getc(0, A); getnew(1, B);            // ad*_V(LdV)
+          get(a.g[2], A); get(a.g[1], B);      // ad*_V(LdV)
           adstar_acc(o, A, B, 1.f);
           break;
-        case PROG_GRAD:
-          getc(0, A); getnew(0, B);            // ad*_V(LU)
+        case PROG_GRAD:  // g: LU, W, V, LV
+          get(a.g[2], A); get(a.g[0], B);      // ad*_V(LU)
           adstar_acc(o, A, B, 1.f);
-          getnew(1, B);                        // ad_V(W)
+          get(a.g[1], B);                      // ad_V(W)
           ad_acc(o + 3, A, B, 1.f);
-          getc(1, A);                          // ad*_W(LV)
+          get(a.g[3], A);                      // ad*_W(LV)
           adstar_acc(o + 6, B, A, 1.f);
           break;
-        case PROG_H5:
-          getc(0, A); getnew(0, B);            // ad*_V(LdU)
+        case PROG_H5:  // g: LdU, dW, V, LV, LU, W, dV, LdV
+          get(a.g[2], A); get(a.g[0], B);      // ad*_V(LdU)
           adstar_acc(o, A, B, 1.f);
-          getnew(1, B);                        // ad_V(dW)
+          get(a.g[1], B);                      // ad_V(dW)
           ad_acc(o + 3, A, B, 1.f);
-          getc(1, A);                          // ad*_dW(LV)
+          get(a.g[3], A);                      // ad*_dW(LV)
           adstar_acc(o + 6, B, A, 1.f);
-          getc(4, A); getc(2, B);              // ad*_dV(LU)
+          get(a.g[6], A); get(a.g[4], B);      // ad*_dV(LU)
           adstar_acc(o, A, B, 1.f);
-          getc(3, B);                          // ad_dV(W)
+          get(a.g[5], B);                      // ad_dV(W)
           ad_acc(o + 3, A, B, 1.f);
-          getc(5, A);                          // ad*_W(LdV)
+          get(a.g[7], A);                      // ad*_W(LdV)
           adstar_acc(o + 6, B, A, 1.f);
           break;
-        case PROG_H5_NOCOUPLE:
-          getc(0, A); getnew(0, B);
+        case PROG_H5_NOCOUPLE:  // g: LdU, dW, V, LV
+          get(a.g[2], A); get(a.g[0], B);
           adstar_acc(o, A, B, 1.f);
-          getnew(1, B);
+          get(a.g[1], B);
           ad_acc(o + 3, A, B, 1.f);
-          getc(1, A);
+          get(a.g[3], A);
           adstar_acc(o + 6, B, A, 1.f);
           break;
         default:
           break;
       }
     }
-    if (x2 < M2)
-      for (int i = 0; i < a.nout; ++i) outv[((size_t)i * R + r) * M2 + x2] = o[i];
+    for (int i = 0; i < a.nout; ++i) outv[(size_t)i * P + p] = o[i];
   }
   __syncthreads();
-  // forward stage 2: contraction over x2, thread (r, kh)
-  if (!rowok) return;
-  for (int kh = lane; kh < Kh; kh += 16) {
-    for (int o = 0; o < a.nout; ++o) {
-      const float* row = outv + ((size_t)o * R + r) * M2;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int x2 = 0; x2 < M2; ++x2) {
-        const float2 w = wfx[(size_t)x2 * Kh + kh];
-        acc.x = fmaf(row[x2], w.x, acc.x);
-        acc.y = fmaf(row[x2], w.y, acc.y);
-      }
-      a.s1[(((size_t)o * Kh + kh) * M0 + x0) * M1 + x1] = acc;
+  // forward stage 2: one thread per (o, r, kh)
+  for (int i = threadIdx.x; i < a.nout * rv * Kh; i += blockDim.x) {
+    const int o = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
+    const float* row = outv + (size_t)o * P + r * M2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x2 = 0; x2 < M2; ++x2) {
+      const float2 w = wfx[(size_t)x2 * Kh + kh];
+      acc.x = fmaf(row[x2], w.x, acc.x);
+      acc.y = fmaf(row[x2], w.y, acc.y);
     }
+    a.s1[(((size_t)o * Kh + kh) * M0 + x0) * M1 + x1b + r] = acc;
   }
 }
 
@@ -386,11 +482,11 @@ __global__ void __launch_bounds__(R * 16) k_mstep(MStepArgs a, Twiddles tw, int 
 // the band update out = base + ca S_a F(a) + cb S_b F(b) + ce extra (S = K~
 // or 1), and the next step's inverse stage 0 (k0 -> x0, value and d0
 // variants, optionally of L~ out) for the same columns.
-template <int KG>
+template <int KG, class S>
 __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, const float* __restrict__ Lsym,
-                                                 const float* __restrict__ Ksym, int M0, int M1,
-                                                 int K0, int K1, int Kh, float invG) {
+                                                 const float* __restrict__ Ksym, S sh, float invG) {
   extern __shared__ float2 shc[];
+  const int M0 = sh.M0(), M1 = sh.M1(), K0 = sh.K0(), K1 = sh.K1(), Kh = sh.Kh();
   const ColJob job = jobs.j[blockIdx.z];
   const int kh = blockIdx.y;
   const int kb = blockIdx.x * KG;
@@ -405,16 +501,19 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
   float2* wf0 = s2 + 2 * M0 * KG;         // [K0][M0]
   float2* bnd = wf0 + K0 * M0;            // [2][K0][KG]  (out, L~ out)
 
-  for (int t = 0; t < nterm; ++t) {
-    const float2* src = (t == 0 ? job.a : job.b) + (size_t)kh * M0 * M1;
-    for (int i = threadIdx.x; i < M0 * M1; i += blockDim.x) sx[(size_t)t * M0 * M1 + i] = src[i];
+  {
+    const float2* sa = job.a + (size_t)kh * M0 * M1;
+    const float2* sb = job.b ? job.b + (size_t)kh * M0 * M1 : sa;
+    const int n1 = M0 * M1;
+    batched_fill<float2>(nterm * n1, [&](int i) { return i < n1 ? sa[i] : sb[i - n1]; },
+                         [&](int i, float2 v) { sx[i] = v; });
   }
-  for (int i = threadIdx.x; i < KG * M1; i += blockDim.x) {
+  batched_fill<float2>(KG * M1, [&](int i) {
     int kk = i / M1, x = i % M1;
     int k1 = kb + kk;
-    wf1[i] = (k1 < K1) ? tw.fwd1[(size_t)k1 * M1 + x] : make_float2(0.f, 0.f);
-  }
-  for (int i = threadIdx.x; i < K0 * M0; i += blockDim.x) wf0[i] = tw.fwd0[i];
+    return (k1 < K1) ? tw.fwd1[(size_t)k1 * M1 + x] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { wf1[i] = v; });
+  batched_fill<float2>(K0 * M0, [&](int i) { return tw.fwd0[i]; }, [&](int i, float2 v) { wf0[i] = v; });
   __syncthreads();
   // stage 1': s2[t][x0][kk] = sum_x1 wf1[kk][x1] S[t][x0][x1]
   for (int i = threadIdx.x; i < nterm * M0 * KG; i += blockDim.x) {
@@ -461,7 +560,7 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
   }
   if (job.nt1 == 0) return;
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * M0 * K0; i += blockDim.x) w0s[i] = tw.inv0[i];
+  batched_fill<float2>(2 * M0 * K0, [&](int i) { return tw.inv0[i]; }, [&](int i, float2 v) { w0s[i] = v; });
   __syncthreads();
   // next inverse stage 0: t1[v][x0][k1][kh] = sum_k0 w0[v][x0][k0] b[k0]
 #pragma unroll
@@ -488,11 +587,11 @@ __global__ void __launch_bounds__(128) k_fwd1(Fwd1Jobs jobs, const float2* __res
   extern __shared__ float2 sh[];
   const Fwd1Job job = jobs.j[blockIdx.z];
   const int qb = blockIdx.y * QT;
-  for (int i = threadIdx.x; i < QT * G1; i += blockDim.x) {
+  batched_fill<float2>(QT * G1, [&](int i) {
     int t = i / G1, x = i % G1;
     int q = qb + t;
-    sh[i] = (q < K1) ? tw[(size_t)q * G1 + x] : make_float2(0.f, 0.f);
-  }
+    return (q < K1) ? tw[(size_t)q * G1 + x] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { sh[i] = v; });
   __syncthreads();
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (x0, kh)
   if (e >= G0 * Kh) return;
@@ -521,11 +620,11 @@ __global__ void __launch_bounds__(128) k_fwd0(Fwd0Jobs jobs, const float2* __res
   extern __shared__ float2 sh[];
   const Fwd0Job job = jobs.j[blockIdx.z];
   const int qb = blockIdx.y * QT;
-  for (int i = threadIdx.x; i < QT * G0; i += blockDim.x) {
+  batched_fill<float2>(QT * G0, [&](int i) {
     int t = i / G0, x = i % G0;
     int q = qb + t;
-    sh[i] = (q < K0) ? tw[(size_t)q * G0 + x] : make_float2(0.f, 0.f);
-  }
+    return (q < K0) ? tw[(size_t)q * G0 + x] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { sh[i] = v; });
   __syncthreads();
   const int C = K1 * Kh;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -594,10 +693,10 @@ __device__ __forceinline__ float central_diff(const float* __restrict__ m, int x
   return (m[((long long)x0 * N1 + x1) * N2 + p] - m[((long long)x0 * N1 + x1) * N2 + q]) * (0.5f * N2);
 }
 
-template <int JN>
-__global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, int N0, int N1,
-                                                  int N2, int K1, int Kh) {
+template <int JN, class G>
+__global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, G gs) {
   extern __shared__ float2 sh2[];
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2(), K1 = gs.K1(), Kh = gs.Kh();
   constexpr int R = kGridRows;
   const int C = K1 * Kh;
   const int x0 = blockIdx.y;
@@ -606,19 +705,19 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, i
   float2* t2s = t1s + 3 * C;         // [3][R][Kh]
   float2* w1s = t2s + 3 * R * Kh;    // [R][K1]
   float2* w2t = w1s + R * K1;        // [Kh][N2]
-  for (int i = threadIdx.x; i < 3 * C; i += blockDim.x) {
+  batched_fill<float2>(3 * C, [&](int i) {
     int c = i / C, e = i % C;
-    t1s[i] = a.t1[((size_t)c * N0 + x0) * C + e];
-  }
-  for (int i = threadIdx.x; i < R * K1; i += blockDim.x) {
+    return a.t1[((size_t)c * N0 + x0) * C + e];
+  }, [&](int i, float2 v) { t1s[i] = v; });
+  batched_fill<float2>(R * K1, [&](int i) {
     int r = i / K1, k = i % K1;
     int x1 = x1b + r;
-    w1s[i] = (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + k] : make_float2(0.f, 0.f);
-  }
-  for (int i = threadIdx.x; i < N2 * Kh; i += blockDim.x) {
+    return (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + k] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { w1s[i] = v; });
+  batched_fill<float2>(N2 * Kh, [&](int i) {
     int kh = i / N2, x2 = i % N2;
-    w2t[i] = tw.inv2[(size_t)x2 * Kh + kh];
-  }
+    return tw.inv2[(size_t)x2 * Kh + kh];
+  }, [&](int i, float2 v) { w2t[i] = v; });
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * R * Kh; i += blockDim.x) {
     int c = i / (R * Kh), r = (i / Kh) % R, kh = i % Kh;
@@ -676,9 +775,11 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, i
 // ----------------------------------------- semi-Lagrangian step (N)
 // dst(x) = src(x - dt v(x)) by periodic trilinear interpolation; v in
 // domain units, converted to voxels per axis.
+template <class G>
 __global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
                                             const float* __restrict__ vel, float* __restrict__ dst,
-                                            float dt, int N0, int N1, int N2) {
+                                            float dt, G gs) {
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2();
   const long long nN = (long long)N0 * N1 * N2;
   long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= nN) return;
@@ -713,12 +814,13 @@ __global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
 // ------------------- image-term source and forward stage 2 (N grid)
 // s_j = coef * (a - b) * d_j m (periodic central differences) at the points
 // of 16 x1 rows of plane x0, contracted over x2: s1[j][x0][x1][kh].
+template <class G>
 __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
                                                   const float* __restrict__ b,
                                                   const float* __restrict__ m, float coef,
-                                                  float2* __restrict__ s1, Twiddles tw, int N0,
-                                                  int N1, int N2, int Kh) {
+                                                  float2* __restrict__ s1, Twiddles tw, G gs) {
   extern __shared__ float shs[];
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2(), Kh = gs.Kh();
   constexpr int R = kGridRows;
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
@@ -726,10 +828,10 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
   const int P = R * N2;
   float* vals = shs;                                   // [3][R][N2]
   float2* wfx = (float2*)(vals + ((3 * P + 3) & ~3));  // [N2][Kh]
-  for (int i = threadIdx.x; i < Kh * N2; i += blockDim.x) {
+  batched_fill<float2>(Kh * N2, [&](int i) {
     int x2 = i / Kh, kh = i % Kh;
-    wfx[i] = tw.fwd2[(size_t)kh * N2 + x2];
-  }
+    return tw.fwd2[(size_t)kh * N2 + x2];
+  }, [&](int i, float2 v) { wfx[i] = v; });
   for (int p = threadIdx.x; p < R * N2; p += blockDim.x) {
     int r = p / N2, x2 = p % N2;
     int x1 = x1b + r;
@@ -923,6 +1025,27 @@ __global__ void k_pcg_update_d(const double* sc, const float2* r, float2* dv, in
 // ================================================= launch wrappers
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+static bool band_iso(const Dims& d, int K, int M) {
+  return d.K[0] == K && d.K[1] == K && d.K[2] == K && d.M[0] == M && d.M[1] == M && d.M[2] == M;
+}
+static bool grid_iso(const Dims& d, int N, int K) {
+  return d.N[0] == N && d.N[1] == N && d.N[2] == N && d.K[1] == K && d.K[2] == K;
+}
+// Calls f with the band shape type for these sizes.
+template <class F>
+static hipError_t with_band(const Dims& d, F&& f) {
+  if (band_iso(d, 32, 48)) return f(BandIso<32, 48>{});
+  if (band_iso(d, 16, 24)) return f(BandIso<16, 24>{});
+  if (band_iso(d, 24, 36)) return f(BandIso<24, 36>{});
+  return f(BandDyn{d.K[0], d.K[1], d.Kh, d.M[0], d.M[1], d.M[2]});
+}
+template <class F>
+static hipError_t with_grid(const Dims& d, F&& f) {
+  if (grid_iso(d, 128, 32)) return f(GridIso<128, 32>{});
+  if (grid_iso(d, 64, 16)) return f(GridIso<64, 16>{});
+  return f(GridDyn{d.N[0], d.N[1], d.N[2], d.K[1], d.Kh});
+}
+
 hipError_t launch_twiddles(float2* dst, int K, int G, int mode, hipStream_t st) {
   int Kq = (mode == 1 || mode == 3) ? K / 2 : K;
   int total = (mode <= 1) ? 2 * G * Kq : Kq * G;
@@ -979,44 +1102,95 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
   return hipGetLastError();
 }
 
-size_t mstep_shared_bytes(const Dims& d, int nnew, int nout) {
-  (void)nnew;
-  const int R = kStepRows;
-  const int C = d.K[1] * d.Kh;
-  size_t inv = 2 * (size_t)C + 3 * (size_t)R * d.Kh + 2 * (size_t)R * d.K[1] + 2 * (size_t)d.Kh * d.M[2];
-  size_t prod = ((size_t)nout * R * d.M[2] + 1) / 2;
-  return ((size_t)d.M[2] * d.Kh + (inv > prod ? inv : prod)) * sizeof(float2);
+static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+void synth_padding(const Dims& d, int* M1p, int* M2p, int* Khp) {
+  *M1p = round_up(d.M[1], 16);
+  *M2p = round_up(d.M[2], 16);
+  *Khp = round_up(d.Kh, 8);
 }
 
-hipError_t launch_mstep(const MStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
-  const int R = kStepRows;
+size_t synth_table_floats(const Dims& d) {
+  int M1p, M2p, Khp;
+  synth_padding(d, &M1p, &M2p, &Khp);
+  return 2 * (size_t)M1p * 2 * d.K[1] + 2 * 2 * (size_t)Khp * M2p;
+}
+
+size_t synth_shared_bytes(const Dims& d) {
+  int M1p, M2p, Khp;
+  synth_padding(d, &M1p, &M2p, &Khp);
+  const int K2r = 2 * d.K[1], N1 = 2 * Khp;
+  return (2 * (size_t)M1p * (K2r + 1) + 2 * (size_t)K2r * N1 + 3 * (size_t)M1p * (N1 + 1)) * sizeof(float);
+}
+
+hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st) {
+  int M1p, M2p, Khp;
+  synth_padding(d, &M1p, &M2p, &Khp);
+  const size_t n = synth_table_floats(d);
+  float* w1a = tables;
+  float* w2b = tables + 2 * (size_t)M1p * 2 * d.K[1];
+  hipLaunchKernelGGL(k_synth_tables, dim3(nblk((long long)n, 256)), dim3(256), 0, st, tw.inv1, tw.inv2, w1a,
+                     w2b, d.M[1], d.M[2], d.K[1], d.Kh, M1p, M2p, Khp);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, float* dst1,
+                        const float* tables, const Dims& d, hipStream_t st) {
+  int M1p, M2p, Khp;
+  synth_padding(d, &M1p, &M2p, &Khp);
+  SynthArgs a{};
+  a.t1[0] = t1g0;
+  a.t1[1] = t1g1;
+  a.dst[0] = dst0;
+  a.dst[1] = dst1;
+  a.w1a = tables;
+  a.w2b = tables + 2 * (size_t)M1p * 2 * d.K[1];
+  const double nM = (double)d.nM;
+  timer_work(1, 6.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0),
+             6.0 * (2.0 * d.M[0] * d.K[1] * d.Kh * 8.0 + 4.0 * nM * 4.0));
+  (void)Khp;
+  (void)M2p;
+  timer_begin(1, st);
+  hipError_t e = with_band(d, [&](auto sh) {
+    hipLaunchKernelGGL((k_synth<decltype(sh)>), dim3(d.M[0], 6), dim3(256), synth_shared_bytes(d), st, a, sh);
+    return hipGetLastError();
+  });
+  timer_end(1, st);
+  return e;
+}
+
+static int prod_rows(const Dims& d) {
+  int R = 256 / d.M[2];
+  if (R < 1) R = 1;
+  if (R > d.M[1]) R = d.M[1];
+  return R;
+}
+
+size_t prods_shared_bytes(const Dims& d, int nout) {
+  return (size_t)d.M[2] * d.Kh * sizeof(float2) + (size_t)nout * prod_rows(d) * d.M[2] * sizeof(float);
+}
+
+hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
+  const int R = prod_rows(d);
   dim3 grid(nblk(d.M[1], R), d.M[0]);
-  size_t shm = mstep_shared_bytes(d, a.nnew, a.nout);
+  size_t shm = prods_shared_bytes(d, a.nout);
   {
     static const double prog_flops[6] = {0, 47, 94, 136, 272, 136};
-    static const int prog_cached[6] = {0, 0, 2, 2, 6, 2};
-    const double nM = (double)d.nM, C = (double)d.K[1] * d.Kh;
-    double fl = a.nnew * 3.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0) +
-                prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
-    int nstore = (a.store[0] != nullptr) + (a.store[1] != nullptr);
-    double by = a.nnew * 3.0 * 2.0 * d.M[0] * C * 8.0 + (nstore + prog_cached[a.prog]) * 12.0 * nM * 4.0 +
-                a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
-    timer_work(1, fl, by);
+    static const int prog_groups[6] = {0, 2, 4, 4, 8, 4};
+    const double nM = (double)d.nM;
+    double fl = prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
+    double by = prog_groups[a.prog] * 12.0 * nM * 4.0 + a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
+    timer_work(6, fl, by);
   }
-  timer_begin(1, st);
-  const int jn = (d.M[2] + 15) / 16;
-#define MSTEP_CASE(J)                                                                          \
-  hipLaunchKernelGGL((k_mstep<J, kStepRows>), grid, dim3(R * 16), shm, st, a, tw, d.M[0], d.M[1], \
-                     d.M[2], d.K[1], d.Kh)
-  if (jn <= 1) MSTEP_CASE(1);
-  else if (jn <= 2) MSTEP_CASE(2);
-  else if (jn <= 3) MSTEP_CASE(3);
-  else if (jn <= 4) MSTEP_CASE(4);
-  else if (jn <= 6) MSTEP_CASE(6);
-  else MSTEP_CASE(8);
-#undef MSTEP_CASE
-  timer_end(1, st);
-  return hipGetLastError();
+  int threads = ((R * d.M[2] + 63) / 64) * 64;
+  if (threads > 256) threads = 256;
+  timer_begin(6, st);
+  hipError_t e = with_band(d, [&](auto sh) {
+    hipLaunchKernelGGL((k_prods<decltype(sh)>), grid, dim3(threads), shm, st, a, tw, sh);
+    return hipGetLastError();
+  });
+  timer_end(6, st);
+  return e;
 }
 
 constexpr int kColGroup = 8;
@@ -1046,10 +1220,13 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   }
   const float invG = (float)(1.0 / ((double)d.M[0] * d.M[1] * d.M[2]));
   timer_begin(5, st);
-  hipLaunchKernelGGL((k_colstep<kColGroup>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, d.M[0],
-                     d.M[1], d.K[0], d.K[1], d.Kh, invG);
+  hipError_t e = with_band(d, [&](auto sh) {
+    hipLaunchKernelGGL((k_colstep<kColGroup, decltype(sh)>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh,
+                       invG);
+    return hipGetLastError();
+  });
   timer_end(5, st);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
@@ -1112,35 +1289,42 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
   }
   timer_begin(2, st);
   const int jn = (d.N[2] + 15) / 16;
-  if (jn <= 2)
-    hipLaunchKernelGGL(k_gridstep<2>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
-  else if (jn <= 4)
-    hipLaunchKernelGGL(k_gridstep<4>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
-  else if (jn <= 8)
-    hipLaunchKernelGGL(k_gridstep<8>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
-  else
-    hipLaunchKernelGGL(k_gridstep<16>, grid, dim3(256), shm, st, a, tw, d.N[0], d.N[1], d.N[2], d.K[1], d.Kh);
+  hipError_t e = with_grid(d, [&](auto gs) {
+    using G = decltype(gs);
+    if (jn <= 2)
+      hipLaunchKernelGGL((k_gridstep<2, G>), grid, dim3(256), shm, st, a, tw, gs);
+    else if (jn <= 4)
+      hipLaunchKernelGGL((k_gridstep<4, G>), grid, dim3(256), shm, st, a, tw, gs);
+    else if (jn <= 8)
+      hipLaunchKernelGGL((k_gridstep<8, G>), grid, dim3(256), shm, st, a, tw, gs);
+    else
+      hipLaunchKernelGGL((k_gridstep<16, G>), grid, dim3(256), shm, st, a, tw, gs);
+    return hipGetLastError();
+  });
   timer_end(2, st);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st) {
   timer_work(3, 40.0 * (double)d.nN, 20.0 * (double)d.nN);
   timer_begin(3, st);
-  hipLaunchKernelGGL(k_sl, dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, d.N[0],
-                     d.N[1], d.N[2]);
+  hipError_t e = with_grid(d, [&](auto gs) {
+    hipLaunchKernelGGL((k_sl<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, gs);
+    return hipGetLastError();
+  });
   timer_end(3, st);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st) {
   dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
   size_t shm = src_shared_bytes(d);
-  hipLaunchKernelGGL(k_src_fwd2, grid, dim3(256), shm, st, a, b, m, coef, s1, tw, d.N[0], d.N[1],
-                     d.N[2], d.Kh);
-  return hipGetLastError();
+  return with_grid(d, [&](auto gs) {
+    hipLaunchKernelGGL((k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, m, coef, s1, tw, gs);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st) {

@@ -30,7 +30,7 @@ E_NONFINITE = -6
 FP32 = 0
 GN_PAPER = 0
 GN_CLASSICAL = 1
-KF_MSTEP, KF_GRID_SRC, KF_SL, KF_INV0, KF_FWD = 1, 2, 3, 4, 5
+KF_SYNTH, KF_GRID, KF_SL, KF_INV0, KF_COLUMN, KF_PRODS = 1, 2, 3, 4, 5, 6
 
 
 class LddmmParams(ctypes.Structure):
