@@ -82,7 +82,7 @@ struct ColJob {
   const float2* base;
   const float2* extra;
   float2* out;
-  float2* t1[2];
+  float2* t1[2];       // [2 vars][M0][Kh][K1]
   float ca, cb, ce;
   int syma, symb;
   int t1l[2];
@@ -123,8 +123,10 @@ hipError_t launch_symbols(float* Lsym, float* Ksym, const Dims& d, hipStream_t s
 hipError_t launch_full_to_half(const float2* full, float2* half, const Dims& d, hipStream_t st);
 hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float2* full,
                                const Dims& d, hipStream_t st);
+// Inverse stage 0; `trans` writes the padded-grid layout [v][x0][kh][k1]
+// instead of [v][x0][k1][kh].
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
-                       int K0, int C, int G0, hipStream_t st);
+                       int K0, int C, int G0, int Kh, bool trans, hipStream_t st);
 hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st);
 size_t synth_table_floats(const Dims& d);
 size_t synth_shared_bytes(const Dims& d);
@@ -133,7 +135,9 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
 size_t prods_shared_bytes(const Dims& d, int nout);
 hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
-                          const float* Lsym, const float* Ksym, hipStream_t st);
+                          const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st);
+size_t col_table_count(const Dims& d);
+hipError_t launch_col_tables(const Twiddles& tw, float2* tab, const Dims& d, hipStream_t st);
 size_t colstep_shared_bytes(const Dims& d);
 hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
                        int Kh, hipStream_t st);

@@ -48,6 +48,8 @@ class Engine {
   hipError_t hessvec(const float2* dvh, float2* out);
 
   const Dims& dims() const { return d_; }
+  // Second stream of this thread and device for the grid chain, and events.
+  hipError_t aux_init(int nevents);
   hipStream_t stream() const { return st_; }
 
   // buffers
@@ -71,16 +73,22 @@ class Engine {
   ColJob col_job(int c, int oa, float ca, int syma, int ob, float cb, int symb, const float2* base,
                  const float2* extra, float ce, float2* out, int g0, int l0, int g1, int l1) const;
   hipError_t colstep(const ColJob* jobs, int n);
-  hipError_t fwd_grid(Fwd0Job* jobs, int njobs);
-  hipError_t grid_velocities(const std::vector<float2*>& bands, int count, std::vector<float*>& out);
+  hipError_t fwd_grid(Fwd0Job* jobs, int njobs, hipStream_t s);
+
+  hipError_t record(hipStream_t s, int ev);
+  hipError_t wait(hipStream_t s, int ev);
+  hipError_t grid_velocity(const float2* band, float* out, hipStream_t s);
 
   Dims d_;
   hipStream_t st_;
+  hipStream_t aux_ = nullptr;
+  std::vector<hipEvent_t>* ev_ = nullptr;
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;
   float2 *T1_ = nullptr, *S1_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
   float* NG_ = nullptr;         // scratch for new groups that are not cached
   float* synth_tab_ = nullptr;  // MFMA-form stage-1/2 twiddles of the padded grid
+  float2* col_tab_ = nullptr;   // MFMA-form twiddles of the column step
 };
 
 }  // namespace lddmm

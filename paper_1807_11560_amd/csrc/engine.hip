@@ -10,6 +10,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <map>
 
 namespace lddmm {
 
@@ -20,13 +21,38 @@ namespace lddmm {
   } while (0)
 
 namespace {
-constexpr int kGridChunk = 10;  // time steps per batched band->grid stage-0 launch
 
 size_t twiddle_count(const int* G, const Dims& d) {
   return 2 * (size_t)G[0] * d.K[0] + 2 * (size_t)G[1] * d.K[1] + 2 * (size_t)G[2] * d.Kh +
          (size_t)d.K[0] * G[0] + (size_t)d.K[1] * G[1] + (size_t)d.Kh * G[2];
 }
 }  // namespace
+
+// Per thread and device: the auxiliary stream (default priority) and a
+// pool of timing-free events; created on first use, kept for the process.
+struct AuxRes {
+  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> events;
+};
+static thread_local std::map<int, AuxRes> t_aux;
+
+hipError_t Engine::aux_init(int nevents) {
+  int dev = 0;
+  TRY(hipGetDevice(&dev));
+  AuxRes& r = t_aux[dev];
+  if (!r.stream) TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
+  while ((int)r.events.size() < nevents) {
+    hipEvent_t e;
+    TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    r.events.push_back(e);
+  }
+  aux_ = r.stream;
+  ev_ = &r.events;
+  return hipSuccess;
+}
+
+hipError_t Engine::record(hipStream_t s, int ev) { return hipEventRecord((*ev_)[ev], s); }
+hipError_t Engine::wait(hipStream_t s, int ev) { return hipStreamWaitEvent(s, (*ev_)[ev], 0); }
 
 void Engine::layout(Carver& c) {
   const Dims& d = d_;
@@ -64,9 +90,9 @@ void Engine::layout(Carver& c) {
   T1_ = c.take<float2>(2 * 3 * 2 * (size_t)d.M[0] * C);
   NG_ = c.take<float>(24 * (size_t)d.nM);
   synth_tab_ = c.take<float>(synth_table_floats(d));
+  col_tab_ = c.take<float2>(col_table_count(d));
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
-  const int chunk = std::min(nt, kGridChunk);
-  T1N_ = c.take<float2>((size_t)chunk * 3 * d.N[0] * C);
+  T1N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
   S1N_ = c.take<float2>(3 * (size_t)d.N[0] * d.N[1] * d.Kh);
   S2N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
 }
@@ -108,6 +134,7 @@ hipError_t Engine::init_tables() {
     TRY(launch_twiddles(const_cast<float2*>(tw.fwd2), d_.K[2], G[2], 3, st_));
   }
   TRY(launch_synth_tables(twM_, synth_tab_, d_, st_));
+  TRY(launch_col_tables(twM_, col_tab_, d_, st_));
   return launch_symbols(Lsym, Ksym, d_, st_);
 }
 
@@ -140,7 +167,7 @@ hipError_t Engine::inv0_groups(const float2* in0, int l0, const float2* in1, int
       jobs.j[nj].lflag = lf[g];
       ++nj;
     }
-  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], st_);
+  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], d_.Kh, true, st_);
 }
 
 // Synthesis of the two new groups (into the cache when given, else into
@@ -189,12 +216,12 @@ ColJob Engine::col_job(int c, int oa, float ca, int syma, int ob, float cb, int 
 hipError_t Engine::colstep(const ColJob* jobs, int n) {
   ColJobs js{};
   for (int i = 0; i < n; ++i) js.j[i] = jobs[i];
-  return launch_colstep(js, n, d_, twM_, Lsym, Ksym, st_);
+  return launch_colstep(js, n, d_, twM_, col_tab_, Lsym, Ksym, st_);
 }
 
 // Forward stages 1 and 0 of the three grid fields in S1N with the given
 // band epilogues.
-hipError_t Engine::fwd_grid(Fwd0Job* jobs, int njobs) {
+hipError_t Engine::fwd_grid(Fwd0Job* jobs, int njobs, hipStream_t s) {
   const int C = d_.K[1] * d_.Kh;
   const int* G = d_.N;
   Fwd1Jobs j1{};
@@ -202,41 +229,31 @@ hipError_t Engine::fwd_grid(Fwd0Job* jobs, int njobs) {
     j1.j[o].in = S1N_ + (size_t)o * G[0] * G[1] * d_.Kh;
     j1.j[o].out = S2N_ + (size_t)o * G[0] * C;
   }
-  TRY(launch_fwd1(j1, 3, twN_.fwd1, G[0], G[1], d_.K[1], d_.Kh, st_));
+  TRY(launch_fwd1(j1, 3, twN_.fwd1, G[0], G[1], d_.K[1], d_.Kh, s));
   Fwd0Jobs j0{};
   for (int k = 0; k < njobs; ++k) j0.j[k] = jobs[k];
   const float invG = (float)(1.0 / ((double)G[0] * G[1] * G[2]));
-  return launch_fwd0(j0, njobs, twN_.fwd0, Ksym, G[0], d_.K[0], d_.K[1], d_.Kh, invG, st_);
+  return launch_fwd0(j0, njobs, twN_.fwd0, Ksym, G[0], d_.K[0], d_.K[1], d_.Kh, invG, s);
 }
 
 const float2* Engine::s2n(int o) const { return S2N_ + (size_t)o * d_.N[0] * d_.K[1] * d_.Kh; }
 
-// Band fields -> grid velocities vg[n] for the first `count` entries.
-hipError_t Engine::grid_velocities(const std::vector<float2*>& bands, int count,
-                                   std::vector<float*>& out) {
+// One band field -> grid velocity (stage 0 then the grid step) on stream s.
+hipError_t Engine::grid_velocity(const float2* band, float* out, hipStream_t s) {
   const int C = d_.K[1] * d_.Kh;
   const size_t t1 = (size_t)d_.N[0] * C;
-  for (int s0 = 0; s0 < count; s0 += kGridChunk) {
-    const int ns = std::min(kGridChunk, count - s0);
-    Inv0Jobs jobs{};
-    int nj = 0;
-    for (int s = 0; s < ns; ++s)
-      for (int c = 0; c < 3; ++c) {
-        jobs.j[nj].in = bands[s0 + s] + (size_t)c * d_.nb;
-        jobs.j[nj].out = T1N_ + (size_t)(s * 3 + c) * t1;
-        jobs.j[nj].lflag = 0;
-        ++nj;
-      }
-    TRY(launch_inv0(jobs, nj, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], st_));
-    for (int s = 0; s < ns; ++s) {
-      GridStepArgs a{};
-      a.t1 = T1N_ + (size_t)s * 3 * t1;
-      a.op = 0;
-      a.vout = out[s0 + s];
-      TRY(launch_gridstep(a, d_, twN_, st_));
-    }
+  Inv0Jobs jobs{};
+  for (int c = 0; c < 3; ++c) {
+    jobs.j[c].in = band + (size_t)c * d_.nb;
+    jobs.j[c].out = T1N_ + (size_t)c * t1;
+    jobs.j[c].lflag = 0;
   }
-  return hipSuccess;
+  TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, s));
+  GridStepArgs a{};
+  a.t1 = T1N_;
+  a.op = 0;
+  a.vout = out;
+  return launch_gridstep(a, d_, twN_, s);
 }
 
 hipError_t Engine::shoot_band(bool cache) {
@@ -252,32 +269,48 @@ hipError_t Engine::shoot_band(bool cache) {
       jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, V[n], nullptr, 0.f, V[n + 1], next ? 0 : -1, 0,
                         next ? 1 : -1, 1);
     TRY(colstep(jobs, 3));
+    if (ev_) TRY(record(st_, n + 1));
   }
   return hipSuccess;
 }
 
+// Shooting on the caller's stream; the grid chain (velocity of step n, then
+// the transport step) on the auxiliary stream as soon as v_n exists.
 hipError_t Engine::forward(const float* I0) {
   const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  TRY(aux_init(nt + 2));
+  TRY(record(st_, 0));
   TRY(shoot_band(true));
-  TRY(grid_velocities(V, d_.nt, vg));
-  TRY(launch_copy(I0, m[0], d_.nN, st_));
-  for (int n = 0; n < d_.nt; ++n) TRY(launch_sl(m[n], vg[n], m[n + 1], dt, d_, st_));
-  return hipSuccess;
+  TRY(wait(aux_, 0));
+  TRY(launch_copy(I0, m[0], d_.nN, aux_));
+  for (int n = 0; n < nt; ++n) {
+    if (n > 0) TRY(wait(aux_, n));
+    TRY(grid_velocity(V[n], vg[n], aux_));
+    TRY(launch_sl(m[n], vg[n], m[n + 1], dt, d_, aux_));
+  }
+  TRY(record(aux_, nt + 1));
+  return wait(st_, nt + 1);
 }
 
 // Shooting and transport without the caches; returns m_nt in *m_out.
 hipError_t Engine::forward_light(const float* I0, const float** m_out) {
   const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  TRY(aux_init(nt + 2));
+  TRY(record(st_, 0));
   TRY(shoot_band(false));
-  std::vector<float*> one(1, vg[0]);
+  TRY(wait(aux_, 0));
   const float* cur = I0;
-  for (int n = 0; n < d_.nt; ++n) {
-    std::vector<float2*> b(1, V[n]);
-    TRY(grid_velocities(b, 1, one));
+  for (int n = 0; n < nt; ++n) {
+    if (n > 0) TRY(wait(aux_, n));
+    TRY(grid_velocity(V[n], vg[0], aux_));
     float* dst = mlight[n & 1];
-    TRY(launch_sl(cur, vg[0], dst, dt, d_, st_));
+    TRY(launch_sl(cur, vg[0], dst, dt, d_, aux_));
     cur = dst;
   }
+  TRY(record(aux_, nt + 1));
+  TRY(wait(st_, nt + 1));
   *m_out = cur;
   return hipSuccess;
 }
@@ -303,7 +336,7 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
     fj[c].syma = 1;
     fj[c].out = U[nt] + (size_t)c * d_.nb;
   }
-  TRY(fwd_grid(fj, 3));
+  TRY(fwd_grid(fj, 3, st_));
   TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
   TRY(inv0_groups(U[nt], 1, W[nt], 0));
   for (int n = nt - 1; n >= 0; --n) {
@@ -329,9 +362,11 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   const int nt = d_.nt;
   const bool coupled = d_.hessian == 0;
   const size_t nM = (size_t)d_.nM;
+  TRY(aux_init(nt + 2));
   if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
                                     6LL * d_.nb, st_));
-  // incremental EPDiff forward
+  TRY(record(st_, 0));
+  // incremental EPDiff forward (caller's stream); event n+1 marks dv_{n+1}
   TRY(inv0_groups(dV[0], 0, dV[0], 1));
   for (int n = 0; n < nt; ++n) {
     const bool last = n == nt - 1;
@@ -345,43 +380,37 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
       for (int c = 0; c < 3; ++c)
         jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1);
       TRY(colstep(jobs, 3));
+      TRY(record(st_, n + 1));
     }
   }
-  // incremental state transport
+  // incremental state transport on the auxiliary stream, step n once dv_n exists
   {
     const int C = d_.K[1] * d_.Kh;
-    const size_t t1n = (size_t)d_.N[0] * C;
     const float* dmcur = nullptr;
-    for (int s0 = 0; s0 < nt; s0 += kGridChunk) {
-      const int ns = std::min(kGridChunk, nt - s0);
+    for (int n = 0; n < nt; ++n) {
+      TRY(wait(aux_, n));
       Inv0Jobs jobs{};
-      int nj = 0;
-      for (int s = 0; s < ns; ++s)
-        for (int c = 0; c < 3; ++c) {
-          jobs.j[nj].in = dV[s0 + s] + (size_t)c * d_.nb;
-          jobs.j[nj].out = T1N_ + (size_t)(s * 3 + c) * t1n;
-          jobs.j[nj].lflag = 0;
-          ++nj;
-        }
-      TRY(launch_inv0(jobs, nj, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], st_));
-      for (int s = 0; s < ns; ++s) {
-        const int n = s0 + s;
-        GridStepArgs a{};
-        a.t1 = T1N_ + (size_t)s * 3 * t1n;
-        a.op = 1;
-        a.m = m[n];
-        a.dm = dmcur;
-        a.q = q;
-        a.dt = dt;
-        TRY(launch_gridstep(a, d_, twN_, st_));
-        float* dst = dm[n & 1];
-        TRY(launch_sl(q, vg[n], dst, dt, d_, st_));
-        dmcur = dst;
+      for (int c = 0; c < 3; ++c) {
+        jobs.j[c].in = dV[n] + (size_t)c * d_.nb;
+        jobs.j[c].out = T1N_ + (size_t)c * d_.N[0] * C;
+        jobs.j[c].lflag = 0;
       }
+      TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, aux_));
+      GridStepArgs a{};
+      a.t1 = T1N_;
+      a.op = 1;
+      a.m = m[n];
+      a.dm = dmcur;
+      a.q = q;
+      a.dt = dt;
+      TRY(launch_gridstep(a, d_, twN_, aux_));
+      float* dst = dm[n & 1];
+      TRY(launch_sl(q, vg[n], dst, dt, d_, aux_));
+      dmcur = dst;
     }
     // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt
     const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
-    TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, st_));
+    TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, aux_));
     Fwd0Job fj[3];
     for (int c = 0; c < 3; ++c) {
       fj[c] = Fwd0Job{};
@@ -390,7 +419,9 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
       fj[c].syma = 1;
       fj[c].out = dU[0] + (size_t)c * d_.nb;
     }
-    TRY(fwd_grid(fj, 3));
+    TRY(fwd_grid(fj, 3, aux_));
+    TRY(record(aux_, nt + 1));
+    TRY(wait(st_, nt + 1));
   }
   // incremental adjoint Jacobi sweep backward
   TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));

@@ -12,6 +12,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace lddmm {
 
@@ -171,10 +172,12 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
 
 // ------------------------------------------------- inverse stage 0 (k0)
 // out[v][x0][c] = sum_k0 tw[v][x0][k0] * in[k0][c] (optionally in * L~).
-template <int NV, int XT>
+// KC > 0: compile-time K0 = KC (all loads of a column issued before use).
+template <int NV, int XT, bool TRANS, int KC>
 __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __restrict__ tw,
-                                              const float* __restrict__ Lsym, int K0, int C,
-                                              int G0) {
+                                              const float* __restrict__ Lsym, int K0r, int C,
+                                              int G0, int Kh) {
+  const int K0 = KC > 0 ? KC : K0r;
   extern __shared__ float2 sh[];
   const Inv0Job job = jobs.j[blockIdx.z];
   const int xb = blockIdx.y * XT;
@@ -191,24 +194,39 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int t = 0; t < XT; ++t) acc[v][t] = make_float2(0.f, 0.f);
-  for (int k = 0; k < K0; ++k) {
-    float2 val = job.in[(size_t)k * C + c];
+  // columns in chunks of eight: the chunk's loads are in flight together
+#pragma unroll 1
+  for (int k0 = 0; k0 < K0; k0 += 8) {
+    float2 col[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) col[u] = (k0 + u < K0) ? job.in[(size_t)(k0 + u) * C + c] : make_float2(0.f, 0.f);
     if (job.lflag) {
-      float l = Lsym[(size_t)k * C + c];
-      val.x *= l;
-      val.y *= l;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        float l = (k0 + u < K0) ? Lsym[(size_t)(k0 + u) * C + c] : 0.f;
+        col[u].x *= l;
+        col[u].y *= l;
+      }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u >= K0) break;
 #pragma unroll
-      for (int t = 0; t < XT; ++t) cmac(acc[v][t], sh[(v * XT + t) * K0 + k], val);
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int t = 0; t < XT; ++t) cmac(acc[v][t], sh[(v * XT + t) * K0 + k0 + u], col[u]);
+    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int t = 0; t < XT; ++t) {
       int x = xb + t;
-      if (x < G0) job.out[((size_t)v * G0 + x) * C + c] = acc[v][t];
+      if (x < G0) {
+        // padded-grid stage-0 buffers are [v][x0][kh][k1]; grid ones [v][x0][k1][kh]
+        const int co = TRANS ? (c % Kh) * (C / Kh) + c / Kh : c;
+        job.out[((size_t)v * G0 + x) * C + co] = acc[v][t];
+      }
     }
 }
 
@@ -288,7 +306,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
   batched_fill<float2>(2 * K1 * Khp, [&](int i) {
     int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
-    return (kh < Kh) ? src[((size_t)vs * M0 + x0) * C + (size_t)k1 * Kh + kh] : make_float2(0.f, 0.f);
+    return (kh < Kh) ? src[((size_t)vs * M0 + x0) * C + (size_t)kh * K1 + k1] : make_float2(0.f, 0.f);
   }, [&](int i, float2 t) {
     int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
     float* b = bt1 + (size_t)vs * K2r * N1;
@@ -575,7 +593,177 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
       const float2* w = w0s + ((size_t)v * M0 + x0) * K0;
       float2 acc = make_float2(0.f, 0.f);
       for (int k0 = 0; k0 < K0; ++k0) cmac(acc, w[k0], bsrc[(size_t)k0 * KG + kk]);
-      dst[((size_t)v * M0 + x0) * C + (size_t)k1 * Kh + kh] = acc;
+      dst[((size_t)v * M0 + x0) * C + (size_t)kh * K1 + k1] = acc;
+    }
+  }
+}
+
+// ------------------------------------------ MFMA column step (tuned shapes)
+// Complex 16x16 output tile by four real MFMAs per k-step of four:
+// acc0 += Ar Br, acc1 += Ai Bi, acc2 += Ar Bi, acc3 += Ai Br, so the tile is
+// (acc0 - acc1) + i (acc2 + acc3).  A(row, k) = A[row * lda + k] and
+// B(k, col) = B[k * ldb + col] for the tile's 16 rows / 16 columns.
+template <int KSTEPS>
+__device__ __forceinline__ void ctile(const float2* __restrict__ A, int lda, const float2* __restrict__ B,
+                                      int ldb, floatx4* acc) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const float2* a = A + li * lda + lk;
+  const float2* b = B + lk * ldb + li;
+#pragma unroll
+  for (int k0 = 0; k0 < KSTEPS; k0 += 4) {
+    float2 av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < KSTEPS) {
+        av[u] = a[4 * (k0 + u)];
+        bv[u] = b[4 * (k0 + u) * ldb];
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < KSTEPS) {
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].x, bv[u].x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].y, bv[u].y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].x, bv[u].y, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].y, bv[u].x, acc[3], 0, 0, 0);
+      }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(floatx4* acc, int n) {
+  for (int i = 0; i < n; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Tables for the MFMA column step: w1t[x1][k1] = fwd1[k1][x1] (columns padded
+// to Kp), w0f[k0][x0] = fwd0 (rows padded to Kp), w0i[v][x0][k0] = inv0 (rows
+// padded to Mp); padding is zero.
+__global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float2* inv0, float2* w1t,
+                             float2* w0f, float2* w0i, int M, int K, int Mp, int Kp) {
+  const int n1 = M * Kp, n2 = Kp * M, n3 = 2 * Mp * K;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const float2 z = make_float2(0.f, 0.f);
+  if (i < n1) {
+    int x1 = i / Kp, k1 = i % Kp;
+    w1t[i] = (k1 < K) ? fwd1[(size_t)k1 * M + x1] : z;
+  } else if (i < n1 + n2) {
+    int e = i - n1, k0 = e / M, x0 = e % M;
+    w0f[e] = (k0 < K) ? fwd0[(size_t)k0 * M + x0] : z;
+  } else if (i < n1 + n2 + n3) {
+    int e = i - n1 - n2, v = e / (Mp * K), x0 = (e / K) % Mp, k0 = e % K;
+    w0i[e] = (x0 < M) ? inv0[((size_t)v * M + x0) * K + k0] : z;
+  }
+}
+
+// One block per (kh, job), four waves; same contract as k_colstep.
+template <class S>
+__global__ void __launch_bounds__(256) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
+                                                      const float2* __restrict__ w0f,
+                                                      const float2* __restrict__ w0i,
+                                                      const float* __restrict__ Lsym,
+                                                      const float* __restrict__ Ksym, float invG) {
+  constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
+  constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
+  constexpr int LS1 = M + 2, LS2 = Kp + 2, LOB = Kp + 2;
+  constexpr int C = K * Kh;
+  constexpr int LW1 = Kp + 2, LW0F = M + 2, LW0I = K + 2;
+  __shared__ float2 s1[2][Mp][LS1];
+  __shared__ float2 s2[2][M][LS2];
+  __shared__ float2 ob[2][K][LOB];
+  __shared__ float2 w1s[M][LW1];        // w1t
+  __shared__ float2 w0fs[Kp][LW0F];     // w0f
+  __shared__ float2 w0is[2][Mp][LW0I];  // w0i
+  const ColJob& job = jobs.j[blockIdx.y];
+  const int kh = blockIdx.x;
+  const int nterm = job.b ? 2 : 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+
+  {  // S1 slices of the terms at this kh -> s1 (rows beyond M zero)
+    const float2* sa = job.a + (size_t)kh * M * M;
+    const float2* sb = job.b ? job.b + (size_t)kh * M * M : sa;
+    batched_fill<float2>(nterm * Mp * M, [&](int i) {
+      const int t = i / (Mp * M), x0 = (i / M) % Mp, x1 = i % M;
+      return (x0 < M) ? (t ? sb : sa)[x0 * M + x1] : make_float2(0.f, 0.f);
+    }, [&](int i, float2 v) {
+      const int t = i / (Mp * M), x0 = (i / M) % Mp, x1 = i % M;
+      s1[t][x0][x1] = v;
+    });
+  }
+  batched_fill<float2>(M * Kp, [&](int i) { return w1t[i]; }, [&](int i, float2 v) { w1s[i / Kp][i % Kp] = v; });
+  batched_fill<float2>(Kp * M, [&](int i) { return w0f[i]; }, [&](int i, float2 v) { w0fs[i / M][i % M] = v; });
+  batched_fill<float2>(2 * Mp * K, [&](int i) { return w0i[i]; },
+                       [&](int i, float2 v) { w0is[i / (Mp * K)][(i / K) % Mp][i % K] = v; });
+  __syncthreads();
+  // stage 1': s2[t][x0][k1] = sum_x1 s1[t][x0][x1] w1t[x1][k1]
+  constexpr int T1R = Mp / 16, T1C = Kp / 16;
+  for (int jb = wave; jb < nterm * T1R * T1C; jb += 4) {
+    const int t = jb / (T1R * T1C), ti = (jb / T1C) % T1R, tj = jb % T1C;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<M / 4>(&s1[t][ti * 16][0], LS1, &w1s[0][tj * 16], LW1, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x0 = ti * 16 + 4 * lk + r;
+      if (x0 < M) s2[t][x0][tj * 16 + li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+    }
+  }
+  __syncthreads();
+  // stage 0' and the band update
+  constexpr int T0 = Kp / 16;
+  for (int jb = wave; jb < T0 * T0; jb += 4) {
+    const int ti = jb / T0, tj = jb % T0;
+    floatx4 aa[4], bb[4];
+    zero_acc(aa, 4);
+    zero_acc(bb, 4);
+    ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][tj * 16], LS2, aa);
+    if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][tj * 16], LS2, bb);
+    const int k1 = tj * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = ti * 16 + 4 * lk + r;
+      if (k0 >= K || k1 >= K) continue;
+      const size_t idx = ((size_t)k0 * K + k1) * Kh + kh;
+      float2 res = make_float2(0.f, 0.f);
+      if (k0 != K / 2 && k1 != K / 2) {
+        if (job.base) res = job.base[idx];
+        const float ks = Ksym[idx];
+        const float sa = job.ca * invG * (job.syma ? ks : 1.f);
+        res.x = fmaf(sa, aa[0][r] - aa[1][r], res.x);
+        res.y = fmaf(sa, aa[2][r] + aa[3][r], res.y);
+        if (nterm == 2) {
+          const float sb = job.cb * invG * (job.symb ? ks : 1.f);
+          res.x = fmaf(sb, bb[0][r] - bb[1][r], res.x);
+          res.y = fmaf(sb, bb[2][r] + bb[3][r], res.y);
+        }
+        if (job.extra) {
+          const float2 e = job.extra[idx];
+          res.x = fmaf(job.ce, e.x, res.x);
+          res.y = fmaf(job.ce, e.y, res.y);
+        }
+      }
+      job.out[idx] = res;
+      ob[0][k0][k1] = res;
+      const float l = Lsym[idx];
+      ob[1][k0][k1] = make_float2(l * res.x, l * res.y);
+    }
+  }
+  if (job.nt1 == 0) return;
+  __syncthreads();
+  // next inverse stage 0: t1[v][x0][kh][k1] = sum_k0 w0i[v][x0][k0] ob[L][k0][k1]
+  constexpr int TIR = Mp / 16, TIC = Kp / 16;
+  const int njb = job.nt1 * 2 * TIR * TIC;
+  for (int jb = wave; jb < njb; jb += 4) {
+    const int u = jb / (2 * TIR * TIC), v = (jb / (TIR * TIC)) % 2, ti = (jb / TIC) % TIR, tj = jb % TIC;
+    const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
+    float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][tj * 16], LOB, acc);
+    const int k1 = tj * 16 + li;
+    if (k1 >= K) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x0 = ti * 16 + 4 * lk + r;
+      if (x0 < M)
+        dst[((size_t)v * M + x0) * C + (size_t)kh * K + k1] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
     }
   }
 }
@@ -768,6 +956,89 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, G
       float dot = g0 * acc[0][j] + g1 * acc[1][j] + g2 * acc[2][j];
       float base = a.dm ? a.dm[gi] : 0.f;
       a.q[gi] = fmaf(-a.dt, dot, base);
+    }
+  }
+}
+
+// Grid step on the matrix cores (tuned shapes): same contract as
+// k_gridstep.  Stage 1 is a complex GEMM per component (16 rows x Kh),
+// stage 2 the real part of a complex GEMM per (component, 16-column tile);
+// a wave owns the three components of its column tiles, so the source
+// term is formed in registers.
+template <class G>
+__global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles tw) {
+  constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
+  constexpr int R = kGridRows, C = K1 * Kh;
+  constexpr int Khp = (Kh + 15) & ~15;  // half-spectrum columns padded to whole tiles (zero)
+  constexpr int LT1 = Khp + 2, LW1 = K1 + 2, LT2 = Khp + 2, LW2 = N2 + 2;
+  static_assert(K1 % 4 == 0 && N2 % 16 == 0, "tuned grid shape");
+  __shared__ float2 t1s[3][K1][LT1];
+  __shared__ float2 w1s[R][LW1];
+  __shared__ float2 t2s[3][R][LT2];
+  __shared__ float2 w2t[Khp][LW2];
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  batched_fill<float2>(3 * K1 * Khp, [&](int i) {
+    const int c = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+    return (kh < Kh) ? a.t1[((size_t)c * N0 + x0) * C + k1 * Kh + kh] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { t1s[i / (K1 * Khp)][(i / Khp) % K1][i % Khp] = v; });
+  batched_fill<float2>(R * K1, [&](int i) {
+    const int x1 = x1b + i / K1;
+    return (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + i % K1] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { w1s[i / K1][i % K1] = v; });
+  batched_fill<float2>(N2 * Khp, [&](int i) {
+    const int x2 = i / Khp, kh = i % Khp;
+    return (kh < Kh) ? tw.inv2[(size_t)x2 * Kh + kh] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { w2t[i % Khp][i / Khp] = v; });
+  __syncthreads();
+  // stage 1: one 16 x Kh complex tile per component (waves 0..2 when Kh = 16)
+  for (int jb = wave; jb < 3 * (Khp / 16); jb += 4) {
+    const int c = jb % 3, tj = jb / 3;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<K1 / 4>(&w1s[0][0], LW1, &t1s[c][0][tj * 16], LT1, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      t2s[c][4 * lk + r][tj * 16 + li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+  }
+  __syncthreads();
+  // stage 2 + epilogue: a wave takes whole column tiles (all components)
+  const long long nN = (long long)N0 * N1 * N2;
+  for (int tj = wave; tj < N2 / 16; tj += 4) {
+    floatx4 vel[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      floatx4 acc[4];
+      zero_acc(acc, 4);
+      // only the real part is needed: acc0 - acc1
+      const float2* A = &t2s[c][0][0] + li * LT2 + lk;
+      const float2* B = &w2t[0][0] + lk * LW2 + tj * 16 + li;
+#pragma unroll
+      for (int ks = 0; ks < Khp / 4; ++ks) {
+        const float2 av = A[4 * ks], bv = B[4 * ks * LW2];
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[1], 0, 0, 0);
+      }
+      vel[c] = acc[0] - acc[1];
+    }
+    const int x2 = tj * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x1 = x1b + 4 * lk + r;
+      if (x1 >= N1) continue;
+      const long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+      if (a.op == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = vel[c][r];
+      } else {
+        const float g0 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 0);
+        const float g1 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 1);
+        const float g2 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 2);
+        const float dot = g0 * vel[0][r] + g1 * vel[1][r] + g2 * vel[2][r];
+        const float base = a.dm ? a.dm[gi] : 0.f;
+        a.q[gi] = fmaf(-a.dt, dot, base);
+      }
     }
   }
 }
@@ -1074,7 +1345,7 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
 }
 
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
-                       int K0, int C, int G0, hipStream_t st) {
+                       int K0, int C, int G0, int Kh, bool trans, hipStream_t st) {
   const int T = 128;
   {
     double fl = 0, by = 0;
@@ -1084,21 +1355,30 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
     }
     timer_work(4, fl, by);
   }
+  auto go = [&](auto nv_tag, auto xt_tag, auto kc_tag) {
+    constexpr int NV = decltype(nv_tag)::value, XT = decltype(xt_tag)::value, KC = decltype(kc_tag)::value;
+    dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
+    size_t shm = NV * XT * K0 * sizeof(float2);
+    if (trans)
+      hipLaunchKernelGGL((k_inv0<NV, XT, true, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
+    else
+      hipLaunchKernelGGL((k_inv0<NV, XT, false, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
+  };
+  using I2 = std::integral_constant<int, 2>;
+  using I1 = std::integral_constant<int, 1>;
+  using X8 = std::integral_constant<int, 8>;
+  using X16 = std::integral_constant<int, 16>;
+  timer_begin(4, st);
   if (nvar == 2) {
-    constexpr int XT = 8;
-    dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
-    size_t shm = 2 * XT * K0 * sizeof(float2);
-    timer_begin(4, st);
-    hipLaunchKernelGGL((k_inv0<2, XT>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0);
-    timer_end(4, st);
+    if (K0 == 32) go(I2{}, X8{}, std::integral_constant<int, 32>{});
+    else if (K0 == 16) go(I2{}, X8{}, std::integral_constant<int, 16>{});
+    else go(I2{}, X8{}, std::integral_constant<int, 0>{});
   } else {
-    constexpr int XT = 16;
-    dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
-    size_t shm = XT * K0 * sizeof(float2);
-    timer_begin(4, st);
-    hipLaunchKernelGGL((k_inv0<1, XT>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0);
-    timer_end(4, st);
+    if (K0 == 32) go(I1{}, X16{}, std::integral_constant<int, 32>{});
+    else if (K0 == 16) go(I1{}, X16{}, std::integral_constant<int, 16>{});
+    else go(I1{}, X16{}, std::integral_constant<int, 0>{});
   }
+  timer_end(4, st);
   return hipGetLastError();
 }
 
@@ -1202,10 +1482,27 @@ size_t colstep_shared_bytes(const Dims& d) {
           2 * (size_t)K0 * kColGroup) * sizeof(float2);
 }
 
+size_t col_table_count(const Dims& d) {
+  const int M = d.M[0], K = d.K[0];
+  const int Mp = round_up(M, 16), Kp = round_up(K, 16);
+  return (size_t)M * Kp + (size_t)Kp * M + 2 * (size_t)Mp * K;
+}
+
+hipError_t launch_col_tables(const Twiddles& tw, float2* tab, const Dims& d, hipStream_t st) {
+  const int M = d.M[0], K = d.K[0];
+  const int Mp = round_up(M, 16), Kp = round_up(K, 16);
+  // the MFMA column kernel runs for shapes with K0 = K1 and M0 = M1 only
+  if (d.M[1] != M || d.K[1] != K) return hipSuccess;
+  float2* w1t = tab;
+  float2* w0f = w1t + (size_t)M * Kp;
+  float2* w0i = w0f + (size_t)Kp * M;
+  hipLaunchKernelGGL(k_col_tables, dim3(nblk((long long)col_table_count(d), 256)), dim3(256), 0, st, tw.fwd1,
+                     tw.fwd0, tw.inv0, w1t, w0f, w0i, M, K, Mp, Kp);
+  return hipGetLastError();
+}
+
 hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
-                          const float* Lsym, const float* Ksym, hipStream_t st) {
-  dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
-  size_t shm = colstep_shared_bytes(d);
+                          const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st) {
   {
     const double M0 = d.M[0], M1 = d.M[1], K0 = d.K[0], K1 = d.K[1], Kh = d.Kh;
     double fl = 0, by = 0;
@@ -1219,12 +1516,31 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
     timer_work(5, fl, by);
   }
   const float invG = (float)(1.0 / ((double)d.M[0] * d.M[1] * d.M[2]));
+  const int M = d.M[0], K = d.K[0];
+  const float2* w1t = coltab;
+  const float2* w0f = w1t + (size_t)M * round_up(K, 16);
+  const float2* w0i = w0f + (size_t)round_up(K, 16) * M;
   timer_begin(5, st);
-  hipError_t e = with_band(d, [&](auto sh) {
-    hipLaunchKernelGGL((k_colstep<kColGroup, decltype(sh)>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh,
-                       invG);
-    return hipGetLastError();
-  });
+  hipError_t e;
+  if (band_iso(d, 32, 48)) {
+    hipLaunchKernelGGL((k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+                       w0i, Lsym, Ksym, invG);
+    e = hipGetLastError();
+  } else if (band_iso(d, 16, 24)) {
+    hipLaunchKernelGGL((k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+                       w0i, Lsym, Ksym, invG);
+    e = hipGetLastError();
+  } else if (band_iso(d, 24, 36)) {
+    hipLaunchKernelGGL((k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+                       w0i, Lsym, Ksym, invG);
+    e = hipGetLastError();
+  } else {
+    dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
+    size_t shm = colstep_shared_bytes(d);
+    BandDyn sh{d.K[0], d.K[1], d.Kh, d.M[0], d.M[1], d.M[2]};
+    hipLaunchKernelGGL((k_colstep<kColGroup, BandDyn>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh, invG);
+    e = hipGetLastError();
+  }
   timer_end(5, st);
   return e;
 }
@@ -1288,19 +1604,26 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
     timer_work(2, fl, by);
   }
   timer_begin(2, st);
-  const int jn = (d.N[2] + 15) / 16;
-  hipError_t e = with_grid(d, [&](auto gs) {
-    using G = decltype(gs);
+  hipError_t e;
+  if (grid_iso(d, 128, 32)) {
+    hipLaunchKernelGGL((k_gridstep_mfma<GridIso<128, 32>>), grid, dim3(256), 0, st, a, tw);
+    e = hipGetLastError();
+  } else if (grid_iso(d, 64, 16)) {
+    hipLaunchKernelGGL((k_gridstep_mfma<GridIso<64, 16>>), grid, dim3(256), 0, st, a, tw);
+    e = hipGetLastError();
+  } else {
+    const int jn = (d.N[2] + 15) / 16;
+    GridDyn gs{d.N[0], d.N[1], d.N[2], d.K[1], d.Kh};
     if (jn <= 2)
-      hipLaunchKernelGGL((k_gridstep<2, G>), grid, dim3(256), shm, st, a, tw, gs);
+      hipLaunchKernelGGL((k_gridstep<2, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else if (jn <= 4)
-      hipLaunchKernelGGL((k_gridstep<4, G>), grid, dim3(256), shm, st, a, tw, gs);
+      hipLaunchKernelGGL((k_gridstep<4, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else if (jn <= 8)
-      hipLaunchKernelGGL((k_gridstep<8, G>), grid, dim3(256), shm, st, a, tw, gs);
+      hipLaunchKernelGGL((k_gridstep<8, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else
-      hipLaunchKernelGGL((k_gridstep<16, G>), grid, dim3(256), shm, st, a, tw, gs);
-    return hipGetLastError();
-  });
+      hipLaunchKernelGGL((k_gridstep<16, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
+    e = hipGetLastError();
+  }
   timer_end(2, st);
   return e;
 }
