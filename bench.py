@@ -26,9 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Hessian-vector products/s + registrations/min, 128³ band 32³, FP32/BF16 vs FP64"
 CONFIG = 3
-PEAK_TFLOPS_FP32 = 157.3
+PEAK_TFLOPS_FP32 = 157.3   # MI355X dense FP32 (MFMA); also the packed-FP32 vector peak
 PEAK_GBS_HBM = 8000.0
-FAMILIES = {1: "k_synth", 2: "k_gridstep", 3: "k_sl", 4: "k_inv0", 5: "k_colstep", 6: "k_prods"}
+TIMER_EVERY = 4            # the timed region brackets one launch in 4 of the dominant kernel
+# kernels whose contractions run on the matrix cores
+MFMA_KERNELS = {1, 2, 5}
 
 
 def log(*a):
@@ -45,19 +47,39 @@ def parse():
     return ap.parse_args()
 
 
-def roofline(fam, launches, ms, flops, nbytes):
+def roofline(fam, name, launches, ms, flops, nbytes, traffic):
     t = ms * 1e-3
     tf = flops / t / 1e12
     gbs = nbytes / t / 1e9
-    f_alu = tf / PEAK_TFLOPS_FP32
+    f_cmp = tf / PEAK_TFLOPS_FP32
     f_hbm = gbs / PEAK_GBS_HBM
-    if f_hbm > f_alu:
-        return {"bound": "hbm", "achieved": gbs, "peak": PEAK_GBS_HBM, "unit": "GB/s", "frac": f_hbm,
-                "traffic": None, "kernel": FAMILIES[fam], "launches": launches,
-                "avg_us": 1e3 * ms / max(launches, 1), "flops_tflops": tf}
-    return {"bound": "alu", "achieved": tf, "peak": PEAK_TFLOPS_FP32, "unit": "TFLOP/s", "frac": f_alu,
-            "traffic": None, "kernel": FAMILIES[fam], "launches": launches,
-            "avg_us": 1e3 * ms / max(launches, 1), "hbm_gbs": gbs}
+    common = {"kernel": name, "timed_launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
+              "flops_per_launch": flops / max(launches, 1), "bytes_per_launch": nbytes / max(launches, 1)}
+    if f_hbm > f_cmp:
+        return dict({"bound": "hbm", "achieved": gbs, "peak": PEAK_GBS_HBM, "unit": "GB/s", "frac": f_hbm,
+                     "traffic": traffic, "tflops": tf}, **common)
+    return dict({"bound": "mfma" if fam in MFMA_KERNELS else "alu", "achieved": tf, "peak": PEAK_TFLOPS_FP32,
+                 "unit": "TFLOP/s", "frac": f_cmp, "traffic": traffic, "gbs": gbs}, **common)
+
+
+def stored_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    or None if there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    src = os.path.join(ROOT, "paper_1807_11560_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] == "traffic" and cells[1] == kernel_name:
+            if cells[3] != digest:
+                log(f"traffic: {kernel_name} changed since its counters were taken")
+                return None
+            return float(cells[2])
+    return None
 
 
 def cpu_baseline(w):
@@ -104,7 +126,6 @@ def main():
                      sigma=pp["sigma"], hessian=L.GN_PAPER)
     gn, pcg = pp["gn"], pp["pcg"]
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
     ws = L.Workspace(prob, dev)
     I0 = torch.from_numpy(w["I0"]).float().to(dev)
     vstar = torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev)
@@ -112,32 +133,31 @@ def main():
     torch.cuda.synchronize()
     log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
 
-    # dominant kernel family, from a short Hessian-vector product loop
-    L.gradient(prob, I0, I1, 0.5 * vstar, ws)
-    d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
-    out = torch.empty_like(d)
-    fam_ms = {}
-    for fam in FAMILIES:
-        L.kernel_timer(fam)
-        for _ in range(3):
-            L.hessvec(prob, d, ws, out=out)
-        torch.cuda.synchronize()
-        fam_ms[fam] = L.kernel_timer_read()[1] / 3
-    L.kernel_timer(0)
-    dominant = max(fam_ms, key=fam_ms.get)
-    log("per-HVP ms by family: " + ", ".join(f"{FAMILIES[f]} {fam_ms[f]:.3f}" for f in FAMILIES))
+    def registration():
+        return L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
 
     for _ in range(args.warmup):
-        L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
+        registration()
     torch.cuda.synchronize()
 
-    L.kernel_timer(dominant)
+    # dominant kernel: the largest summed duration over one registration
+    fam_ms = {}
+    for fam in L.KERNEL_FAMILIES:
+        L.kernel_timer(fam, 1)
+        registration()
+        fam_ms[fam] = L.kernel_timer_read()[1]
+    L.kernel_timer(0)
+    dominant = max(fam_ms, key=fam_ms.get)
+    log("ms per registration by kernel: " + ", ".join(f"{L.KERNEL_FAMILIES[f]} {fam_ms[f]:.2f}" for f in fam_ms))
+
+    # timed region: K registrations, one launch in TIMER_EVERY of the dominant kernel bracketed by events
+    L.kernel_timer(dominant, TIMER_EVERY)
     hvps = 0
     stats = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        v, stats, rc, n = L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
+        v, stats, rc, n = registration()
         hvps += n
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
@@ -148,16 +168,36 @@ def main():
         log(f"  GN {i}: E {s['energy']:.5f} MSE_rel {s['mse_rel']:.3f} |g|rel {s['grad_inf_rel']:.4f} "
             f"eps {s['step']} pcg {s['pcg_iters']}")
 
+    # the same registrations without the timing events
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hvps_u = 0
+    for _ in range(args.steps):
+        hvps_u += registration()[3]
+    torch.cuda.synchronize()
+    T_u = time.perf_counter() - t0
+
     # pure Hessian-vector product rate (same problem, last iterate)
-    L.gradient(prob, I0, I1, v, ws)
-    for _ in range(3):
-        L.hessvec(prob, d, ws, out=out)
+    hvp_only = None
+    if args.hvp_loop > 0:
+        L.gradient(prob, I0, I1, v, ws)
+        d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
+        out = torch.empty_like(d)
+        for _ in range(3):
+            L.hessvec(prob, d, ws, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.hvp_loop):
+            L.hessvec(prob, d, ws, out=out)
+        torch.cuda.synchronize()
+        hvp_only = args.hvp_loop / (time.perf_counter() - t1)
+
+    # plain copy of known size: the calibration for the FETCH_SIZE / WRITE_SIZE counters
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.hvp_loop):
-        L.hessvec(prob, d, ws, out=out)
-    torch.cuda.synchronize()
-    hvp_only = args.hvp_loop / (time.perf_counter() - t1)
+    del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -165,6 +205,7 @@ def main():
         cpu = cpu_baseline(w)
         log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
 
+    name = L.KERNEL_FAMILIES[dominant]
     res = {
         "metric": METRIC,
         "value": hvps / T,
@@ -187,9 +228,10 @@ def main():
         },
         "registrations_per_min": 60.0 * args.steps / T,
         "hvps_per_registration": hvps / args.steps,
+        "value_without_timer_events": hvps_u / T_u,
         "hvp_only_per_s": hvp_only,
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
-        "roofline": roofline(dominant, launches, kms, kfl, kby),
+        "roofline": roofline(dominant, name, launches, kms, kfl, kby, stored_traffic(name)),
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -164,26 +164,49 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
  * evaluated (host only). */
 int64_t lddmm_last_register_hvps(void);
 
-/* Launch timing of one kernel family, for roofline accounting.  While
- * enabled, every launch of family `family` (LDDMM_KF_*) made by this process
- * is bracketed by HIP events on its stream, and the algorithmic work of the
- * launch (flops of the separable contractions and Lie products, HBM bytes of
- * its inputs and outputs read or written once) is summed.
- * lddmm_kernel_timer_read synchronises those events and returns the number
- * of timed launches, their summed duration in milliseconds and the summed
- * algorithmic flops and bytes.  Enabling (or LDDMM_KF_NONE) resets the
- * counters.  Host only; not thread-safe against concurrent enabling. */
+/* Launch timing of one kernel, for roofline accounting.  While enabled,
+ * one launch in `every` (the first, then every `every`-th, counted over the
+ * launches of that kernel this process makes) of kernel family `family`
+ * (LDDMM_KF_*) is bracketed by HIP events on its stream, and the
+ * algorithmic work of those launches (flops of the partial DFT contractions,
+ * Lie products and interpolation; HBM bytes of their inputs and outputs, each
+ * read or written once) is summed.  lddmm_kernel_timer_read synchronises the
+ * events and returns the number of timed launches, their summed duration in
+ * milliseconds and their summed algorithmic flops and bytes.  Enabling (or
+ * LDDMM_KF_NONE) resets the counters.  `every` must be in [1, 1000] and
+ * `family` in [0, LDDMM_KF_SRC] (else LDDMM_E_INVALID_ARG).  With graphs on
+ * (lddmm_use_graphs), the sampled launches are fixed when a sequence is
+ * captured and carry event nodes in its graph.  Host only; not thread-safe
+ * against concurrent enabling. */
 enum {
   LDDMM_KF_NONE = 0,
-  LDDMM_KF_SYNTH = 1,   /* padded-grid synthesis of new fields (MFMA inverse stages 1-2) */
-  LDDMM_KF_GRID = 2,    /* grid velocity / incremental-state source (inverse stages 1-2 on the grid) */
-  LDDMM_KF_SL = 3,      /* semi-Lagrangian transport step */
-  LDDMM_KF_INV0 = 4,    /* inverse stage 0 at the start of a sweep and for the grid velocities */
-  LDDMM_KF_COLUMN = 5,  /* forward stages 1-0, band update, next inverse stage 0 */
-  LDDMM_KF_PRODS = 6    /* Lie products and forward stage 2 on the padded grid */
+  LDDMM_KF_SYNTH = 1,      /* k_synth: padded-grid synthesis of new fields (inverse stages 1-2, MFMA) */
+  LDDMM_KF_GRID = 2,       /* k_gridstep: grid velocity / incremental-state source (inverse stages 1-2) */
+  LDDMM_KF_SL = 3,         /* k_sl: semi-Lagrangian transport step */
+  LDDMM_KF_INV0 = 4,       /* k_inv0 (padded grid): inverse stage 0 at the start of a sweep */
+  LDDMM_KF_COLUMN = 5,     /* k_colstep: forward stages 1-0, band update, next inverse stage 0 */
+  LDDMM_KF_PRODS = 6,      /* k_prods: Lie products and forward stage 2 on the padded grid */
+  LDDMM_KF_INV0_GRID = 7,  /* k_inv0 (image grid): inverse stage 0 of a grid velocity */
+  LDDMM_KF_FWD1_GRID = 8,  /* k_fwd1: forward stage 1 of a grid field */
+  LDDMM_KF_FWD0_GRID = 9,  /* k_fwd0: forward stage 0 of a grid field and its band epilogue */
+  LDDMM_KF_SRC = 10        /* k_src_fwd2: image-matching source and forward stage 2 */
 };
-int lddmm_kernel_timer(int32_t family);
+int lddmm_kernel_timer(int32_t family, int32_t every);
 int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, double* bytes);
+
+/* Graph replay of the launch-bound sequences (default off).  With graphs on,
+ * lddmm_hessvec and the per-iteration sequences of lddmm_register (the
+ * gradient at the head of a Gauss-Newton iteration, one CG iteration, one
+ * line-search trial) are captured into a HIP graph on a library-owned stream
+ * the first time they run for a given device, workspace, problem, external
+ * input pointers and timed kernel family, and replayed on the caller's
+ * stream afterwards; the kernels and their order are the same as without.
+ * The captured graphs hold workspace addresses: a workspace that is freed
+ * and reallocated at the same address with the same problem reuses them,
+ * which is correct because all of its buffers are recomputed.  Graphs live
+ * until the process ends.  `enable` must be 0 or 1 (else
+ * LDDMM_E_INVALID_ARG).  Process-wide; host only. */
+int lddmm_use_graphs(int32_t enable);
 
 /* Static description of a status code. */
 const char* lddmm_status_string(int code);

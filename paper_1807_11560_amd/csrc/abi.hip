@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -109,16 +110,73 @@ int check_ws(const Dims& d, const void* ws, size_t ws_bytes) {
 }
 
 // ---------------------------------------------------------------- timer
+using EventPair = std::pair<hipEvent_t, hipEvent_t>;
 struct Timer {
   std::mutex mu;
   int family = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  int every = 1;        // time one launch of the family in `every`
+  int64_t seen = 0;     // launches of the family enqueued or captured
+  bool take = false;    // whether the current launch is sampled
+  bool error = false;
+  std::vector<EventPair> pending;
+  std::vector<EventPair> pool;
   int64_t launches = 0;
   double ms = 0.0;
   double flops = 0.0, bytes = 0.0;
 };
 Timer g_timer;
+
+// ---------------------------------------------------------------- graphs
+// Launch-bound sequences (one CG iteration, the gradient at the head of a
+// Gauss-Newton iteration, one line-search trial, one Hessian-vector
+// product) are captured once per device, workspace, problem, external
+// pointers and timed kernel family into a HIP graph on a library stream,
+// and replayed on the caller's stream.  While a family is timed, its
+// launches are bracketed by external event nodes inside the graph; the
+// durations of a replay are collected before the next replay of the same
+// graph and by lddmm_kernel_timer_read.  The event nodes are added to the
+// captured graph around each kernel node of the family (event records made
+// during capture would only order streams).
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int family = 0;
+  std::vector<hipGraphNode_t> knodes;  // kernel nodes of the timed family (during capture)
+  std::vector<EventPair> pairs;
+  double flops = 0.0, bytes = 0.0;
+  bool unharvested = false;
+};
+bool g_use_graphs = false;
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;  // entries live until the process ends
+std::map<int, hipStream_t> g_cap_streams;
+thread_local GraphEntry* t_capturing = nullptr;
+
+bool take_pair(EventPair* ev) {
+  if (!g_timer.pool.empty()) {
+    *ev = g_timer.pool.back();
+    g_timer.pool.pop_back();
+    return true;
+  }
+  if (hipEventCreate(&ev->first) != hipSuccess) return false;
+  if (hipEventCreate(&ev->second) != hipSuccess) return false;
+  return true;
+}
+
+// Adds the durations of the last replay of a timed graph (waits for it).
+// Call with g_timer.mu held.
+void harvest(GraphEntry& g) {
+  if (!g.unharvested) return;
+  g.unharvested = false;
+  for (auto& ev : g.pairs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(ev.second) != hipSuccess || hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess) {
+      g_timer.error = true;
+      return;
+    }
+    g_timer.ms += ms;
+    g_timer.launches += 1;
+  }
+}
 
 }  // namespace
 
@@ -126,35 +184,167 @@ namespace lddmm {
 void timer_work(int family, double flops, double bytes) {
   if (g_timer.family == 0 || family != g_timer.family) return;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  g_timer.flops += flops;
-  g_timer.bytes += bytes;
+  g_timer.take = g_timer.seen++ % g_timer.every == 0;
+  if (!g_timer.take) return;
+  double& f = t_capturing ? t_capturing->flops : g_timer.flops;
+  double& b = t_capturing ? t_capturing->bytes : g_timer.bytes;
+  f += flops;
+  b += bytes;
 }
-void timer_begin(int family, hipStream_t st) {
-  if (g_timer.family == 0 || family != g_timer.family) return;
+bool timer_events(int family, hipEvent_t* start, hipEvent_t* stop) {
+  if (g_timer.family == 0 || family != g_timer.family || t_capturing) return false;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  if (!g_timer.pool.empty()) {
-    ev = g_timer.pool.back();
-    g_timer.pool.pop_back();
-  } else {
-    if (hipEventCreate(&ev.first) != hipSuccess) return;
-    if (hipEventCreate(&ev.second) != hipSuccess) return;
+  if (!g_timer.take) return false;
+  EventPair ev;
+  if (!take_pair(&ev)) {
+    g_timer.error = true;
+    return false;
   }
-  if (hipEventRecord(ev.first, st) != hipSuccess) return;
   g_timer.pending.push_back(ev);
+  *start = ev.first;
+  *stop = ev.second;
+  return true;
 }
-void timer_end(int family, hipStream_t st) {
-  if (g_timer.family == 0 || family != g_timer.family) return;
+void timer_captured(int family, hipStream_t st) {
+  if (g_timer.family == 0 || family != g_timer.family || !t_capturing) return;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  if (!g_timer.pending.empty()) (void)hipEventRecord(g_timer.pending.back().second, st);
+  if (!g_timer.take) return;
+  // the node the next captured operation would depend on: the kernel just launched
+  hipStreamCaptureStatus cs;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  if (hipStreamGetCaptureInfo_v2(st, &cs, nullptr, nullptr, &deps, &nd) != hipSuccess || nd != 1)
+    g_timer.error = true;
+  else
+    t_capturing->knodes.push_back(deps[0]);
 }
 }  // namespace lddmm
 
 namespace {
 
+std::string graph_key(const Engine& e, const void* ws, int kind, std::initializer_list<const void*> ext) {
+  const Dims& d = e.dims();
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  // a timed graph samples the launches the timer picked while it was captured
+  const int fam = g_timer.family ? g_timer.family + 256 * g_timer.every : 0;
+  std::string k;
+  auto put = [&k](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  put(&dev, sizeof dev);
+  put(&ws, sizeof ws);
+  put(&kind, sizeof kind);
+  put(&fam, sizeof fam);
+  put(d.N, sizeof d.N);
+  put(d.K, sizeof d.K);
+  put(d.M, sizeof d.M);
+  put(&d.nt, sizeof d.nt);
+  put(&d.s, sizeof d.s);
+  put(&d.alpha, sizeof d.alpha);
+  put(&d.sigma, sizeof d.sigma);
+  put(&d.hessian, sizeof d.hessian);
+  for (const void* p : ext) put(&p, sizeof p);
+  return k;
+}
+
+hipError_t capture_stream(hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  hipStream_t& s = g_cap_streams[dev];
+  if (!s && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+  *out = s;
+  return hipSuccess;
+}
+
+// Brackets each recorded kernel node of a captured graph by two event
+// record nodes: its dependencies -> start -> kernel -> stop -> its dependents.
+hipError_t add_timing_nodes(hipGraph_t graph, GraphEntry& ne) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  hipError_t e;
+  for (hipGraphNode_t K : ne.knodes) {
+    EventPair ev;
+    if (!take_pair(&ev)) return hipErrorOutOfMemory;
+    ne.pairs.push_back(ev);
+    size_t nd = 0, nn = 0;
+    if ((e = hipGraphNodeGetDependencies(K, nullptr, &nd)) != hipSuccess) return e;
+    if ((e = hipGraphNodeGetDependentNodes(K, nullptr, &nn)) != hipSuccess) return e;
+    std::vector<hipGraphNode_t> deps(nd), dn(nn);
+    if (nd && (e = hipGraphNodeGetDependencies(K, deps.data(), &nd)) != hipSuccess) return e;
+    if (nn && (e = hipGraphNodeGetDependentNodes(K, dn.data(), &nn)) != hipSuccess) return e;
+    hipGraphNode_t e1, e2;
+    if ((e = hipGraphAddEventRecordNode(&e1, graph, deps.data(), nd, ev.first)) != hipSuccess) return e;
+    if ((e = hipGraphAddDependencies(graph, &e1, &K, 1)) != hipSuccess) return e;
+    if ((e = hipGraphAddEventRecordNode(&e2, graph, &K, 1, ev.second)) != hipSuccess) return e;
+    for (hipGraphNode_t d : dn) {
+      if ((e = hipGraphRemoveDependencies(graph, &K, &d, 1)) != hipSuccess) return e;
+      if ((e = hipGraphAddDependencies(graph, &e2, &d, 1)) != hipSuccess) return e;
+    }
+  }
+  ne.knodes.clear();
+  return hipSuccess;
+}
+
+// Runs `body` (which enqueues on e.stream() and may fork onto the engine's
+// auxiliary stream, joining back before it returns) through the graph of
+// `key`, capturing it on first use; with graphs disabled, runs it directly.
+hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipError_t()>& body) {
+  if (!g_use_graphs) return body();
+  GraphEntry* g = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) g = &it->second;
+  }
+  const hipStream_t st = e.stream();
+  hipError_t err;
+  if (!g) {
+    hipStream_t cap = nullptr;
+    if ((err = capture_stream(&cap)) != hipSuccess) return err;
+    if ((err = e.aux_init(e.dims().nt + 2)) != hipSuccess) return err;
+    GraphEntry ne;
+    ne.family = g_timer.family;
+    e.set_stream(cap);
+    t_capturing = &ne;
+    err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      const hipError_t eb = body();
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(cap, &graph);
+      err = eb != hipSuccess ? eb : ee;
+      if (err == hipSuccess && !ne.knodes.empty()) err = add_timing_nodes(graph, ne);
+      if (err == hipSuccess) err = hipGraphInstantiateWithFlags(&ne.exec, graph, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    t_capturing = nullptr;
+    e.set_stream(st);
+    if (err != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_timer.mu);
+      for (auto& ev : ne.pairs) g_timer.pool.push_back(ev);
+      return err;
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g = &(g_graphs[key] = std::move(ne));
+  }
+  if (!g->pairs.empty()) {
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    harvest(*g);
+  }
+  if ((err = hipGraphLaunch(g->exec, st)) != hipSuccess) return err;
+  if (g->family != 0 && g->family == g_timer.family) {
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.flops += g->flops;
+    g_timer.bytes += g->bytes;
+    if (!g->pairs.empty()) g->unharvested = true;
+  }
+  return hipSuccess;
+}
+
+enum GraphKind { GK_HESSVEC = 1, GK_GN_HEAD = 2, GK_PCG_ITER = 3, GK_TRIAL = 16 };
+
 // ------------------------------------------------------ register loop
-int run_register(Engine& e, const float* I0, const float* I1, void* v0_inout, int gn_iters,
-                 int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
+int run_register(Engine& e, const void* ws, const float* I0, const float* I1, void* v0_inout,
+                 int gn_iters, int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
   const Dims& d = e.dims();
   hipStream_t st = e.stream();
   const int n = 3 * d.nb;
@@ -176,11 +366,15 @@ int run_register(Engine& e, const float* I0, const float* I1, void* v0_inout, in
   double g0_inf = -1.0;
   int status = LDDMM_OK;
   for (int it = 0; it < gn_iters; ++it) {
-    HTRY(launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n, st));
-    HTRY(e.forward(I0));
-    HTRY(e.energy(e.m[d.nt], I1));
-    HTRY(e.backward(I1, e.gh));
-    HTRY(launch_band_maxabs(e.gh, d, e.partial, e.scal + 3, st));
+    // energy and gradient at v0 (and max |g|)
+    HTRY(run_graph(e, graph_key(e, ws, GK_GN_HEAD, {I0, I1}), [&]() -> hipError_t {
+      hipError_t r;
+      const hipStream_t s = e.stream();
+      if ((r = launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n, s)))
+        return r;
+      if ((r = e.forward(I0)) || (r = e.energy(e.m[d.nt], I1)) || (r = e.backward(I1, e.gh))) return r;
+      return launch_band_maxabs(e.gh, d, e.partial, e.scal + 3, s);
+    }));
     double sc[4];
     HTRY(hipMemcpyAsync(sc, e.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HTRY(hipStreamSynchronize(st));
@@ -192,15 +386,21 @@ int run_register(Engine& e, const float* I0, const float* I1, void* v0_inout, in
     HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
     HTRY(launch_pcg_reset(e.pcg, st));
     int used = 0;
+    const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {});
     for (int k = 0; k < pcg_iters; ++k) {
-      HTRY(e.hessvec(e.dh, e.Hdh));
+      // H d, then the CG updates (decisions taken on the device)
+      HTRY(run_graph(e, iter_key, [&]() -> hipError_t {
+        hipError_t r;
+        const hipStream_t s = e.stream();
+        if ((r = e.hessvec(e.dh, e.Hdh))) return r;
+        if ((r = launch_band_dot(e.dh, e.Hdh, e.Lsym, d, e.partial, e.pcg + SC_DHD, 1.0, s))) return r;
+        if ((r = launch_pcg_phase_a(e.pcg, s))) return r;
+        if ((r = launch_pcg_update_pr(e.pcg, e.dh, e.Hdh, e.ph, e.rh, n, s))) return r;
+        if ((r = launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, s))) return r;
+        if ((r = launch_pcg_phase_b(e.pcg, s))) return r;
+        return launch_pcg_update_d(e.pcg, e.rh, e.dh, n, s);
+      }));
       ++*hvps;
-      HTRY(launch_band_dot(e.dh, e.Hdh, e.Lsym, d, e.partial, e.pcg + SC_DHD, 1.0, st));
-      HTRY(launch_pcg_phase_a(e.pcg, k, st));
-      HTRY(launch_pcg_update_pr(e.pcg, e.dh, e.Hdh, e.ph, e.rh, n, st));
-      HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, st));
-      HTRY(launch_pcg_phase_b(e.pcg, st));
-      HTRY(launch_pcg_update_d(e.pcg, e.rh, e.dh, n, st));
       double stopped = 0.0;
       HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
       HTRY(hipStreamSynchronize(st));
@@ -227,11 +427,17 @@ int run_register(Engine& e, const float* I0, const float* I1, void* v0_inout, in
     int trials = 0;
     for (int t = 0; t < max_trials; ++t) {
       ++trials;
-      HTRY(launch_axpy_band(e.v0h, e.ph, (float)eps, e.vtry, n, st));
-      HTRY(launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.V[0]), 2LL * n, st));
-      const float* mnt = nullptr;
-      HTRY(e.forward_light(I0, &mnt));
-      HTRY(e.energy(mnt, I1));
+      // E(v0 + eps p)
+      HTRY(run_graph(e, graph_key(e, ws, GK_TRIAL + t, {I0, I1}), [&]() -> hipError_t {
+        hipError_t r;
+        const hipStream_t s = e.stream();
+        const float* mnt = nullptr;
+        if ((r = launch_axpy_band(e.v0h, e.ph, (float)eps, e.vtry, n, s))) return r;
+        if ((r = launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.V[0]), 2LL * n, s)))
+          return r;
+        if ((r = e.forward_light(I0, &mnt))) return r;
+        return e.energy(mnt, I1);
+      }));
       HTRY(hipMemcpyAsync(&Etry, e.scal, sizeof(double), hipMemcpyDeviceToHost, st));
       HTRY(hipStreamSynchronize(st));
       if (std::isfinite(Etry) && Etry <= sc[0] + c1 * eps * slope) {
@@ -339,7 +545,9 @@ int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, s
   Engine e(d, ws, static_cast<hipStream_t>(stream));
   hipError_t err;
   if ((err = e.load_band(dv0, e.dV[0])) != hipSuccess) return hip_fail(err, "load dv0");
-  if ((err = e.hessvec(e.dV[0], e.Hdh)) != hipSuccess) return hip_fail(err, "hessvec");
+  if ((err = run_graph(e, graph_key(e, ws, GK_HESSVEC, {}), [&] { return e.hessvec(e.dV[0], e.Hdh); })) !=
+      hipSuccess)
+    return hip_fail(err, "hessvec");
   if ((err = e.store_band(e.Hdh, nullptr, 0.f, Hdv)) != hipSuccess) return hip_fail(err, "store");
   g_last_error.clear();
   return LDDMM_OK;
@@ -360,18 +568,26 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
   hipError_t err = launch_fill(reinterpret_cast<float*>(e.tmph), 6LL * d.nb, 0.f, e.stream());
   if (err != hipSuccess) return hip_fail(err, "fill");
   g_last_hvps = 0;
-  rc = run_register(e, I0, I1, v0_inout, gn_iters, pcg_iters, stats, stats_len, &g_last_hvps);
+  rc = run_register(e, ws, I0, I1, v0_inout, gn_iters, pcg_iters, stats, stats_len, &g_last_hvps);
   if (rc >= 0) g_last_error.clear();
   return rc;
 }
 
 int64_t lddmm_last_register_hvps(void) { return g_last_hvps; }
 
-int lddmm_kernel_timer(int32_t family) {
+int lddmm_kernel_timer(int32_t family, int32_t every) {
+  if (family < LDDMM_KF_NONE || family > KF_LAST) return fail(LDDMM_E_INVALID_ARG, "unknown kernel family");
+  if (every < 1 || every > 1000) return fail(LDDMM_E_INVALID_ARG, "every must be in [1, 1000]");
+  std::lock_guard<std::mutex> lg(g_graph_mu);
   std::lock_guard<std::mutex> lk(g_timer.mu);
   for (auto& ev : g_timer.pending) g_timer.pool.push_back(ev);
   g_timer.pending.clear();
+  for (auto& kv : g_graphs) kv.second.unharvested = false;
+  g_timer.error = false;
   g_timer.family = family;
+  g_timer.every = every;
+  g_timer.seen = 0;
+  g_timer.take = false;
   g_timer.launches = 0;
   g_timer.ms = 0.0;
   g_timer.flops = 0.0;
@@ -380,7 +596,9 @@ int lddmm_kernel_timer(int32_t family) {
 }
 
 int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, double* bytes) {
+  std::lock_guard<std::mutex> lg(g_graph_mu);
   std::lock_guard<std::mutex> lk(g_timer.mu);
+  for (auto& kv : g_graphs) harvest(kv.second);
   for (auto& ev : g_timer.pending) {
     if (hipEventSynchronize(ev.second) != hipSuccess) return fail(LDDMM_E_HIP, "event sync");
     float ms = 0.f;
@@ -391,10 +609,17 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, 
     g_timer.pool.push_back(ev);
   }
   g_timer.pending.clear();
+  if (g_timer.error) return fail(LDDMM_E_HIP, "a timing event could not be created, recorded or read");
   if (launches) *launches = g_timer.launches;
   if (total_ms) *total_ms = g_timer.ms;
   if (flops) *flops = g_timer.flops;
   if (bytes) *bytes = g_timer.bytes;
+  return LDDMM_OK;
+}
+
+int lddmm_use_graphs(int32_t enable) {
+  if (enable != 0 && enable != 1) return fail(LDDMM_E_INVALID_ARG, "enable must be 0 or 1");
+  g_use_graphs = enable != 0;
   return LDDMM_OK;
 }
 

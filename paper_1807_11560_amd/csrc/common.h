@@ -167,19 +167,27 @@ size_t src_shared_bytes(const Dims& d);
 hipError_t launch_pcg_reset(double* sc, hipStream_t st);
 hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dvec, int n,
                            hipStream_t st);
-hipError_t launch_pcg_phase_a(double* sc, int it, hipStream_t st);
+hipError_t launch_pcg_phase_a(double* sc, hipStream_t st);
 hipError_t launch_pcg_update_pr(const double* sc, const float2* dvec, const float2* Hd, float2* p,
                                 float2* r, int n, hipStream_t st);
 hipError_t launch_pcg_phase_b(double* sc, hipStream_t st);
 hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dvec, int n,
                                hipStream_t st);
 
-// Kernel-family timing (see lddmm_kernel_timer).
+// Kernel-family timing (see lddmm_kernel_timer); one family per kernel.
+enum KernelFamily {
+  KF_SYNTH = 1, KF_GRID = 2, KF_SL = 3, KF_INV0 = 4, KF_COLUMN = 5, KF_PRODS = 6, KF_INV0_GRID = 7,
+  KF_FWD1_GRID = 8, KF_FWD0_GRID = 9, KF_SRC = 10, KF_LAST = 10
+};
 // timer_work records the algorithmic flops and HBM bytes of the launch that
-// follows (counted only while its family is being timed).
+// follows and decides whether that launch is sampled; timer_events hands out
+// the start/stop events a sampled launch carries (false when the launch is
+// not sampled or a graph is being captured); timer_captured, after the
+// launch, hands the kernel node of a sampled launch in a capture to the
+// timer.  Each timed launch calls the three in this order.
 void timer_work(int family, double flops, double bytes);
-void timer_begin(int family, hipStream_t st);
-void timer_end(int family, hipStream_t st);
+bool timer_events(int family, hipEvent_t* start, hipEvent_t* stop);
+void timer_captured(int family, hipStream_t st);
 
 // Scalar slots of the CG state.
 enum PcgSlot {

@@ -3,6 +3,7 @@
 // Hessian-vector product and the Gauss-Newton-Krylov loop.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "common.h"
@@ -33,9 +34,11 @@ class Engine {
   hipError_t load_band(const void* full, float2* half);
   hipError_t store_band(const float2* a, const float2* b, float cb, void* full);
 
+  // Called after the band step that produces v_n has been enqueued.
+  using StepHook = std::function<hipError_t(int)>;
   // Band shooting from V[0] (fills V[1..nt]; caches the padded-grid fields
-  // when `cache`).
-  hipError_t shoot_band(bool cache);
+  // when `cache`); `hook(n)` after the step that makes V[n].
+  hipError_t shoot_band(bool cache, const StepHook& hook = StepHook());
   // Shooting with caches, grid velocities vg[n] and states m[0..nt].
   hipError_t forward(const float* I0);
   // Shooting and transport without caches; *m_out = m_nt.
@@ -51,6 +54,8 @@ class Engine {
   // Second stream of this thread and device for the grid chain, and events.
   hipError_t aux_init(int nevents);
   hipStream_t stream() const { return st_; }
+  // Redirects all further work (used while capturing a graph).
+  void set_stream(hipStream_t s) { st_ = s; }
 
   // buffers
   std::vector<float2*> V, U, W, dV;
@@ -78,6 +83,7 @@ class Engine {
   hipError_t record(hipStream_t s, int ev);
   hipError_t wait(hipStream_t s, int ev);
   hipError_t grid_velocity(const float2* band, float* out, hipStream_t s);
+  hipError_t grid_source(const float2* dv, const float* mn, const float* dmn, hipStream_t s);
 
   Dims d_;
   hipStream_t st_;

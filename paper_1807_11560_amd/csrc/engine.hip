@@ -256,7 +256,29 @@ hipError_t Engine::grid_velocity(const float2* band, float* out, hipStream_t s) 
   return launch_gridstep(a, d_, twN_, s);
 }
 
-hipError_t Engine::shoot_band(bool cache) {
+// Incremental transport source q = dm_n - dt grad_h m_n . dv_n of one step
+// (stage 0 of dv_n, then the grid step) on stream s.
+hipError_t Engine::grid_source(const float2* dv, const float* mn, const float* dmn, hipStream_t s) {
+  const int C = d_.K[1] * d_.Kh;
+  const size_t t1 = (size_t)d_.N[0] * C;
+  Inv0Jobs jobs{};
+  for (int c = 0; c < 3; ++c) {
+    jobs.j[c].in = dv + (size_t)c * d_.nb;
+    jobs.j[c].out = T1N_ + (size_t)c * t1;
+    jobs.j[c].lflag = 0;
+  }
+  TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, s));
+  GridStepArgs a{};
+  a.t1 = T1N_;
+  a.op = 1;
+  a.m = mn;
+  a.dm = dmn;
+  a.q = q;
+  a.dt = 1.0f / d_.nt;
+  return launch_gridstep(a, d_, twN_, s);
+}
+
+hipError_t Engine::shoot_band(bool cache, const StepHook& hook) {
   const float dt = 1.0f / d_.nt;
   TRY(inv0_groups(V[0], 0, V[0], 1));
   for (int n = 0; n < d_.nt; ++n) {
@@ -270,25 +292,29 @@ hipError_t Engine::shoot_band(bool cache) {
                         next ? 1 : -1, 1);
     TRY(colstep(jobs, 3));
     if (ev_) TRY(record(st_, n + 1));
+    if (hook) TRY(hook(n + 1));
   }
   return hipSuccess;
 }
 
 // Shooting on the caller's stream; the grid chain (velocity of step n, then
-// the transport step) on the auxiliary stream as soon as v_n exists.
+// the transport step) on the auxiliary stream.  Each grid step is enqueued
+// right after the band step that produces v_n, so that the host issues both
+// streams' work in the order the device can run it.
 hipError_t Engine::forward(const float* I0) {
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   TRY(aux_init(nt + 2));
   TRY(record(st_, 0));
-  TRY(shoot_band(true));
-  TRY(wait(aux_, 0));
-  TRY(launch_copy(I0, m[0], d_.nN, aux_));
-  for (int n = 0; n < nt; ++n) {
-    if (n > 0) TRY(wait(aux_, n));
+  auto grid_step = [&](int n) -> hipError_t {
+    if (n >= nt) return hipSuccess;
+    TRY(wait(aux_, n));
+    if (n == 0) TRY(launch_copy(I0, m[0], d_.nN, aux_));
     TRY(grid_velocity(V[n], vg[n], aux_));
-    TRY(launch_sl(m[n], vg[n], m[n + 1], dt, d_, aux_));
-  }
+    return launch_sl(m[n], vg[n], m[n + 1], dt, d_, aux_);
+  };
+  TRY(grid_step(0));
+  TRY(shoot_band(true, grid_step));
   TRY(record(aux_, nt + 1));
   return wait(st_, nt + 1);
 }
@@ -299,16 +325,18 @@ hipError_t Engine::forward_light(const float* I0, const float** m_out) {
   const int nt = d_.nt;
   TRY(aux_init(nt + 2));
   TRY(record(st_, 0));
-  TRY(shoot_band(false));
-  TRY(wait(aux_, 0));
   const float* cur = I0;
-  for (int n = 0; n < nt; ++n) {
-    if (n > 0) TRY(wait(aux_, n));
+  auto grid_step = [&](int n) -> hipError_t {
+    if (n >= nt) return hipSuccess;
+    TRY(wait(aux_, n));
     TRY(grid_velocity(V[n], vg[0], aux_));
     float* dst = mlight[n & 1];
     TRY(launch_sl(cur, vg[0], dst, dt, d_, aux_));
     cur = dst;
-  }
+    return hipSuccess;
+  };
+  TRY(grid_step(0));
+  TRY(shoot_band(false, grid_step));
   TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
   *m_out = cur;
@@ -366,6 +394,32 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
                                     6LL * d_.nb, st_));
   TRY(record(st_, 0));
+  // Incremental state transport on the auxiliary stream: step n waits for
+  // dv_n (event n) and is enqueued as soon as the band step that makes dv_n
+  // has been, so the two streams overlap.
+  const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
+  const float* dmcur = nullptr;
+  auto grid_step = [&](int n) -> hipError_t {
+    TRY(wait(aux_, n));
+    TRY(grid_source(dV[n], m[n], dmcur, aux_));
+    float* dst = dm[n & 1];
+    TRY(launch_sl(q, vg[n], dst, dt, d_, aux_));
+    dmcur = dst;
+    if (n + 1 < nt) return hipSuccess;
+    // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt
+    TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, aux_));
+    Fwd0Job fj[3];
+    for (int c = 0; c < 3; ++c) {
+      fj[c] = Fwd0Job{};
+      fj[c].a = s2n(c);
+      fj[c].ca = 1.f;
+      fj[c].syma = 1;
+      fj[c].out = dU[0] + (size_t)c * d_.nb;
+    }
+    TRY(fwd_grid(fj, 3, aux_));
+    return record(aux_, nt + 1);
+  };
+  TRY(grid_step(0));
   // incremental EPDiff forward (caller's stream); event n+1 marks dv_{n+1}
   TRY(inv0_groups(dV[0], 0, dV[0], 1));
   for (int n = 0; n < nt; ++n) {
@@ -381,48 +435,10 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
         jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1);
       TRY(colstep(jobs, 3));
       TRY(record(st_, n + 1));
+      TRY(grid_step(n + 1));
     }
   }
-  // incremental state transport on the auxiliary stream, step n once dv_n exists
-  {
-    const int C = d_.K[1] * d_.Kh;
-    const float* dmcur = nullptr;
-    for (int n = 0; n < nt; ++n) {
-      TRY(wait(aux_, n));
-      Inv0Jobs jobs{};
-      for (int c = 0; c < 3; ++c) {
-        jobs.j[c].in = dV[n] + (size_t)c * d_.nb;
-        jobs.j[c].out = T1N_ + (size_t)c * d_.N[0] * C;
-        jobs.j[c].lflag = 0;
-      }
-      TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, aux_));
-      GridStepArgs a{};
-      a.t1 = T1N_;
-      a.op = 1;
-      a.m = m[n];
-      a.dm = dmcur;
-      a.q = q;
-      a.dt = dt;
-      TRY(launch_gridstep(a, d_, twN_, aux_));
-      float* dst = dm[n & 1];
-      TRY(launch_sl(q, vg[n], dst, dt, d_, aux_));
-      dmcur = dst;
-    }
-    // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt
-    const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
-    TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, aux_));
-    Fwd0Job fj[3];
-    for (int c = 0; c < 3; ++c) {
-      fj[c] = Fwd0Job{};
-      fj[c].a = s2n(c);
-      fj[c].ca = 1.f;
-      fj[c].syma = 1;
-      fj[c].out = dU[0] + (size_t)c * d_.nb;
-    }
-    TRY(fwd_grid(fj, 3, aux_));
-    TRY(record(aux_, nt + 1));
-    TRY(wait(st_, nt + 1));
-  }
+  TRY(wait(st_, nt + 1));
   // incremental adjoint Jacobi sweep backward
   TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
   TRY(inv0_groups(dU[0], 1, dW[0], 0));

@@ -9,6 +9,8 @@
 // tables of the axis they act on.
 #include "common.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #include <algorithm>
@@ -1247,8 +1249,9 @@ __global__ void k_pcg_init(const float2* g, float2* p, float2* r, float2* dv, in
   dv[i] = v;
 }
 
-// After <d, H d>_V: decide whether this iteration updates.
-__global__ void k_pcg_phase_a(double* sc, int it) {
+// After <d, H d>_V: decide whether this iteration updates.  The first
+// iteration is the one before any update (SC_ITERS == 0 and not stopped).
+__global__ void k_pcg_phase_a(double* sc) {
   if (threadIdx.x != 0) return;
   sc[SC_DOUPD] = 0.0;
   sc[SC_NEGG] = 0.0;
@@ -1257,7 +1260,7 @@ __global__ void k_pcg_phase_a(double* sc, int it) {
   if (!(sc[SC_DHD] > 0.0)) {
     sc[SC_STOPPED] = 1.0;
     sc[SC_GUARD] = 1.0;
-    if (it == 0) sc[SC_NEGG] = 1.0;
+    if (sc[SC_ITERS] == 0.0) sc[SC_NEGG] = 1.0;
     return;
   }
   sc[SC_ALPHA] = sc[SC_RR] / sc[SC_DHD];
@@ -1294,6 +1297,20 @@ __global__ void k_pcg_update_d(const double* sc, const float2* r, float2* dv, in
 }
 
 // ================================================= launch wrappers
+// Launch of a kernel the timer may sample: a sampled launch carries the
+// timer's start and stop events in its dispatch (they then hold the kernel's
+// own begin and end times); while a graph is being captured, the kernel node
+// is handed to the timer instead.
+#define LAUNCH_TIMED(fam, kernel, grid, block, shm, st, ...)                              \
+  do {                                                                                     \
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                             \
+    if (timer_events((fam), &ev0_, &ev1_))                                                 \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ev0_, ev1_, 0, __VA_ARGS__);    \
+    else                                                                                   \
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                       \
+    timer_captured((fam), st);                                                             \
+  } while (0)
+
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 static bool band_iso(const Dims& d, int K, int M) {
@@ -1353,22 +1370,22 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
       fl += 8.0 * nvar * G0 * K0 * (double)C;
       by += 8.0 * K0 * (double)C * (1 + nvar * (double)G0 / K0) + (jobs.j[i].lflag ? 4.0 * K0 * C : 0.0);
     }
-    timer_work(4, fl, by);
+    timer_work(trans ? KF_INV0 : KF_INV0_GRID, fl, by);
   }
   auto go = [&](auto nv_tag, auto xt_tag, auto kc_tag) {
     constexpr int NV = decltype(nv_tag)::value, XT = decltype(xt_tag)::value, KC = decltype(kc_tag)::value;
     dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
     size_t shm = NV * XT * K0 * sizeof(float2);
     if (trans)
-      hipLaunchKernelGGL((k_inv0<NV, XT, true, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
+      LAUNCH_TIMED(KF_INV0, (k_inv0<NV, XT, true, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
     else
-      hipLaunchKernelGGL((k_inv0<NV, XT, false, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
+      LAUNCH_TIMED(KF_INV0_GRID, (k_inv0<NV, XT, false, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0,
+                   Kh);
   };
   using I2 = std::integral_constant<int, 2>;
   using I1 = std::integral_constant<int, 1>;
   using X8 = std::integral_constant<int, 8>;
   using X16 = std::integral_constant<int, 16>;
-  timer_begin(4, st);
   if (nvar == 2) {
     if (K0 == 32) go(I2{}, X8{}, std::integral_constant<int, 32>{});
     else if (K0 == 16) go(I2{}, X8{}, std::integral_constant<int, 16>{});
@@ -1378,7 +1395,6 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
     else if (K0 == 16) go(I1{}, X16{}, std::integral_constant<int, 16>{});
     else go(I1{}, X16{}, std::integral_constant<int, 0>{});
   }
-  timer_end(4, st);
   return hipGetLastError();
 }
 
@@ -1426,16 +1442,14 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
   a.w1a = tables;
   a.w2b = tables + 2 * (size_t)M1p * 2 * d.K[1];
   const double nM = (double)d.nM;
-  timer_work(1, 6.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0),
+  timer_work(KF_SYNTH, 6.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0),
              6.0 * (2.0 * d.M[0] * d.K[1] * d.Kh * 8.0 + 4.0 * nM * 4.0));
   (void)Khp;
   (void)M2p;
-  timer_begin(1, st);
   hipError_t e = with_band(d, [&](auto sh) {
-    hipLaunchKernelGGL((k_synth<decltype(sh)>), dim3(d.M[0], 6), dim3(256), synth_shared_bytes(d), st, a, sh);
+    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], 6), dim3(256), synth_shared_bytes(d), st, a, sh);
     return hipGetLastError();
   });
-  timer_end(1, st);
   return e;
 }
 
@@ -1460,16 +1474,14 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
     const double nM = (double)d.nM;
     double fl = prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
     double by = prog_groups[a.prog] * 12.0 * nM * 4.0 + a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
-    timer_work(6, fl, by);
+    timer_work(KF_PRODS, fl, by);
   }
   int threads = ((R * d.M[2] + 63) / 64) * 64;
   if (threads > 256) threads = 256;
-  timer_begin(6, st);
   hipError_t e = with_band(d, [&](auto sh) {
-    hipLaunchKernelGGL((k_prods<decltype(sh)>), grid, dim3(threads), shm, st, a, tw, sh);
+    LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh)>), grid, dim3(threads), shm, st, a, tw, sh);
     return hipGetLastError();
   });
-  timer_end(6, st);
   return e;
 }
 
@@ -1513,35 +1525,33 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
       by += terms * M0 * M1 * Kh * 8.0 + K0 * K1 * Kh * 8.0 * (2 + (j.base != nullptr) + (j.extra != nullptr)) +
             j.nt1 * 2.0 * M0 * K1 * Kh * 8.0;
     }
-    timer_work(5, fl, by);
+    timer_work(KF_COLUMN, fl, by);
   }
   const float invG = (float)(1.0 / ((double)d.M[0] * d.M[1] * d.M[2]));
   const int M = d.M[0], K = d.K[0];
   const float2* w1t = coltab;
   const float2* w0f = w1t + (size_t)M * round_up(K, 16);
   const float2* w0i = w0f + (size_t)round_up(K, 16) * M;
-  timer_begin(5, st);
   hipError_t e;
   if (band_iso(d, 32, 48)) {
-    hipLaunchKernelGGL((k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else if (band_iso(d, 16, 24)) {
-    hipLaunchKernelGGL((k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else if (band_iso(d, 24, 36)) {
-    hipLaunchKernelGGL((k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else {
     dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
     size_t shm = colstep_shared_bytes(d);
     BandDyn sh{d.K[0], d.K[1], d.Kh, d.M[0], d.M[1], d.M[2]};
-    hipLaunchKernelGGL((k_colstep<kColGroup, BandDyn>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh, invG);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep<kColGroup, BandDyn>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh, invG);
     e = hipGetLastError();
   }
-  timer_end(5, st);
   return e;
 }
 
@@ -1551,11 +1561,9 @@ hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0
   const int T = 128;
   dim3 grid(nblk((long long)G0 * Kh, T), nblk(K1, QT), njobs);
   size_t shm = QT * G1 * sizeof(float2);
-  timer_work(5, njobs * 8.0 * G0 * Kh * (double)K1 * G1,
+  timer_work(KF_FWD1_GRID, njobs * 8.0 * G0 * Kh * (double)K1 * G1,
              njobs * 8.0 * ((double)G0 * G1 * Kh + (double)G0 * K1 * Kh));
-  timer_begin(5, st);
-  hipLaunchKernelGGL((k_fwd1<QT>), grid, dim3(T), shm, st, jobs, tw, G0, G1, K1, Kh);
-  timer_end(5, st);
+  LAUNCH_TIMED(KF_FWD1_GRID, (k_fwd1<QT>), grid, dim3(T), shm, st, jobs, tw, G0, G1, K1, Kh);
   return hipGetLastError();
 }
 
@@ -1574,11 +1582,9 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
       fl += terms * 8.0 * K0 * C * G0;
       by += terms * 8.0 * G0 * C + 8.0 * K0 * C * (1 + (j.base != nullptr) + (j.extra != nullptr)) + 4.0 * K0 * C;
     }
-    timer_work(5, fl, by);
+    timer_work(KF_FWD0_GRID, fl, by);
   }
-  timer_begin(5, st);
-  hipLaunchKernelGGL((k_fwd0<QT>), grid, dim3(T), shm, st, jobs, tw, Ksym, G0, K0, K1, Kh, invG);
-  timer_end(5, st);
+  LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0<QT>), grid, dim3(T), shm, st, jobs, tw, Ksym, G0, K0, K1, Kh, invG);
   return hipGetLastError();
 }
 
@@ -1601,42 +1607,38 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
     const double nN = (double)d.nN;
     double fl = 3.0 * d.N[0] * d.N[1] * d.Kh * d.K[1] * 8.0 + 3.0 * nN * d.Kh * 4.0 + (a.op ? 15.0 * nN : 0.0);
     double by = 3.0 * d.N[0] * (double)C * 8.0 + (a.op ? (a.dm ? 12.0 : 8.0) * nN : 12.0 * nN);
-    timer_work(2, fl, by);
+    timer_work(KF_GRID, fl, by);
   }
-  timer_begin(2, st);
   hipError_t e;
   if (grid_iso(d, 128, 32)) {
-    hipLaunchKernelGGL((k_gridstep_mfma<GridIso<128, 32>>), grid, dim3(256), 0, st, a, tw);
+    LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>>), grid, dim3(256), 0, st, a, tw);
     e = hipGetLastError();
   } else if (grid_iso(d, 64, 16)) {
-    hipLaunchKernelGGL((k_gridstep_mfma<GridIso<64, 16>>), grid, dim3(256), 0, st, a, tw);
+    LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>>), grid, dim3(256), 0, st, a, tw);
     e = hipGetLastError();
   } else {
     const int jn = (d.N[2] + 15) / 16;
     GridDyn gs{d.N[0], d.N[1], d.N[2], d.K[1], d.Kh};
     if (jn <= 2)
-      hipLaunchKernelGGL((k_gridstep<2, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
+      LAUNCH_TIMED(KF_GRID, (k_gridstep<2, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else if (jn <= 4)
-      hipLaunchKernelGGL((k_gridstep<4, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
+      LAUNCH_TIMED(KF_GRID, (k_gridstep<4, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else if (jn <= 8)
-      hipLaunchKernelGGL((k_gridstep<8, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
+      LAUNCH_TIMED(KF_GRID, (k_gridstep<8, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     else
-      hipLaunchKernelGGL((k_gridstep<16, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
+      LAUNCH_TIMED(KF_GRID, (k_gridstep<16, GridDyn>), grid, dim3(256), shm, st, a, tw, gs);
     e = hipGetLastError();
   }
-  timer_end(2, st);
   return e;
 }
 
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st) {
-  timer_work(3, 40.0 * (double)d.nN, 20.0 * (double)d.nN);
-  timer_begin(3, st);
+  timer_work(KF_SL, 40.0 * (double)d.nN, 20.0 * (double)d.nN);
   hipError_t e = with_grid(d, [&](auto gs) {
-    hipLaunchKernelGGL((k_sl<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, gs);
+    LAUNCH_TIMED(KF_SL, (k_sl<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, gs);
     return hipGetLastError();
   });
-  timer_end(3, st);
   return e;
 }
 
@@ -1644,10 +1646,16 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float
                            const Dims& d, const Twiddles& tw, hipStream_t st) {
   dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
   size_t shm = src_shared_bytes(d);
-  return with_grid(d, [&](auto gs) {
-    hipLaunchKernelGGL((k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, m, coef, s1, tw, gs);
+  {
+    // gradient of m (6 flops / point / axis), the source, forward stage 2 of 3 fields
+    const double nN = (double)d.nN;
+    timer_work(KF_SRC, 3.0 * nN * d.Kh * 4.0 + 25.0 * nN, (b ? 12.0 : 8.0) * nN + 3.0 * d.N[0] * (double)d.N[1] * d.Kh * 8.0);
+  }
+  hipError_t e = with_grid(d, [&](auto gs) {
+    LAUNCH_TIMED(KF_SRC, (k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, m, coef, s1, tw, gs);
     return hipGetLastError();
   });
+  return e;
 }
 
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st) {
@@ -1708,8 +1716,8 @@ hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dv, in
   hipLaunchKernelGGL(k_pcg_init, dim3(nblk(n, 256)), dim3(256), 0, st, g, p, r, dv, n);
   return hipGetLastError();
 }
-hipError_t launch_pcg_phase_a(double* sc, int it, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_phase_a, dim3(1), dim3(64), 0, st, sc, it);
+hipError_t launch_pcg_phase_a(double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_phase_a, dim3(1), dim3(64), 0, st, sc);
   return hipGetLastError();
 }
 hipError_t launch_pcg_update_pr(const double* sc, const float2* dv, const float2* Hd, float2* p,

@@ -14,6 +14,11 @@ from typing import List, Optional, Sequence, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblddmm.so")
 
+# torch is imported first so that the library's HIP calls bind to the HIP
+# runtime torch has loaded: device memory and streams come from torch, and a
+# second runtime in the same process would not see them.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first (python -m paper_1807_11560_amd.build)")
@@ -31,6 +36,10 @@ FP32 = 0
 GN_PAPER = 0
 GN_CLASSICAL = 1
 KF_SYNTH, KF_GRID, KF_SL, KF_INV0, KF_COLUMN, KF_PRODS = 1, 2, 3, 4, 5, 6
+KF_INV0_GRID, KF_FWD1_GRID, KF_FWD0_GRID, KF_SRC = 7, 8, 9, 10
+KERNEL_FAMILIES = {KF_SYNTH: "k_synth", KF_GRID: "k_gridstep", KF_SL: "k_sl", KF_INV0: "k_inv0 (padded grid)",
+                   KF_COLUMN: "k_colstep", KF_PRODS: "k_prods", KF_INV0_GRID: "k_inv0 (image grid)",
+                   KF_FWD1_GRID: "k_fwd1", KF_FWD0_GRID: "k_fwd0", KF_SRC: "k_src_fwd2"}
 
 
 class LddmmParams(ctypes.Structure):
@@ -74,11 +83,12 @@ _SIGS = {
                                       ctypes.POINTER(LddmmStats), ctypes.c_int32, _vp,
                                       ctypes.c_size_t, _vp]),
     "lddmm_last_register_hvps": (ctypes.c_int64, []),
-    "lddmm_kernel_timer": (ctypes.c_int, [ctypes.c_int32]),
+    "lddmm_kernel_timer": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "lddmm_kernel_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double)]),
+    "lddmm_use_graphs": (ctypes.c_int, [ctypes.c_int32]),
     "lddmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, []),
 }
@@ -245,8 +255,9 @@ def register(problem: Problem, I0, I1, ws: Workspace, gn_iters=10, pcg_iters=20,
     return v0, recs, rc, int(_lib.lddmm_last_register_hvps())
 
 
-def kernel_timer(family: int):
-    _check(_lib.lddmm_kernel_timer(int(family)), "lddmm_kernel_timer")
+def kernel_timer(family: int, every: int = 1):
+    """Time one launch in `every` of kernel family `family` (0 switches the timer off)."""
+    _check(_lib.lddmm_kernel_timer(int(family), int(every)), "lddmm_kernel_timer")
 
 
 def kernel_timer_read():
@@ -258,6 +269,11 @@ def kernel_timer_read():
     _check(_lib.lddmm_kernel_timer_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)),
            "lddmm_kernel_timer_read")
     return n.value, ms.value, fl.value, by.value
+
+
+def use_graphs(enable: bool):
+    """Graph replay of the launch-bound sequences on or off (default; lddmm_use_graphs)."""
+    _check(_lib.lddmm_use_graphs(1 if enable else 0), "lddmm_use_graphs")
 
 
 def raw():

@@ -94,3 +94,18 @@ def test_entry_points_validate_before_touching_the_device():
     assert lib.lddmm_register(ctypes.byref(p), fake, fake, fake, 1, 0, None, 0, fake, 1 << 40,
                               null) == L.E_INVALID_ARG
     assert b"grid" in lib.lddmm_status_string(L.E_SHAPE) or lib.lddmm_status_string(L.E_SHAPE)
+
+
+def test_switches_reject_bad_values():
+    """lddmm_use_graphs and lddmm_kernel_timer validate their argument on the host."""
+    lib = L.raw()
+    assert lib.lddmm_use_graphs(2) == L.E_INVALID_ARG
+    assert lib.lddmm_use_graphs(-1) == L.E_INVALID_ARG
+    assert lib.lddmm_kernel_timer(11, 1) == L.E_INVALID_ARG
+    assert lib.lddmm_kernel_timer(-1, 1) == L.E_INVALID_ARG
+    assert lib.lddmm_kernel_timer(5, 0) == L.E_INVALID_ARG
+    assert lib.lddmm_kernel_timer(5, 1001) == L.E_INVALID_ARG
+    assert lib.lddmm_use_graphs(1) == L.OK
+    assert lib.lddmm_use_graphs(0) == L.OK
+    assert lib.lddmm_kernel_timer(L.KF_SRC, 4) == L.OK
+    assert lib.lddmm_kernel_timer(0, 1) == L.OK

@@ -1,0 +1,123 @@
+"""Graph replay of the launch-bound sequences against direct launches.
+
+Every replay of a captured Hessian-vector product, with direct work and
+synchronisations of the program in between, must give the result of the
+same product launched directly (the kernels and their order are the same,
+and all reductions are deterministic, so the results are bitwise equal);
+a registration with graphs gives the registration without them; and the
+kernel-family timer counts the same launches with graphs as without."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Params  # noqa: E402
+from oracle.jacobi import forward  # noqa: E402
+from paper_1807_11560_amd import synth  # noqa: E402
+
+
+def L():
+    from paper_1807_11560_amd import lddmm
+    return lddmm
+
+
+@pytest.fixture(scope="module")
+def setup():
+    grid, band, nt = (40, 36, 32), (12, 16, 8), 5
+    w = synth.workload(2, grid=grid, band=band)
+    p = Params(grid=grid, band=band, nt=nt, alpha=synth.ALPHA, s=2, sigma=synth.SIGMA)
+    vstar = synth.scale_to_displacement(w["v_star"], grid, 2.0)
+    I1 = forward(vstar, w["I0"], p)[2][-1]
+    prob = L().Problem(grid=grid, band=band, time_steps=nt, alpha=synth.ALPHA, s=2, sigma=synth.SIGMA)
+    I0 = torch.from_numpy(w["I0"]).float().cuda()
+    I1 = torch.from_numpy(I1).float().cuda()
+    v0 = torch.from_numpy(0.5 * vstar).to(torch.complex64).cuda()
+    dirs = [torch.from_numpy(synth.random_direction(40 + i, band)).to(torch.complex64).cuda() for i in range(3)]
+    yield prob, I0, I1, v0, dirs
+    L().use_graphs(False)
+    L().kernel_timer(0)
+
+
+def test_hessvec_replays_match_direct_launches(setup):
+    prob, I0, I1, v0, dirs = setup
+    lib = L()
+    ws = lib.Workspace(prob)
+    lib.use_graphs(False)
+    lib.gradient(prob, I0, I1, v0, ws)
+    ref = [lib.hessvec(prob, d, ws).clone() for d in dirs]
+    torch.cuda.synchronize()
+    lib.use_graphs(True)
+    order = [0, 1, 2, 0, 2, 1, 1]
+    for r, i in enumerate(order):
+        print(f"replay {r}: direction {i}", flush=True)
+        h = lib.hessvec(prob, dirs[i], ws)
+        # direct work of the program between replays
+        lib.use_graphs(False)
+        g, _ = lib.gradient(prob, I0, I1, v0, ws)
+        lib.use_graphs(True)
+        torch.cuda.synchronize()
+        assert torch.equal(h, ref[i]), f"replay {r} differs from the direct launch"
+        assert torch.isfinite(g.real).all()
+
+
+def test_register_with_and_without_graphs(setup):
+    prob, I0, I1, v0, dirs = setup
+    lib = L()
+    ws = lib.Workspace(prob)
+    out = {}
+    for flag in (False, True, True):
+        lib.use_graphs(flag)
+        v, stats, rc, hvps = lib.register(prob, I0, I1, ws, gn_iters=3, pcg_iters=5)
+        torch.cuda.synchronize()
+        out.setdefault(flag, []).append((v.clone(), stats, rc, hvps))
+    v_ref, st_ref, rc_ref, n_ref = out[False][0]
+    for v, st, rc, n in out[True]:
+        assert rc == rc_ref and n == n_ref
+        assert torch.equal(v, v_ref)
+        assert [s["energy"] for s in st] == [s["energy"] for s in st_ref]
+
+
+def test_timer_counts_the_same_launches_with_graphs(setup):
+    prob, I0, I1, v0, dirs = setup
+    lib = L()
+    ws = lib.Workspace(prob)
+    lib.gradient(prob, I0, I1, v0, ws)
+    res = {}
+    for flag in (False, True):
+        lib.use_graphs(flag)
+        lib.hessvec(prob, dirs[0], ws)  # capture outside the timed calls
+        lib.kernel_timer(lib.KF_COLUMN, 1)
+        lib.hessvec(prob, dirs[0], ws)  # graphs: capture with timing nodes
+        for _ in range(3):
+            lib.hessvec(prob, dirs[0], ws)
+        torch.cuda.synchronize()
+        res[flag] = lib.kernel_timer_read()
+        lib.kernel_timer(0)
+    (n0, ms0, f0, b0), (n1, ms1, f1, b1) = res[False], res[True]
+    print(f"direct: {n0} launches {ms0:.3f} ms; graphs: {n1} launches {ms1:.3f} ms")
+    assert n0 == n1 and n0 > 0
+    assert f1 == pytest.approx(f0, rel=1e-12) and b1 == pytest.approx(b0, rel=1e-12)
+    assert 0.0 < ms1 < 3.0 * ms0 and 0.0 < ms0 < 3.0 * ms1
+
+
+def test_timer_samples_one_launch_in_every(setup):
+    prob, I0, I1, v0, dirs = setup
+    lib = L()
+    lib.use_graphs(False)
+    ws = lib.Workspace(prob)
+    lib.gradient(prob, I0, I1, v0, ws)
+    counts = {}
+    for every in (1, 4):
+        lib.kernel_timer(lib.KF_PRODS, every)
+        for _ in range(3):
+            lib.hessvec(prob, dirs[1], ws)
+        torch.cuda.synchronize()
+        counts[every] = lib.kernel_timer_read()
+    lib.kernel_timer(0)
+    n1, n4 = counts[1][0], counts[4][0]
+    assert n4 == (n1 + 3) // 4
+    # the sampled work is the work of the sampled launches
+    assert counts[4][2] == pytest.approx(counts[1][2] * n4 / n1, rel=0.2)
