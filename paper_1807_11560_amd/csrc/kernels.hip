@@ -1298,9 +1298,10 @@ __global__ void k_pcg_update_d(const double* sc, const float2* r, float2* dv, in
 
 // ================================================= launch wrappers
 // Launch of a kernel the timer may sample: a sampled launch carries the
-// timer's start and stop events in its dispatch (they then hold the kernel's
-// own begin and end times); while a graph is being captured, the kernel node
-// is handed to the timer instead.
+// timer's start and stop events in its dispatch (they then hold the times the
+// dispatch began and completed, which include the command processor's
+// per-dispatch work around the kernel); while a graph is being captured, the
+// kernel node is handed to the timer instead.
 #define LAUNCH_TIMED(fam, kernel, grid, block, shm, st, ...)                              \
   do {                                                                                     \
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                             \

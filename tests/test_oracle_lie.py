@@ -190,3 +190,22 @@ def test_ad_dagger_definition_consistency():
     lhs = inner(Ls * ad_dagger(a, b, Ls, M), c)
     rhs = inner(Ls * b, ad(a, c, M))
     assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+
+
+def test_ad_golden_sine_pair():
+    """Hand-derived coefficients of ad_a b for a = (sin 2 pi x1, 0),
+    b = (0, sin 2 pi x0) (tests/golden/ad_sine_pair_2d.txt), set up directly
+    in band coefficients (no transform on the input side)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ad_sine_pair_2d.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    band = (8, 8)
+    a = np.zeros((2,) + band, dtype=np.complex128)
+    b = np.zeros((2,) + band, dtype=np.complex128)
+    a[0, 0, 1], a[0, 0, -1] = -0.5j, 0.5j
+    b[1, 1, 0], b[1, -1, 0] = -0.5j, 0.5j
+    expect = np.zeros((2,) + band, dtype=np.complex128)
+    for c, k0, k1, re, im in rows:
+        expect[int(c), int(k0), int(k1)] = float(re) + 1j * float(im)
+    assert len(rows) == 8
+    np.testing.assert_allclose(ad(a, b, (12, 12)), expect, atol=1e-12)
