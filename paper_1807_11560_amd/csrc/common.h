@@ -41,7 +41,7 @@ struct Twiddles {
 // ---------------------------------------------------------------- jobs
 struct Inv0Job {
   const float2* in;   // band half spectrum of one component [K0][K1*Kh]
-  float2* out;        // [nvar][G0][K1*Kh]
+  float2* out;        // [nvar][G0][Kh][K1]
   int lflag;          // multiply the input by L~ on load
 };
 struct Inv0Jobs { Inv0Job j[kMaxJobs]; };
@@ -73,9 +73,10 @@ struct ProdArgs {
 
 // Band-side step of one output component (k_colstep): forward stages 1 and
 // 0 of one or two product fields s1 ([Kh][M0][M1] each), the update
-// out = base + ca*(K~ if syma)*F(a) + cb*(K~ if symb)*F(b) + ce*extra, and
-// the inverse stage 0 of out (of L~ out where t1l) into up to two stage-0
-// buffers [2 vars][M0][K1*Kh] for the next step.
+// out = base + ca*(K~ if syma)*F(a) + cb*(K~ if symb)*F(b) + ce*extra, the
+// inverse stage 0 of out (of L~ out where t1l) into up to two padded-grid
+// stage-0 buffers [2 vars][M0][Kh][K1] for the next step, and, if t1n is
+// set, the image-grid inverse stage 0 of out into t1n [N0][Kh][K1].
 struct ColJob {
   const float2* a;
   const float2* b;
@@ -83,12 +84,17 @@ struct ColJob {
   const float2* extra;
   float2* out;
   float2* t1[2];       // [2 vars][M0][Kh][K1]
+  float2* t1n;         // [N0][Kh][K1] or null
   float ca, cb, ce;
   int syma, symb;
   int t1l[2];
   int nt1;
 };
-struct ColJobs { ColJob j[8]; };
+struct ColJobs {
+  ColJob j[8];
+  const float2* w0n;   // image-grid stage-0 inverse twiddles [N0][K0] (for t1n)
+  int N0;
+};
 
 struct Fwd1Job { const float2* in; float2* out; };   // [G0][G1][Kh] -> [G0][K1][Kh]
 struct Fwd1Jobs { Fwd1Job j[kMaxJobs]; };
@@ -107,7 +113,7 @@ struct Fwd0Job {
 struct Fwd0Jobs { Fwd0Job j[kMaxJobs]; };
 
 struct GridStepArgs {
-  const float2* t1;   // [3][N0][K1*Kh]
+  const float2* t1;   // [3][N0][Kh][K1]
   int op;             // 0: write the velocity; 1: incremental-state source
   float* vout;        // op 0: [3][nN]
   const float* m;     // op 1: state m_n
@@ -125,8 +131,9 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
                                const Dims& d, hipStream_t st);
 // Inverse stage 0; `trans` writes the padded-grid layout [v][x0][kh][k1]
 // instead of [v][x0][k1][kh].
+// Output [nvar][G0][Kh][K1]; image_grid selects the timer family of the launch.
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
-                       int K0, int C, int G0, int Kh, bool trans, hipStream_t st);
+                       int K0, int C, int G0, int Kh, bool image_grid, hipStream_t st);
 hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st);
 size_t synth_table_floats(const Dims& d);
 size_t synth_shared_bytes(const Dims& d);
@@ -137,6 +144,8 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
 hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
                           const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st);
 size_t col_table_count(const Dims& d);
+// Whether the column kernel can form the image-grid stage 0 (t1n) for this shape.
+bool colstep_fuses_grid0(const Dims& d);
 hipError_t launch_col_tables(const Twiddles& tw, float2* tab, const Dims& d, hipStream_t st);
 size_t colstep_shared_bytes(const Dims& d);
 hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,

@@ -76,14 +76,17 @@ class Engine {
   hipError_t inv0_groups(const float2* in0, int l0, const float2* in1, int l1);
   hipError_t mstep(int prog, int nout, float* store0, float* store1, const float* const* cached);
   ColJob col_job(int c, int oa, float ca, int syma, int ob, float cb, int symb, const float2* base,
-                 const float2* extra, float ce, float2* out, int g0, int l0, int g1, int l1) const;
+                 const float2* extra, float ce, float2* out, int g0, int l0, int g1, int l1,
+                 float2* t1n = nullptr) const;
   hipError_t colstep(const ColJob* jobs, int n);
   hipError_t fwd_grid(Fwd0Job* jobs, int njobs, hipStream_t s);
 
   hipError_t record(hipStream_t s, int ev);
   hipError_t wait(hipStream_t s, int ev);
-  hipError_t grid_velocity(const float2* band, float* out, hipStream_t s);
-  hipError_t grid_source(const float2* dv, const float* mn, const float* dmn, hipStream_t s);
+  hipError_t grid_stage0(const float2* band, float2* t1n, hipStream_t s);
+  hipError_t grid_t1(int n, const float2* band, hipStream_t s);
+  hipError_t grid_velocity(int n, float* out, hipStream_t s);
+  hipError_t grid_source(int n, const float* dmn, hipStream_t s);
 
   Dims d_;
   hipStream_t st_;
@@ -91,7 +94,9 @@ class Engine {
   std::vector<hipEvent_t>* ev_ = nullptr;
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;
-  float2 *T1_ = nullptr, *S1_ = nullptr, *T1N_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
+  float2 *T1_ = nullptr, *S1_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
+  std::vector<float2*> T1N;     // image-grid stage-0 output of each time step [3][N0][Kh][K1]
+  bool fuse_grid0_ = false;     // the column kernel forms T1N[n + 1]
   float* NG_ = nullptr;         // scratch for new groups that are not cached
   float* synth_tab_ = nullptr;  // MFMA-form stage-1/2 twiddles of the padded grid
   float2* col_tab_ = nullptr;   // MFMA-form twiddles of the column step

@@ -41,9 +41,14 @@ hipError_t Engine::aux_init(int nevents) {
   TRY(hipGetDevice(&dev));
   AuxRes& r = t_aux[dev];
   if (!r.stream) TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
+  // The events only order the two streams of one device: a device-scope
+  // release suffices (runtimes without that flag get the default).
   while ((int)r.events.size() < nevents) {
     hipEvent_t e;
-    TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventReleaseToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     r.events.push_back(e);
   }
   aux_ = r.stream;
@@ -92,12 +97,13 @@ void Engine::layout(Carver& c) {
   synth_tab_ = c.take<float>(synth_table_floats(d));
   col_tab_ = c.take<float2>(col_table_count(d));
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
-  T1N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
+  T1N.resize(nt);
+  for (auto& p : T1N) p = c.take<float2>(3 * (size_t)d.N[0] * C);
   S1N_ = c.take<float2>(3 * (size_t)d.N[0] * d.N[1] * d.Kh);
   S2N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
 }
 
-Engine::Engine(const Dims& d, void* ws, hipStream_t st) : d_(d), st_(st) {
+Engine::Engine(const Dims& d, void* ws, hipStream_t st) : d_(d), st_(st), fuse_grid0_(colstep_fuses_grid0(d)) {
   Carver c{static_cast<char*>(ws)};
   layout(c);
   // twiddle table views
@@ -167,7 +173,7 @@ hipError_t Engine::inv0_groups(const float2* in0, int l0, const float2* in1, int
       jobs.j[nj].lflag = lf[g];
       ++nj;
     }
-  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], d_.Kh, true, st_);
+  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], d_.Kh, false, st_);
 }
 
 // Synthesis of the two new groups (into the cache when given, else into
@@ -193,8 +199,9 @@ hipError_t Engine::mstep(int prog, int nout, float* store0, float* store1, const
 // next-step stage 0 into group g0 (L flag l0) and optionally g1 (l1).
 ColJob Engine::col_job(int c, int oa, float ca, int syma, int ob, float cb, int symb,
                        const float2* base, const float2* extra, float ce, float2* out, int g0, int l0,
-                       int g1, int l1) const {
+                       int g1, int l1, float2* t1n) const {
   ColJob j{};
+  j.t1n = t1n ? t1n + (size_t)c * d_.N[0] * d_.K[1] * d_.Kh : nullptr;
   j.a = s1(oa);
   j.ca = ca;
   j.syma = syma;
@@ -216,6 +223,8 @@ ColJob Engine::col_job(int c, int oa, float ca, int syma, int ob, float cb, int 
 hipError_t Engine::colstep(const ColJob* jobs, int n) {
   ColJobs js{};
   for (int i = 0; i < n; ++i) js.j[i] = jobs[i];
+  js.w0n = twN_.inv0;  // value variant [N0][K0]
+  js.N0 = d_.N[0];
   return launch_colstep(js, n, d_, twM_, col_tab_, Lsym, Ksym, st_);
 }
 
@@ -238,40 +247,43 @@ hipError_t Engine::fwd_grid(Fwd0Job* jobs, int njobs, hipStream_t s) {
 
 const float2* Engine::s2n(int o) const { return S2N_ + (size_t)o * d_.N[0] * d_.K[1] * d_.Kh; }
 
-// One band field -> grid velocity (stage 0 then the grid step) on stream s.
-hipError_t Engine::grid_velocity(const float2* band, float* out, hipStream_t s) {
+// Image-grid inverse stage 0 of one band field into t1n [3][N0][Kh][K1].
+hipError_t Engine::grid_stage0(const float2* band, float2* t1n, hipStream_t s) {
   const int C = d_.K[1] * d_.Kh;
-  const size_t t1 = (size_t)d_.N[0] * C;
   Inv0Jobs jobs{};
   for (int c = 0; c < 3; ++c) {
     jobs.j[c].in = band + (size_t)c * d_.nb;
-    jobs.j[c].out = T1N_ + (size_t)c * t1;
+    jobs.j[c].out = t1n + (size_t)c * d_.N[0] * C;
     jobs.j[c].lflag = 0;
   }
-  TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, s));
+  return launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, true, s);
+}
+
+// Stage-0 buffer of the grid step of time step n: formed by the column
+// kernel of step n-1 (fused), or here (step 0, or shapes without fusion).
+hipError_t Engine::grid_t1(int n, const float2* band, hipStream_t s) {
+  if (n == 0 || !fuse_grid0_) return grid_stage0(band, T1N[n], s);
+  return hipSuccess;
+}
+
+// Grid velocity of time step n (band field V[n]) on stream s.
+hipError_t Engine::grid_velocity(int n, float* out, hipStream_t s) {
+  TRY(grid_t1(n, V[n], s));
   GridStepArgs a{};
-  a.t1 = T1N_;
+  a.t1 = T1N[n];
   a.op = 0;
   a.vout = out;
   return launch_gridstep(a, d_, twN_, s);
 }
 
-// Incremental transport source q = dm_n - dt grad_h m_n . dv_n of one step
-// (stage 0 of dv_n, then the grid step) on stream s.
-hipError_t Engine::grid_source(const float2* dv, const float* mn, const float* dmn, hipStream_t s) {
-  const int C = d_.K[1] * d_.Kh;
-  const size_t t1 = (size_t)d_.N[0] * C;
-  Inv0Jobs jobs{};
-  for (int c = 0; c < 3; ++c) {
-    jobs.j[c].in = dv + (size_t)c * d_.nb;
-    jobs.j[c].out = T1N_ + (size_t)c * t1;
-    jobs.j[c].lflag = 0;
-  }
-  TRY(launch_inv0(jobs, 3, 1, twN_.inv0, Lsym, d_.K[0], C, d_.N[0], d_.Kh, false, s));
+// Incremental transport source q = dm_n - dt grad_h m_n . dv_n of time step n
+// on stream s.
+hipError_t Engine::grid_source(int n, const float* dmn, hipStream_t s) {
+  TRY(grid_t1(n, dV[n], s));
   GridStepArgs a{};
-  a.t1 = T1N_;
+  a.t1 = T1N[n];
   a.op = 1;
-  a.m = mn;
+  a.m = m[n];
   a.dm = dmn;
   a.q = q;
   a.dt = 1.0f / d_.nt;
@@ -289,7 +301,7 @@ hipError_t Engine::shoot_band(bool cache, const StepHook& hook) {
     ColJob jobs[3];
     for (int c = 0; c < 3; ++c)
       jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, V[n], nullptr, 0.f, V[n + 1], next ? 0 : -1, 0,
-                        next ? 1 : -1, 1);
+                        next ? 1 : -1, 1, next && fuse_grid0_ ? T1N[n + 1] : nullptr);
     TRY(colstep(jobs, 3));
     if (ev_) TRY(record(st_, n + 1));
     if (hook) TRY(hook(n + 1));
@@ -310,7 +322,7 @@ hipError_t Engine::forward(const float* I0) {
     if (n >= nt) return hipSuccess;
     TRY(wait(aux_, n));
     if (n == 0) TRY(launch_copy(I0, m[0], d_.nN, aux_));
-    TRY(grid_velocity(V[n], vg[n], aux_));
+    TRY(grid_velocity(n, vg[n], aux_));
     return launch_sl(m[n], vg[n], m[n + 1], dt, d_, aux_);
   };
   TRY(grid_step(0));
@@ -329,7 +341,7 @@ hipError_t Engine::forward_light(const float* I0, const float** m_out) {
   auto grid_step = [&](int n) -> hipError_t {
     if (n >= nt) return hipSuccess;
     TRY(wait(aux_, n));
-    TRY(grid_velocity(V[n], vg[0], aux_));
+    TRY(grid_velocity(n, vg[0], aux_));
     float* dst = mlight[n & 1];
     TRY(launch_sl(cur, vg[0], dst, dt, d_, aux_));
     cur = dst;
@@ -401,7 +413,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   const float* dmcur = nullptr;
   auto grid_step = [&](int n) -> hipError_t {
     TRY(wait(aux_, n));
-    TRY(grid_source(dV[n], m[n], dmcur, aux_));
+    TRY(grid_source(n, dmcur, aux_));
     float* dst = dm[n & 1];
     TRY(launch_sl(q, vg[n], dst, dt, d_, aux_));
     dmcur = dst;
@@ -432,7 +444,8 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
     if (!last) {
       ColJob jobs[3];
       for (int c = 0; c < 3; ++c)
-        jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1);
+        jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1,
+                          fuse_grid0_ ? T1N[n + 1] : nullptr);
       TRY(colstep(jobs, 3));
       TRY(record(st_, n + 1));
       TRY(grid_step(n + 1));

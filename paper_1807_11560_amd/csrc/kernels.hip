@@ -47,6 +47,33 @@ __device__ __forceinline__ void batched_fill(int n, Load load, Store store) {
   }
 }
 
+// Two-phase copy for 256-thread blocks with every load of a thread in
+// flight at once: load() fills r[u] for element i = threadIdx.x + 256 u
+// (u < CAP, i < n), store() puts them.  The caller guarantees n <= 256 CAP.
+template <int CAP, class T>
+struct RegStage {
+  T r[CAP];
+  template <class Load>
+  __device__ __forceinline__ void load(int n, Load f) {
+#pragma unroll
+    for (int u = 0; u < CAP; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i < n) r[u] = f(i);
+    }
+  }
+  template <class Store>
+  __device__ __forceinline__ void store(int n, Store f) const {
+#pragma unroll
+    for (int u = 0; u < CAP; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i < n) f(i, r[u]);
+    }
+  }
+};
+
+__device__ __forceinline__ float4 ld4(const float2* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float2* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
 // ---------------------------------------------------------------- shapes
 // Sizes seen by a kernel: compile-time for the shapes this library is tuned
 // for (index arithmetic then folds into constants), runtime otherwise.
@@ -173,9 +200,9 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
 }
 
 // ------------------------------------------------- inverse stage 0 (k0)
-// out[v][x0][c] = sum_k0 tw[v][x0][k0] * in[k0][c] (optionally in * L~).
+// out[v][x0][kh][k1] = sum_k0 tw[v][x0][k0] * in[k0][k1][kh] (optionally in * L~).
 // KC > 0: compile-time K0 = KC (all loads of a column issued before use).
-template <int NV, int XT, bool TRANS, int KC>
+template <int NV, int XT, int KC>
 __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __restrict__ tw,
                                               const float* __restrict__ Lsym, int K0r, int C,
                                               int G0, int Kh) {
@@ -225,8 +252,7 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
     for (int t = 0; t < XT; ++t) {
       int x = xb + t;
       if (x < G0) {
-        // padded-grid stage-0 buffers are [v][x0][kh][k1]; grid ones [v][x0][k1][kh]
-        const int co = TRANS ? (c % Kh) * (C / Kh) + c / Kh : c;
+        const int co = (c % Kh) * (C / Kh) + c / Kh;  // column c = k1 * Kh + kh
         job.out[((size_t)v * G0 + x) * C + co] = acc[v][t];
       }
     }
@@ -283,6 +309,7 @@ struct SynthArgs {
   const float* w2b;     // [2][2Khp][M2p]   real block form of the stage-2 twiddles
 };
 
+constexpr int kSynthW2Pre = 16;
 template <class S>
 __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   extern __shared__ float sms[];
@@ -300,6 +327,19 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   float* t2s = bt1 + 2 * K2r * N1;           // [3][M1p][ldt2]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  // The stage-2 table w2b [2][N1][M2p] is loaded into registers now and put
+  // into the LDS of bt1 once GEMM1 has consumed it (when it fits; else GEMM2
+  // reads it from global memory).
+  const int nw2 = 2 * N1 * M2p;
+  const bool w2_lds = nw2 <= 256 * kSynthW2Pre && M2p <= K2r;
+  float w2pre[kSynthW2Pre];
+  if (w2_lds) {
+#pragma unroll
+    for (int u = 0; u < kSynthW2Pre; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      w2pre[u] = (i < nw2) ? a.w2b[i] : 0.f;
+    }
+  }
 
   batched_fill<float>(2 * M1p * K2r, [&](int i) { return a.w1a[i]; }, [&](int i, float v) {
     int vv = i / (M1p * K2r), row = (i / K2r) % M1p, k = i % K2r;
@@ -343,6 +383,16 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     for (int r = 0; r < 4; ++r) T[(size_t)r * ldt2] = acc[r];
   }
   __syncthreads();
+  const float* w2src = a.w2b;
+  if (w2_lds) {
+#pragma unroll
+    for (int u = 0; u < kSynthW2Pre; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i < nw2) bt1[i] = w2pre[u];
+    }
+    __syncthreads();
+    w2src = bt1;
+  }
   // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p)
   const int ti2 = M1p / 16, tj2 = M2p / 16;
   const long long nM = (long long)M0 * M1 * M2;
@@ -352,7 +402,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
     const int wv = (ov == 1);
     const float* A = t2s + ((size_t)srcv * M1p + ti * 16 + li) * ldt2 + lk;
-    const float* B = a.w2b + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
+    const float* B = w2src + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < N1 / 4; k0 += 8) {
       float av[8], bv[8];
@@ -578,8 +628,21 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
     float l = (k1 < K1) ? Lsym[((size_t)k0 * K1 + k1) * Kh + kh] : 0.f;
     bnd[K0 * KG + i] = make_float2(l * res.x, l * res.y);
   }
-  if (job.nt1 == 0) return;
+  if (job.nt1 == 0 && !job.t1n) return;
   __syncthreads();
+  if (job.t1n) {
+    // image-grid stage 0 of out: t1n[x0][kh][k1] = sum_k0 w0n[x0][k0] out[k0][k1]
+    const int N0 = jobs.N0;
+    for (int i = threadIdx.x; i < N0 * KG; i += blockDim.x) {
+      const int x0 = i / KG, kk = i % KG, k1 = kb + kk;
+      if (k1 >= K1) continue;
+      const float2* w = jobs.w0n + (size_t)x0 * K0;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int k0 = 0; k0 < K0; ++k0) cmac(acc, w[k0], bnd[(size_t)k0 * KG + kk]);
+      job.t1n[((size_t)x0 * Kh + kh) * K1 + k1] = acc;
+    }
+  }
+  if (job.nt1 == 0) return;
   batched_fill<float2>(2 * M0 * K0, [&](int i) { return tw.inv0[i]; }, [&](int i, float2 v) { w0s[i] = v; });
   __syncthreads();
   // next inverse stage 0: t1[v][x0][k1][kh] = sum_k0 w0[v][x0][k0] b[k0]
@@ -655,69 +718,111 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
   }
 }
 
-// One block per (kh, job), four waves; same contract as k_colstep.
+// One block per (kh, job, 16-wide tile of k1), four waves; same contract as
+// k_colstep: every phase after the stage-1 input is separable along k1.  All
+// global loads of the block (the stage-1 input, the twiddle tables, the
+// image-grid stage-0 table and the band values of the update) are issued at
+// the start, two complex values per load; the image-grid table waits in
+// registers until the LDS of the stage-1 input is free.
+constexpr int kGrid0Pre = 16;  // image-grid stage-0 table: complex values per thread
 template <class S>
-__global__ void __launch_bounds__(256) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
                                                       const float2* __restrict__ w0f,
                                                       const float2* __restrict__ w0i,
                                                       const float* __restrict__ Lsym,
                                                       const float* __restrict__ Ksym, float invG) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
-  constexpr int LS1 = M + 2, LS2 = Kp + 2, LOB = Kp + 2;
+  constexpr int LS1 = M + 2, LS2 = 18, LOB = 18;
   constexpr int C = K * Kh;
-  constexpr int LW1 = Kp + 2, LW0F = M + 2, LW0I = K + 2;
+  constexpr int LW1 = 18, LW0F = M + 2, LW0I = K + 2, LG = K + 2;
+  static_assert(M % 2 == 0 && K % 2 == 0, "pairs of complex values per load");
   __shared__ float2 s1[2][Mp][LS1];
   __shared__ float2 s2[2][M][LS2];
   __shared__ float2 ob[2][K][LOB];
-  __shared__ float2 w1s[M][LW1];        // w1t
+  __shared__ float2 w1s[M][LW1];        // w1t columns of this k1 tile
   __shared__ float2 w0fs[Kp][LW0F];     // w0f
   __shared__ float2 w0is[2][Mp][LW0I];  // w0i
+  float2* g0s = &s1[0][0][0];           // [N0][LG] image-grid stage-0 table, after stage 1'
   const ColJob& job = jobs.j[blockIdx.y];
   const int kh = blockIdx.x;
+  const int kc = blockIdx.z * 16;       // first k1 of the tile
   const int nterm = job.b ? 2 : 1;
+  const bool grid0 = job.t1n != nullptr;
+  const int N0 = jobs.N0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  constexpr int T0 = Kp / 16;
+  const int k1 = kc + li;
 
-  {  // S1 slices of the terms at this kh -> s1 (rows beyond M zero)
-    const float2* sa = job.a + (size_t)kh * M * M;
-    const float2* sb = job.b ? job.b + (size_t)kh * M * M : sa;
-    batched_fill<float2>(nterm * Mp * M, [&](int i) {
-      const int t = i / (Mp * M), x0 = (i / M) % Mp, x1 = i % M;
-      return (x0 < M) ? (t ? sb : sa)[x0 * M + x1] : make_float2(0.f, 0.f);
-    }, [&](int i, float2 v) {
-      const int t = i / (Mp * M), x0 = (i / M) % Mp, x1 = i % M;
-      s1[t][x0][x1] = v;
-    });
+  // ---- loads
+  constexpr int H = M / 2, KH2 = K / 2;
+  const int ns1 = nterm * Mp * H;
+  const float2* sa = job.a + (size_t)kh * M * M;
+  const float2* sb = job.b ? job.b + (size_t)kh * M * M : sa;
+  RegStage<(2 * Mp * H + 255) / 256, float4> rs1;
+  RegStage<(M * 8 + 255) / 256, float4> rw1;
+  RegStage<(Kp * H + 255) / 256, float4> rw0f;
+  RegStage<(2 * Mp * KH2 + 255) / 256, float4> rw0i;
+  RegStage<kGrid0Pre / 2, float4> rg;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  rs1.load(ns1, [&](int i) {
+    const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
+    return (x0 < M) ? ld4((t ? sb : sa) + x0 * M + x1) : z4;
+  });
+  rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
+  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
+  rw0i.load(2 * Mp * KH2, [&](int i) { return ld4(w0i + 2 * i); });
+  const int ng = grid0 ? N0 * KH2 : 0;
+  rg.load(ng, [&](int i) { return ld4(jobs.w0n + 2 * i); });
+  // band values of the update at (k0 = 16 wave + 4 lk + r, k1)
+  float2 pbase[4], pextra[4];
+  float pks[4], pls[4];
+  if (wave < T0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = wave * 16 + 4 * lk + r;
+      const bool ok = k0 < K && k1 < K;
+      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
+      pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
+      pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
+      pks[r] = ok ? Ksym[idx] : 0.f;
+      pls[r] = ok ? Lsym[idx] : 0.f;
+    }
   }
-  batched_fill<float2>(M * Kp, [&](int i) { return w1t[i]; }, [&](int i, float2 v) { w1s[i / Kp][i % Kp] = v; });
-  batched_fill<float2>(Kp * M, [&](int i) { return w0f[i]; }, [&](int i, float2 v) { w0fs[i / M][i % M] = v; });
-  batched_fill<float2>(2 * Mp * K, [&](int i) { return w0i[i]; },
-                       [&](int i, float2 v) { w0is[i / (Mp * K)][(i / K) % Mp][i % K] = v; });
+  // ---- stores
+  rs1.store(ns1, [&](int i, float4 v) {
+    const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
+    st4(&s1[t][x0][x1], v);
+  });
+  rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
+  rw0f.store(Kp * H, [&](int i, float4 v) { st4(&w0fs[i / H][2 * (i % H)], v); });
+  rw0i.store(2 * Mp * KH2, [&](int i, float4 v) {
+    st4(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
+  });
   __syncthreads();
-  // stage 1': s2[t][x0][k1] = sum_x1 s1[t][x0][x1] w1t[x1][k1]
-  constexpr int T1R = Mp / 16, T1C = Kp / 16;
-  for (int jb = wave; jb < nterm * T1R * T1C; jb += 4) {
-    const int t = jb / (T1R * T1C), ti = (jb / T1C) % T1R, tj = jb % T1C;
+  // stage 1': s2[t][x0][j] = sum_x1 s1[t][x0][x1] w1t[x1][kc + j]
+  constexpr int T1R = Mp / 16;
+  for (int jb = wave; jb < nterm * T1R; jb += 4) {
+    const int t = jb / T1R, ti = jb % T1R;
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<M / 4>(&s1[t][ti * 16][0], LS1, &w1s[0][tj * 16], LW1, acc);
+    ctile<M / 4>(&s1[t][ti * 16][0], LS1, &w1s[0][0], LW1, acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int x0 = ti * 16 + 4 * lk + r;
-      if (x0 < M) s2[t][x0][tj * 16 + li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+      if (x0 < M) s2[t][x0][li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
     }
   }
   __syncthreads();
-  // stage 0' and the band update
-  constexpr int T0 = Kp / 16;
-  for (int jb = wave; jb < T0 * T0; jb += 4) {
-    const int ti = jb / T0, tj = jb % T0;
+  rg.store(ng, [&](int i, float4 v) { st4(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
+  // stage 0' and the band update (one k0 tile per wave)
+  if (wave < T0) {
+    const int ti = wave;
     floatx4 aa[4], bb[4];
     zero_acc(aa, 4);
     zero_acc(bb, 4);
-    ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][tj * 16], LS2, aa);
-    if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][tj * 16], LS2, bb);
-    const int k1 = tj * 16 + li;
+    ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, aa);
+    if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][0], LS2, bb);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k0 = ti * 16 + 4 * lk + r;
@@ -725,41 +830,48 @@ __global__ void __launch_bounds__(256) k_colstep_mfma(ColJobs jobs, const float2
       const size_t idx = ((size_t)k0 * K + k1) * Kh + kh;
       float2 res = make_float2(0.f, 0.f);
       if (k0 != K / 2 && k1 != K / 2) {
-        if (job.base) res = job.base[idx];
-        const float ks = Ksym[idx];
-        const float sa = job.ca * invG * (job.syma ? ks : 1.f);
-        res.x = fmaf(sa, aa[0][r] - aa[1][r], res.x);
-        res.y = fmaf(sa, aa[2][r] + aa[3][r], res.y);
+        res = pbase[r];
+        const float sa_ = job.ca * invG * (job.syma ? pks[r] : 1.f);
+        res.x = fmaf(sa_, aa[0][r] - aa[1][r], res.x);
+        res.y = fmaf(sa_, aa[2][r] + aa[3][r], res.y);
         if (nterm == 2) {
-          const float sb = job.cb * invG * (job.symb ? ks : 1.f);
-          res.x = fmaf(sb, bb[0][r] - bb[1][r], res.x);
-          res.y = fmaf(sb, bb[2][r] + bb[3][r], res.y);
+          const float sb_ = job.cb * invG * (job.symb ? pks[r] : 1.f);
+          res.x = fmaf(sb_, bb[0][r] - bb[1][r], res.x);
+          res.y = fmaf(sb_, bb[2][r] + bb[3][r], res.y);
         }
-        if (job.extra) {
-          const float2 e = job.extra[idx];
-          res.x = fmaf(job.ce, e.x, res.x);
-          res.y = fmaf(job.ce, e.y, res.y);
-        }
+        res.x = fmaf(job.ce, pextra[r].x, res.x);
+        res.y = fmaf(job.ce, pextra[r].y, res.y);
       }
       job.out[idx] = res;
-      ob[0][k0][k1] = res;
-      const float l = Lsym[idx];
-      ob[1][k0][k1] = make_float2(l * res.x, l * res.y);
+      ob[0][k0][li] = res;
+      ob[1][k0][li] = make_float2(pls[r] * res.x, pls[r] * res.y);
     }
   }
-  if (job.nt1 == 0) return;
+  if (job.nt1 == 0 && !grid0) return;
   __syncthreads();
-  // next inverse stage 0: t1[v][x0][kh][k1] = sum_k0 w0i[v][x0][k0] ob[L][k0][k1]
-  constexpr int TIR = Mp / 16, TIC = Kp / 16;
-  const int njb = job.nt1 * 2 * TIR * TIC;
-  for (int jb = wave; jb < njb; jb += 4) {
-    const int u = jb / (2 * TIR * TIC), v = (jb / (TIR * TIC)) % 2, ti = (jb / TIC) % TIR, tj = jb % TIC;
-    const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
-    float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
+  // next inverse stage 0 on the padded grid: t1[v][x0][kh][k1] = sum_k0 w0i[v][x0][k0] ob[L][k0][k1],
+  // then on the image grid: t1n[x0][kh][k1] = sum_k0 w0n[x0][k0] ob[0][k0][k1]
+  constexpr int TIR = Mp / 16;
+  const int njb = job.nt1 * 2 * TIR;
+  const int ngb = grid0 ? N0 / 16 : 0;
+  for (int jb = wave; jb < njb + ngb; jb += 4) {
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][tj * 16], LOB, acc);
-    const int k1 = tj * 16 + li;
+    if (jb >= njb) {
+      const int ti = jb - njb;
+      ctile<K / 4>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
+      if (k1 >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x0 = ti * 16 + 4 * lk + r;
+        job.t1n[((size_t)x0 * Kh + kh) * K + k1] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+      }
+      continue;
+    }
+    const int u = jb / (2 * TIR), v = (jb / TIR) % 2, ti = jb % TIR;
+    const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
+    float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
+    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
     if (k1 >= K) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -895,10 +1007,12 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, G
   float2* t2s = t1s + 3 * C;         // [3][R][Kh]
   float2* w1s = t2s + 3 * R * Kh;    // [R][K1]
   float2* w2t = w1s + R * K1;        // [Kh][N2]
-  batched_fill<float2>(3 * C, [&](int i) {
-    int c = i / C, e = i % C;
-    return a.t1[((size_t)c * N0 + x0) * C + e];
-  }, [&](int i, float2 v) { t1s[i] = v; });
+  batched_fill<float2>(3 * C, [&](int i) {  // global [c][x0][kh][k1] -> t1s[c][k1][kh]
+    return a.t1[((size_t)(i / C) * N0 + x0) * C + i % C];
+  }, [&](int i, float2 v) {
+    const int c = i / C, kh = (i % C) / K1, k1 = i % K1;
+    t1s[(size_t)c * C + k1 * Kh + kh] = v;
+  });
   batched_fill<float2>(R * K1, [&](int i) {
     int r = i / K1, k = i % K1;
     int x1 = x1b + r;
@@ -981,10 +1095,10 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  batched_fill<float2>(3 * K1 * Khp, [&](int i) {
-    const int c = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
-    return (kh < Kh) ? a.t1[((size_t)c * N0 + x0) * C + k1 * Kh + kh] : make_float2(0.f, 0.f);
-  }, [&](int i, float2 v) { t1s[i / (K1 * Khp)][(i / Khp) % K1][i % Khp] = v; });
+  batched_fill<float2>(3 * Khp * K1, [&](int i) {
+    const int c = i / (Khp * K1), kh = (i / K1) % Khp, k1 = i % K1;
+    return (kh < Kh) ? a.t1[(((size_t)c * N0 + x0) * Kh + kh) * K1 + k1] : make_float2(0.f, 0.f);
+  }, [&](int i, float2 v) { t1s[i / (Khp * K1)][i % K1][(i / K1) % Khp] = v; });
   batched_fill<float2>(R * K1, [&](int i) {
     const int x1 = x1b + i / K1;
     return (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + i % K1] : make_float2(0.f, 0.f);
@@ -1363,7 +1477,8 @@ hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float
 }
 
 hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* tw, const float* Lsym,
-                       int K0, int C, int G0, int Kh, bool trans, hipStream_t st) {
+                       int K0, int C, int G0, int Kh, bool image_grid, hipStream_t st) {
+  const int fam = image_grid ? KF_INV0_GRID : KF_INV0;
   const int T = 128;
   {
     double fl = 0, by = 0;
@@ -1371,17 +1486,13 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
       fl += 8.0 * nvar * G0 * K0 * (double)C;
       by += 8.0 * K0 * (double)C * (1 + nvar * (double)G0 / K0) + (jobs.j[i].lflag ? 4.0 * K0 * C : 0.0);
     }
-    timer_work(trans ? KF_INV0 : KF_INV0_GRID, fl, by);
+    timer_work(fam, fl, by);
   }
   auto go = [&](auto nv_tag, auto xt_tag, auto kc_tag) {
     constexpr int NV = decltype(nv_tag)::value, XT = decltype(xt_tag)::value, KC = decltype(kc_tag)::value;
     dim3 grid(nblk(C, T), nblk(G0, XT), njobs);
     size_t shm = NV * XT * K0 * sizeof(float2);
-    if (trans)
-      LAUNCH_TIMED(KF_INV0, (k_inv0<NV, XT, true, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
-    else
-      LAUNCH_TIMED(KF_INV0_GRID, (k_inv0<NV, XT, false, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0,
-                   Kh);
+    LAUNCH_TIMED(fam, (k_inv0<NV, XT, KC>), grid, dim3(T), shm, st, jobs, tw, Lsym, K0, C, G0, Kh);
   };
   using I2 = std::integral_constant<int, 2>;
   using I1 = std::integral_constant<int, 1>;
@@ -1514,17 +1625,36 @@ hipError_t launch_col_tables(const Twiddles& tw, float2* tab, const Dims& d, hip
   return hipGetLastError();
 }
 
+static bool colstep_mfma_shape(const Dims& d) {
+  return band_iso(d, 32, 48) || band_iso(d, 16, 24) || band_iso(d, 24, 36);
+}
+
+bool colstep_fuses_grid0(const Dims& d) {
+  if (!colstep_mfma_shape(d)) return true;  // the generic kernel reads the table from global memory
+  const int K = d.K[0], M = d.M[0], Mp = round_up(M, 16);
+  return d.N[0] % 16 == 0 && d.N[0] * K <= 256 * kGrid0Pre && d.N[0] * (K + 2) <= 2 * Mp * (M + 2);
+}
+
 hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const Twiddles& tw,
                           const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st) {
+  for (int i = 0; i < njobs; ++i) {
+    if (jobs.j[i].t1n && (!colstep_fuses_grid0(d) || jobs.N0 != d.N[0] || !jobs.w0n)) return hipErrorInvalidValue;
+    // the tuned kernel loads pairs of complex values
+    if (colstep_mfma_shape(d) && (((uintptr_t)jobs.j[i].a | (uintptr_t)jobs.j[i].b | (uintptr_t)coltab |
+                                   (uintptr_t)jobs.w0n) & 15))
+      return hipErrorInvalidValue;
+  }
   {
     const double M0 = d.M[0], M1 = d.M[1], K0 = d.K[0], K1 = d.K[1], Kh = d.Kh;
     double fl = 0, by = 0;
     for (int i = 0; i < njobs; ++i) {
       const ColJob& j = jobs.j[i];
       int terms = 1 + (j.b != nullptr);
-      fl += terms * (M0 * M1 * K1 + K0 * K1 * M0) * Kh * 8.0 + j.nt1 * 2.0 * M0 * K0 * K1 * Kh * 8.0;
+      const double N0 = j.t1n ? d.N[0] : 0.0;
+      fl += terms * (M0 * M1 * K1 + K0 * K1 * M0) * Kh * 8.0 + j.nt1 * 2.0 * M0 * K0 * K1 * Kh * 8.0 +
+            N0 * K0 * K1 * Kh * 8.0;
       by += terms * M0 * M1 * Kh * 8.0 + K0 * K1 * Kh * 8.0 * (2 + (j.base != nullptr) + (j.extra != nullptr)) +
-            j.nt1 * 2.0 * M0 * K1 * Kh * 8.0;
+            j.nt1 * 2.0 * M0 * K1 * Kh * 8.0 + N0 * K1 * Kh * 8.0;
     }
     timer_work(KF_COLUMN, fl, by);
   }
@@ -1535,15 +1665,15 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   const float2* w0i = w0f + (size_t)round_up(K, 16) * M;
   hipError_t e;
   if (band_iso(d, 32, 48)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else if (band_iso(d, 16, 24)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else if (band_iso(d, 24, 36)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs), dim3(256), 0, st, jobs, w1t, w0f,
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
                        w0i, Lsym, Ksym, invG);
     e = hipGetLastError();
   } else {
