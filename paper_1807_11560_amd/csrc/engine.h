@@ -84,6 +84,8 @@ class Engine {
   hipError_t record(hipStream_t s, int ev);
   hipError_t wait(hipStream_t s, int ev);
   hipError_t grid_stage0(const float2* band, float2* t1n, hipStream_t s);
+  hipError_t tail(const float* a, const float* b, float coef, float2* out, const float2* zero_band,
+                  hipStream_t s);
   hipError_t grid_t1(int n, const float2* band, hipStream_t s);
   hipError_t grid_velocity(int n, float* out, hipStream_t s);
   hipError_t grid_source(int n, const float* dmn, hipStream_t s);

@@ -290,6 +290,45 @@ hipError_t Engine::grid_source(int n, const float* dmn, hipStream_t s) {
   return launch_gridstep(a, d_, twN_, s);
 }
 
+// t = 1 tail: out = K~ pi(coef (a - b) grad_h m_nt) (b may be null), then the
+// padded-grid stage-0 buffers of the first backward step from (out with L~,
+// zero_band) on stream s.
+hipError_t Engine::tail(const float* a, const float* b, float coef, float2* out, const float2* zero_band,
+                        hipStream_t s) {
+  const float* mnt = m[d_.nt];
+  if (tail_fused(d_)) {
+    float2* t1u[3];
+    float2* t1z[3];
+    for (int c = 0; c < 3; ++c) {
+      t1u[c] = t1(0, c);
+      t1z[c] = t1(1, c);
+    }
+    return launch_tail(a, b, mnt, coef, S1N_, out, t1u, t1z, d_, twN_, col_tab_, Lsym, Ksym, s);
+  }
+  TRY(launch_src_fwd2(a, b, mnt, coef, S1N_, d_, twN_, s));
+  Fwd0Job fj[3];
+  for (int c = 0; c < 3; ++c) {
+    fj[c] = Fwd0Job{};
+    fj[c].a = s2n(c);
+    fj[c].ca = 1.f;
+    fj[c].syma = 1;
+    fj[c].out = out + (size_t)c * d_.nb;
+  }
+  TRY(fwd_grid(fj, 3, s));
+  const int C = d_.K[1] * d_.Kh;
+  Inv0Jobs jobs{};
+  int nj = 0;
+  const float2* ins[2] = {out, zero_band};
+  for (int g = 0; g < 2; ++g)
+    for (int c = 0; c < 3; ++c) {
+      jobs.j[nj].in = ins[g] + (size_t)c * d_.nb;
+      jobs.j[nj].out = t1(g, c);
+      jobs.j[nj].lflag = g == 0;
+      ++nj;
+    }
+  return launch_inv0(jobs, nj, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], d_.Kh, false, s);
+}
+
 hipError_t Engine::shoot_band(bool cache, const StepHook& hook) {
   const float dt = 1.0f / d_.nt;
   TRY(inv0_groups(V[0], 0, V[0], 1));
@@ -366,19 +405,9 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
-  // U_nt = K~ pi(lambda_1 grad_h m_nt), lambda_1 = -(2/sigma^2)(m_nt - I1)
-  TRY(launch_src_fwd2(m[nt], I1, m[nt], coef, S1N_, d_, twN_, st_));
-  Fwd0Job fj[3];
-  for (int c = 0; c < 3; ++c) {
-    fj[c] = Fwd0Job{};
-    fj[c].a = s2n(c);
-    fj[c].ca = 1.f;
-    fj[c].syma = 1;
-    fj[c].out = U[nt] + (size_t)c * d_.nb;
-  }
-  TRY(fwd_grid(fj, 3, st_));
+  // U_nt = K~ pi(lambda_1 grad_h m_nt), lambda_1 = -(2/sigma^2)(m_nt - I1); W_nt = 0
   TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
-  TRY(inv0_groups(U[nt], 1, W[nt], 0));
+  TRY(tail(m[nt], I1, coef, U[nt], W[nt], st_));
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * (size_t)d_.nM, nullptr, nullptr, nullptr, nullptr};
     TRY(mstep(PROG_GRAD, 9, UG[n], WG[n], cached));
@@ -402,7 +431,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   const int nt = d_.nt;
   const bool coupled = d_.hessian == 0;
   const size_t nM = (size_t)d_.nM;
-  TRY(aux_init(nt + 2));
+  TRY(aux_init(nt + 3));
   if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
                                     6LL * d_.nb, st_));
   TRY(record(st_, 0));
@@ -417,19 +446,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
     float* dst = dm[n & 1];
     TRY(launch_sl(q, vg[n], dst, dt, d_, aux_));
     dmcur = dst;
-    if (n + 1 < nt) return hipSuccess;
-    // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt
-    TRY(launch_src_fwd2(dmcur, nullptr, m[nt], coef, S1N_, d_, twN_, aux_));
-    Fwd0Job fj[3];
-    for (int c = 0; c < 3; ++c) {
-      fj[c] = Fwd0Job{};
-      fj[c].a = s2n(c);
-      fj[c].ca = 1.f;
-      fj[c].syma = 1;
-      fj[c].out = dU[0] + (size_t)c * d_.nb;
-    }
-    TRY(fwd_grid(fj, 3, aux_));
-    return record(aux_, nt + 1);
+    return hipSuccess;
   };
   TRY(grid_step(0));
   // incremental EPDiff forward (caller's stream); event n+1 marks dv_{n+1}
@@ -451,10 +468,17 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
       TRY(grid_step(n + 1));
     }
   }
+  // dU_nt = K~ pi(dlambda_1 grad_h m_nt), dlambda_1 = -(2/sigma^2) dm_nt, on the
+  // auxiliary stream after the last transport step; dW_nt = 0.  The fused
+  // tail also writes the padded-grid stage-0 buffers, which the main stream
+  // reads until its last step above: it waits for that (event nt + 2).
+  TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
+  TRY(record(st_, nt + 2));
+  TRY(wait(aux_, nt + 2));
+  TRY(tail(dmcur, nullptr, coef, dU[0], dW[0], aux_));
+  TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
   // incremental adjoint Jacobi sweep backward
-  TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
-  TRY(inv0_groups(dU[0], 1, dW[0], 0));
   int cur = 0;
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * nM, UG[n], WG[n], dVG[n], dVG[n] + 12 * nM};

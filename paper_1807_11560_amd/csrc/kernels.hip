@@ -78,6 +78,7 @@ __device__ __forceinline__ void st4(float2* p, float4 v) { *reinterpret_cast<flo
 // Sizes seen by a kernel: compile-time for the shapes this library is tuned
 // for (index arithmetic then folds into constants), runtime otherwise.
 struct BandDyn {
+  static constexpr bool kStatic = false;
   int k0, k1, kh, m0, m1, m2;
   __device__ __forceinline__ int K0() const { return k0; }
   __device__ __forceinline__ int K1() const { return k1; }
@@ -88,6 +89,7 @@ struct BandDyn {
 };
 template <int K, int M>
 struct BandIso {
+  static constexpr bool kStatic = true;
   __device__ static constexpr int K0() { return K; }
   __device__ static constexpr int K1() { return K; }
   __device__ static constexpr int Kh() { return K / 2; }
@@ -96,6 +98,7 @@ struct BandIso {
   __device__ static constexpr int M2() { return M; }
 };
 struct GridDyn {
+  static constexpr bool kStatic = false;
   int n0, n1, n2, k1, kh;
   __device__ __forceinline__ int N0() const { return n0; }
   __device__ __forceinline__ int N1() const { return n1; }
@@ -105,6 +108,7 @@ struct GridDyn {
 };
 template <int N, int K>
 struct GridIso {
+  static constexpr bool kStatic = true;
   __device__ static constexpr int N0() { return N; }
   __device__ static constexpr int N1() { return N; }
   __device__ static constexpr int N2() { return N; }
@@ -332,31 +336,56 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   // reads it from global memory).
   const int nw2 = 2 * N1 * M2p;
   const bool w2_lds = nw2 <= 256 * kSynthW2Pre && M2p <= K2r;
-  float w2pre[kSynthW2Pre];
-  if (w2_lds) {
-#pragma unroll
-    for (int u = 0; u < kSynthW2Pre; ++u) {
-      const int i = threadIdx.x + 256 * u;
-      w2pre[u] = (i < nw2) ? a.w2b[i] : 0.f;
-    }
-  }
-
-  batched_fill<float>(2 * M1p * K2r, [&](int i) { return a.w1a[i]; }, [&](int i, float v) {
-    int vv = i / (M1p * K2r), row = (i / K2r) % M1p, k = i % K2r;
-    w1s[((size_t)vv * M1p + row) * lda1 + k] = v;
-  });
+  RegStage<kSynthW2Pre / 4, float4> rw2;
+  if (w2_lds) rw2.load(nw2 / 4, [&](int i) { return reinterpret_cast<const float4*>(a.w2b)[i]; });
   const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
-  batched_fill<float2>(2 * K1 * Khp, [&](int i) {
-    int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
-    return (kh < Kh) ? src[((size_t)vs * M0 + x0) * C + (size_t)kh * K1 + k1] : make_float2(0.f, 0.f);
-  }, [&](int i, float2 t) {
-    int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+  auto put_t1 = [&](int vs, int k1, int kh, float2 t) {
     float* b = bt1 + (size_t)vs * K2r * N1;
     b[(size_t)k1 * N1 + kh] = t.x;
     b[(size_t)k1 * N1 + Khp + kh] = t.y;
     b[(size_t)(K1 + k1) * N1 + kh] = t.y;
     b[(size_t)(K1 + k1) * N1 + Khp + kh] = -t.x;
-  });
+  };
+  if constexpr (S::kStatic) {
+    // all loads of the block in flight at once, four floats per load
+    constexpr int sM1p = (S::M1() + 15) & ~15, sK1 = S::K1(), sKh = S::Kh(), sKhp = (sKh + 7) & ~7;
+    constexpr int sK2r = 2 * sK1, KP = sK1 / 2;
+    constexpr int NW1 = 2 * sM1p * sK2r / 4, NT1 = 2 * sKhp * KP;
+    static_assert(sK1 % 2 == 0, "pairs of k1 per load");
+    RegStage<(NW1 + 255) / 256, float4> rw1;
+    RegStage<(NT1 + 255) / 256, float4> rt1;
+    rw1.load(NW1, [&](int i) { return reinterpret_cast<const float4*>(a.w1a)[i]; });
+    rt1.load(NT1, [&](int i) {
+      const int vs = i / (sKhp * KP), kh = (i / KP) % sKhp, k1 = 2 * (i % KP);
+      return (kh < sKh) ? ld4(src + ((size_t)vs * M0 + x0) * C + (size_t)kh * sK1 + k1)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    });
+    rw1.store(NW1, [&](int i, float4 v) {
+      const int e = 4 * i, vv = e / (sM1p * sK2r), row = (e / sK2r) % sM1p, k = e % sK2r;
+      float* d = w1s + ((size_t)vv * sM1p + row) * lda1 + k;
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
+    });
+    rt1.store(NT1, [&](int i, float4 v) {
+      const int vs = i / (sKhp * KP), kh = (i / KP) % sKhp, k1 = 2 * (i % KP);
+      put_t1(vs, k1, kh, make_float2(v.x, v.y));
+      put_t1(vs, k1 + 1, kh, make_float2(v.z, v.w));
+    });
+  } else {
+    batched_fill<float>(2 * M1p * K2r, [&](int i) { return a.w1a[i]; }, [&](int i, float v) {
+      int vv = i / (M1p * K2r), row = (i / K2r) % M1p, k = i % K2r;
+      w1s[((size_t)vv * M1p + row) * lda1 + k] = v;
+    });
+    batched_fill<float2>(2 * K1 * Khp, [&](int i) {
+      int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+      return (kh < Kh) ? src[((size_t)vs * M0 + x0) * C + (size_t)kh * K1 + k1] : make_float2(0.f, 0.f);
+    }, [&](int i, float2 t) {
+      int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
+      put_t1(vs, k1, kh, t);
+    });
+  }
   __syncthreads();
   // GEMM1: var 0 = pp (plain stage 0, plain stage 1), 1 = p1 (d1), 2 = 0p (d0 input).
   // Operands are fetched eight k-steps ahead of the matrix instructions.
@@ -385,11 +414,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   __syncthreads();
   const float* w2src = a.w2b;
   if (w2_lds) {
-#pragma unroll
-    for (int u = 0; u < kSynthW2Pre; ++u) {
-      const int i = threadIdx.x + 256 * u;
-      if (i < nw2) bt1[i] = w2pre[u];
-    }
+    rw2.store(nw2 / 4, [&](int i, float4 v) { reinterpret_cast<float4*>(bt1)[i] = v; });
     __syncthreads();
     w2src = bt1;
   }
@@ -468,69 +493,82 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
   const long long nM = (long long)M0 * M1 * M2;
   float2* wfx = (float2*)smp;                  // [M2][Kh]
   float* outv = (float*)(wfx + M2 * Kh);       // [nout][R][M2]
-  batched_fill<float2>(M2 * Kh, [&](int i) {
-    int x2 = i / Kh, kh = i % Kh;
-    return tw.fwd2[(size_t)kh * M2 + x2];
-  }, [&](int i, float2 v) { wfx[i] = v; });
+  // the stage-2 table goes to LDS after the products (its loads overlap theirs)
+  const int nw = M2 * Kh;
+  const bool wreg = nw <= 256 * 4;
+  RegStage<4, float2> rw;
+  if (wreg) rw.load(nw, [&](int i) { return tw.fwd2[(size_t)(i % Kh) * M2 + i / Kh]; });
   for (int p = threadIdx.x; p < P; p += blockDim.x) {
     const int r = p / M2;
     float o[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) o[i] = 0.f;
     if (r < rv) {
-      float A[12], B[12];
       const long long gp = ((long long)x0 * M1 + x1b) * M2 + p;
       auto get = [&](const float* base, float* dst) {
 #pragma unroll
         for (int f = 0; f < 12; ++f) dst[f] = base[(size_t)f * nM + gp];
       };
+      // every group the program needs is loaded before any product is formed
       switch (a.prog) {
-        case PROG_SHOOT:
-          get(a.g[0], A); get(a.g[1], B);
-          adstar_acc(o, A, B, 1.f);
+        case PROG_SHOOT: {  // g: V, LV
+          float gV[12], gLV[12];
+          get(a.g[0], gV);
+          get(a.g[1], gLV);
+          adstar_acc(o, gV, gLV, 1.f);
           break;
-        case PROG_H1:  // g: dV, LdV, V, LV
-          get(a.g[0], A); get(a.g[3], B);      // ad*_dV(LV)
-          adstar_acc(o, A, B, 1.f);
-          get(a.g[2], A); get(a.g[1], B);      // ad*_V(LdV)
-          adstar_acc(o, A, B, 1.f);
+        }
+        case PROG_H1: {  // g: dV, LdV, V, LV
+          float gdV[12], gLdV[12], gV[12], gLV[12];
+          get(a.g[0], gdV);
+          get(a.g[1], gLdV);
+          get(a.g[2], gV);
+          get(a.g[3], gLV);
+          adstar_acc(o, gdV, gLV, 1.f);   // ad*_dV(LV)
+          adstar_acc(o, gV, gLdV, 1.f);   // ad*_V(LdV)
           break;
-        case PROG_GRAD:  // g: LU, W, V, LV
-          get(a.g[2], A); get(a.g[0], B);      // ad*_V(LU)
-          adstar_acc(o, A, B, 1.f);
-          get(a.g[1], B);                      // ad_V(W)
-          ad_acc(o + 3, A, B, 1.f);
-          get(a.g[3], A);                      // ad*_W(LV)
-          adstar_acc(o + 6, B, A, 1.f);
+        }
+        case PROG_GRAD:           // g: LU, W, V, LV
+        case PROG_H5_NOCOUPLE: {  // g: LdU, dW, V, LV
+          float gLU[12], gW[12], gV[12], gLV[12];
+          get(a.g[0], gLU);
+          get(a.g[1], gW);
+          get(a.g[2], gV);
+          get(a.g[3], gLV);
+          adstar_acc(o, gV, gLU, 1.f);     // ad*_V(LU)
+          ad_acc(o + 3, gV, gW, 1.f);      // ad_V(W)
+          adstar_acc(o + 6, gW, gLV, 1.f); // ad*_W(LV)
           break;
-        case PROG_H5:  // g: LdU, dW, V, LV, LU, W, dV, LdV
-          get(a.g[2], A); get(a.g[0], B);      // ad*_V(LdU)
-          adstar_acc(o, A, B, 1.f);
-          get(a.g[1], B);                      // ad_V(dW)
-          ad_acc(o + 3, A, B, 1.f);
-          get(a.g[3], A);                      // ad*_dW(LV)
-          adstar_acc(o + 6, B, A, 1.f);
-          get(a.g[6], A); get(a.g[4], B);      // ad*_dV(LU)
-          adstar_acc(o, A, B, 1.f);
-          get(a.g[5], B);                      // ad_dV(W)
-          ad_acc(o + 3, A, B, 1.f);
-          get(a.g[7], A);                      // ad*_W(LdV)
-          adstar_acc(o + 6, B, A, 1.f);
+        }
+        case PROG_H5: {  // g: LdU, dW, V, LV, LU, W, dV, LdV
+          float gLdU[12], gdW[12], gV[12], gLV[12], gLU[12], gW[12], gdV[12], gLdV[12];
+          get(a.g[0], gLdU);
+          get(a.g[1], gdW);
+          get(a.g[2], gV);
+          get(a.g[3], gLV);
+          get(a.g[4], gLU);
+          get(a.g[5], gW);
+          get(a.g[6], gdV);
+          get(a.g[7], gLdV);
+          adstar_acc(o, gV, gLdU, 1.f);      // ad*_V(LdU)
+          ad_acc(o + 3, gV, gdW, 1.f);       // ad_V(dW)
+          adstar_acc(o + 6, gdW, gLV, 1.f);  // ad*_dW(LV)
+          adstar_acc(o, gdV, gLU, 1.f);      // ad*_dV(LU)
+          ad_acc(o + 3, gdV, gW, 1.f);       // ad_dV(W)
+          adstar_acc(o + 6, gW, gLdV, 1.f);  // ad*_W(LdV)
           break;
-        case PROG_H5_NOCOUPLE:  // g: LdU, dW, V, LV
-          get(a.g[2], A); get(a.g[0], B);
-          adstar_acc(o, A, B, 1.f);
-          get(a.g[1], B);
-          ad_acc(o + 3, A, B, 1.f);
-          get(a.g[3], A);
-          adstar_acc(o + 6, B, A, 1.f);
-          break;
+        }
         default:
           break;
       }
     }
     for (int i = 0; i < a.nout; ++i) outv[(size_t)i * P + p] = o[i];
   }
+  if (wreg)
+    rw.store(nw, [&](int i, float2 v) { wfx[i] = v; });
+  else
+    batched_fill<float2>(nw, [&](int i) { return tw.fwd2[(size_t)(i % Kh) * M2 + i / Kh]; },
+                         [&](int i, float2 v) { wfx[i] = v; });
   __syncthreads();
   // forward stage 2: one thread per (o, r, kh)
   for (int i = threadIdx.x; i < a.nout * rv * Kh; i += blockDim.x) {
@@ -737,12 +775,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   constexpr int C = K * Kh;
   constexpr int LW1 = 18, LW0F = M + 2, LW0I = K + 2, LG = K + 2;
   static_assert(M % 2 == 0 && K % 2 == 0, "pairs of complex values per load");
-  __shared__ float2 s1[2][Mp][LS1];
-  __shared__ float2 s2[2][M][LS2];
-  __shared__ float2 ob[2][K][LOB];
-  __shared__ float2 w1s[M][LW1];        // w1t columns of this k1 tile
-  __shared__ float2 w0fs[Kp][LW0F];     // w0f
-  __shared__ float2 w0is[2][Mp][LW0I];  // w0i
+  __shared__ __align__(16) float2 s1[2][Mp][LS1];
+  __shared__ __align__(16) float2 s2[2][M][LS2];
+  __shared__ __align__(16) float2 ob[2][K][LOB];
+  __shared__ __align__(16) float2 w1s[M][LW1];        // w1t columns of this k1 tile
+  __shared__ __align__(16) float2 w0fs[Kp][LW0F];     // w0f
+  __shared__ __align__(16) float2 w0is[2][Mp][LW0I];  // w0i
   float2* g0s = &s1[0][0][0];           // [N0][LG] image-grid stage-0 table, after stage 1'
   const ColJob& job = jobs.j[blockIdx.y];
   const int kh = blockIdx.x;
@@ -1084,29 +1122,75 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, G
 template <class G>
 __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles tw) {
   constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
-  constexpr int R = kGridRows, C = K1 * Kh;
+  constexpr int R = kGridRows;
   constexpr int Khp = (Kh + 15) & ~15;  // half-spectrum columns padded to whole tiles (zero)
   constexpr int LT1 = Khp + 2, LW1 = K1 + 2, LT2 = Khp + 2, LW2 = N2 + 2;
-  static_assert(K1 % 4 == 0 && N2 % 16 == 0, "tuned grid shape");
-  __shared__ float2 t1s[3][K1][LT1];
-  __shared__ float2 w1s[R][LW1];
-  __shared__ float2 t2s[3][R][LT2];
-  __shared__ float2 w2t[Khp][LW2];
+  constexpr int KP = K1 / 2, KHP = Kh / 2;
+  static_assert(K1 % 4 == 0 && Kh % 2 == 0 && N2 % 16 == 0, "tuned grid shape");
+  __shared__ __align__(16) float2 t1s[3][K1][LT1];
+  __shared__ __align__(16) float2 w1s[R][LW1];
+  __shared__ __align__(16) float2 t2s[3][R][LT2];
+  __shared__ __align__(16) float2 w2t[Khp][LW2];
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  batched_fill<float2>(3 * Khp * K1, [&](int i) {
-    const int c = i / (Khp * K1), kh = (i / K1) % Khp, k1 = i % K1;
-    return (kh < Kh) ? a.t1[(((size_t)c * N0 + x0) * Kh + kh) * K1 + k1] : make_float2(0.f, 0.f);
-  }, [&](int i, float2 v) { t1s[i / (Khp * K1)][i % K1][(i / K1) % Khp] = v; });
-  batched_fill<float2>(R * K1, [&](int i) {
-    const int x1 = x1b + i / K1;
-    return (x1 < N1) ? tw.inv1[(size_t)x1 * K1 + i % K1] : make_float2(0.f, 0.f);
-  }, [&](int i, float2 v) { w1s[i / K1][i % K1] = v; });
-  batched_fill<float2>(N2 * Khp, [&](int i) {
-    const int x2 = i / Khp, kh = i % Khp;
-    return (kh < Kh) ? tw.inv2[(size_t)x2 * Kh + kh] : make_float2(0.f, 0.f);
-  }, [&](int i, float2 v) { w2t[i % Khp][i / Khp] = v; });
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // ---- all global loads of the block at once: the stage-0 input of this
+  // plane, the stage-1 rows, the stage-2 table, and (source) the neighbours
+  // of the points this lane will write
+  RegStage<(3 * Kh * KP + 255) / 256, float4> rt;
+  RegStage<(R * KP + 255) / 256, float4> rw1;
+  RegStage<(N2 * KHP + 255) / 256, float4> rw2;
+  rt.load(3 * Kh * KP, [&](int i) {
+    const int c = i / (Kh * KP), kh = (i / KP) % Kh, k1 = 2 * (i % KP);
+    return ld4(a.t1 + (((size_t)c * N0 + x0) * Kh + kh) * K1 + k1);
+  });
+  rw1.load(R * KP, [&](int i) {
+    const int x1 = x1b + i / KP;
+    return (x1 < N1) ? ld4(tw.inv1 + (size_t)x1 * K1 + 2 * (i % KP)) : z4;
+  });
+  rw2.load(N2 * KHP, [&](int i) { return ld4(tw.inv2 + (size_t)(i / KHP) * Kh + 2 * (i % KHP)); });
+  constexpr int NTJ = N2 / 16, TPW = (NTJ + 3) / 4;
+  float nb[TPW][4][6], dmv[TPW][4];
+  if (a.op == 1) {
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int tj = wave + 4 * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x1 = x1b + 4 * lk + r, x2 = tj * 16 + li;
+        if (tj >= NTJ || x1 >= N1) continue;
+        const int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
+        const int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
+        const int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
+        auto at = [&](int i0, int i1, int i2) { return a.m[((long long)i0 * N1 + i1) * N2 + i2]; };
+        nb[q][r][0] = at(xp0, x1, x2);
+        nb[q][r][1] = at(xm0, x1, x2);
+        nb[q][r][2] = at(x0, xp1, x2);
+        nb[q][r][3] = at(x0, xm1, x2);
+        nb[q][r][4] = at(x0, x1, xp2);
+        nb[q][r][5] = at(x0, x1, xm2);
+        dmv[q][r] = a.dm ? a.dm[((long long)x0 * N1 + x1) * N2 + x2] : 0.f;
+      }
+    }
+  }
+  // ---- stores
+  rt.store(3 * Kh * KP, [&](int i, float4 v) {
+    const int c = i / (Kh * KP), kh = (i / KP) % Kh, k1 = 2 * (i % KP);
+    t1s[c][k1][kh] = make_float2(v.x, v.y);
+    t1s[c][k1 + 1][kh] = make_float2(v.z, v.w);
+  });
+  rw1.store(R * KP, [&](int i, float4 v) { st4(&w1s[i / KP][2 * (i % KP)], v); });
+  rw2.store(N2 * KHP, [&](int i, float4 v) {
+    const int x2 = i / KHP, kh = 2 * (i % KHP);
+    w2t[kh][x2] = make_float2(v.x, v.y);
+    w2t[kh + 1][x2] = make_float2(v.z, v.w);
+  });
+  if (Khp > Kh) {  // zero padding columns of the half spectrum
+    for (int i = threadIdx.x; i < 3 * K1 * (Khp - Kh); i += 256)
+      t1s[i / (K1 * (Khp - Kh))][(i / (Khp - Kh)) % K1][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
+    for (int i = threadIdx.x; i < (Khp - Kh) * N2; i += 256) w2t[Kh + i / N2][i % N2] = make_float2(0.f, 0.f);
+  }
   __syncthreads();
   // stage 1: one 16 x Kh complex tile per component (waves 0..2 when Kh = 16)
   for (int jb = wave; jb < 3 * (Khp / 16); jb += 4) {
@@ -1121,7 +1205,10 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
   __syncthreads();
   // stage 2 + epilogue: a wave takes whole column tiles (all components)
   const long long nN = (long long)N0 * N1 * N2;
-  for (int tj = wave; tj < N2 / 16; tj += 4) {
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int tj = wave + 4 * q;
+    if (tj >= NTJ) break;
     floatx4 vel[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1148,12 +1235,11 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = vel[c][r];
       } else {
-        const float g0 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 0);
-        const float g1 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 1);
-        const float g2 = central_diff(a.m, x0, x1, x2, N0, N1, N2, 2);
+        const float g0 = (nb[q][r][0] - nb[q][r][1]) * (0.5f * N0);
+        const float g1 = (nb[q][r][2] - nb[q][r][3]) * (0.5f * N1);
+        const float g2 = (nb[q][r][4] - nb[q][r][5]) * (0.5f * N2);
         const float dot = g0 * vel[0][r] + g1 * vel[1][r] + g2 * vel[2][r];
-        const float base = a.dm ? a.dm[gi] : 0.f;
-        a.q[gi] = fmaf(-a.dt, dot, base);
+        a.q[gi] = fmaf(-a.dt, dot, dmv[q][r]);
       }
     }
   }
@@ -1245,6 +1331,257 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
       acc.y = fmaf(row[x2], w.y, acc.y);
     }
     s1[(((size_t)j * N0 + x0) * N1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
+// ------------------------------------------------- fused t = 1 tail (tuned)
+// k_srcfwd: one block per (64-row chunk of x1, x0 plane), four waves, in
+// sub-chunks of 32 rows: the source s_j = coef (a - b) d_j m (periodic
+// central differences), forward stage 2 (x2 -> kh) on the matrix cores, and
+// the chunk's part of forward stage 1 (x1 -> k1), accumulated in the matrix
+// accumulators over the sub-chunks: P[part][j][kh][x0][k1].
+constexpr int kTailRows = 64, kTailSub = 32;
+template <class G>
+__global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, const float* __restrict__ b,
+                                                const float* __restrict__ m, float coef,
+                                                float2* __restrict__ P, Twiddles tw) {
+  constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
+  constexpr int SR = kTailSub, RC = kTailRows < N1 ? kTailRows : N1, NSUB = RC / SR;
+  constexpr int Q = N2 / 4;  // float4 per grid row
+  constexpr int LM = N2 + 4, LV = N2 + 1, LW2 = 2 * Kh + 1;
+  constexpr int Khp = (Kh + 15) & ~15, LO = Khp + 2, LW1 = RC + 2;
+  constexpr int TR = SR / 16, TC = 2 * Kh / 16;
+  constexpr int TK1 = K1 / 16, TKH = Khp / 16, NT1 = 3 * TK1 * TKH, TPW = (NT1 + 3) / 4;
+  static_assert(N2 % 4 == 0 && N1 % RC == 0 && RC % SR == 0 && (2 * Kh) % 16 == 0 && K1 % 16 == 0 &&
+                    N2 % 2 == 0 && RC % 2 == 0,
+                "tail shape");
+  __shared__ __align__(16) float mr[SR + 2][LM];   // m rows x1 - 1 .. x1 + SR of the sub-chunk
+  __shared__ __align__(16) float vals[3][SR][LV];  // source fields
+  __shared__ __align__(16) float w2r[N2][LW2];     // forward stage 2: re (j < Kh) | im (j >= Kh)
+  __shared__ __align__(16) float2 o2[3][SR][LO];   // stage-2 output, kh columns padded with zero
+  __shared__ __align__(16) float2 w1f[K1][LW1];    // forward stage-1 columns of this chunk
+  const int x0 = blockIdx.y, part = blockIdx.x, x1c = part * RC;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  {
+    RegStage<(Kh * N2 / 2 + 255) / 256, float4> r2;
+    RegStage<(K1 * RC / 2 + 255) / 256, float4> r1;
+    r2.load(Kh * N2 / 2, [&](int i) { return ld4(tw.fwd2 + 2 * i); });
+    r1.load(K1 * RC / 2, [&](int i) {
+      return ld4(tw.fwd1 + (size_t)(i / (RC / 2)) * N1 + x1c + 2 * (i % (RC / 2)));
+    });
+    r2.store(Kh * N2 / 2, [&](int i, float4 v) {
+      const int kh = (2 * i) / N2, x2 = (2 * i) % N2;
+      w2r[x2][kh] = v.x;
+      w2r[x2][Kh + kh] = v.y;
+      w2r[x2 + 1][kh] = v.z;
+      w2r[x2 + 1][Kh + kh] = v.w;
+    });
+    r1.store(K1 * RC / 2, [&](int i, float4 v) { st4(&w1f[i / (RC / 2)][2 * (i % (RC / 2))], v); });
+    for (int i = threadIdx.x; i < 3 * SR * (Khp - Kh); i += 256)
+      o2[i / (SR * (Khp - Kh))][(i / (Khp - Kh)) % SR][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
+  }
+  floatx4 acc[TPW][4];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) zero_acc(acc[q], 4);
+  const int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
+  auto row4 = [&](const float* f, int plane, int x1, int q) {
+    return *reinterpret_cast<const float4*>(f + ((size_t)plane * N1 + x1) * N2 + 4 * q);
+  };
+  for (int sub = 0; sub < NSUB; ++sub) {
+    const int x1s = x1c + sub * SR;
+    RegStage<(SR * Q + 255) / 256, float4> ra, rb, rp, rn;
+    RegStage<((SR + 2) * Q + 255) / 256, float4> rm;
+    ra.load(SR * Q, [&](int i) { return row4(a, x0, x1s + i / Q, i % Q); });
+    if (b) rb.load(SR * Q, [&](int i) { return row4(b, x0, x1s + i / Q, i % Q); });
+    rp.load(SR * Q, [&](int i) { return row4(m, xp0, x1s + i / Q, i % Q); });
+    rn.load(SR * Q, [&](int i) { return row4(m, xm0, x1s + i / Q, i % Q); });
+    rm.load((SR + 2) * Q, [&](int i) {
+      int x1 = x1s - 1 + i / Q;
+      x1 = (x1 < 0) ? x1 + N1 : (x1 >= N1 ? x1 - N1 : x1);
+      return row4(m, x0, x1, i % Q);
+    });
+    rm.store((SR + 2) * Q, [&](int i, float4 v) {
+      *reinterpret_cast<float4*>(&mr[i / Q][4 * (i % Q)]) = v;
+    });
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (SR * Q + 255) / 256; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (i >= SR * Q) continue;
+      const int r = i / Q, q = i % Q;
+      const float av[4] = {ra.r[u].x, ra.r[u].y, ra.r[u].z, ra.r[u].w};
+      const float4 bw = b ? rb.r[u] : z4;
+      const float bv[4] = {bw.x, bw.y, bw.z, bw.w};
+      const float pv[4] = {rp.r[u].x, rp.r[u].y, rp.r[u].z, rp.r[u].w};
+      const float nv[4] = {rn.r[u].x, rn.r[u].y, rn.r[u].z, rn.r[u].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int x2 = 4 * q + e;
+        const int x2p = (x2 + 1 == N2) ? 0 : x2 + 1, x2m = (x2 == 0) ? N2 - 1 : x2 - 1;
+        const float sv = coef * (av[e] - bv[e]);
+        vals[0][r][x2] = sv * ((pv[e] - nv[e]) * (0.5f * N0));
+        vals[1][r][x2] = sv * ((mr[r + 2][x2] - mr[r][x2]) * (0.5f * N1));
+        vals[2][r][x2] = sv * ((mr[r + 1][x2p] - mr[r + 1][x2m]) * (0.5f * N2));
+      }
+    }
+    __syncthreads();
+    // forward stage 2: o2[j][r][kh] = sum_x2 vals[j][r][x2] fwd2[kh][x2]
+    for (int jb = wave; jb < 3 * TR * TC; jb += 4) {
+      const int c = jb / (TR * TC), ti = (jb / TC) % TR, tj = jb % TC;
+      floatx4 a2 = {0.f, 0.f, 0.f, 0.f};
+      const float* A = &vals[c][ti * 16][0] + li * LV + lk;
+      const float* B = &w2r[0][0] + lk * LW2 + tj * 16 + li;
+#pragma unroll 8
+      for (int ks = 0; ks < N2 / 4; ++ks)
+        a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 * ks], B[4 * ks * LW2], a2, 0, 0, 0);
+      const int j = tj * 16 + li;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = ti * 16 + 4 * lk + rr;
+        if (j < Kh) o2[c][r][j].x = a2[rr];
+        else o2[c][r][j - Kh].y = a2[rr];
+      }
+    }
+    __syncthreads();
+    // this sub-chunk's part of forward stage 1: acc += w1f[k1][x1] o2[j][x1][kh]
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + 4 * q;
+      if (t >= NT1) break;
+      const int c = t / (TK1 * TKH), ti = (t / TKH) % TK1, tj = t % TKH;
+      ctile<SR / 4>(&w1f[ti * 16][sub * SR], LW1, &o2[c][0][tj * 16], LO, acc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + 4 * q;
+    if (t >= NT1) break;
+    const int c = t / (TK1 * TKH), ti = (t / TKH) % TK1, tj = t % TKH;
+    const int kh = tj * 16 + li;
+    if (kh >= Kh) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int k1 = ti * 16 + 4 * lk + rr;
+      P[((((size_t)part * 3 + c) * Kh + kh) * N0 + x0) * K1 + k1] =
+          make_float2(acc[q][0][rr] - acc[q][1][rr], acc[q][2][rr] + acc[q][3][rr]);
+    }
+  }
+}
+
+// k_fwd0_mfma: one block per (kh, component, 16-wide tile of k1), four
+// waves: forward stage 0 over (part, x0) of P (the parts add up), split over
+// the waves of each output tile; the epilogue out = ca K~ F / |N| (zero on
+// the k = -K/2 slots); the padded-grid inverse stage 0 of L~ out into the
+// group-0 stage-0 buffer and zero into the group-1 buffer.
+struct TailJobs {
+  const float2* P;
+  float2* out;       // band field [3][K0][K1][Kh]
+  float2* t1u[3];    // [2][M0][Kh][K1] per component
+  float2* t1z[3];
+  float ca;
+};
+template <class S, int NG0, int NP>
+__global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __restrict__ w0n,
+                                                   const float2* __restrict__ w0i,
+                                                   const float* __restrict__ Lsym,
+                                                   const float* __restrict__ Ksym, float invG) {
+  constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
+  constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15, C = K * Kh;
+  constexpr int LB = 18, LA = NG0 + 2, LW0I = K + 2, LOB = 18;
+  constexpr int T0 = Kp / 16, SPL = 4 / T0, DEPTH = NP * NG0, LEN = DEPTH / SPL;
+  static_assert(K % 16 == 0, "whole k1 tiles");
+  static_assert(4 % T0 == 0 && DEPTH % SPL == 0 && (LEN <= NG0 ? NG0 % LEN == 0 : LEN % NG0 == 0) &&
+                    LEN % 4 == 0 && LEN <= NG0 && NG0 % 2 == 0 && K % 2 == 0,
+                "tail stage-0 shape");
+  __shared__ __align__(16) float2 bs[DEPTH][LB];     // P rows (part, x0) of this column tile
+  __shared__ __align__(16) float2 as[Kp][LA];        // forward stage-0 table [k0][x0]
+  __shared__ __align__(16) float2 w0is[2][Mp][LW0I];
+  __shared__ __align__(16) float2 ob[2][K][LOB];
+  __shared__ __align__(16) floatx4 red[4][4][64];
+  const int kh = blockIdx.x, c = blockIdx.y, kc = blockIdx.z * 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int k1 = kc + li;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  RegStage<(DEPTH * 8 + 255) / 256, float4> rb;
+  RegStage<(Kp * NG0 / 2 + 255) / 256, float4> ra;
+  RegStage<(2 * Mp * K / 2 + 255) / 256, float4> rw;
+  rb.load(DEPTH * 8, [&](int i) {
+    const int row = i / 8, p = row / NG0, x0 = row % NG0;
+    return ld4(tj.P + ((((size_t)p * 3 + c) * Kh + kh) * NG0 + x0) * K + kc + 2 * (i % 8));
+  });
+  ra.load(Kp * NG0 / 2, [&](int i) {
+    const int k0 = i / (NG0 / 2);
+    return (k0 < K) ? ld4(w0n + (size_t)k0 * NG0 + 2 * (i % (NG0 / 2))) : z4;
+  });
+  rw.load(2 * Mp * K / 2, [&](int i) { return ld4(w0i + 2 * i); });
+  float pks[4], pls[4];
+  if (wave < T0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = wave * 16 + 4 * lk + r;
+      const bool ok = k0 < K && k1 < K;
+      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
+      pks[r] = ok ? Ksym[idx] : 0.f;
+      pls[r] = ok ? Lsym[idx] : 0.f;
+    }
+  }
+  rb.store(DEPTH * 8, [&](int i, float4 v) { st4(&bs[i / 8][2 * (i % 8)], v); });
+  ra.store(Kp * NG0 / 2, [&](int i, float4 v) { st4(&as[i / (NG0 / 2)][2 * (i % (NG0 / 2))], v); });
+  rw.store(2 * Mp * K / 2, [&](int i, float4 v) {
+    st4(&w0is[i / (Mp * K / 2)][(i / (K / 2)) % Mp][2 * (i % (K / 2))], v);
+  });
+  __syncthreads();
+  {  // tile ti = wave % T0, depth split h = wave / T0
+    const int ti = wave % T0, h = wave / T0, d0 = h * LEN;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<LEN / 4>(&as[ti * 16][d0 % NG0], LA, &bs[d0][0], LB, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][i][lane] = acc[i];
+  }
+  __syncthreads();
+  if (wave < T0) {
+    const int ti = wave;
+    floatx4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[i] = red[ti][i][lane];
+#pragma unroll
+      for (int h = 1; h < SPL; ++h) acc[i] += red[ti + T0 * h][i][lane];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = ti * 16 + 4 * lk + r;
+      if (k0 >= K || k1 >= K) continue;
+      float2 res = make_float2(0.f, 0.f);
+      if (k0 != K / 2 && k1 != K / 2) {
+        const float sc = tj.ca * invG * pks[r];
+        res = make_float2(sc * (acc[0][r] - acc[1][r]), sc * (acc[2][r] + acc[3][r]));
+      }
+      tj.out[(size_t)c * K * C + ((size_t)k0 * K + k1) * Kh + kh] = res;
+      ob[0][k0][li] = res;
+      ob[1][k0][li] = make_float2(pls[r] * res.x, pls[r] * res.y);
+    }
+  }
+  __syncthreads();
+  // padded-grid inverse stage 0 of L~ out (both variants); group 1 is zero
+  constexpr int TIR = Mp / 16;
+  for (int jb = wave; jb < 2 * TIR; jb += 4) {
+    const int v = jb / TIR, ti = jb % TIR;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[1][0][0], LOB, acc);
+    if (k1 >= K) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x0 = ti * 16 + 4 * lk + r;
+      if (x0 >= M) continue;
+      const size_t o = ((size_t)v * M + x0) * C + (size_t)kh * K + k1;
+      tj.t1u[c][o] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+      tj.t1z[c][o] = make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -1787,6 +2124,56 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float
     return hipGetLastError();
   });
   return e;
+}
+
+bool tail_fused(const Dims& d) {
+  return (band_iso(d, 32, 48) && grid_iso(d, 128, 32)) || (band_iso(d, 16, 24) && grid_iso(d, 64, 16));
+}
+
+size_t tail_parts_bytes(const Dims& d) {
+  const int np = d.N[1] > kTailRows ? d.N[1] / kTailRows : 1;
+  return (size_t)np * 3 * d.N[0] * d.K[1] * d.Kh * sizeof(float2);
+}
+
+hipError_t launch_tail(const float* a, const float* b, const float* m, float coef, float2* P, float2* out,
+                       float2* const t1u[3], float2* const t1z[3], const Dims& d, const Twiddles& twN,
+                       const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st) {
+  if (!tail_fused(d)) return hipErrorInvalidValue;
+  const int K = d.K[0], M = d.M[0], N = d.N[0], Kh = d.Kh;
+  const int np = N > kTailRows ? N / kTailRows : 1;
+  const double nN = (double)d.nN, C = (double)K * Kh;
+  if ((((uintptr_t)a | (uintptr_t)m | (uintptr_t)(b ? b : a) | (uintptr_t)P | (uintptr_t)twN.fwd1 |
+        (uintptr_t)twN.fwd2 | (uintptr_t)twN.fwd0 | (uintptr_t)coltab) & 15))
+    return hipErrorInvalidValue;
+  timer_work(KF_SRC, 25.0 * nN + 3.0 * nN * Kh * 4.0 + 3.0 * N * (double)N * K * Kh * 8.0,
+             (b ? 12.0 : 8.0) * nN + np * 3.0 * N * C * 8.0);
+  hipError_t e;
+  if (N == 128)
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>>), dim3(N / kTailRows, N), dim3(256), 0, st, a, b, m, coef, P,
+                 twN);
+  else
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>>), dim3(1, N), dim3(256), 0, st, a, b, m, coef, P, twN);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  TailJobs tj{};
+  tj.P = P;
+  tj.out = out;
+  for (int c = 0; c < 3; ++c) {
+    tj.t1u[c] = t1u[c];
+    tj.t1z[c] = t1z[c];
+  }
+  tj.ca = 1.f;
+  const float2* w0i = coltab + (size_t)M * round_up(K, 16) + (size_t)round_up(K, 16) * M;
+  const float invG = (float)(1.0 / d.nN);
+  timer_work(KF_FWD0_GRID, 3.0 * K * C * N * np * 8.0 + 3.0 * 2.0 * M * K * C * 8.0,
+             np * 3.0 * N * C * 8.0 + 3.0 * K * C * 8.0 + 3.0 * 2.0 * 2.0 * M * C * 8.0 + 8.0 * 3.0 * K * C);
+  const dim3 grid(Kh, 3, round_up(K, 16) / 16);
+  if (N == 128)
+    LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<32, 48>, 128, 2>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                 Lsym, Ksym, invG);
+  else
+    LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<16, 24>, 64, 1>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                 Lsym, Ksym, invG);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st) {
