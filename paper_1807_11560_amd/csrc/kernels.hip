@@ -314,6 +314,7 @@ struct SynthArgs {
 };
 
 constexpr int kSynthW2Pre = 16;
+constexpr int kSynthT = 3;  // tiles a wave computes together
 template <class S>
 __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   extern __shared__ float sms[];
@@ -321,16 +322,18 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const int M1p = (M1 + 15) & ~15, M2p = (M2 + 15) & ~15, Khp = (Kh + 7) & ~7;
   const int x0 = blockIdx.x;
   const int g = blockIdx.y / 3, c = blockIdx.y % 3;
+  const int rt = blockIdx.z;  // 16-row tile of x1
   const int C = K1 * Kh;
   const int K2r = 2 * K1;    // GEMM1 depth
   const int N1 = 2 * Khp;    // GEMM1 width = GEMM2 depth
   const int lda1 = K2r + 1;  // padded LDS strides
   const int ldt2 = N1 + 1;
-  float* w1s = sms;                          // [2][M1p][lda1]
-  float* bt1 = w1s + 2 * M1p * lda1;         // [2][K2r][N1]
-  float* t2s = bt1 + 2 * K2r * N1;           // [3][M1p][ldt2]
+  float* w1s = sms;                          // [2][16][lda1]   stage-1 rows of this tile
+  float* bt1 = w1s + 2 * 16 * lda1;          // [2][K2r][N1]
+  float* t2s = bt1 + 2 * K2r * N1;           // [3][16][ldt2]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  (void)M1p;
   // The stage-2 table w2b [2][N1][M2p] is loaded into registers now and put
   // into the LDS of bt1 once GEMM1 has consumed it (when it fits; else GEMM2
   // reads it from global memory).
@@ -346,23 +349,29 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     b[(size_t)(K1 + k1) * N1 + kh] = t.y;
     b[(size_t)(K1 + k1) * N1 + Khp + kh] = -t.x;
   };
+  // stage-1 table rows of this tile: w1a [2][M1p][K2r]
+  const float* w1rows = a.w1a + (size_t)rt * 16 * K2r;
+  const size_t w1var = (size_t)M1p * K2r;
   if constexpr (S::kStatic) {
     // all loads of the block in flight at once, four floats per load
     constexpr int sM1p = (S::M1() + 15) & ~15, sK1 = S::K1(), sKh = S::Kh(), sKhp = (sKh + 7) & ~7;
-    constexpr int sK2r = 2 * sK1, KP = sK1 / 2;
-    constexpr int NW1 = 2 * sM1p * sK2r / 4, NT1 = 2 * sKhp * KP;
+    constexpr int sK2r = 2 * sK1, KP = sK1 / 2, R4 = sK2r / 4;
+    constexpr int NW1 = 2 * 16 * R4, NT1 = 2 * sKhp * KP;
     static_assert(sK1 % 2 == 0, "pairs of k1 per load");
     RegStage<(NW1 + 255) / 256, float4> rw1;
     RegStage<(NT1 + 255) / 256, float4> rt1;
-    rw1.load(NW1, [&](int i) { return reinterpret_cast<const float4*>(a.w1a)[i]; });
+    rw1.load(NW1, [&](int i) {
+      const int vv = i / (16 * R4), row = (i / R4) % 16, k = 4 * (i % R4);
+      return *reinterpret_cast<const float4*>(w1rows + vv * (size_t)sM1p * sK2r + (size_t)row * sK2r + k);
+    });
     rt1.load(NT1, [&](int i) {
       const int vs = i / (sKhp * KP), kh = (i / KP) % sKhp, k1 = 2 * (i % KP);
       return (kh < sKh) ? ld4(src + ((size_t)vs * M0 + x0) * C + (size_t)kh * sK1 + k1)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     });
     rw1.store(NW1, [&](int i, float4 v) {
-      const int e = 4 * i, vv = e / (sM1p * sK2r), row = (e / sK2r) % sM1p, k = e % sK2r;
-      float* d = w1s + ((size_t)vv * sM1p + row) * lda1 + k;
+      const int vv = i / (16 * R4), row = (i / R4) % 16, k = 4 * (i % R4);
+      float* d = w1s + ((size_t)vv * 16 + row) * lda1 + k;
       d[0] = v.x;
       d[1] = v.y;
       d[2] = v.z;
@@ -374,9 +383,12 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       put_t1(vs, k1 + 1, kh, make_float2(v.z, v.w));
     });
   } else {
-    batched_fill<float>(2 * M1p * K2r, [&](int i) { return a.w1a[i]; }, [&](int i, float v) {
-      int vv = i / (M1p * K2r), row = (i / K2r) % M1p, k = i % K2r;
-      w1s[((size_t)vv * M1p + row) * lda1 + k] = v;
+    batched_fill<float>(2 * 16 * K2r, [&](int i) {
+      const int vv = i / (16 * K2r), row = (i / K2r) % 16, k = i % K2r;
+      return w1rows[vv * w1var + (size_t)row * K2r + k];
+    }, [&](int i, float v) {
+      const int vv = i / (16 * K2r), row = (i / K2r) % 16, k = i % K2r;
+      w1s[((size_t)vv * 16 + row) * lda1 + k] = v;
     });
     batched_fill<float2>(2 * K1 * Khp, [&](int i) {
       int vs = i / (K1 * Khp), k1 = (i / Khp) % K1, kh = i % Khp;
@@ -387,29 +399,48 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     });
   }
   __syncthreads();
-  // GEMM1: var 0 = pp (plain stage 0, plain stage 1), 1 = p1 (d1), 2 = 0p (d0 input).
-  // Operands are fetched eight k-steps ahead of the matrix instructions.
-  const int ti1 = M1p / 16, tj1 = N1 / 16;
-  for (int job = wave; job < 3 * ti1 * tj1; job += 4) {
-    const int var = job / (ti1 * tj1), ti = (job / tj1) % ti1, tj = job % tj1;
-    const int vs = (var == 2), vt = (var == 1);
-    const float* A = w1s + ((size_t)vt * M1p + ti * 16 + li) * lda1 + lk;
-    const float* B = bt1 + (size_t)vs * K2r * N1 + (size_t)lk * N1 + tj * 16 + li;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K2r / 4; k0 += 8) {
-      float av[8], bv[8];
+  // GEMM1 on this tile's 16 rows: var 0 = pp (plain stage 0, plain stage 1),
+  // 1 = p1 (d1), 2 = 0p (d0 input).  A wave runs kSynthT tiles at once, their
+  // matrix instructions interleaved, operands fetched four k-steps ahead.
+  const int tj1 = N1 / 16, nj1 = 3 * tj1;
+  for (int j0 = wave; j0 < nj1; j0 += 4 * kSynthT) {
+    const float* A[kSynthT];
+    const float* B[kSynthT];
+    floatx4 acc[kSynthT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int ks = k0 + u;
-        av[u] = (ks < K2r / 4) ? A[4 * ks] : 0.f;
-        bv[u] = (ks < K2r / 4) ? B[(size_t)4 * ks * N1] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
+    for (int t = 0; t < kSynthT; ++t) {
+      const int job = min(j0 + 4 * t, nj1 - 1);  // a missing tile recomputes the last one, unstored
+      const int var = job / tj1, tj = job % tj1;
+      const int vs = (var == 2), vt = (var == 1);
+      A[t] = w1s + ((size_t)vt * 16 + li) * lda1 + lk;
+      B[t] = bt1 + (size_t)vs * K2r * N1 + (size_t)lk * N1 + tj * 16 + li;
+      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    float* T = t2s + ((size_t)var * M1p + ti * 16 + 4 * lk) * ldt2 + tj * 16 + li;
+    for (int k0 = 0; k0 < K2r / 4; k0 += 4) {
+      float av[kSynthT][4], bv[kSynthT][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) T[(size_t)r * ldt2] = acc[r];
+      for (int t = 0; t < kSynthT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ks = k0 + u;
+          av[t][u] = (ks < K2r / 4) ? A[t][4 * ks] : 0.f;
+          bv[t][u] = (ks < K2r / 4) ? B[t][(size_t)4 * ks * N1] : 0.f;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < kSynthT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < kSynthT; ++t) {
+      const int job = j0 + 4 * t;
+      if (job >= nj1) break;
+      const int var = job / tj1, tj = job % tj1;
+      float* T = t2s + ((size_t)var * 16 + 4 * lk) * ldt2 + tj * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(size_t)r * ldt2] = acc[t][r];
+    }
   }
   __syncthreads();
   const float* w2src = a.w2b;
@@ -419,33 +450,52 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     w2src = bt1;
   }
   // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p)
-  const int ti2 = M1p / 16, tj2 = M2p / 16;
+  const int tj2 = M2p / 16;
   const long long nM = (long long)M0 * M1 * M2;
   float* out = a.dst[g];
-  for (int job = wave; job < 4 * ti2 * tj2; job += 4) {
-    const int ov = job / (ti2 * tj2), ti = (job / tj2) % ti2, tj = job % tj2;
-    const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
-    const int wv = (ov == 1);
-    const float* A = t2s + ((size_t)srcv * M1p + ti * 16 + li) * ldt2 + lk;
-    const float* B = w2src + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < N1 / 4; k0 += 8) {
-      float av[8], bv[8];
+  const int nj2 = 4 * tj2;
+  for (int j0 = wave; j0 < nj2; j0 += 4 * kSynthT) {
+    const float* A[kSynthT];
+    const float* B[kSynthT];
+    floatx4 acc[kSynthT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int ks = k0 + u;
-        bv[u] = (ks < N1 / 4) ? B[(size_t)4 * ks * M2p] : 0.f;
-        av[u] = (ks < N1 / 4) ? A[4 * ks] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
+    for (int t = 0; t < kSynthT; ++t) {
+      const int job = min(j0 + 4 * t, nj2 - 1);
+      const int ov = job / tj2, tj = job % tj2;
+      const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
+      const int wv = (ov == 1);
+      A[t] = t2s + ((size_t)srcv * 16 + li) * ldt2 + lk;
+      B[t] = w2src + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
+      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    const int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
-    const int x2 = tj * 16 + li;
+    for (int k0 = 0; k0 < N1 / 4; k0 += 4) {
+      float av[kSynthT][4], bv[kSynthT][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int x1 = ti * 16 + 4 * lk + r;
-      if (x1 < M1 && x2 < M2) out[(size_t)f * nM + ((long long)x0 * M1 + x1) * M2 + x2] = acc[r];
+      for (int t = 0; t < kSynthT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ks = k0 + u;
+          bv[t][u] = (ks < N1 / 4) ? B[t][(size_t)4 * ks * M2p] : 0.f;
+          av[t][u] = (ks < N1 / 4) ? A[t][4 * ks] : 0.f;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < kSynthT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < kSynthT; ++t) {
+      const int job = j0 + 4 * t;
+      if (job >= nj2) break;
+      const int ov = job / tj2, tj = job % tj2;
+      const int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
+      const int x2 = tj * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x1 = rt * 16 + 4 * lk + r;
+        if (x1 < M1 && x2 < M2) out[(size_t)f * nM + ((long long)x0 * M1 + x1) * M2 + x2] = acc[t][r];
+      }
     }
   }
 }
@@ -1865,7 +1915,7 @@ size_t synth_shared_bytes(const Dims& d) {
   int M1p, M2p, Khp;
   synth_padding(d, &M1p, &M2p, &Khp);
   const int K2r = 2 * d.K[1], N1 = 2 * Khp;
-  return (2 * (size_t)M1p * (K2r + 1) + 2 * (size_t)K2r * N1 + 3 * (size_t)M1p * (N1 + 1)) * sizeof(float);
+  return (2 * 16 * (size_t)(K2r + 1) + 2 * (size_t)K2r * N1 + 3 * 16 * (size_t)(N1 + 1)) * sizeof(float);
 }
 
 hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st) {
@@ -1896,7 +1946,8 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
   (void)Khp;
   (void)M2p;
   hipError_t e = with_band(d, [&](auto sh) {
-    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], 6), dim3(256), synth_shared_bytes(d), st, a, sh);
+    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], 6, M1p / 16), dim3(256), synth_shared_bytes(d), st,
+                 a, sh);
     return hipGetLastError();
   });
   return e;
