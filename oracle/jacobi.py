@@ -44,6 +44,12 @@ Readings:
     ad~dagger_w dv).  The two coincide when lambda_1 = 0.
   * K~ and pi commute (both act per frequency), so the paper's K~(pi(.)) for
     U(1) and pi(K~(.)) for dU(1) are the same operation.
+  * Full Newton (mode "FULL", the incremental equations of §2.3/§3.2 with no
+    term dropped): dU(1) = K~ pi(dlambda_1 grad m_1 + lambda_1 grad dm_1),
+    the derivative of U(1) = K~ pi(lambda_1 grad m_1).  The paper prints a
+    minus before lambda_1 grad dm_1; with it the product is not the
+    derivative of the gradient (a test pins the plus sign: at v_0 = 0 the
+    "FULL" product equals the central difference of the gradient).
 """
 
 import numpy as np
@@ -115,12 +121,12 @@ def incremental_shoot(vs, dv0, p):
 def incremental_backward(vs, dvs, Us, ws, dU_nt, p, mode="R1"):
     """Reduced incremental adjoint Jacobi equations (§3.2) from dU_nt,
     dw_nt = 0.  Returns dw_0."""
-    if mode not in ("R1", "R2"):
-        raise ValueError("mode must be 'R1' or 'R2'")
+    if mode not in ("R1", "R2", "FULL"):
+        raise ValueError("mode must be 'R1', 'R2' or 'FULL'")
     Lsym = symbol_L(p.band, p.alpha, p.s)
     dU = dU_nt
     dw = np.zeros_like(dU)
-    coupling = mode == "R1"
+    coupling = mode != "R2"
     for n in range(p.nt - 1, -1, -1):
         v, dv = vs[n], dvs[n]
         rhs_w = dU - ad(v, dw, p.spectral) + ad_dagger(dw, v, Lsym, p.spectral)
@@ -134,12 +140,16 @@ def incremental_backward(vs, dvs, Us, ws, dU_nt, p, mode="R1"):
 
 
 def hessvec(cache, dv0, p, mode="R1"):
-    """Gauss-Newton Hessian-vector product H_V dv_0 (paper §3.2, §2.7)."""
+    """Hessian-vector product H_V dv_0 (paper §3.2, §2.7): Gauss-Newton
+    modes "R1" and "R2", or the full Newton product "FULL"."""
     Ksym = symbol_K(p.band, p.alpha, p.s)
     vs, vgrid, ms, Us, ws = (cache[k] for k in ("vs", "vgrid", "ms", "Us", "ws"))
     dvs = incremental_shoot(vs, dv0, p)
     dvgrid = [iota_vec(dvs[n], p.grid) for n in range(p.nt)]
     dm = incremental_transport(ms, vgrid, dvgrid, p.dt)
     dlam1 = -(2.0 / p.sigma ** 2) * dm
-    dU = Ksym * pi_vec(dlam1 * grad_h(ms[-1]), p.band)
+    src = dlam1 * grad_h(ms[-1])
+    if mode == "FULL":
+        src = src + cache["lam1"] * grad_h(dm)
+    dU = Ksym * pi_vec(src, p.band)
     return dv0 + incremental_backward(vs, dvs, Us, ws, dU, p, mode)

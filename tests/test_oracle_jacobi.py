@@ -213,3 +213,37 @@ def test_method_gap_to_energy_derivative_is_reported():
         gaps.append(abs(inner(Ls * g, d) - fd) / abs(fd))
     print("Jacobi-gradient gap to the energy derivative:", gaps)
     assert gaps[1] < 0.5
+
+
+def test_full_newton_at_zero_is_gradient_derivative():
+    """At v0 = 0 with a nonzero residual the full Newton product ("FULL")
+    is the derivative of the gradient: the central difference of the
+    gradient approaches it linearly in the step (the trilinear interpolant
+    has kinks at the nodes, so the difference is first order).  The
+    Gauss-Newton product and the paper's printed sign of lambda_1 grad dm_1
+    stay far from it."""
+    p, I0, I1, _ = problem()
+    v0 = np.zeros((p.d,) + p.band, dtype=complex)
+    _, _, cache = gradient(v0, I0, I1, p)
+    d = synth.random_direction(15, p.band)
+    full = hessvec(cache, d, p, "FULL")
+    r1 = hessvec(cache, d, p, "R1")
+    printed_sign = 2 * r1 - full  # dU(1) with -lambda_1 grad dm_1
+    errs = []
+    for h in (1e-3, 1e-4):
+        fd = (gradient(h * d, I0, I1, p)[0] - gradient(-h * d, I0, I1, p)[0]) / (2 * h)
+        errs.append(np.linalg.norm(full - fd) / np.linalg.norm(fd))
+        assert np.linalg.norm(r1 - fd) > 0.05 * np.linalg.norm(fd)
+        assert np.linalg.norm(printed_sign - fd) > 0.15 * np.linalg.norm(fd)
+    assert errs[1] < 5e-3 and errs[0] / errs[1] > 5.0
+
+
+def test_full_newton_equals_gauss_newton_at_zero_residual():
+    """With I1 = m_1(v0) (lambda_1 = 0) the full Newton product is the
+    Gauss-Newton product of the paper reading."""
+    p, I0, _, vstar = problem()
+    v0 = 0.5 * vstar
+    I1 = forward(v0, I0, p)[2][-1]
+    _, _, cache = gradient(v0, I0, I1, p)
+    d = synth.random_direction(16, p.band)
+    np.testing.assert_array_equal(hessvec(cache, d, p, "FULL"), hessvec(cache, d, p, "R1"))
