@@ -65,7 +65,8 @@ enum {
 };
 
 enum { LDDMM_FP32 = 0 };                              /* arithmetic of the bulk path */
-enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1 };  /* Gauss-Newton reading, see lddmm_params */
+/* Hessian of the Krylov solves, see lddmm_params */
+enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2 };
 
 typedef struct lddmm_params {
   int32_t ndim;         /* spatial dimension; this library computes ndim == 3 */
@@ -83,7 +84,13 @@ typedef struct lddmm_params {
   int32_t hessian;      /* LDDMM_GN_PAPER: Gauss-Newton drops only the -lambda(1) grad dm(1) term
                            of dU(1) and keeps every coupling term of the incremental adjoint
                            Jacobi equations; LDDMM_GN_CLASSICAL also drops the coupling terms
-                           that carry U or w (paper §2.7: "dropping expressions" of the Hessian). */
+                           that carry U or w (paper §2.7: "dropping expressions" of the Hessian);
+                           LDDMM_NEWTON keeps every term, with
+                           dU(1) = K~ pi(dlambda(1) grad m(1) + lambda(1) grad dm(1)), the
+                           derivative of the gradient's U(1) (the paper prints a minus before
+                           lambda(1) grad dm(1) in §2.3/§3.2; the plus sign is the derivative,
+                           see the oracle's pins).  This Hessian need not be positive definite:
+                           the CG of lddmm_register stops on non-positive curvature. */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */
@@ -127,7 +134,7 @@ int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m
 int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
                    void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream);
 
-/* Gauss-Newton Hessian-vector product in the V metric at the v0 of the last
+/* Hessian-vector product in the V metric at the v0 of the last
  * lddmm_gradient on this workspace with equal parameters (paper §3.2: the
  * incremental EPDiff and incremental state equations forward, then the
  * reduced incremental adjoint Jacobi equations backward from
@@ -138,7 +145,9 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
  *   dw_n = dw_{n+1} + dt[dU_{n+1} - ad~_{v_n} dw_{n+1} - ad~_{dv_n} w_{n+1}
  *                       + K~ ad~*_{dw_{n+1}}(L~ v_n) + K~ ad~*_{w_{n+1}}(L~ dv_n)]
  *   Hdv = dv0 + dw_0
- * (terms with U or w are dropped under LDDMM_GN_CLASSICAL).
+ * (terms with U or w are dropped under LDDMM_GN_CLASSICAL; LDDMM_NEWTON adds
+ * lambda(1) grad dm(1) to the source of dU(1), lambda(1) = -(2/sigma^2)(m(1) - I1)
+ * from the gradient's I1).
  *   dv0  [3][K0][K1][K2] complex64 (device, read)
  *   Hdv  [3][K0][K1][K2] complex64 (device, written; may not alias dv0)
  * Returns LDDMM_E_NOT_PREPARED if no such gradient preceded it. */

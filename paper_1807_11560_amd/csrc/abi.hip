@@ -65,7 +65,7 @@ int validate(const lddmm_params* p, Dims* d) {
   if (p->time_steps < 1 || p->time_steps > 1000)
     return fail(LDDMM_E_INVALID_ARG, "time_steps must be in [1, 1000]");
   if (p->precision != LDDMM_FP32) return fail(LDDMM_E_INVALID_ARG, "unknown precision");
-  if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL)
+  if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL && p->hessian != LDDMM_NEWTON)
     return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
   Dims& o = *d;
   o = Dims{};

@@ -23,7 +23,7 @@ struct Dims {
   int nt;
   int s;
   double alpha, sigma;
-  int hessian;      // 0: couplings kept (paper reading), 1: dropped
+  int hessian;      // 0: couplings kept (paper reading), 1: dropped, 2: full Newton
 };
 
 // ---------------------------------------------------------------- tables
@@ -155,20 +155,25 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
 hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st);
-// Fused t = 1 tail on the tuned shapes: image-matching source, forward
+// Fused t = 1 tail on the tuned shapes: image-matching source (with the
+// r d_j a term of the full Newton product when r is given), forward
 // stages 2 and 1 (partial over 64-row chunks of x1) into P
 // [nparts][3][Kh][N0][K1], then forward stage 0 with the K~/|N| epilogue into
 // the band field `out`, and the padded-grid stage-0 buffers of the first
 // backward step: group 0 from L~ out (t1u), group 1 zero (t1z).
 bool tail_fused(const Dims& d);
 size_t tail_parts_bytes(const Dims& d);
-hipError_t launch_tail(const float* a, const float* b, const float* m, float coef, float2* P, float2* out,
+hipError_t launch_tail(const float* a, const float* b, const float* r, const float* m, float coef, float2* P,
+                       float2* out,
                        float2* const t1u[3], float2* const t1z[3], const Dims& d, const Twiddles& twN,
                        const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st);
-hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
+// s_j = coef [(a - b) d_j m + r d_j a]; b and r may be null.
+hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,
+                           float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, long long n, hipStream_t st);
+hipError_t launch_diff(const float* a, const float* b, float* out, long long n, hipStream_t st);  // a - b
 hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* out, int n,
                             hipStream_t st);   // out = x + a*y
 // Reductions, deterministic two-pass; results in double on the device.

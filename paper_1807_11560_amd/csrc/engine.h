@@ -64,6 +64,7 @@ class Engine {
   std::vector<float*> VG, UG, WG, dVG;
   std::vector<float*> m, vg;
   float *dm[2], *q;
+  float* resid;  // m_nt - I1 of the last gradient (full Newton only)
   float *mlight[2];
   double *partial, *scal, *pcg;
   float *Lsym, *Ksym;
@@ -84,8 +85,8 @@ class Engine {
   hipError_t record(hipStream_t s, int ev);
   hipError_t wait(hipStream_t s, int ev);
   hipError_t grid_stage0(const float2* band, float2* t1n, hipStream_t s);
-  hipError_t tail(const float* a, const float* b, float coef, float2* out, const float2* zero_band,
-                  hipStream_t s);
+  hipError_t tail(const float* a, const float* b, const float* r, float coef, float2* out,
+                  const float2* zero_band, hipStream_t s);
   hipError_t grid_t1(int n, const float2* band, hipStream_t s);
   hipError_t grid_velocity(int n, float* out, hipStream_t s);
   hipError_t grid_source(int n, const float* dmn, hipStream_t s);

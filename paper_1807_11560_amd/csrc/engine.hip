@@ -83,6 +83,7 @@ void Engine::layout(Carver& c) {
   dm[0] = c.take<float>((size_t)d.nN);
   dm[1] = c.take<float>((size_t)d.nN);
   q = c.take<float>((size_t)d.nN);
+  resid = c.take<float>(d.hessian == 2 ? (size_t)d.nN : 1);
   mlight[0] = c.take<float>((size_t)d.nN);
   mlight[1] = c.take<float>((size_t)d.nN);
   partial = c.take<double>(1024);
@@ -290,11 +291,11 @@ hipError_t Engine::grid_source(int n, const float* dmn, hipStream_t s) {
   return launch_gridstep(a, d_, twN_, s);
 }
 
-// t = 1 tail: out = K~ pi(coef (a - b) grad_h m_nt) (b may be null), then the
+// t = 1 tail: out = K~ pi(coef [(a - b) grad_h m_nt + r grad_h a]) (b, r may be null), then the
 // padded-grid stage-0 buffers of the first backward step from (out with L~,
 // zero_band) on stream s.
-hipError_t Engine::tail(const float* a, const float* b, float coef, float2* out, const float2* zero_band,
-                        hipStream_t s) {
+hipError_t Engine::tail(const float* a, const float* b, const float* r, float coef, float2* out,
+                        const float2* zero_band, hipStream_t s) {
   const float* mnt = m[d_.nt];
   if (tail_fused(d_)) {
     float2* t1u[3];
@@ -303,9 +304,9 @@ hipError_t Engine::tail(const float* a, const float* b, float coef, float2* out,
       t1u[c] = t1(0, c);
       t1z[c] = t1(1, c);
     }
-    return launch_tail(a, b, mnt, coef, S1N_, out, t1u, t1z, d_, twN_, col_tab_, Lsym, Ksym, s);
+    return launch_tail(a, b, r, mnt, coef, S1N_, out, t1u, t1z, d_, twN_, col_tab_, Lsym, Ksym, s);
   }
-  TRY(launch_src_fwd2(a, b, mnt, coef, S1N_, d_, twN_, s));
+  TRY(launch_src_fwd2(a, b, r, mnt, coef, S1N_, d_, twN_, s));
   Fwd0Job fj[3];
   for (int c = 0; c < 3; ++c) {
     fj[c] = Fwd0Job{};
@@ -407,7 +408,9 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
   const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
   // U_nt = K~ pi(lambda_1 grad_h m_nt), lambda_1 = -(2/sigma^2)(m_nt - I1); W_nt = 0
   TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
-  TRY(tail(m[nt], I1, coef, U[nt], W[nt], st_));
+  TRY(tail(m[nt], I1, nullptr, coef, U[nt], W[nt], st_));
+  // the full Newton product needs lambda_1 (as m_nt - I1) in later hessvec calls
+  if (d_.hessian == 2) TRY(launch_diff(m[nt], I1, resid, d_.nN, st_));
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * (size_t)d_.nM, nullptr, nullptr, nullptr, nullptr};
     TRY(mstep(PROG_GRAD, 9, UG[n], WG[n], cached));
@@ -429,7 +432,7 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
 hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
-  const bool coupled = d_.hessian == 0;
+  const bool coupled = d_.hessian != 1;  // paper reading and full Newton keep the coupling terms
   const size_t nM = (size_t)d_.nM;
   TRY(aux_init(nt + 3));
   if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
@@ -475,7 +478,7 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
   TRY(record(st_, nt + 2));
   TRY(wait(aux_, nt + 2));
-  TRY(tail(dmcur, nullptr, coef, dU[0], dW[0], aux_));
+  TRY(tail(dmcur, nullptr, d_.hessian == 2 ? resid : nullptr, coef, dU[0], dW[0], aux_));
   TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
   // incremental adjoint Jacobi sweep backward

@@ -1236,7 +1236,7 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     w2t[kh][x2] = make_float2(v.x, v.y);
     w2t[kh + 1][x2] = make_float2(v.z, v.w);
   });
-  if (Khp > Kh) {  // zero padding columns of the half spectrum
+  if constexpr (Khp > Kh) {  // zero padding columns of the half spectrum
     for (int i = threadIdx.x; i < 3 * K1 * (Khp - Kh); i += 256)
       t1s[i / (K1 * (Khp - Kh))][(i / (Khp - Kh)) % K1][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
     for (int i = threadIdx.x; i < (Khp - Kh) * N2; i += 256) w2t[Kh + i / N2][i % N2] = make_float2(0.f, 0.f);
@@ -1335,11 +1335,13 @@ __global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
 }
 
 // ------------------- image-term source and forward stage 2 (N grid)
-// s_j = coef * (a - b) * d_j m (periodic central differences) at the points
-// of 16 x1 rows of plane x0, contracted over x2: s1[j][x0][x1][kh].
+// s_j = coef * [(a - b) * d_j m + res * d_j a] (periodic central
+// differences; b and res may be null) at the points of 16 x1 rows of plane x0, contracted
+// over x2: s1[j][x0][x1][kh].
 template <class G>
 __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
                                                   const float* __restrict__ b,
+                                                  const float* __restrict__ res,
                                                   const float* __restrict__ m, float coef,
                                                   float2* __restrict__ s1, Twiddles tw, G gs) {
   extern __shared__ float shs[];
@@ -1365,6 +1367,12 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
       v0 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 0);
       v1 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 1);
       v2 = s * central_diff(m, x0, x1, x2, N0, N1, N2, 2);
+      if (res) {
+        const float t = coef * res[gi];
+        v0 = fmaf(t, central_diff(a, x0, x1, x2, N0, N1, N2, 0), v0);
+        v1 = fmaf(t, central_diff(a, x0, x1, x2, N0, N1, N2, 1), v1);
+        v2 = fmaf(t, central_diff(a, x0, x1, x2, N0, N1, N2, 2), v2);
+      }
     }
     vals[p] = v0;
     vals[P + p] = v1;
@@ -1386,15 +1394,16 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
 
 // ------------------------------------------------- fused t = 1 tail (tuned)
 // k_srcfwd: one block per (64-row chunk of x1, x0 plane), four waves, in
-// sub-chunks of 32 rows: the source s_j = coef (a - b) d_j m (periodic
-// central differences), forward stage 2 (x2 -> kh) on the matrix cores, and
+// sub-chunks of 32 rows: the source s_j = coef [(a - b) d_j m + res d_j a]
+// (periodic central differences; the res term with FULL), forward stage 2
+// (x2 -> kh) on the matrix cores, and
 // the chunk's part of forward stage 1 (x1 -> k1), accumulated in the matrix
 // accumulators over the sub-chunks: P[part][j][kh][x0][k1].
 constexpr int kTailRows = 64, kTailSub = 32;
-template <class G>
+template <class G, bool FULL>
 __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, const float* __restrict__ b,
-                                                const float* __restrict__ m, float coef,
-                                                float2* __restrict__ P, Twiddles tw) {
+                                                const float* __restrict__ res, const float* __restrict__ m,
+                                                float coef, float2* __restrict__ P, Twiddles tw) {
   constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
   constexpr int SR = kTailSub, RC = kTailRows < N1 ? kTailRows : N1, NSUB = RC / SR;
   constexpr int Q = N2 / 4;  // float4 per grid row
@@ -1406,6 +1415,7 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
                     N2 % 2 == 0 && RC % 2 == 0,
                 "tail shape");
   __shared__ __align__(16) float mr[SR + 2][LM];   // m rows x1 - 1 .. x1 + SR of the sub-chunk
+  __shared__ __align__(16) float ar[FULL ? SR + 2 : 1][LM];  // the same rows of a (FULL)
   __shared__ __align__(16) float vals[3][SR][LV];  // source fields
   __shared__ __align__(16) float w2r[N2][LW2];     // forward stage 2: re (j < Kh) | im (j >= Kh)
   __shared__ __align__(16) float2 o2[3][SR][LO];   // stage-2 output, kh columns padded with zero
@@ -1428,8 +1438,9 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
       w2r[x2 + 1][Kh + kh] = v.w;
     });
     r1.store(K1 * RC / 2, [&](int i, float4 v) { st4(&w1f[i / (RC / 2)][2 * (i % (RC / 2))], v); });
-    for (int i = threadIdx.x; i < 3 * SR * (Khp - Kh); i += 256)
-      o2[i / (SR * (Khp - Kh))][(i / (Khp - Kh)) % SR][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
+    if constexpr (Khp > Kh)
+      for (int i = threadIdx.x; i < 3 * SR * (Khp - Kh); i += 256)
+        o2[i / (SR * (Khp - Kh))][(i / (Khp - Kh)) % SR][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
   }
   floatx4 acc[TPW][4];
 #pragma unroll
@@ -1446,11 +1457,19 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
     if (b) rb.load(SR * Q, [&](int i) { return row4(b, x0, x1s + i / Q, i % Q); });
     rp.load(SR * Q, [&](int i) { return row4(m, xp0, x1s + i / Q, i % Q); });
     rn.load(SR * Q, [&](int i) { return row4(m, xm0, x1s + i / Q, i % Q); });
-    rm.load((SR + 2) * Q, [&](int i) {
-      int x1 = x1s - 1 + i / Q;
-      x1 = (x1 < 0) ? x1 + N1 : (x1 >= N1 ? x1 - N1 : x1);
-      return row4(m, x0, x1, i % Q);
-    });
+    auto wrap1 = [&](int x1) { return (x1 < 0) ? x1 + N1 : (x1 >= N1 ? x1 - N1 : x1); };
+    rm.load((SR + 2) * Q, [&](int i) { return row4(m, x0, wrap1(x1s - 1 + i / Q), i % Q); });
+    RegStage<FULL ? (SR * Q + 255) / 256 : 1, float4> rres, rap, ran;
+    RegStage<FULL ? ((SR + 2) * Q + 255) / 256 : 1, float4> ram;
+    if constexpr (FULL) {
+      rres.load(SR * Q, [&](int i) { return row4(res, x0, x1s + i / Q, i % Q); });
+      rap.load(SR * Q, [&](int i) { return row4(a, xp0, x1s + i / Q, i % Q); });
+      ran.load(SR * Q, [&](int i) { return row4(a, xm0, x1s + i / Q, i % Q); });
+      ram.load((SR + 2) * Q, [&](int i) { return row4(a, x0, wrap1(x1s - 1 + i / Q), i % Q); });
+      ram.store((SR + 2) * Q, [&](int i, float4 v) {
+        *reinterpret_cast<float4*>(&ar[i / Q][4 * (i % Q)]) = v;
+      });
+    }
     rm.store((SR + 2) * Q, [&](int i, float4 v) {
       *reinterpret_cast<float4*>(&mr[i / Q][4 * (i % Q)]) = v;
     });
@@ -1459,7 +1478,7 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
     for (int u = 0; u < (SR * Q + 255) / 256; ++u) {
       const int i = threadIdx.x + 256 * u;
       if (i >= SR * Q) continue;
-      const int r = i / Q, q = i % Q;
+      const int r0 = i / Q, q = i % Q;
       const float av[4] = {ra.r[u].x, ra.r[u].y, ra.r[u].z, ra.r[u].w};
       const float4 bw = b ? rb.r[u] : z4;
       const float bv[4] = {bw.x, bw.y, bw.z, bw.w};
@@ -1470,9 +1489,21 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
         const int x2 = 4 * q + e;
         const int x2p = (x2 + 1 == N2) ? 0 : x2 + 1, x2m = (x2 == 0) ? N2 - 1 : x2 - 1;
         const float sv = coef * (av[e] - bv[e]);
-        vals[0][r][x2] = sv * ((pv[e] - nv[e]) * (0.5f * N0));
-        vals[1][r][x2] = sv * ((mr[r + 2][x2] - mr[r][x2]) * (0.5f * N1));
-        vals[2][r][x2] = sv * ((mr[r + 1][x2p] - mr[r + 1][x2m]) * (0.5f * N2));
+        float s0 = sv * ((pv[e] - nv[e]) * (0.5f * N0));
+        float s1 = sv * ((mr[r0 + 2][x2] - mr[r0][x2]) * (0.5f * N1));
+        float s2 = sv * ((mr[r0 + 1][x2p] - mr[r0 + 1][x2m]) * (0.5f * N2));
+        if constexpr (FULL) {
+          const float rv[4] = {rres.r[u].x, rres.r[u].y, rres.r[u].z, rres.r[u].w};
+          const float apv[4] = {rap.r[u].x, rap.r[u].y, rap.r[u].z, rap.r[u].w};
+          const float anv[4] = {ran.r[u].x, ran.r[u].y, ran.r[u].z, ran.r[u].w};
+          const float t = coef * rv[e];
+          s0 = fmaf(t, (apv[e] - anv[e]) * (0.5f * N0), s0);
+          s1 = fmaf(t, (ar[r0 + 2][x2] - ar[r0][x2]) * (0.5f * N1), s1);
+          s2 = fmaf(t, (ar[r0 + 1][x2p] - ar[r0 + 1][x2m]) * (0.5f * N2), s2);
+        }
+        vals[0][r0][x2] = s0;
+        vals[1][r0][x2] = s1;
+        vals[2][r0][x2] = s2;
       }
     }
     __syncthreads();
@@ -1643,6 +1674,11 @@ __global__ void k_fill(float* p, long long n, float v) {
 __global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
+}
+__global__ void k_diff(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ d,
+                       long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = a[i] - b[i];
 }
 __global__ void k_axpy_band(const float2* x, const float2* y, float a, float2* out, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2161,17 +2197,18 @@ hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, c
   return e;
 }
 
-hipError_t launch_src_fwd2(const float* a, const float* b, const float* m, float coef, float2* s1,
-                           const Dims& d, const Twiddles& tw, hipStream_t st) {
+hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,
+                           float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st) {
   dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
   size_t shm = src_shared_bytes(d);
   {
     // gradient of m (6 flops / point / axis), the source, forward stage 2 of 3 fields
     const double nN = (double)d.nN;
-    timer_work(KF_SRC, 3.0 * nN * d.Kh * 4.0 + 25.0 * nN, (b ? 12.0 : 8.0) * nN + 3.0 * d.N[0] * (double)d.N[1] * d.Kh * 8.0);
+    timer_work(KF_SRC, 3.0 * nN * d.Kh * 4.0 + (r ? 43.0 : 25.0) * nN,
+               (b ? 12.0 : 8.0) * nN + (r ? 4.0 : 0.0) * nN + 3.0 * d.N[0] * (double)d.N[1] * d.Kh * 8.0);
   }
   hipError_t e = with_grid(d, [&](auto gs) {
-    LAUNCH_TIMED(KF_SRC, (k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, m, coef, s1, tw, gs);
+    LAUNCH_TIMED(KF_SRC, (k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, r, m, coef, s1, tw, gs);
     return hipGetLastError();
   });
   return e;
@@ -2186,24 +2223,30 @@ size_t tail_parts_bytes(const Dims& d) {
   return (size_t)np * 3 * d.N[0] * d.K[1] * d.Kh * sizeof(float2);
 }
 
-hipError_t launch_tail(const float* a, const float* b, const float* m, float coef, float2* P, float2* out,
-                       float2* const t1u[3], float2* const t1z[3], const Dims& d, const Twiddles& twN,
-                       const float2* coltab, const float* Lsym, const float* Ksym, hipStream_t st) {
+hipError_t launch_tail(const float* a, const float* b, const float* r, const float* m, float coef, float2* P,
+                       float2* out, float2* const t1u[3], float2* const t1z[3], const Dims& d,
+                       const Twiddles& twN, const float2* coltab, const float* Lsym, const float* Ksym,
+                       hipStream_t st) {
   if (!tail_fused(d)) return hipErrorInvalidValue;
   const int K = d.K[0], M = d.M[0], N = d.N[0], Kh = d.Kh;
   const int np = N > kTailRows ? N / kTailRows : 1;
   const double nN = (double)d.nN, C = (double)K * Kh;
-  if ((((uintptr_t)a | (uintptr_t)m | (uintptr_t)(b ? b : a) | (uintptr_t)P | (uintptr_t)twN.fwd1 |
+  if ((((uintptr_t)a | (uintptr_t)m | (uintptr_t)(b ? b : a) | (uintptr_t)(r ? r : a) | (uintptr_t)P |
+        (uintptr_t)twN.fwd1 |
         (uintptr_t)twN.fwd2 | (uintptr_t)twN.fwd0 | (uintptr_t)coltab) & 15))
     return hipErrorInvalidValue;
-  timer_work(KF_SRC, 25.0 * nN + 3.0 * nN * Kh * 4.0 + 3.0 * N * (double)N * K * Kh * 8.0,
-             (b ? 12.0 : 8.0) * nN + np * 3.0 * N * C * 8.0);
+  timer_work(KF_SRC, (r ? 43.0 : 25.0) * nN + 3.0 * nN * Kh * 4.0 + 3.0 * N * (double)N * K * Kh * 8.0,
+             (b ? 12.0 : 8.0) * nN + (r ? 4.0 : 0.0) * nN + np * 3.0 * N * C * 8.0);
   hipError_t e;
-  if (N == 128)
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>>), dim3(N / kTailRows, N), dim3(256), 0, st, a, b, m, coef, P,
-                 twN);
+  const dim3 g1(N > kTailRows ? N / kTailRows : 1, N);
+  if (N == 128 && r)
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+  else if (N == 128)
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+  else if (r)
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
   else
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>>), dim3(1, N), dim3(256), 0, st, a, b, m, coef, P, twN);
+    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   TailJobs tj{};
   tj.P = P;
@@ -2229,6 +2272,11 @@ hipError_t launch_tail(const float* a, const float* b, const float* m, float coe
 
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff(const float* a, const float* b, float* out, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_diff, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, out, n);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ E_NONFINITE = -6
 FP32 = 0
 GN_PAPER = 0
 GN_CLASSICAL = 1
+NEWTON = 2
 KF_SYNTH, KF_GRID, KF_SL, KF_INV0, KF_COLUMN, KF_PRODS = 1, 2, 3, 4, 5, 6
 KF_INV0_GRID, KF_FWD1_GRID, KF_FWD0_GRID, KF_SRC = 7, 8, 9, 10
 KERNEL_FAMILIES = {KF_SYNTH: "k_synth", KF_GRID: "k_gridstep", KF_SL: "k_sl", KF_INV0: "k_inv0 (padded grid)",

@@ -92,3 +92,12 @@ def test_full_size_gradient_and_hessvec(problem):
     eE = max(abs(e3[i] - E_ref[i]) / abs(E_ref[i]) for i in range(3))
     print(f"full: gradient rel {eg:.2e}  hessvec rel {eh:.2e}  energy rel {eE:.2e}")
     assert eg < 1e-4 and eh < 1e-4 and eE < 1e-5
+    # the full Newton product on the same gradient state
+    import dataclasses
+    hf_ref = hessvec(cache, d, p, "FULL")
+    probn = dataclasses.replace(s["prob"], hessian=L().NEWTON)
+    wsn = L().Workspace(probn)
+    L().gradient(probn, dev(s["I0"], torch.float32), dev(s["I1"], torch.float32), dev(v0, torch.complex64), wsn)
+    ehf = rel(host(L().hessvec(probn, dev(d, torch.complex64), wsn)), hf_ref)
+    print(f"full: full Newton hessvec rel {ehf:.2e}")
+    assert ehf < 1e-4

@@ -1,6 +1,6 @@
 """Parity of the HIP library (through its C-ABI) with the FP64 oracle on
 seeded synthetic inputs: shooting, transport, energy, gradient and both
-Gauss-Newton Hessian-vector products, at sizes whose padded-grid and grid
+Gauss-Newton Hessian-vector products and the full Newton one, at sizes whose padded-grid and grid
 tiles have ragged tails, on the 64^3 / band 16^3 problem and on the
 128^3 / band 32^3 problem used for measurement.
 
@@ -112,7 +112,7 @@ def test_energy_and_gradient(grad_state):
     assert max(eE) < 1e-5
 
 
-@pytest.mark.parametrize("mode", ["R1", "R2"])
+@pytest.mark.parametrize("mode", ["R1", "R2", "FULL"])
 def test_hessvec(grad_state, mode):
     import dataclasses
     s = grad_state
@@ -121,7 +121,8 @@ def test_hessvec(grad_state, mode):
     if mode == "R1":
         prob, ws = s["prob"], s["ws"]
     else:
-        prob = dataclasses.replace(s["prob"], hessian=L().GN_CLASSICAL)
+        hess = L().GN_CLASSICAL if mode == "R2" else L().NEWTON
+        prob = dataclasses.replace(s["prob"], hessian=hess)
         ws = L().Workspace(prob)
         L().gradient(prob, *s["args"], ws)
     out = L().hessvec(prob, dev(d, torch.complex64), ws)

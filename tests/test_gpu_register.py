@@ -84,3 +84,27 @@ def test_register_matches_oracle(reg_case):
     assert e < 1e-3
     # the registration decreases the energy
     assert stats[-1]["energy"] < stats[0]["energy"]
+
+
+def test_register_full_newton_matches_oracle():
+    """The Newton-Krylov loop with the full Newton product (curvature guard
+    in CG) against the oracle's mode FULL, per iteration."""
+    import dataclasses
+    c = CASES["small"]
+    w = synth.workload(2, grid=c["grid"], band=c["band"])
+    p = Params(grid=c["grid"], band=c["band"], nt=c["nt"], alpha=synth.ALPHA, s=c["s"], sigma=synth.SIGMA)
+    vstar = synth.scale_to_displacement(w["v_star"], c["grid"], c["dmax"])
+    I0 = w["I0"]
+    I1 = forward(vstar, I0, p)[2][-1]
+    v_ref, st_ref, status_ref = register(I0, I1, p, c["gn"], c["pcg"], mode="FULL")
+    prob = L().Problem(grid=c["grid"], band=c["band"], time_steps=c["nt"], alpha=synth.ALPHA, s=c["s"],
+                       sigma=synth.SIGMA, hessian=L().NEWTON)
+    v, stats, rc, hvps = run_gpu(prob, I0, I1, c)
+    assert rc == status_ref and len(stats) == len(st_ref)
+    for k, (a, b) in enumerate(zip(stats, st_ref)):
+        print(f"newton GN {k}: E {a['energy']:.6f}/{b['E']:.6f} pcg {a['pcg_iters']}/{b['pcg_iters']} "
+              f"guard {a['pcg_guard']}/{b['pcg_guard']} eps {a['step']}/{b['eps']}")
+        assert abs(a["energy"] - b["E"]) <= 1e-4 * abs(b["E"])
+        assert a["pcg_iters"] == b["pcg_iters"] and bool(a["pcg_guard"]) == bool(b["pcg_guard"])
+        assert a["step"] == b["eps"] and a["trials"] == b["trials"]
+    assert rel(v, v_ref) < 1e-3
