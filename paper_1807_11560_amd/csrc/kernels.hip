@@ -326,11 +326,15 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const int C = K1 * Kh;
   const int K2r = 2 * K1;    // GEMM1 depth
   const int N1 = 2 * Khp;    // GEMM1 width = GEMM2 depth
-  const int lda1 = K2r + 1;  // padded LDS strides
-  const int ldt2 = N1 + 1;
+  // LDS strides: the 16 rows an MFMA operand reads lie in distinct banks
+  // (row strides of 2 mod 4 floats for operands read along rows, 16 mod 32
+  // for the stage-2 table read across rows)
+  const int lda1 = K2r + 2, ldt2 = N1 + 2, ldbT = K2r + 2;
+  const int ldw2 = (M2p % 32 == 0) ? M2p + 16 : M2p;
+  const int nbt = 2 * N1 * (ldbT > ldw2 ? ldbT : ldw2);
   float* w1s = sms;                          // [2][16][lda1]   stage-1 rows of this tile
-  float* bt1 = w1s + 2 * 16 * lda1;          // [2][K2r][N1]
-  float* t2s = bt1 + 2 * K2r * N1;           // [3][16][ldt2]
+  float* bt1 = w1s + 2 * 16 * lda1;          // [2][N1][ldbT]   stage-0 input, transposed; then [2][N1][ldw2]
+  float* t2s = bt1 + nbt;                    // [3][16][ldt2]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   (void)M1p;
@@ -338,16 +342,16 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   // into the LDS of bt1 once GEMM1 has consumed it (when it fits; else GEMM2
   // reads it from global memory).
   const int nw2 = 2 * N1 * M2p;
-  const bool w2_lds = nw2 <= 256 * kSynthW2Pre && M2p <= K2r;
+  const bool w2_lds = nw2 <= 256 * kSynthW2Pre;
   RegStage<kSynthW2Pre / 4, float4> rw2;
   if (w2_lds) rw2.load(nw2 / 4, [&](int i) { return reinterpret_cast<const float4*>(a.w2b)[i]; });
   const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
-  auto put_t1 = [&](int vs, int k1, int kh, float2 t) {
-    float* b = bt1 + (size_t)vs * K2r * N1;
-    b[(size_t)k1 * N1 + kh] = t.x;
-    b[(size_t)k1 * N1 + Khp + kh] = t.y;
-    b[(size_t)(K1 + k1) * N1 + kh] = t.y;
-    b[(size_t)(K1 + k1) * N1 + Khp + kh] = -t.x;
+  auto put_t1 = [&](int vs, int k1, int kh, float2 t) {  // B[k][col] kept as bT[col][k]
+    float* b = bt1 + (size_t)vs * N1 * ldbT;
+    b[(size_t)kh * ldbT + k1] = t.x;
+    b[(size_t)(Khp + kh) * ldbT + k1] = t.y;
+    b[(size_t)kh * ldbT + K1 + k1] = t.y;
+    b[(size_t)(Khp + kh) * ldbT + K1 + k1] = -t.x;
   };
   // stage-1 table rows of this tile: w1a [2][M1p][K2r]
   const float* w1rows = a.w1a + (size_t)rt * 16 * K2r;
@@ -413,7 +417,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       const int var = job / tj1, tj = job % tj1;
       const int vs = (var == 2), vt = (var == 1);
       A[t] = w1s + ((size_t)vt * 16 + li) * lda1 + lk;
-      B[t] = bt1 + (size_t)vs * K2r * N1 + (size_t)lk * N1 + tj * 16 + li;
+      B[t] = bt1 + ((size_t)vs * N1 + tj * 16 + li) * ldbT + lk;
       acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < K2r / 4; k0 += 4) {
@@ -424,7 +428,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
         for (int u = 0; u < 4; ++u) {
           const int ks = k0 + u;
           av[t][u] = (ks < K2r / 4) ? A[t][4 * ks] : 0.f;
-          bv[t][u] = (ks < K2r / 4) ? B[t][(size_t)4 * ks * N1] : 0.f;
+          bv[t][u] = (ks < K2r / 4) ? B[t][4 * ks] : 0.f;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -444,10 +448,14 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   }
   __syncthreads();
   const float* w2src = a.w2b;
+  int w2ld = M2p;
   if (w2_lds) {
-    rw2.store(nw2 / 4, [&](int i, float4 v) { reinterpret_cast<float4*>(bt1)[i] = v; });
+    rw2.store(nw2 / 4, [&](int i, float4 v) {
+      *reinterpret_cast<float4*>(bt1 + (size_t)((4 * i) / M2p) * ldw2 + (4 * i) % M2p) = v;
+    });
     __syncthreads();
     w2src = bt1;
+    w2ld = ldw2;
   }
   // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p)
   const int tj2 = M2p / 16;
@@ -465,7 +473,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
       const int wv = (ov == 1);
       A[t] = t2s + ((size_t)srcv * 16 + li) * ldt2 + lk;
-      B[t] = w2src + ((size_t)wv * N1 + lk) * M2p + tj * 16 + li;
+      B[t] = w2src + ((size_t)wv * N1 + lk) * w2ld + tj * 16 + li;
       acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < N1 / 4; k0 += 4) {
@@ -475,7 +483,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ks = k0 + u;
-          bv[t][u] = (ks < N1 / 4) ? B[t][(size_t)4 * ks * M2p] : 0.f;
+          bv[t][u] = (ks < N1 / 4) ? B[t][(size_t)4 * ks * w2ld] : 0.f;
           av[t][u] = (ks < N1 / 4) ? A[t][4 * ks] : 0.f;
         }
 #pragma unroll
@@ -1951,7 +1959,9 @@ size_t synth_shared_bytes(const Dims& d) {
   int M1p, M2p, Khp;
   synth_padding(d, &M1p, &M2p, &Khp);
   const int K2r = 2 * d.K[1], N1 = 2 * Khp;
-  return (2 * 16 * (size_t)(K2r + 1) + 2 * (size_t)K2r * N1 + 3 * 16 * (size_t)(N1 + 1)) * sizeof(float);
+  const int ldbT = K2r + 2, ldw2 = (M2p % 32 == 0) ? M2p + 16 : M2p;
+  return (2 * 16 * (size_t)(K2r + 2) + 2 * (size_t)N1 * (ldbT > ldw2 ? ldbT : ldw2) + 3 * 16 * (size_t)(N1 + 2)) *
+         sizeof(float);
 }
 
 hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st) {
