@@ -73,6 +73,12 @@ struct RegStage {
 
 __device__ __forceinline__ float4 ld4(const float2* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void st4(float2* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+// two complex values to an 8-byte aligned LDS address (rows of odd complex
+// stride, which keep an MFMA operand's 16 rows in distinct banks)
+__device__ __forceinline__ void st22(float2* p, float4 v) {
+  p[0] = make_float2(v.x, v.y);
+  p[1] = make_float2(v.z, v.w);
+}
 
 // ---------------------------------------------------------------- shapes
 // Sizes seen by a kernel: compile-time for the shapes this library is tuned
@@ -829,9 +835,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
                                                       const float* __restrict__ Ksym, float invG) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
-  constexpr int LS1 = M + 2, LS2 = 18, LOB = 18;
+  // A operands (read along rows) get odd complex strides, B operands 18
+  constexpr int LS1 = M + 1, LS2 = 18, LOB = 18;
   constexpr int C = K * Kh;
-  constexpr int LW1 = 18, LW0F = M + 2, LW0I = K + 2, LG = K + 2;
+  constexpr int LW1 = 18, LW0F = M + 1, LW0I = K + 1, LG = K + 1;
   static_assert(M % 2 == 0 && K % 2 == 0, "pairs of complex values per load");
   __shared__ __align__(16) float2 s1[2][Mp][LS1];
   __shared__ __align__(16) float2 s2[2][M][LS2];
@@ -888,12 +895,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   // ---- stores
   rs1.store(ns1, [&](int i, float4 v) {
     const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
-    st4(&s1[t][x0][x1], v);
+    st22(&s1[t][x0][x1], v);
   });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
-  rw0f.store(Kp * H, [&](int i, float4 v) { st4(&w0fs[i / H][2 * (i % H)], v); });
+  rw0f.store(Kp * H, [&](int i, float4 v) { st22(&w0fs[i / H][2 * (i % H)], v); });
   rw0i.store(2 * Mp * KH2, [&](int i, float4 v) {
-    st4(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
+    st22(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
   });
   __syncthreads();
   // stage 1': s2[t][x0][j] = sum_x1 s1[t][x0][x1] w1t[x1][kc + j]
@@ -910,7 +917,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     }
   }
   __syncthreads();
-  rg.store(ng, [&](int i, float4 v) { st4(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
+  rg.store(ng, [&](int i, float4 v) { st22(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
   // stage 0' and the band update (one k0 tile per wave)
   if (wave < T0) {
     const int ti = wave;
@@ -1182,7 +1189,7 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
   constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
   constexpr int R = kGridRows;
   constexpr int Khp = (Kh + 15) & ~15;  // half-spectrum columns padded to whole tiles (zero)
-  constexpr int LT1 = Khp + 2, LW1 = K1 + 2, LT2 = Khp + 2, LW2 = N2 + 2;
+  constexpr int LT1 = Khp + 2, LW1 = K1 + 1, LT2 = Khp + 1, LW2 = N2 + 2;  // A operands: odd strides
   constexpr int KP = K1 / 2, KHP = Kh / 2;
   static_assert(K1 % 4 == 0 && Kh % 2 == 0 && N2 % 16 == 0, "tuned grid shape");
   __shared__ __align__(16) float2 t1s[3][K1][LT1];
@@ -1238,7 +1245,7 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     t1s[c][k1][kh] = make_float2(v.x, v.y);
     t1s[c][k1 + 1][kh] = make_float2(v.z, v.w);
   });
-  rw1.store(R * KP, [&](int i, float4 v) { st4(&w1s[i / KP][2 * (i % KP)], v); });
+  rw1.store(R * KP, [&](int i, float4 v) { st22(&w1s[i / KP][2 * (i % KP)], v); });
   rw2.store(N2 * KHP, [&](int i, float4 v) {
     const int x2 = i / KHP, kh = 2 * (i % KHP);
     w2t[kh][x2] = make_float2(v.x, v.y);
@@ -1415,8 +1422,10 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
   constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
   constexpr int SR = kTailSub, RC = kTailRows < N1 ? kTailRows : N1, NSUB = RC / SR;
   constexpr int Q = N2 / 4;  // float4 per grid row
-  constexpr int LM = N2 + 4, LV = N2 + 1, LW2 = 2 * Kh + 1;
-  constexpr int Khp = (Kh + 15) & ~15, LO = Khp + 2, LW1 = RC + 2;
+  // MFMA A operands: rows 2 mod 32 floats (vals) or odd complex strides (w1f);
+  // the stage-2 table (a B operand) 16 mod 32
+  constexpr int LM = N2 + 4, LV = N2 + 2, LW2 = ((2 * Kh) % 32 == 16) ? 2 * Kh : 2 * Kh + 16;
+  constexpr int Khp = (Kh + 15) & ~15, LO = Khp + 2, LW1 = RC + 1;
   constexpr int TR = SR / 16, TC = 2 * Kh / 16;
   constexpr int TK1 = K1 / 16, TKH = Khp / 16, NT1 = 3 * TK1 * TKH, TPW = (NT1 + 3) / 4;
   static_assert(N2 % 4 == 0 && N1 % RC == 0 && RC % SR == 0 && (2 * Kh) % 16 == 0 && K1 % 16 == 0 &&
@@ -1438,14 +1447,17 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
     r1.load(K1 * RC / 2, [&](int i) {
       return ld4(tw.fwd1 + (size_t)(i / (RC / 2)) * N1 + x1c + 2 * (i % (RC / 2)));
     });
+    // columns XOR-swizzled by (x2 / 2) % 16 within their 16-column group, so
+    // that these stores (consecutive threads: consecutive even x2) spread
+    // over the banks while the MFMA reads below stay conflict free
     r2.store(Kh * N2 / 2, [&](int i, float4 v) {
-      const int kh = (2 * i) / N2, x2 = (2 * i) % N2;
-      w2r[x2][kh] = v.x;
-      w2r[x2][Kh + kh] = v.y;
-      w2r[x2 + 1][kh] = v.z;
-      w2r[x2 + 1][Kh + kh] = v.w;
+      const int kh = (2 * i) / N2, x2 = (2 * i) % N2, sw = (x2 >> 1) & 15;
+      w2r[x2][kh ^ sw] = v.x;
+      w2r[x2][(Kh + kh) ^ sw] = v.y;
+      w2r[x2 + 1][kh ^ sw] = v.z;
+      w2r[x2 + 1][(Kh + kh) ^ sw] = v.w;
     });
-    r1.store(K1 * RC / 2, [&](int i, float4 v) { st4(&w1f[i / (RC / 2)][2 * (i % (RC / 2))], v); });
+    r1.store(K1 * RC / 2, [&](int i, float4 v) { st22(&w1f[i / (RC / 2)][2 * (i % (RC / 2))], v); });
     if constexpr (Khp > Kh)
       for (int i = threadIdx.x; i < 3 * SR * (Khp - Kh); i += 256)
         o2[i / (SR * (Khp - Kh))][(i / (Khp - Kh)) % SR][Kh + i % (Khp - Kh)] = make_float2(0.f, 0.f);
@@ -1520,10 +1532,11 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
       const int c = jb / (TR * TC), ti = (jb / TC) % TR, tj = jb % TC;
       floatx4 a2 = {0.f, 0.f, 0.f, 0.f};
       const float* A = &vals[c][ti * 16][0] + li * LV + lk;
-      const float* B = &w2r[0][0] + lk * LW2 + tj * 16 + li;
+      const float* B = &w2r[0][0] + lk * LW2 + tj * 16;
 #pragma unroll 8
-      for (int ks = 0; ks < N2 / 4; ++ks)
-        a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 * ks], B[4 * ks * LW2], a2, 0, 0, 0);
+      for (int ks = 0; ks < N2 / 4; ++ks)  // row 4 ks + lk, swizzle (2 ks + lk / 2) % 16
+        a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 * ks], B[4 * ks * LW2 + (li ^ ((2 * ks + (lk >> 1)) & 15))],
+                                                  a2, 0, 0, 0);
       const int j = tj * 16 + li;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
@@ -1578,7 +1591,7 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
                                                    const float* __restrict__ Ksym, float invG) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15, C = K * Kh;
-  constexpr int LB = 18, LA = NG0 + 2, LW0I = K + 2, LOB = 18;
+  constexpr int LB = 18, LA = NG0 + 1, LW0I = K + 1, LOB = 18;  // A operands: odd complex strides
   constexpr int T0 = Kp / 16, SPL = 4 / T0, DEPTH = NP * NG0, LEN = DEPTH / SPL;
   static_assert(K % 16 == 0, "whole k1 tiles");
   static_assert(4 % T0 == 0 && DEPTH % SPL == 0 && (LEN <= NG0 ? NG0 % LEN == 0 : LEN % NG0 == 0) &&
@@ -1617,9 +1630,9 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     }
   }
   rb.store(DEPTH * 8, [&](int i, float4 v) { st4(&bs[i / 8][2 * (i % 8)], v); });
-  ra.store(Kp * NG0 / 2, [&](int i, float4 v) { st4(&as[i / (NG0 / 2)][2 * (i % (NG0 / 2))], v); });
+  ra.store(Kp * NG0 / 2, [&](int i, float4 v) { st22(&as[i / (NG0 / 2)][2 * (i % (NG0 / 2))], v); });
   rw.store(2 * Mp * K / 2, [&](int i, float4 v) {
-    st4(&w0is[i / (Mp * K / 2)][(i / (K / 2)) % Mp][2 * (i % (K / 2))], v);
+    st22(&w0is[i / (Mp * K / 2)][(i / (K / 2)) % Mp][2 * (i % (K / 2))], v);
   });
   __syncthreads();
   {  // tile ti = wave % T0, depth split h = wave / T0
