@@ -17,6 +17,8 @@ Modules
              (paper §2.3 state equation, §2.5 incremental state equation)
   jacobi     energy, adjoint Jacobi gradient and incremental adjoint Jacobi
              Hessian-vector product (paper §3.2)
+  deformation  the same problem subject to the deformation state equation,
+             phi = id + u carried in the band, m(1) = I0 o phi(1) (paper §3.3)
   gn         CG in the V metric and the Gauss-Newton-Krylov loop (paper §2.7)
 
 Every function cites the passage it restates.  Readings of passages where the
