@@ -43,10 +43,19 @@ Readings:
     D phi(1)^T rho(1) = lambda_1 grad m(1), and U(1) is the band form of the
     U(1) of §3.2.  "D~phi~ * rho~" is read as the contraction with the
     transposed Jacobian (the derivative of <rho, D phi v> with respect to v).
-  * (grad I0)(phi(1)) is the gradient of the multilinear interpolant of I0 at
-    phi(1)(x): the exact derivative of the discrete m(1) with respect to the
-    displacement.  (Hess I0) is that interpolant's Hessian; its pure second
-    derivatives vanish inside a cell.
+  * How (grad I0)(phi(1)) and (Hess I0)(phi(1)) are sampled (``sampling``):
+    "central" (the product path) interpolates the periodic central-difference
+    gradient grad_h I0 and Hessian grad_h grad_h I0 multilinearly at
+    phi(1)(x), the image gradient of §3.2 carried to phi(1); both are
+    continuous in phi(1).  "interpolant" takes the gradient and Hessian of the
+    multilinear interpolant of I0 itself, the exact derivatives of the
+    discrete m(1) (pure second derivatives vanish inside a cell); with it the
+    discrete gradient is differentiated exactly, which the tests use to pin
+    every other step.  The two differ at first order in h on smooth images
+    (inside a cell the interpolant's gradient is a one-sided difference), and
+    the interpolant's gradient jumps across cell faces, which would make FP32
+    and FP64 evaluations disagree where phi(1)(x) lies within rounding of a
+    face.
   * The paper prints a minus before D~phi~(1) * drho~(1) in dU(1).  The
     derivative of U(1) has a plus, which is taken; a test pins it (at zero
     residual the classical Gauss-Newton product equals the central
@@ -66,6 +75,7 @@ import numpy as np
 from .band import iota, iota_vec, pi, pi_vec, symbol_D, symbol_K
 from .epdiff import shoot
 from .jacobi import backward_sweep, energy, incremental_backward, incremental_shoot
+from .transport import grad_h, interpolate
 
 
 def jac_star(u, v, spectral):
@@ -137,29 +147,39 @@ def interpolate_derivatives(f, X):
     return val, grad, hess
 
 
-def compose(I0, ugrid):
-    """m = I0(x + u(x)) at every grid node, with the gradient and Hessian of
-    the interpolant there (§3.3, m(1) = I0 o phi(1))."""
+def compose(I0, ugrid, sampling="central"):
+    """m = I0(x + u(x)) at every grid node with the image gradient and Hessian
+    sampled there (§3.3, m(1) = I0 o phi(1); ``sampling`` as in the module
+    doc)."""
     grid = I0.shape
     d = I0.ndim
     nodes = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in grid], indexing="ij")
     X = np.stack([nodes[j] + ugrid[j] * grid[j] for j in range(d)])
-    return interpolate_derivatives(I0, X)
+    if sampling == "interpolant":
+        return interpolate_derivatives(I0, X)
+    if sampling != "central":
+        raise ValueError("sampling must be 'central' or 'interpolant'")
+    G = grad_h(I0)
+    H = np.stack([grad_h(G[b]) for b in range(d)], axis=1)  # H[a, b] = d_a d_b
+    val = interpolate(I0, X)
+    grad = np.stack([interpolate(G[a], X) for a in range(d)])
+    hess = np.stack([np.stack([interpolate(H[a, b], X) for b in range(d)]) for a in range(d)])
+    return val, grad, hess
 
 
-def forward(v0, I0, p):
-    """Band trajectory, displacements and m(1) with the interpolant's
-    derivatives at phi(1)."""
+def forward(v0, I0, p, sampling="central"):
+    """Band trajectory, displacements and m(1) with the image derivatives
+    sampled at phi(1)."""
     vs = shoot(v0, p)
     us = deformation_transport(vs, p)
-    m1, gI, hI = compose(I0, iota_vec(us[-1], p.grid))
+    m1, gI, hI = compose(I0, iota_vec(us[-1], p.grid), sampling)
     return vs, us, m1, gI, hI
 
 
-def gradient(v0, I0, I1, p):
+def gradient(v0, I0, I1, p, sampling="central"):
     """V-metric gradient g_V = v_0 + w_0 (§3.3) and the trajectories it used."""
     Ksym = symbol_K(p.band, p.alpha, p.s)
-    vs, us, m1, gI, hI = forward(v0, I0, p)
+    vs, us, m1, gI, hI = forward(v0, I0, p, sampling)
     E = energy(v0, m1, I1, p)
     lam1 = -(2.0 / p.sigma ** 2) * (m1 - I1)
     rho = pi_vec(lam1 * gI, p.band)

@@ -31,6 +31,9 @@ def energy_at(v, I0, I1, p):
     return D.energy(v, D.forward(v, I0, p)[2], I1, p)[0]
 
 
+EXACT = "interpolant"  # image derivatives of the discrete m(1): exact pins
+
+
 def band_eval(v, X):
     """v(X) at arbitrary points of the unit square by the direct Fourier sum
     (no grid, no interpolation).  X: (2, P)."""
@@ -110,12 +113,44 @@ def test_interpolant_derivatives_match_finite_differences():
 def test_composition_identity_and_integer_shift():
     rng = np.random.default_rng(4)
     I0 = rng.standard_normal((6, 10, 8))
-    m, _, _ = D.compose(I0, np.zeros((3,) + I0.shape))
-    assert np.array_equal(m, I0)
-    s = (2, -3, 5)
-    u = np.stack([np.full(I0.shape, s[j] / I0.shape[j]) for j in range(3)])
-    m, _, _ = D.compose(I0, u)
-    assert np.allclose(m, np.roll(I0, [-x for x in s], axis=(0, 1, 2)), atol=1e-12)
+    for sampling in ("central", EXACT):
+        m, _, _ = D.compose(I0, np.zeros((3,) + I0.shape), sampling)
+        assert np.array_equal(m, I0)
+        s = (2, -3, 5)
+        u = np.stack([np.full(I0.shape, s[j] / I0.shape[j]) for j in range(3)])
+        m, _, _ = D.compose(I0, u, sampling)
+        assert np.allclose(m, np.roll(I0, [-x for x in s], axis=(0, 1, 2)), atol=1e-12)
+
+
+def test_central_sampling_at_nodes_is_the_central_difference():
+    """At phi = id the central sampling returns grad_h I0 (closed form
+    (I[i+1] - I[i-1]) N / 2) and the central second differences."""
+    rng = np.random.default_rng(6)
+    I0 = rng.standard_normal((6, 10, 8))
+    _, g, h = D.compose(I0, np.zeros((3,) + I0.shape), "central")
+    for a in range(3):
+        n = I0.shape[a]
+        ref = (np.roll(I0, -1, axis=a) - np.roll(I0, 1, axis=a)) * n / 2
+        assert np.allclose(g[a], ref, atol=1e-12)
+        wide = (np.roll(I0, -2, axis=a) - 2 * I0 + np.roll(I0, 2, axis=a)) * n * n / 4
+        assert np.allclose(h[a, a], wide, atol=1e-10)
+    assert np.allclose(h[0, 1], h[1, 0], atol=1e-10)
+
+
+def test_samplings_agree_on_smooth_images():
+    """The two samplings differ at first order in h (inside a cell the
+    interpolant's gradient is a one-sided difference): a smooth periodic image
+    on grids of 16 and 32 points."""
+    errs = []
+    for n in (16, 32):
+        x = np.arange(n) / n
+        X0, X1 = np.meshgrid(x, x, indexing="ij")
+        I0 = np.sin(2 * np.pi * X0) * np.cos(4 * np.pi * X1)
+        u = np.stack([0.3 / n + 0.1 * np.sin(2 * np.pi * X1), 0.2 / n + 0.05 * np.cos(2 * np.pi * X0)])
+        _, gc, _ = D.compose(I0, u, "central")
+        _, gi, _ = D.compose(I0, u, EXACT)
+        errs.append(np.abs(gc - gi).max() / np.abs(gi).max())
+    assert errs[0] < 0.4 and 0.4 < errs[1] / errs[0] < 0.6
 
 
 def test_zero_velocity_keeps_the_source():
@@ -140,7 +175,7 @@ def test_gradient_is_consistent_with_the_energy():
         p, I0, I1, vstar = problem(nt=nt)
         Ls = symbol_L(p.band, p.alpha, p.s)
         v0 = 0.5 * vstar
-        g = D.gradient(v0, I0, I1, p)[0]
+        g = D.gradient(v0, I0, I1, p, EXACT)[0]
         d = synth.random_direction(7, p.band)
         h = 1e-6
         fd = (energy_at(v0 + h * d, I0, I1, p) - energy_at(v0 - h * d, I0, I1, p)) / (2 * h)
@@ -149,9 +184,9 @@ def test_gradient_is_consistent_with_the_energy():
     assert errs[1] < 0.65 * errs[0] and errs[2] < 0.65 * errs[1]
 
 
-def _fd_gradient(v0, d, I0, I1, p, h=1e-6):
-    gp = D.gradient(v0 + h * d, I0, I1, p)[0]
-    gm = D.gradient(v0 - h * d, I0, I1, p)[0]
+def _fd_gradient(v0, d, I0, I1, p, h=1e-6, sampling=EXACT):
+    gp = D.gradient(v0 + h * d, I0, I1, p, sampling)[0]
+    gm = D.gradient(v0 - h * d, I0, I1, p, sampling)[0]
     return (gp - gm) / (2 * h)
 
 
@@ -166,7 +201,7 @@ def test_gauss_newton_at_zero_residual_is_gradient_derivative(dims):
         p, I0, _, vstar = problem(grid=(12, 12, 12), band=(6, 6, 6), nt=3, dmax=1.0)
     v0 = 0.5 * vstar
     I1 = D.forward(v0, I0, p)[2]
-    _, _, cache = D.gradient(v0, I0, I1, p)
+    _, _, cache = D.gradient(v0, I0, I1, p, EXACT)
     d = synth.random_direction(7, p.band)
     fd = _fd_gradient(v0, d, I0, I1, p)
     scale = np.abs(fd).max()
@@ -181,13 +216,32 @@ def test_full_newton_is_gradient_derivative():
     of the gradient; the Gauss-Newton modes drop terms of visible size."""
     p, I0, I1, vstar = problem()
     v0 = 0.5 * vstar
-    _, _, cache = D.gradient(v0, I0, I1, p)
+    _, _, cache = D.gradient(v0, I0, I1, p, EXACT)
     d = synth.random_direction(7, p.band)
     fd = _fd_gradient(v0, d, I0, I1, p)
     scale = np.abs(fd).max()
     assert np.abs(D.hessvec(cache, d, p, "FULL") - fd).max() < 1e-7 * scale
     assert np.abs(D.hessvec(cache, d, p, "R1") - fd).max() > 1e-3 * scale
     assert np.abs(D.hessvec(cache, d, p, "R2") - fd).max() > 1e-2 * scale
+
+
+def test_central_sampling_products_are_close_to_the_derivative():
+    """With the product path's sampling the products are no longer exact
+    derivatives of its gradient (the sampled Hessian is not the derivative of
+    the sampled gradient) but stay within the sampling difference of them on
+    this coarse problem; the sharp pins above use the exact sampling."""
+    p, I0, I1, vstar = problem()
+    v0 = 0.5 * vstar
+    d = synth.random_direction(7, p.band)
+    _, _, cache = D.gradient(v0, I0, I1, p)
+    fd = _fd_gradient(v0, d, I0, I1, p, sampling="central")
+    e = np.abs(D.hessvec(cache, d, p, "FULL") - fd).max() / np.abs(fd).max()
+    assert e < 0.15
+    Iz = D.forward(v0, I0, p)[2]
+    _, _, cz = D.gradient(v0, I0, Iz, p)
+    fdz = _fd_gradient(v0, d, I0, Iz, p, sampling="central")
+    ez = np.abs(D.hessvec(cz, d, p, "R2") - fdz).max() / np.abs(fdz).max()
+    assert ez < 0.15
 
 
 def test_modes_agree_only_at_zero_residual():
