@@ -67,6 +67,8 @@ enum {
 enum { LDDMM_FP32 = 0 };                              /* arithmetic of the bulk path */
 /* Hessian of the Krylov solves, see lddmm_params */
 enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2 };
+/* State that carries the deformation, see lddmm_params */
+enum { LDDMM_STATE_IMAGE = 0, LDDMM_STATE_DEFORMATION = 1 };
 
 typedef struct lddmm_params {
   int32_t ndim;         /* spatial dimension; this library computes ndim == 3 */
@@ -91,6 +93,27 @@ typedef struct lddmm_params {
                            lambda(1) grad dm(1) in §2.3/§3.2; the plus sign is the derivative,
                            see the oracle's pins).  This Hessian need not be positive definite:
                            the CG of lddmm_register stops on non-positive curvature. */
+  int32_t state;        /* LDDMM_STATE_IMAGE: the image is transported on the grid (paper §3.2,
+                           everything documented above).  LDDMM_STATE_DEFORMATION: the
+                           deformation phi = id + u is transported in the band and the image
+                           is only formed at t = 1 (paper §3.3):
+                             u_{n+1} = u_n - dt [v_n + D~u_n * v_n],  u_0 = 0,
+                             (D~u * v)_i = sum_j (d_j u_i) * v_j (truncated products),
+                             m(1)(x) = I0(x + iota(u_nt)(x)) (periodic trilinear interpolation),
+                           gradient: U(1) = K~(D~phi(1) * rho~), rho~ = pi(lambda(1)
+                           (grad I0)(phi(1))), (D~phi * r)_j = r_j + sum_i (d_j u_i) * r_i,
+                           with (grad I0) the gradient of the trilinear interpolant; the
+                           adjoint sweeps are those of §3.2.  Hessian-vector product: the
+                           incremental deformation du_{n+1} = du_n - dt [D~du_n * v_n + dv_n
+                           + D~u_n * dv_n], dm(1) = (grad I0)(phi(1)) . iota(du_nt) and
+                           dU(1) = K~(D~du_nt * rho~ + D~phi(1) * pi(dlambda(1) (grad I0)(phi(1))
+                           [+ lambda(1) (Hess I0)(phi(1)) iota(du_nt)])), where
+                           LDDMM_GN_CLASSICAL drops D~du_nt * rho~ and the coupling terms,
+                           LDDMM_GN_PAPER drops the bracket, LDDMM_NEWTON keeps everything
+                           ((Hess I0): the interpolant's mixed second derivatives).  The plus
+                           signs are the derivative of U(1) (the paper prints a minus before
+                           D~phi(1) * drho~(1)).  No per-step image or grid velocity is kept,
+                           so the workspace is smaller. */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */

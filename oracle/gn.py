@@ -22,8 +22,19 @@ Readings:
 
 import numpy as np
 
+from . import deformation, jacobi
 from .band import inner, symbol_L
-from .jacobi import energy, forward, gradient, hessvec
+from .jacobi import energy
+
+# the constrained problem: image state (§3.2) or deformation state (§3.3)
+STATES = ("image", "deformation")
+
+
+def final_state(v, I0, p, state="image"):
+    """m(1) of the forward model of the given state."""
+    if state == "image":
+        return jacobi.forward(v, I0, p)[2][-1]
+    return deformation.forward(v, I0, p)[2]
 
 
 def pcg(apply_H, g, Lsym, iters):
@@ -54,21 +65,24 @@ def pcg(apply_H, g, Lsym, iters):
     return p, info
 
 
-def line_search(v0, p_dir, E0, slope, I0, I1, p, c1=1e-4, max_trials=10):
+def line_search(v0, p_dir, E0, slope, I0, I1, p, c1=1e-4, max_trials=10, state="image"):
     """Armijo backtracking.  Returns (accepted, eps, E, trials)."""
     eps = 1.0
     for trial in range(1, max_trials + 1):
         v_try = v0 + eps * p_dir
-        _, _, ms = forward(v_try, I0, p)
-        E = energy(v_try, ms[-1], I1, p)
+        E = energy(v_try, final_state(v_try, I0, p, state), I1, p)
         if E[0] <= E0 + c1 * eps * slope:
             return True, eps, E, trial
         eps *= 0.5
     return False, 0.0, None, max_trials
 
 
-def register(I0, I1, p, gn_iters, pcg_iters, v0=None, mode="R1", max_trials=10):
-    """Gauss-Newton-Krylov registration from v0 (zero by default)."""
+def register(I0, I1, p, gn_iters, pcg_iters, v0=None, mode="R1", max_trials=10, state="image"):
+    """Gauss-Newton-Krylov registration from v0 (zero by default) for the
+    problem subject to the image state (§3.2) or the deformation state (§3.3)."""
+    if state not in STATES:
+        raise ValueError("state must be 'image' or 'deformation'")
+    model = jacobi if state == "image" else deformation
     Lsym = symbol_L(p.band, p.alpha, p.s)
     if v0 is None:
         v0 = np.zeros((p.d,) + tuple(p.band), dtype=np.complex128)
@@ -77,19 +91,20 @@ def register(I0, I1, p, gn_iters, pcg_iters, v0=None, mode="R1", max_trials=10):
     g0_inf = None
     status = 0
     for it in range(gn_iters):
-        g, E, cache = gradient(v0, I0, I1, p)
+        g, E, cache = model.gradient(v0, I0, I1, p)
+        m1 = cache["ms"][-1] if state == "image" else cache["m1"]
         g_inf = float(np.max(np.abs(g)))
         if g0_inf is None:
             g0_inf = g_inf
-        p_dir, info = pcg(lambda dvec: hessvec(cache, dvec, p, mode), g, Lsym, pcg_iters)
+        p_dir, info = pcg(lambda dvec: model.hessvec(cache, dvec, p, mode), g, Lsym, pcg_iters)
         slope = inner(Lsym * g, p_dir)
         if slope >= 0.0:
             p_dir = -g
             slope = inner(Lsym * g, p_dir)
         ok, eps, E_new, trials = line_search(v0, p_dir, E[0], slope, I0, I1, p,
-                                             max_trials=max_trials)
+                                             max_trials=max_trials, state=state)
         rec = {"E": E[0], "E_reg": E[1], "E_data": E[2],
-               "mse_rel": 100.0 * float(np.sum((cache["ms"][-1] - I1) ** 2)) / denom if denom > 0 else 0.0,
+               "mse_rel": 100.0 * float(np.sum((m1 - I1) ** 2)) / denom if denom > 0 else 0.0,
                "g_inf_rel": g_inf / g0_inf if g0_inf > 0 else 0.0,
                "pcg_iters": info["iters"], "pcg_guard": info["guard"],
                "eps": eps, "trials": trials}

@@ -44,7 +44,7 @@ bool same_dims(const Dims& a, const Dims& b) {
   for (int j = 0; j < 3; ++j)
     if (a.N[j] != b.N[j] || a.K[j] != b.K[j] || a.M[j] != b.M[j]) return false;
   return a.nt == b.nt && a.s == b.s && a.alpha == b.alpha && a.sigma == b.sigma &&
-         a.hessian == b.hessian;
+         a.hessian == b.hessian && a.state == b.state;
 }
 
 void set_prepared(const void* ws, bool prepared, const Dims& d) {
@@ -67,6 +67,8 @@ int validate(const lddmm_params* p, Dims* d) {
   if (p->precision != LDDMM_FP32) return fail(LDDMM_E_INVALID_ARG, "unknown precision");
   if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL && p->hessian != LDDMM_NEWTON)
     return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
+  if (p->state != LDDMM_STATE_IMAGE && p->state != LDDMM_STATE_DEFORMATION)
+    return fail(LDDMM_E_INVALID_ARG, "unknown state");
   Dims& o = *d;
   o = Dims{};
   for (int j = 0; j < 3; ++j) {
@@ -91,6 +93,7 @@ int validate(const lddmm_params* p, Dims* d) {
   o.alpha = p->alpha;
   o.sigma = p->sigma;
   o.hessian = p->hessian;
+  o.state = p->state;
   // the fused step kernel keeps a block's fields in LDS
   // each block keeps its rows in LDS (at most 64 KiB per block)
   if (synth_shared_bytes(o) > 64 * 1024 || prods_shared_bytes(o, 9) > 64 * 1024 ||
@@ -372,7 +375,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
       const hipStream_t s = e.stream();
       if ((r = launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n, s)))
         return r;
-      if ((r = e.forward(I0)) || (r = e.energy(e.m[d.nt], I1)) || (r = e.backward(I1, e.gh))) return r;
+      if ((r = e.forward(I0)) || (r = e.energy(e.final_state(), I1)) || (r = e.backward(I1, e.gh))) return r;
       return launch_band_maxabs(e.gh, d, e.partial, e.scal + 3, s);
     }));
     double sc[4];
@@ -518,7 +521,7 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
   if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
   if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
   if ((err = e.forward(I0)) != hipSuccess) return hip_fail(err, "forward");
-  if ((err = e.energy(e.m[d.nt], I1)) != hipSuccess) return hip_fail(err, "energy");
+  if ((err = e.energy(e.final_state(), I1)) != hipSuccess) return hip_fail(err, "energy");
   if ((err = e.backward(I1, nullptr)) != hipSuccess) return hip_fail(err, "backward");
   if ((err = e.store_band(e.V[0], e.W[0], 1.f, grad)) != hipSuccess) return hip_fail(err, "store");
   if (energy3 && (err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess)

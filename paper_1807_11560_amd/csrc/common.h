@@ -24,6 +24,7 @@ struct Dims {
   int s;
   double alpha, sigma;
   int hessian;      // 0: couplings kept (paper reading), 1: dropped, 2: full Newton
+  int state;        // 0: image state on the grid; 1: deformation state in the band
 };
 
 // ---------------------------------------------------------------- tables
@@ -58,9 +59,17 @@ enum MProg {
                     // out1 = ad_V(dW) + ad_dV(W)
                     // out2 = ad*_dW(LV) + ad*_W(LdV)
                     //                   new: LdU, dW; cached: V, LV, LU, W, dV, LdV
-  PROG_H5_NOCOUPLE = 5  // out0 = ad*_V(LdU), out1 = ad_V(dW), out2 = ad*_dW(LV)
+  PROG_H5_NOCOUPLE = 5, // out0 = ad*_V(LdU), out1 = ad_V(dW), out2 = ad*_dW(LV)
+  // deformation state (D~A * B)_i = sum_j (d_j A_i) B_j, ((D~A)^T * B)_j = sum_i (d_j A_i) B_i:
+  PROG_DEF_FWD = 6,     // out0 = D~Phi * V                             new: Phi; cached: V
+  PROG_DEF_H = 7,       // out0 = D~dPhi * V + D~Phi * dV               new: dPhi; cached: V, Phi, dV
+  PROG_DEF_TAIL = 8,    // out0 = (D~A)^T * R                           new: A and/or R
+  PROG_DEF_HTAIL = 9    // out0 = (D~dPhi)^T * R + (D~Phi)^T * dR       new: dPhi, dR; cached: Phi, R
   // k_prods group order: SHOOT (V, LV); H1 (dV, LdV, V, LV); GRAD (LU, W, V, LV);
-  // H5 (LdU, dW, V, LV, LU, W, dV, LdV); H5_NOCOUPLE (LdU, dW, V, LV)
+  // H5 (LdU, dW, V, LV, LU, W, dV, LdV); H5_NOCOUPLE (LdU, dW, V, LV);
+  // DEF_FWD (Phi, V); DEF_H (dPhi, V, Phi, dV); DEF_TAIL (A, R); DEF_HTAIL (dPhi, dR, Phi, R).
+  // Of a group that enters through its Jacobian only the nine derivative
+  // fields are read, of one that enters through its values only the three values.
 };
 
 // Lie products on the padded grid (k_prods): group pointers [12][nM] in
@@ -137,6 +146,7 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
 hipError_t launch_synth_tables(const Twiddles& tw, float* tables, const Dims& d, hipStream_t st);
 size_t synth_table_floats(const Dims& d);
 size_t synth_shared_bytes(const Dims& d);
+// Synthesis of group 0 and, when t1g1 is set, group 1.
 hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, float* dst1,
                         const float* tables, const Dims& d, hipStream_t st);
 size_t prods_shared_bytes(const Dims& d, int nout);
@@ -171,6 +181,22 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,
                            float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st);
+// Deformation state at t = 1 (see k_rho_fwd2): the image-term source at
+// phi(1) = id + u and its forward stage 2 into s1 [3][N0][N1][Kh].
+struct RhoArgs {
+  const float* I0;
+  const float* G;     // [3][nN] central-difference gradient of I0
+  const float* H;     // [6][nN] its Hessian (00, 01, 02, 11, 12, 22), full Newton only
+  const float* u;     // [3][nN] displacement iota(u_nt)
+  const float* I1;    // op 0
+  const float* du;    // op 1: [3][nN] iota(du_nt)
+  const float* res;   // op 1, full Newton: m(1) - I1, or null
+  float coef;
+  int op;
+};
+// Central differences of I0: G [3][nN] and, when H is set, H [6][nN].
+hipError_t launch_image_derivs(const float* I0, float* G, float* H, const Dims& d, hipStream_t st);
+hipError_t launch_rho_fwd2(const RhoArgs& a, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_diff(const float* a, const float* b, float* out, long long n, hipStream_t st);  // a - b

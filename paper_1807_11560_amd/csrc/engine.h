@@ -50,6 +50,9 @@ class Engine {
   // Hessian-vector product on half-spectrum vectors.
   hipError_t hessvec(const float2* dvh, float2* out);
 
+  // m(1) of the last forward: m_nt (image state) or I0 o phi(1) (deformation state).
+  const float* final_state() const { return d_.state ? m1 : m[d_.nt]; }
+
   const Dims& dims() const { return d_; }
   // Second stream of this thread and device for the grid chain, and events.
   hipError_t aux_init(int nevents);
@@ -64,7 +67,17 @@ class Engine {
   std::vector<float*> VG, UG, WG, dVG;
   std::vector<float*> m, vg;
   float *dm[2], *q;
-  float* resid;  // m_nt - I1 of the last gradient (full Newton only)
+  float* resid;  // m(1) - I1 of the last gradient (full Newton only)
+  // deformation state: band displacements u_0..u_nt, incremental pair,
+  // their padded-grid groups (PG[1..nt]), rho~ (R, K~ R), its group, drho~,
+  // iota(u_nt) and iota(du_nt) on the image grid, m(1), a copy of I0 and its
+  // derivatives
+  std::vector<float2*> Phi;
+  float2* dPhi[2];
+  std::vector<float*> PG;
+  float* RG;
+  float2 *R, *KR, *dR, *KdR;
+  float *ug, *dug, *m1, *I0c, *IG, *IH;  // IG, IH: central-difference gradient / Hessian of I0
   float *mlight[2];
   double *partial, *scal, *pcg;
   float *Lsym, *Ksym;
@@ -90,6 +103,17 @@ class Engine {
   hipError_t grid_t1(int n, const float2* band, hipStream_t s);
   hipError_t grid_velocity(int n, float* out, hipStream_t s);
   hipError_t grid_source(int n, const float* dmn, hipStream_t s);
+  // deformation state (paper §3.3)
+  hipError_t forward_def(const float* I0);
+  hipError_t tail_def(const float* I1);
+  hipError_t hessvec_def(const float2* dvh, float2* out);
+  hipError_t hessvec_sweep(float2* out);
+  hipError_t inv0_group(const float2* in, int g, int lflag, hipStream_t s);
+  hipError_t colstep_on(const ColJob* jobs, int n, hipStream_t s);
+  hipError_t prods_on(int prog, const float* const* g, int ng, float2* out, hipStream_t s);
+  hipError_t grid_field(const float2* band, bool have_t1n, float* out, hipStream_t s);
+  hipError_t band_pair(float2* plain, float2* smooth, hipStream_t s);
+  hipError_t def_head(int prog, const float* const* g, int ng, const float2* base, float2* out);
 
   Dims d_;
   hipStream_t st_;
@@ -98,6 +122,8 @@ class Engine {
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;
   float2 *T1_ = nullptr, *S1_ = nullptr, *S1N_ = nullptr, *S2N_ = nullptr;
+  float2 *T1NA_ = nullptr, *S1A_ = nullptr;  // displacement chain: image-grid stage 0, products
+  float* NGA_ = nullptr;                     // displacement chain: scratch for two groups
   std::vector<float2*> T1N;     // image-grid stage-0 output of each time step [3][N0][Kh][K1]
   bool fuse_grid0_ = false;     // the column kernel forms T1N[n + 1]
   float* NG_ = nullptr;         // scratch for new groups that are not cached

@@ -77,15 +77,22 @@ void Engine::layout(Carver& c) {
   for (auto& p : UG) p = c.take<float>(12 * (size_t)d.nM);
   for (auto& p : WG) p = c.take<float>(12 * (size_t)d.nM);
   for (auto& p : dVG) p = c.take<float>(24 * (size_t)d.nM);
-  m.resize(nt + 1); vg.resize(nt);
+  // the image state keeps m_n and the grid velocities of every step; the
+  // deformation state needs neither
+  const bool def = d.state == 1;
+  m.assign(def ? 0 : nt + 1, nullptr);
+  vg.assign(def ? 0 : nt, nullptr);
   for (auto& p : m) p = c.take<float>((size_t)d.nN);
   for (auto& p : vg) p = c.take<float>(3 * (size_t)d.nN);
-  dm[0] = c.take<float>((size_t)d.nN);
-  dm[1] = c.take<float>((size_t)d.nN);
-  q = c.take<float>((size_t)d.nN);
+  dm[0] = dm[1] = q = mlight[0] = mlight[1] = nullptr;
+  if (!def) {
+    dm[0] = c.take<float>((size_t)d.nN);
+    dm[1] = c.take<float>((size_t)d.nN);
+    q = c.take<float>((size_t)d.nN);
+    mlight[0] = c.take<float>((size_t)d.nN);
+    mlight[1] = c.take<float>((size_t)d.nN);
+  }
   resid = c.take<float>(d.hessian == 2 ? (size_t)d.nN : 1);
-  mlight[0] = c.take<float>((size_t)d.nN);
-  mlight[1] = c.take<float>((size_t)d.nN);
   partial = c.take<double>(1024);
   scal = c.take<double>(64);
   pcg = c.take<double>(SC_COUNT);
@@ -93,15 +100,40 @@ void Engine::layout(Carver& c) {
   Ksym = c.take<float>((size_t)d.nb);
   twbuf_ = c.take<float2>(twiddle_count(d.M, d) + twiddle_count(d.N, d));
   const size_t C = (size_t)d.K[1] * d.Kh;
-  T1_ = c.take<float2>(2 * 3 * 2 * (size_t)d.M[0] * C);
+  T1_ = c.take<float2>((def ? 4 : 2) * 3 * 2 * (size_t)d.M[0] * C);
   NG_ = c.take<float>(24 * (size_t)d.nM);
   synth_tab_ = c.take<float>(synth_table_floats(d));
   col_tab_ = c.take<float2>(col_table_count(d));
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
-  T1N.resize(nt);
+  T1N.assign(def ? 0 : nt, nullptr);
   for (auto& p : T1N) p = c.take<float2>(3 * (size_t)d.N[0] * C);
   S1N_ = c.take<float2>(3 * (size_t)d.N[0] * d.N[1] * d.Kh);
   S2N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
+  Phi.assign(def ? nt + 1 : 0, nullptr);
+  PG.assign(def ? nt + 1 : 0, nullptr);
+  dPhi[0] = dPhi[1] = R = KR = dR = KdR = nullptr;
+  RG = ug = dug = m1 = I0c = IG = IH = NGA_ = nullptr;
+  T1NA_ = S1A_ = nullptr;
+  if (def) {
+    for (auto& p : Phi) p = c.take<float2>(nbv);
+    for (int k = 1; k <= nt; ++k) PG[k] = c.take<float>(12 * (size_t)d.nM);  // u_0 = 0 has no group
+    dPhi[0] = c.take<float2>(nbv);
+    dPhi[1] = c.take<float2>(nbv);
+    R = c.take<float2>(nbv);
+    KR = c.take<float2>(nbv);
+    dR = c.take<float2>(nbv);
+    KdR = c.take<float2>(nbv);
+    RG = c.take<float>(12 * (size_t)d.nM);
+    NGA_ = c.take<float>(24 * (size_t)d.nM);
+    S1A_ = c.take<float2>(3 * (size_t)d.M[0] * d.M[1] * d.Kh);
+    T1NA_ = c.take<float2>(3 * (size_t)d.N[0] * C);
+    ug = c.take<float>(3 * (size_t)d.nN);
+    dug = c.take<float>(3 * (size_t)d.nN);
+    m1 = c.take<float>((size_t)d.nN);
+    I0c = c.take<float>((size_t)d.nN);
+    IG = c.take<float>(3 * (size_t)d.nN);
+    if (d.hessian == 2) IH = c.take<float>(6 * (size_t)d.nN);
+  }
 }
 
 Engine::Engine(const Dims& d, void* ws, hipStream_t st) : d_(d), st_(st), fuse_grid0_(colstep_fuses_grid0(d)) {
@@ -221,12 +253,14 @@ ColJob Engine::col_job(int c, int oa, float ca, int syma, int ob, float cb, int 
   return j;
 }
 
-hipError_t Engine::colstep(const ColJob* jobs, int n) {
+hipError_t Engine::colstep(const ColJob* jobs, int n) { return colstep_on(jobs, n, st_); }
+
+hipError_t Engine::colstep_on(const ColJob* jobs, int n, hipStream_t s) {
   ColJobs js{};
   for (int i = 0; i < n; ++i) js.j[i] = jobs[i];
   js.w0n = twN_.inv0;  // value variant [N0][K0]
   js.N0 = d_.N[0];
-  return launch_colstep(js, n, d_, twM_, col_tab_, Lsym, Ksym, st_);
+  return launch_colstep(js, n, d_, twM_, col_tab_, Lsym, Ksym, s);
 }
 
 // Forward stages 1 and 0 of the three grid fields in S1N with the given
@@ -341,7 +375,7 @@ hipError_t Engine::shoot_band(bool cache, const StepHook& hook) {
     ColJob jobs[3];
     for (int c = 0; c < 3; ++c)
       jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, V[n], nullptr, 0.f, V[n + 1], next ? 0 : -1, 0,
-                        next ? 1 : -1, 1, next && fuse_grid0_ ? T1N[n + 1] : nullptr);
+                        next ? 1 : -1, 1, next && fuse_grid0_ && !d_.state ? T1N[n + 1] : nullptr);
     TRY(colstep(jobs, 3));
     if (ev_) TRY(record(st_, n + 1));
     if (hook) TRY(hook(n + 1));
@@ -354,6 +388,7 @@ hipError_t Engine::shoot_band(bool cache, const StepHook& hook) {
 // right after the band step that produces v_n, so that the host issues both
 // streams' work in the order the device can run it.
 hipError_t Engine::forward(const float* I0) {
+  if (d_.state) return forward_def(I0);
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   TRY(aux_init(nt + 2));
@@ -373,6 +408,13 @@ hipError_t Engine::forward(const float* I0) {
 
 // Shooting and transport without the caches; returns m_nt in *m_out.
 hipError_t Engine::forward_light(const float* I0, const float** m_out) {
+  if (d_.state) {
+    // the displacement chain reads the cached trajectory fields, so the
+    // deformation state always runs the caching forward
+    TRY(forward_def(I0));
+    *m_out = m1;
+    return hipSuccess;
+  }
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   TRY(aux_init(nt + 2));
@@ -408,9 +450,12 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
   const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
   // U_nt = K~ pi(lambda_1 grad_h m_nt), lambda_1 = -(2/sigma^2)(m_nt - I1); W_nt = 0
   TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
-  TRY(tail(m[nt], I1, nullptr, coef, U[nt], W[nt], st_));
-  // the full Newton product needs lambda_1 (as m_nt - I1) in later hessvec calls
-  if (d_.hessian == 2) TRY(launch_diff(m[nt], I1, resid, d_.nN, st_));
+  if (d_.state)
+    TRY(tail_def(I1));
+  else
+    TRY(tail(m[nt], I1, nullptr, coef, U[nt], W[nt], st_));
+  // the full Newton product needs lambda_1 (as m(1) - I1) in later hessvec calls
+  if (d_.hessian == 2) TRY(launch_diff(final_state(), I1, resid, d_.nN, st_));
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * (size_t)d_.nM, nullptr, nullptr, nullptr, nullptr};
     TRY(mstep(PROG_GRAD, 9, UG[n], WG[n], cached));
@@ -430,6 +475,7 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
 }
 
 hipError_t Engine::hessvec(const float2* dvh, float2* out) {
+  if (d_.state) return hessvec_def(dvh, out);
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   const bool coupled = d_.hessian != 1;  // paper reading and full Newton keep the coupling terms
@@ -481,7 +527,16 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   TRY(tail(dmcur, nullptr, d_.hessian == 2 ? resid : nullptr, coef, dU[0], dW[0], aux_));
   TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
-  // incremental adjoint Jacobi sweep backward
+  return hessvec_sweep(out);
+}
+
+// Incremental adjoint Jacobi sweep backward from dU[0] (dU_nt) and dW[0] = 0
+// with the stage-0 buffers of its first step in place; Hdv = dv0 + dw_0.
+hipError_t Engine::hessvec_sweep(float2* out) {
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  const bool coupled = d_.hessian != 1;
+  const size_t nM = (size_t)d_.nM;
   int cur = 0;
   for (int n = nt - 1; n >= 0; --n) {
     const float* cached[6] = {VG[n], VG[n] + 12 * nM, UG[n], WG[n], dVG[n], dVG[n] + 12 * nM};
@@ -497,6 +552,207 @@ hipError_t Engine::hessvec(const float2* dvh, float2* out) {
     cur = 1 - cur;
   }
   return launch_axpy_band(dV[0], dW[cur], 1.f, out, 3 * d_.nb, st_);
+}
+
+// ------------------------------------------------ deformation state (§3.3)
+// Stage-0 group 2 belongs to the displacement chain (u_k or du_k), group 3
+// to rho~ / drho~ at t = 1; groups 0 and 1 stay with the main chain.
+
+hipError_t Engine::inv0_group(const float2* in, int g, int lflag, hipStream_t s) {
+  const int C = d_.K[1] * d_.Kh;
+  Inv0Jobs jobs{};
+  for (int c = 0; c < 3; ++c) {
+    jobs.j[c].in = in + (size_t)c * d_.nb;
+    jobs.j[c].out = t1(g, c);
+    jobs.j[c].lflag = lflag;
+  }
+  return launch_inv0(jobs, 3, 2, twM_.inv0, Lsym, d_.K[0], C, d_.M[0], d_.Kh, false, s);
+}
+
+hipError_t Engine::prods_on(int prog, const float* const* g, int ng, float2* out, hipStream_t s) {
+  ProdArgs a{};
+  for (int k = 0; k < ng; ++k) a.g[k] = g[k];
+  a.s1 = out;
+  a.nout = 3;
+  a.prog = prog;
+  return launch_prods(a, d_, twM_, s);
+}
+
+// iota of a band field on the image grid into out [3][nN], through the
+// image-grid stage-0 buffer of the chain (already formed when have_t1n).
+hipError_t Engine::grid_field(const float2* band, bool have_t1n, float* out, hipStream_t s) {
+  if (!have_t1n) TRY(grid_stage0(band, T1NA_, s));
+  GridStepArgs a{};
+  a.t1 = T1NA_;
+  a.op = 0;
+  a.vout = out;
+  return launch_gridstep(a, d_, twN_, s);
+}
+
+// Forward stages 1 and 0 of the three fields in S1N: pi(s) into `plain` and
+// K~ pi(s) into `smooth`.
+hipError_t Engine::band_pair(float2* plain, float2* smooth, hipStream_t s) {
+  Fwd0Job fj[6];
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 2; ++k) {
+      Fwd0Job& j = fj[2 * c + k];
+      j = Fwd0Job{};
+      j.a = s2n(c);
+      j.ca = 1.f;
+      j.syma = k;
+      j.out = (k ? smooth : plain) + (size_t)c * d_.nb;
+    }
+  return fwd_grid(fj, 6, s);
+}
+
+// out = base + K~ F(products of the program) on the caller's stream, with the
+// stage-0 buffers of the first backward step: group 0 from L~ out, group 1
+// zero (w = 0 at t = 1).
+hipError_t Engine::def_head(int prog, const float* const* g, int ng, const float2* base, float2* out) {
+  TRY(prods_on(prog, g, ng, S1_, st_));
+  TRY(launch_fill(reinterpret_cast<float*>(t1(1, 0)), 12LL * d_.M[0] * d_.K[1] * d_.Kh, 0.f, st_));
+  ColJob jobs[3];
+  for (int c = 0; c < 3; ++c) jobs[c] = col_job(c, c, 1.f, 1, -1, 0.f, 0, base, nullptr, 0.f, out, 0, 1, -1, 0);
+  return colstep_on(jobs, 3, st_);
+}
+
+// Shooting on the caller's stream; the band displacement chain
+//   u_{k+1} = u_k - dt [v_k + D~u_k * v_k],  u_0 = 0,
+// on the auxiliary stream, step k enqueued right after the band step that
+// makes v_{k+1} (the fields of v_k are cached by then); then iota(u_nt) on
+// the image grid and m(1) = I0(x + iota(u_nt)(x)).
+hipError_t Engine::forward_def(const float* I0) {
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  const size_t ns1 = (size_t)d_.Kh * d_.M[0] * d_.M[1];
+  TRY(aux_init(nt + 3));
+  TRY(record(st_, 0));
+  TRY(wait(aux_, 0));
+  TRY(launch_fill(reinterpret_cast<float*>(Phi[0]), 6LL * d_.nb, 0.f, aux_));
+  TRY(launch_copy(I0, I0c, d_.nN, aux_));
+  TRY(launch_image_derivs(I0c, IG, IH, d_, aux_));
+  auto chain = [&](int n) -> hipError_t {  // v_n exists: displacement step n - 1
+    const int k = n - 1;
+    TRY(wait(aux_, n));
+    if (k == 0) {  // D~u_0 = 0
+      TRY(launch_axpy_band(Phi[0], V[0], -dt, Phi[1], 3 * d_.nb, aux_));
+      return inv0_group(Phi[1], 2, 0, aux_);
+    }
+    TRY(launch_synth(t1(2, 0), nullptr, PG[k], nullptr, synth_tab_, d_, aux_));
+    const float* g[2] = {PG[k], VG[k]};
+    TRY(prods_on(PROG_DEF_FWD, g, 2, S1A_, aux_));
+    const bool last = k + 1 == nt;
+    ColJob jobs[3];
+    for (int c = 0; c < 3; ++c) {
+      jobs[c] = col_job(c, c, -dt, 0, -1, 0.f, 0, Phi[k], V[k], -dt, Phi[k + 1], 2, 0, -1, 0,
+                        last && fuse_grid0_ ? T1NA_ : nullptr);
+      jobs[c].a = S1A_ + c * ns1;
+    }
+    return colstep_on(jobs, 3, aux_);
+  };
+  TRY(shoot_band(true, chain));
+  TRY(grid_field(Phi[nt], nt > 1 && fuse_grid0_, ug, aux_));
+  TRY(launch_sl(I0c, ug, m1, -1.0f, d_, aux_));
+  TRY(record(aux_, nt + 1));
+  return wait(st_, nt + 1);
+}
+
+// t = 1 of the gradient: rho~ = pi(lambda_1 (grad I0)(phi(1))) and
+// U_nt = K~ rho~ + K~ ((D~u_nt)^T * rho~).
+hipError_t Engine::tail_def(const float* I1) {
+  const int nt = d_.nt;
+  RhoArgs ra{};
+  ra.I0 = I0c;
+  ra.G = IG;
+  ra.u = ug;
+  ra.I1 = I1;
+  ra.coef = (float)(-2.0 / (d_.sigma * d_.sigma));
+  ra.op = 0;
+  TRY(launch_rho_fwd2(ra, S1N_, d_, twN_, st_));
+  TRY(band_pair(R, KR, st_));
+  TRY(inv0_group(R, 3, 0, st_));
+  TRY(launch_synth(t1(2, 0), t1(3, 0), PG[nt], RG, synth_tab_, d_, st_));
+  const float* g[2] = {PG[nt], RG};
+  return def_head(PROG_DEF_TAIL, g, 2, KR, U[nt]);
+}
+
+// Incremental EPDiff on the caller's stream (every step's fields kept), the
+// incremental displacement chain
+//   du_{k+1} = du_k - dt [D~du_k * v_k + dv_k + D~u_k * dv_k],  du_0 = 0,
+// on the auxiliary stream, then drho~ and dU_nt and the incremental sweep.
+hipError_t Engine::hessvec_def(const float2* dvh, float2* out) {
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  const size_t nM = (size_t)d_.nM;
+  const size_t ns1 = (size_t)d_.Kh * d_.M[0] * d_.M[1];
+  TRY(aux_init(nt + 3));
+  if (dvh != dV[0]) TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]),
+                                    6LL * d_.nb, st_));
+  TRY(record(st_, 0));
+  int cur = 0;  // dPhi[cur] holds du_k
+  auto chain = [&](int k) -> hipError_t {  // dv_k and its fields exist (event k + 1)
+    TRY(wait(aux_, k + 1));
+    if (k == 0) {  // du_0 = 0 and u_0 = 0
+      TRY(launch_axpy_band(Phi[0], dV[0], -dt, dPhi[0], 3 * d_.nb, aux_));
+      return inv0_group(dPhi[0], 2, 0, aux_);
+    }
+    TRY(launch_synth(t1(2, 0), nullptr, NGA_, nullptr, synth_tab_, d_, aux_));
+    const float* g[4] = {NGA_, VG[k], PG[k], dVG[k]};
+    TRY(prods_on(PROG_DEF_H, g, 4, S1A_, aux_));
+    const bool last = k + 1 == nt;
+    ColJob jobs[3];
+    for (int c = 0; c < 3; ++c) {
+      jobs[c] = col_job(c, c, -dt, 0, -1, 0.f, 0, dPhi[cur], dV[k], -dt, dPhi[1 - cur], 2, 0, -1, 0,
+                        last && fuse_grid0_ ? T1NA_ : nullptr);
+      jobs[c].a = S1A_ + c * ns1;
+    }
+    TRY(colstep_on(jobs, 3, aux_));
+    cur = 1 - cur;
+    return hipSuccess;
+  };
+  TRY(inv0_groups(dV[0], 0, dV[0], 1));
+  for (int n = 0; n < nt; ++n) {
+    const bool last = n == nt - 1;
+    const float* cached[6] = {VG[n], VG[n] + 12 * nM, nullptr, nullptr, nullptr, nullptr};
+    TRY(mstep(last ? PROG_STORE : PROG_H1, last ? 0 : 3, dVG[n], dVG[n] + 12 * nM, cached));
+    TRY(record(st_, n + 1));
+    TRY(chain(n));
+    if (!last) {
+      ColJob jobs[3];
+      for (int c = 0; c < 3; ++c)
+        jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1);
+      TRY(colstep(jobs, 3));
+    }
+  }
+  // t = 1 on the auxiliary stream: iota(du_nt), drho~ = pi(dlambda_1 (grad I0)(phi(1))
+  // [+ lambda_1 (Hess I0)(phi(1)) iota(du_nt)]) and its stage 0
+  TRY(grid_field(dPhi[cur], nt > 1 && fuse_grid0_, dug, aux_));
+  RhoArgs ra{};
+  ra.I0 = I0c;
+  ra.G = IG;
+  ra.H = IH;
+  ra.u = ug;
+  ra.du = dug;
+  ra.res = d_.hessian == 2 ? resid : nullptr;
+  ra.coef = (float)(-2.0 / (d_.sigma * d_.sigma));
+  ra.op = 1;
+  TRY(launch_rho_fwd2(ra, S1N_, d_, twN_, aux_));
+  TRY(band_pair(dR, KdR, aux_));
+  TRY(inv0_group(dR, 3, 0, aux_));
+  TRY(record(aux_, nt + 1));
+  TRY(wait(st_, nt + 1));
+  // dU_nt = K~ drho~ + K~ ((D~u_nt)^T * drho~ [+ (D~du_nt)^T * rho~])
+  TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
+  if (d_.hessian == 1) {
+    TRY(launch_synth(t1(3, 0), nullptr, NGA_, nullptr, synth_tab_, d_, st_));
+    const float* g[2] = {PG[nt], NGA_};
+    TRY(def_head(PROG_DEF_TAIL, g, 2, KdR, dU[0]));
+  } else {
+    TRY(launch_synth(t1(2, 0), t1(3, 0), NGA_, NGA_ + 12 * nM, synth_tab_, d_, st_));
+    const float* g[4] = {NGA_, NGA_ + 12 * nM, PG[nt], RG};
+    TRY(def_head(PROG_DEF_HTAIL, g, 4, KdR, dU[0]));
+  }
+  return hessvec_sweep(out);
 }
 
 }  // namespace lddmm

@@ -300,6 +300,22 @@ __device__ __forceinline__ void ad_acc(float* o, const float* a, const float* b,
   }
 }
 
+// (D~a * b)_i += sum_j (d_j a_i) b_j; ja[3 i + j] = d_j a_i
+__device__ __forceinline__ void jac_acc(float* o, const float* ja, const float* b) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o[i] = fmaf(ja[3 * i + j], b[j], o[i]);
+}
+
+// ((D~a)^T * r)_j += sum_i (d_j a_i) r_i
+__device__ __forceinline__ void jact_acc(float* o, const float* ja, const float* r) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[j] = fmaf(ja[3 * i + j], r[i], o[j]);
+}
+
 // ------------------------------------------- MFMA synthesis on the padded grid
 // One block per (x0 plane, new field (g, c)), four waves.  The inverse
 // stages 1 (k1 -> x1, complex) and 2 (half spectrum k2 -> real x2) are two
@@ -573,6 +589,14 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
 #pragma unroll
         for (int f = 0; f < 12; ++f) dst[f] = base[(size_t)f * nM + gp];
       };
+      auto get_jac = [&](const float* base, float* dst) {  // dst[3 i + j] = d_j a_i
+#pragma unroll
+        for (int f = 0; f < 9; ++f) dst[f] = base[(size_t)(3 + f) * nM + gp];
+      };
+      auto get_val = [&](const float* base, float* dst) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) dst[f] = base[(size_t)f * nM + gp];
+      };
       // every group the program needs is loaded before any product is formed
       switch (a.prog) {
         case PROG_SHOOT: {  // g: V, LV
@@ -620,6 +644,40 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
           adstar_acc(o, gdV, gLU, 1.f);      // ad*_dV(LU)
           ad_acc(o + 3, gdV, gW, 1.f);       // ad_dV(W)
           adstar_acc(o + 6, gW, gLdV, 1.f);  // ad*_W(LdV)
+          break;
+        }
+        case PROG_DEF_FWD: {  // g: Phi, V
+          float jP[9], gV[3];
+          get_jac(a.g[0], jP);
+          get_val(a.g[1], gV);
+          jac_acc(o, jP, gV);
+          break;
+        }
+        case PROG_DEF_H: {  // g: dPhi, V, Phi, dV
+          float jdP[9], gV[3], jP[9], gdV[3];
+          get_jac(a.g[0], jdP);
+          get_val(a.g[1], gV);
+          get_jac(a.g[2], jP);
+          get_val(a.g[3], gdV);
+          jac_acc(o, jdP, gV);
+          jac_acc(o, jP, gdV);
+          break;
+        }
+        case PROG_DEF_TAIL: {  // g: A, R
+          float jA[9], gR[3];
+          get_jac(a.g[0], jA);
+          get_val(a.g[1], gR);
+          jact_acc(o, jA, gR);
+          break;
+        }
+        case PROG_DEF_HTAIL: {  // g: dPhi, dR, Phi, R
+          float jdP[9], gdR[3], jP[9], gR[3];
+          get_jac(a.g[0], jdP);
+          get_val(a.g[1], gdR);
+          get_jac(a.g[2], jP);
+          get_val(a.g[3], gR);
+          jact_acc(o, jdP, gR);
+          jact_acc(o, jP, gdR);
           break;
         }
         default:
@@ -1407,6 +1465,134 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
   }
 }
 
+// ------------- deformation-state image term and forward stage 2 (N grid)
+// Central differences of I0 at every node: G_a = d_a I0 and, when H is set,
+// H = (d0d0, d0d1, d0d2, d1d1, d1d2, d2d2) I0 (the same central difference
+// applied twice; per unit length).
+template <class G>
+__global__ void __launch_bounds__(256) k_image_derivs(const float* __restrict__ I0, float* __restrict__ Gr,
+                                                      float* __restrict__ H, G gs) {
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2();
+  const long long nN = (long long)N0 * N1 * N2;
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= nN) return;
+  const int x2 = (int)(gi % N2), x1 = (int)((gi / N2) % N1), x0 = (int)(gi / ((long long)N1 * N2));
+  const int n[3] = {N0, N1, N2}, x[3] = {x0, x1, x2};
+  auto at = [&](int d0, int d1, int d2) {
+    int i = x0 + d0, j = x1 + d1, k = x2 + d2;
+    i = (i % N0 + N0) % N0;
+    j = (j % N1 + N1) % N1;
+    k = (k % N2 + N2) % N2;
+    return I0[((long long)i * N1 + j) * N2 + k];
+  };
+  (void)x;
+  Gr[gi] = (at(1, 0, 0) - at(-1, 0, 0)) * (0.5f * N0);
+  Gr[nN + gi] = (at(0, 1, 0) - at(0, -1, 0)) * (0.5f * N1);
+  Gr[2 * nN + gi] = (at(0, 0, 1) - at(0, 0, -1)) * (0.5f * N2);
+  if (!H) return;
+  const float c = at(0, 0, 0);
+  H[gi] = (at(2, 0, 0) - 2.f * c + at(-2, 0, 0)) * (0.25f * n[0] * n[0]);
+  H[nN + gi] = (at(1, 1, 0) - at(1, -1, 0) - at(-1, 1, 0) + at(-1, -1, 0)) * (0.25f * n[0] * n[1]);
+  H[2 * nN + gi] = (at(1, 0, 1) - at(1, 0, -1) - at(-1, 0, 1) + at(-1, 0, -1)) * (0.25f * n[0] * n[2]);
+  H[3 * nN + gi] = (at(0, 2, 0) - 2.f * c + at(0, -2, 0)) * (0.25f * n[1] * n[1]);
+  H[4 * nN + gi] = (at(0, 1, 1) - at(0, 1, -1) - at(0, -1, 1) + at(0, -1, -1)) * (0.25f * n[1] * n[2]);
+  H[5 * nN + gi] = (at(0, 0, 2) - 2.f * c + at(0, 0, -2)) * (0.25f * n[2] * n[2]);
+}
+
+// At phi(x) = x + u(x) (voxel coordinates x_j + N_j u_j) the periodic
+// trilinear interpolation of I0, of its central-difference gradient G and
+// (full Newton) of its central-difference Hessian H gives m, g and h.
+// op 0: s_j = coef (m - I1) g_j.  op 1: s_j = coef (g . du) g_j
+// [+ coef res (h du)_j when res is set].  Then forward stage 2 of the three
+// sources like k_src_fwd2.
+template <class G>
+__global__ void __launch_bounds__(256) k_rho_fwd2(RhoArgs a, float2* __restrict__ s1, Twiddles tw, G gs) {
+  extern __shared__ float shs[];
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2(), Kh = gs.Kh();
+  const long long nN = (long long)N0 * N1 * N2;
+  constexpr int R = kGridRows;
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, N1 - x1b);
+  const int P = R * N2;
+  float* vals = shs;                                   // [3][R][N2]
+  float2* wfx = (float2*)(vals + ((3 * P + 3) & ~3));  // [N2][Kh]
+  batched_fill<float2>(Kh * N2, [&](int i) {
+    int x2 = i / Kh, kh = i % Kh;
+    return tw.fwd2[(size_t)kh * N2 + x2];
+  }, [&](int i, float2 v) { wfx[i] = v; });
+  for (int p = threadIdx.x; p < R * N2; p += blockDim.x) {
+    const int r = p / N2, x2 = p % N2;
+    const int x1 = x1b + r;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (r < rv) {
+      const long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+      float X0 = (float)x0 + a.u[gi] * (float)N0;
+      float X1 = (float)x1 + a.u[nN + gi] * (float)N1;
+      float X2 = (float)x2 + a.u[2 * nN + gi] * (float)N2;
+      // a non-finite displacement must not turn into an out-of-range index
+      if (!isfinite(X0)) X0 = (float)x0;
+      if (!isfinite(X1)) X1 = (float)x1;
+      if (!isfinite(X2)) X2 = (float)x2;
+      const float f0 = floorf(X0), f1 = floorf(X1), f2 = floorf(X2);
+      const float w0 = X0 - f0, w1 = X1 - f1, w2 = X2 - f2;
+      int a0 = (int)f0 % N0; if (a0 < 0) a0 += N0;
+      int a1 = (int)f1 % N1; if (a1 < 0) a1 += N1;
+      int a2 = (int)f2 % N2; if (a2 < 0) a2 += N2;
+      const int b0 = (a0 + 1 == N0) ? 0 : a0 + 1;
+      const int b1 = (a1 + 1 == N1) ? 0 : a1 + 1;
+      const int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
+      const long long r00 = ((long long)a0 * N1 + a1) * N2, r01 = ((long long)a0 * N1 + b1) * N2;
+      const long long r10 = ((long long)b0 * N1 + a1) * N2, r11 = ((long long)b0 * N1 + b1) * N2;
+      auto interp = [&](const float* f) {
+        const float c00 = f[r00 + a2] + w2 * (f[r00 + b2] - f[r00 + a2]);
+        const float c01 = f[r01 + a2] + w2 * (f[r01 + b2] - f[r01 + a2]);
+        const float c10 = f[r10 + a2] + w2 * (f[r10 + b2] - f[r10 + a2]);
+        const float c11 = f[r11 + a2] + w2 * (f[r11 + b2] - f[r11 + a2]);
+        const float c0 = c00 + w1 * (c01 - c00);
+        const float c1 = c10 + w1 * (c11 - c10);
+        return c0 + w0 * (c1 - c0);
+      };
+      const float g0 = interp(a.G), g1 = interp(a.G + nN), g2 = interp(a.G + 2 * nN);
+      if (a.op == 0) {
+        const float l = a.coef * (interp(a.I0) - a.I1[gi]);
+        v0 = l * g0;
+        v1 = l * g1;
+        v2 = l * g2;
+      } else {
+        const float du0 = a.du[gi], du1 = a.du[nN + gi], du2 = a.du[2 * nN + gi];
+        const float l = a.coef * (g0 * du0 + g1 * du1 + g2 * du2);
+        v0 = l * g0;
+        v1 = l * g1;
+        v2 = l * g2;
+        if (a.res) {
+          const float h00 = interp(a.H), h01 = interp(a.H + nN), h02 = interp(a.H + 2 * nN);
+          const float h11 = interp(a.H + 3 * nN), h12 = interp(a.H + 4 * nN), h22 = interp(a.H + 5 * nN);
+          const float t = a.coef * a.res[gi];
+          v0 = fmaf(t, h00 * du0 + h01 * du1 + h02 * du2, v0);
+          v1 = fmaf(t, h01 * du0 + h11 * du1 + h12 * du2, v1);
+          v2 = fmaf(t, h02 * du0 + h12 * du1 + h22 * du2, v2);
+        }
+      }
+    }
+    vals[p] = v0;
+    vals[P + p] = v1;
+    vals[2 * P + p] = v2;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * rv * Kh; i += blockDim.x) {
+    int j = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
+    const float* row = vals + (size_t)j * P + r * N2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x2 = 0; x2 < N2; ++x2) {
+      float2 w = wfx[(size_t)x2 * Kh + kh];
+      acc.x = fmaf(row[x2], w.x, acc.x);
+      acc.y = fmaf(row[x2], w.y, acc.y);
+    }
+    s1[(((size_t)j * N0 + x0) * N1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
 // ------------------------------------------------- fused t = 1 tail (tuned)
 // k_srcfwd: one block per (64-row chunk of x1, x0 plane), four waves, in
 // sub-chunks of 32 rows: the source s_j = coef [(a - b) d_j m + res d_j a]
@@ -2000,12 +2186,13 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
   a.w1a = tables;
   a.w2b = tables + 2 * (size_t)M1p * 2 * d.K[1];
   const double nM = (double)d.nM;
-  timer_work(KF_SYNTH, 6.0 * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0),
-             6.0 * (2.0 * d.M[0] * d.K[1] * d.Kh * 8.0 + 4.0 * nM * 4.0));
+  const int nf = t1g1 ? 6 : 3;  // new fields (group, component)
+  timer_work(KF_SYNTH, nf * (3.0 * d.M[0] * d.M[1] * d.Kh * d.K[1] * 8.0 + 4.0 * nM * d.Kh * 4.0),
+             nf * (2.0 * d.M[0] * d.K[1] * d.Kh * 8.0 + 4.0 * nM * 4.0));
   (void)Khp;
   (void)M2p;
   hipError_t e = with_band(d, [&](auto sh) {
-    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], 6, M1p / 16), dim3(256), synth_shared_bytes(d), st,
+    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], nf, M1p / 16), dim3(256), synth_shared_bytes(d), st,
                  a, sh);
     return hipGetLastError();
   });
@@ -2028,11 +2215,11 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
   dim3 grid(nblk(d.M[1], R), d.M[0]);
   size_t shm = prods_shared_bytes(d, a.nout);
   {
-    static const double prog_flops[6] = {0, 47, 94, 136, 272, 136};
-    static const int prog_groups[6] = {0, 2, 4, 4, 8, 4};
+    static const double prog_flops[10] = {0, 47, 94, 136, 272, 136, 18, 36, 18, 36};
+    static const int prog_fields[10] = {0, 24, 48, 48, 96, 48, 12, 24, 12, 24};
     const double nM = (double)d.nM;
     double fl = prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
-    double by = prog_groups[a.prog] * 12.0 * nM * 4.0 + a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
+    double by = prog_fields[a.prog] * nM * 4.0 + a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
     timer_work(KF_PRODS, fl, by);
   }
   int threads = ((R * d.M[2] + 63) / 64) * 64;
@@ -2232,6 +2419,33 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const
   }
   hipError_t e = with_grid(d, [&](auto gs) {
     LAUNCH_TIMED(KF_SRC, (k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, r, m, coef, s1, tw, gs);
+    return hipGetLastError();
+  });
+  return e;
+}
+
+hipError_t launch_image_derivs(const float* I0, float* G, float* H, const Dims& d, hipStream_t st) {
+  return with_grid(d, [&](auto gs) {
+    hipLaunchKernelGGL((k_image_derivs<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, I0, G, H, gs);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_rho_fwd2(const RhoArgs& a, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st) {
+  dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
+  size_t shm = src_shared_bytes(d);
+  {
+    // trilinear interpolation of 4 (op 0), 3 or 9 (op 1) fields, the source,
+    // forward stage 2 of 3 fields; point reads u (3) and I1 | du (3), res
+    const double nN = (double)d.nN;
+    const bool full = a.op == 1 && a.res;
+    const double nf = a.op == 0 ? 4.0 : (full ? 9.0 : 3.0);
+    const double rd = a.op == 0 ? 4.0 : (full ? 7.0 : 6.0);
+    timer_work(KF_SRC, 3.0 * nN * d.Kh * 4.0 + (nf * 14.0 + (full ? 30.0 : 12.0)) * nN,
+               (nf + rd) * 4.0 * nN + 3.0 * d.N[0] * (double)d.N[1] * d.Kh * 8.0);
+  }
+  hipError_t e = with_grid(d, [&](auto gs) {
+    LAUNCH_TIMED(KF_SRC, (k_rho_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, s1, tw, gs);
     return hipGetLastError();
   });
   return e;

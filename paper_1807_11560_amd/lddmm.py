@@ -36,6 +36,8 @@ FP32 = 0
 GN_PAPER = 0
 GN_CLASSICAL = 1
 NEWTON = 2
+STATE_IMAGE = 0
+STATE_DEFORMATION = 1
 KF_SYNTH, KF_GRID, KF_SL, KF_INV0, KF_COLUMN, KF_PRODS = 1, 2, 3, 4, 5, 6
 KF_INV0_GRID, KF_FWD1_GRID, KF_FWD0_GRID, KF_SRC = 7, 8, 9, 10
 KERNEL_FAMILIES = {KF_SYNTH: "k_synth", KF_GRID: "k_gridstep", KF_SL: "k_sl", KF_INV0: "k_inv0 (padded grid)",
@@ -55,6 +57,7 @@ class LddmmParams(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("hessian", ctypes.c_int32),
+        ("state", ctypes.c_int32),
     ]
 
 
@@ -124,6 +127,7 @@ class Problem:
     sigma: float = 0.03
     spectral: Tuple[int, int, int] = (0, 0, 0)
     hessian: int = GN_PAPER
+    state: int = STATE_IMAGE
 
     def c_params(self) -> LddmmParams:
         p = LddmmParams()
@@ -138,6 +142,7 @@ class Problem:
         p.sigma = float(self.sigma)
         p.precision = FP32
         p.hessian = int(self.hessian)
+        p.state = int(self.state)
         return p
 
     def workspace_bytes(self) -> int:

@@ -86,6 +86,35 @@ def test_register_matches_oracle(reg_case):
     assert stats[-1]["energy"] < stats[0]["energy"]
 
 
+@pytest.mark.parametrize("mode", ["R1", "FULL"])
+def test_register_deformation_state_matches_oracle(mode):
+    """The Gauss-Newton-Krylov loop subject to the deformation state equation
+    (paper §3.3) against the oracle's, per iteration."""
+    from oracle import deformation
+    c = CASES["aniso"]
+    w = synth.workload(2, grid=c["grid"], band=c["band"])
+    p = Params(grid=c["grid"], band=c["band"], nt=c["nt"], alpha=synth.ALPHA, s=c["s"], sigma=synth.SIGMA)
+    vstar = synth.scale_to_displacement(w["v_star"], c["grid"], c["dmax"])
+    I0 = w["I0"]
+    I1 = deformation.forward(vstar, I0, p)[2]
+    v_ref, st_ref, status_ref = register(I0, I1, p, c["gn"], c["pcg"], mode=mode, state="deformation")
+    prob = L().Problem(grid=c["grid"], band=c["band"], time_steps=c["nt"], alpha=synth.ALPHA, s=c["s"],
+                       sigma=synth.SIGMA, hessian=L().GN_PAPER if mode == "R1" else L().NEWTON,
+                       state=L().STATE_DEFORMATION)
+    v, stats, rc, hvps = run_gpu(prob, I0, I1, c)
+    assert rc == status_ref and len(stats) == len(st_ref)
+    for k, (a, b) in enumerate(zip(stats, st_ref)):
+        print(f"deformation {mode} GN {k}: E {a['energy']:.6f}/{b['E']:.6f} mse {a['mse_rel']:.4f}/"
+              f"{b['mse_rel']:.4f} pcg {a['pcg_iters']}/{b['pcg_iters']} guard {a['pcg_guard']}/{b['pcg_guard']} "
+              f"eps {a['step']}/{b['eps']}")
+        assert abs(a["energy"] - b["E"]) <= 1e-4 * abs(b["E"])
+        assert abs(a["mse_rel"] - b["mse_rel"]) <= 1e-4 * abs(b["mse_rel"])
+        assert a["pcg_iters"] == b["pcg_iters"] and bool(a["pcg_guard"]) == bool(b["pcg_guard"])
+        assert a["step"] == b["eps"] and a["trials"] == b["trials"]
+    assert rel(v, v_ref) < 1e-3
+    assert stats[-1]["energy"] < stats[0]["energy"]
+
+
 def test_register_full_newton_matches_oracle():
     """The Newton-Krylov loop with the full Newton product (curvature guard
     in CG) against the oracle's mode FULL, per iteration."""
