@@ -14,6 +14,7 @@ Prints one JSON line on stdout (everything else goes to stderr).
 """
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -192,6 +193,47 @@ def main():
         torch.cuda.synchronize()
         hvp_only = args.hvp_loop / (time.perf_counter() - t1)
 
+    # the deformation-state variant (paper §3.3) on the same images: K timed
+    # registrations and the pure Hessian-vector product rate
+    prob_d = dataclasses.replace(prob, state=L.STATE_DEFORMATION)
+    ws_d = L.Workspace(prob_d, dev)
+
+    def registration_d():
+        return L.register(prob_d, I0, I1, ws_d, gn_iters=gn, pcg_iters=pcg)
+
+    for _ in range(args.warmup):
+        registration_d()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hvps_d = 0
+    for _ in range(args.steps):
+        v_d, stats_d, rc_d, n = registration_d()
+        hvps_d += n
+    torch.cuda.synchronize()
+    T_d = time.perf_counter() - t0
+    hvp_only_d = None
+    if args.hvp_loop > 0:
+        L.gradient(prob_d, I0, I1, v_d, ws_d)
+        d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
+        out = torch.empty_like(d)
+        for _ in range(3):
+            L.hessvec(prob_d, d, ws_d, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.hvp_loop):
+            L.hessvec(prob_d, d, ws_d, out=out)
+        torch.cuda.synchronize()
+        hvp_only_d = args.hvp_loop / (time.perf_counter() - t1)
+    log(f"deformation state: {args.steps} registrations in {T_d:.3f} s, {hvps_d} HVPs, status {rc_d}, "
+        f"final MSE_rel {stats_d[-1]['mse_rel']:.3f}")
+    variant_d = {
+        "value": hvps_d / T_d, "unit": "HVP/s", "ms_per_step": 1e3 * T_d / args.steps,
+        "registrations_per_min": 60.0 * args.steps / T_d, "hvps_per_registration": hvps_d / args.steps,
+        "hvp_only_per_s": hvp_only_d, "final_mse_rel": stats_d[-1]["mse_rel"],
+        "workspace_mib": ws_d.nbytes / 2**20,
+    }
+    del ws_d
+
     # plain copy of known size: the calibration for the FETCH_SIZE / WRITE_SIZE counters
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
@@ -231,6 +273,8 @@ def main():
         "value_without_timer_events": hvps_u / T_u,
         "hvp_only_per_s": hvp_only,
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
+        "workspace_mib": ws.nbytes / 2**20,
+        "variants": {"deformation_state": variant_d},
         "roofline": roofline(dominant, name, launches, kms, kfl, kby, stored_traffic(name)),
         "cpu_baseline": cpu,
     }

@@ -101,19 +101,20 @@ typedef struct lddmm_params {
                              (D~u * v)_i = sum_j (d_j u_i) * v_j (truncated products),
                              m(1)(x) = I0(x + iota(u_nt)(x)) (periodic trilinear interpolation),
                            gradient: U(1) = K~(D~phi(1) * rho~), rho~ = pi(lambda(1)
-                           (grad I0)(phi(1))), (D~phi * r)_j = r_j + sum_i (d_j u_i) * r_i,
-                           with (grad I0) the gradient of the trilinear interpolant; the
-                           adjoint sweeps are those of §3.2.  Hessian-vector product: the
+                           (grad I0)(phi(1))), (D~phi * r)_j = r_j + sum_i (d_j u_i) * r_i;
+                           the adjoint sweeps are those of §3.2.  Hessian-vector product: the
                            incremental deformation du_{n+1} = du_n - dt [D~du_n * v_n + dv_n
                            + D~u_n * dv_n], dm(1) = (grad I0)(phi(1)) . iota(du_nt) and
-                           dU(1) = K~(D~du_nt * rho~ + D~phi(1) * pi(dlambda(1) (grad I0)(phi(1))
-                           [+ lambda(1) (Hess I0)(phi(1)) iota(du_nt)])), where
-                           LDDMM_GN_CLASSICAL drops D~du_nt * rho~ and the coupling terms,
-                           LDDMM_GN_PAPER drops the bracket, LDDMM_NEWTON keeps everything
-                           ((Hess I0): the interpolant's mixed second derivatives).  The plus
-                           signs are the derivative of U(1) (the paper prints a minus before
-                           D~phi(1) * drho~(1)).  No per-step image or grid velocity is kept,
-                           so the workspace is smaller. */
+                           dU(1) = K~([D~du_nt * rho~] + D~phi(1) * pi(dlambda(1)
+                           (grad I0)(phi(1)) [+ lambda(1) (Hess I0)(phi(1)) iota(du_nt)])).
+                           LDDMM_GN_PAPER drops both bracketed terms (the residual times a
+                           derivative of the increment, like lambda(1) grad dm(1) of the image
+                           state) and keeps the coupling terms, LDDMM_GN_CLASSICAL also drops
+                           the coupling terms, LDDMM_NEWTON keeps everything.  grad I0 and
+                           Hess I0 are the periodic central differences of I0, interpolated
+                           trilinearly at phi(1).  The plus signs are the derivative of U(1)
+                           (the paper prints a minus before D~phi(1) * drho~(1)).  No per-step
+                           image or grid velocity is kept, so the workspace is smaller. */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */

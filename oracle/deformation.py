@@ -27,7 +27,7 @@ paper's order:
              dlambda_1 = -(2/sigma^2) dm(1),
              drho(1) = dlambda_1 (grad I0)(phi(1))
                        [+ lambda_1 (Hess I0)(phi(1)) iota(du_nt)],
-             dU_nt = K~ (D~du_nt * rho~ + D~phi(1) * pi(drho(1))),
+             dU_nt = K~ ([D~du_nt * rho~] + D~phi(1) * pi(drho(1))),
                (D~du * r)_j = sum_i (d_j du_i) * r_i,
              then the incremental adjoint Jacobi sweep of §3.2;
              H_V dv_0 = dv_0 + dw_0.
@@ -60,12 +60,17 @@ Readings:
     derivative of U(1) has a plus, which is taken; a test pins it (at zero
     residual the classical Gauss-Newton product equals the central
     difference of the gradient).
-  * Gauss-Newton (§2.7), as for §3.2: mode "R1" drops only the
-    lambda_1 (Hess I0) term of drho(1) and keeps D~du * rho~ and every
-    coupling term; "R2" also drops the terms that carry rho or the adjoint
-    fields (D~du * rho~ and the coupling terms of the sweep); "FULL" keeps
-    every term and is the derivative of the discrete gradient (away from
-    cell faces of the interpolant).
+  * Gauss-Newton (§2.7), as for §3.2, where the paper's reading drops the
+    term lambda_1 grad(dm_1) of dU(1), the residual times a derivative of the
+    increment: mode "R1" drops both such terms of dU(1) here, D~du * rho~
+    (rho carries lambda_1) and lambda_1 (Hess I0) iota(du), and keeps every
+    coupling term of the sweep; "R2" also drops the coupling terms; "FULL"
+    keeps every term and is the derivative of the discrete gradient (away
+    from cell faces of the interpolant).  Keeping D~du * rho~ without the
+    Hessian term, as the printed dU(1) does, gives a product that is
+    indefinite far from the minimum (the CG curvature guard stops the first
+    Gauss-Newton iteration of a 32^3 registration and it converges several
+    times slower).
 """
 
 import itertools
@@ -215,6 +220,6 @@ def hessvec(cache, dv0, p, mode="R1"):
         src = src + cache["lam1"] * np.einsum("ab...,b...->a...", cache["hI"], dug)
     drho = pi_vec(src, p.band)
     dU = drho + jac_t_star(us[-1], drho, p.spectral)
-    if mode != "R2":
+    if mode == "FULL":
         dU = dU + jac_t_star(du, cache["rho"], p.spectral)
     return dv0 + incremental_backward(vs, dvs, Us, ws, Ksym * dU, p, mode)

@@ -741,9 +741,9 @@ hipError_t Engine::hessvec_def(const float2* dvh, float2* out) {
   TRY(inv0_group(dR, 3, 0, aux_));
   TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
-  // dU_nt = K~ drho~ + K~ ((D~u_nt)^T * drho~ [+ (D~du_nt)^T * rho~])
+  // dU_nt = K~ drho~ + K~ ((D~u_nt)^T * drho~ [+ (D~du_nt)^T * rho~, full Newton])
   TRY(launch_fill(reinterpret_cast<float*>(dW[0]), 6LL * d_.nb, 0.f, st_));
-  if (d_.hessian == 1) {
+  if (d_.hessian != 2) {
     TRY(launch_synth(t1(3, 0), nullptr, NGA_, nullptr, synth_tab_, d_, st_));
     const float* g[2] = {PG[nt], NGA_};
     TRY(def_head(PROG_DEF_TAIL, g, 2, KdR, dU[0]));

@@ -117,7 +117,8 @@ def _check(code, where):
 
 @dataclass(frozen=True)
 class Problem:
-    """Parameters of one registration problem (paper §3.2 problem statement)."""
+    """Parameters of one registration problem (paper §3.2 problem statement;
+    ``state`` selects the image state of §3.2 or the deformation state of §3.3)."""
 
     grid: Tuple[int, int, int]
     band: Tuple[int, int, int]

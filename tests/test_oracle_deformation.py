@@ -244,6 +244,16 @@ def test_central_sampling_products_are_close_to_the_derivative():
     assert ez < 0.15
 
 
+def test_gauss_newton_modes_differ_by_the_coupling_terms_only():
+    """R1 - R2 is the coupling part of the incremental sweep: with U = w = 0
+    substituted into the cache the two modes agree."""
+    p, I0, I1, vstar = problem()
+    d = synth.random_direction(9, p.band)
+    _, _, cache = D.gradient(0.5 * vstar, I0, I1, p)
+    zeroed = dict(cache, Us=[np.zeros_like(u) for u in cache["Us"]], ws=[np.zeros_like(u) for u in cache["ws"]])
+    assert np.allclose(D.hessvec(zeroed, d, p, "R1"), D.hessvec(zeroed, d, p, "R2"), atol=1e-12, rtol=0)
+
+
 def test_modes_agree_only_at_zero_residual():
     p, I0, I1, vstar = problem()
     d = synth.random_direction(9, p.band)
