@@ -10,6 +10,9 @@ iterations, each with the gradient, 20 CG iterations (one Hessian-vector
 product each) and the Armijo line search.  Inputs are resident in HBM before
 the timed region.
 
+``--state deformation`` registers the same images subject to the deformation
+state equation (paper §3.3) instead of the image state (paper §3.2).
+
 Prints one JSON line on stdout (everything else goes to stderr).
 """
 
@@ -44,6 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--state", choices=("image", "deformation"), default="image",
+                    help="constraint of the registered problem: the image state (paper §3.2, the "
+                         "default) or the deformation state (paper §3.3)")
     ap.add_argument("--hvp-loop", type=int, default=50, help="extra pure hessvec calls timed")
     return ap.parse_args()
 
@@ -83,12 +89,16 @@ def stored_traffic(kernel_name):
     return None
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, state="image"):
     """The FP64 oracle on the host: one Hessian-vector product of the same
     problem at v0 = v*/2, after an untimed oracle gradient."""
     from oracle import Params
-    from oracle.jacobi import forward, gradient, hessvec
+    from oracle.jacobi import forward
     from paper_1807_11560_amd import synth
+    if state == "image":
+        from oracle.jacobi import gradient, hessvec
+    else:
+        from oracle.deformation import gradient, hessvec
     try:
         import threadpoolctl
         cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) or os.cpu_count()
@@ -104,8 +114,8 @@ def cpu_baseline(w):
     hessvec(cache, d, p, "R1")
     t = time.perf_counter() - t0
     return {"value": 1.0 / t, "unit": "HVP/s", "cores": int(cores), "kind": "oracle",
-            "sample": "one Hessian-vector product of the 128^3 / band 32^3 problem at v0 = v*/2 "
-                      "(FP64 NumPy, after an untimed oracle gradient)",
+            "sample": f"one Hessian-vector product of the 128^3 / band 32^3 problem ({state} state) "
+                      "at v0 = v*/2 (FP64 NumPy, after an untimed oracle gradient)",
             "seconds": t}
 
 
@@ -123,14 +133,16 @@ def main():
 
     w = synth.workload(CONFIG)
     pp = w["params"]
-    prob = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
-                     sigma=pp["sigma"], hessian=L.GN_PAPER)
+    # the target is the phantom warped by the image-state model in both cases
+    prob_img = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
+                         sigma=pp["sigma"], hessian=L.GN_PAPER)
+    prob = dataclasses.replace(prob_img, state=L.STATE_IMAGE if args.state == "image" else L.STATE_DEFORMATION)
     gn, pcg = pp["gn"], pp["pcg"]
     dev = torch.device("cuda:0")
     ws = L.Workspace(prob, dev)
     I0 = torch.from_numpy(w["I0"]).float().to(dev)
     vstar = torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev)
-    I1 = L.shoot(prob, I0, vstar, ws)
+    I1 = L.shoot(prob_img, I0, vstar, L.Workspace(prob_img, dev) if args.state != "image" else ws)
     torch.cuda.synchronize()
     log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
 
@@ -193,47 +205,6 @@ def main():
         torch.cuda.synchronize()
         hvp_only = args.hvp_loop / (time.perf_counter() - t1)
 
-    # the deformation-state variant (paper §3.3) on the same images: K timed
-    # registrations and the pure Hessian-vector product rate
-    prob_d = dataclasses.replace(prob, state=L.STATE_DEFORMATION)
-    ws_d = L.Workspace(prob_d, dev)
-
-    def registration_d():
-        return L.register(prob_d, I0, I1, ws_d, gn_iters=gn, pcg_iters=pcg)
-
-    for _ in range(args.warmup):
-        registration_d()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hvps_d = 0
-    for _ in range(args.steps):
-        v_d, stats_d, rc_d, n = registration_d()
-        hvps_d += n
-    torch.cuda.synchronize()
-    T_d = time.perf_counter() - t0
-    hvp_only_d = None
-    if args.hvp_loop > 0:
-        L.gradient(prob_d, I0, I1, v_d, ws_d)
-        d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
-        out = torch.empty_like(d)
-        for _ in range(3):
-            L.hessvec(prob_d, d, ws_d, out=out)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.hvp_loop):
-            L.hessvec(prob_d, d, ws_d, out=out)
-        torch.cuda.synchronize()
-        hvp_only_d = args.hvp_loop / (time.perf_counter() - t1)
-    log(f"deformation state: {args.steps} registrations in {T_d:.3f} s, {hvps_d} HVPs, status {rc_d}, "
-        f"final MSE_rel {stats_d[-1]['mse_rel']:.3f}")
-    variant_d = {
-        "value": hvps_d / T_d, "unit": "HVP/s", "ms_per_step": 1e3 * T_d / args.steps,
-        "registrations_per_min": 60.0 * args.steps / T_d, "hvps_per_registration": hvps_d / args.steps,
-        "hvp_only_per_s": hvp_only_d, "final_mse_rel": stats_d[-1]["mse_rel"],
-        "workspace_mib": ws_d.nbytes / 2**20,
-    }
-    del ws_d
-
     # plain copy of known size: the calibration for the FETCH_SIZE / WRITE_SIZE counters
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
@@ -244,7 +215,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, args.state)
         log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
 
     name = L.KERNEL_FAMILIES[dominant]
@@ -264,7 +235,9 @@ def main():
         "config": {
             "workload": "tissue phantom 128^3 registered to its warp by a random band-limited geodesic "
                         "(8 voxels), band 32^3, padded grid 48^3, s=3, alpha=0.0025, sigma=0.03, nt=10, "
-                        "10 Gauss-Newton x 20 CG iterations, paper Gauss-Newton reading",
+                        "10 Gauss-Newton x 20 CG iterations, paper Gauss-Newton reading"
+                        + ("" if args.state == "image" else ", subject to the deformation state equation"),
+            "state": args.state,
             "grid": list(prob.grid), "band": list(prob.band), "time_steps": prob.time_steps,
             "gn_iters": gn, "pcg_iters": pcg,
         },
@@ -274,7 +247,6 @@ def main():
         "hvp_only_per_s": hvp_only,
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
         "workspace_mib": ws.nbytes / 2**20,
-        "variants": {"deformation_state": variant_d},
         "roofline": roofline(dominant, name, launches, kms, kfl, kby, stored_traffic(name)),
         "cpu_baseline": cpu,
     }
