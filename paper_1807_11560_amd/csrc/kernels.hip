@@ -878,8 +878,12 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
   }
 }
 
-// One block per (kh, job, 16-wide tile of k1), four waves; same contract as
-// k_colstep: every phase after the stage-1 input is separable along k1.  All
+// One block per (kh, job, 16-wide tile of k1, part), four waves; same contract
+// as k_colstep: every phase after the stage-1 input is separable along k1.
+// With nparts > 1 the blocks of one tile all form the band update (only part
+// 0 stores it) and split the output tiles of the next inverse stage 0 between
+// them in contiguous ranges, which multiplies the blocks of launches that
+// would leave most compute units idle.  All
 // global loads of the block (the stage-1 input, the twiddle tables, the
 // image-grid stage-0 table and the band values of the update) are issued at
 // the start, two complex values per load; the image-grid table waits in
@@ -890,7 +894,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
                                                       const float2* __restrict__ w0f,
                                                       const float2* __restrict__ w0i,
                                                       const float* __restrict__ Lsym,
-                                                      const float* __restrict__ Ksym, float invG) {
+                                                      const float* __restrict__ Ksym, float invG,
+                                                      int nparts) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
   // A operands (read along rows) get odd complex strides, B operands 18
@@ -907,12 +912,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   float2* g0s = &s1[0][0][0];           // [N0][LG] image-grid stage-0 table, after stage 1'
   const ColJob& job = jobs.j[blockIdx.y];
   const int kh = blockIdx.x;
-  const int kc = blockIdx.z * 16;       // first k1 of the tile
+  constexpr int T0 = Kp / 16;
+  const int kc = (blockIdx.z % T0) * 16;  // first k1 of the tile
+  const int part = blockIdx.z / T0;
   const int nterm = job.b ? 2 : 1;
   const bool grid0 = job.t1n != nullptr;
   const int N0 = jobs.N0;
+  // this part's range [jb0, jb1) of the next-stage output tiles: padded-grid
+  // tiles first, then the image-grid ones
+  constexpr int TIR = Mp / 16;
+  const int njb = job.nt1 * 2 * TIR;
+  const int ngb = grid0 ? N0 / 16 : 0;
+  const int jb0 = (njb + ngb) * part / nparts, jb1 = (njb + ngb) * (part + 1) / nparts;
+  const bool my_grid0 = grid0 && jb1 > njb;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  constexpr int T0 = Kp / 16;
   const int k1 = kc + li;
 
   // ---- loads
@@ -933,7 +946,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
   rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
   rw0i.load(2 * Mp * KH2, [&](int i) { return ld4(w0i + 2 * i); });
-  const int ng = grid0 ? N0 * KH2 : 0;
+  const int ng = my_grid0 ? N0 * KH2 : 0;
   rg.load(ng, [&](int i) { return ld4(jobs.w0n + 2 * i); });
   // band values of the update at (k0 = 16 wave + 4 lk + r, k1)
   float2 pbase[4], pextra[4];
@@ -1003,19 +1016,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
         res.x = fmaf(job.ce, pextra[r].x, res.x);
         res.y = fmaf(job.ce, pextra[r].y, res.y);
       }
-      job.out[idx] = res;
+      if (part == 0) job.out[idx] = res;
       ob[0][k0][li] = res;
       ob[1][k0][li] = make_float2(pls[r] * res.x, pls[r] * res.y);
     }
   }
-  if (job.nt1 == 0 && !grid0) return;
+  if (jb0 == jb1) return;
   __syncthreads();
   // next inverse stage 0 on the padded grid: t1[v][x0][kh][k1] = sum_k0 w0i[v][x0][k0] ob[L][k0][k1],
   // then on the image grid: t1n[x0][kh][k1] = sum_k0 w0n[x0][k0] ob[0][k0][k1]
-  constexpr int TIR = Mp / 16;
-  const int njb = job.nt1 * 2 * TIR;
-  const int ngb = grid0 ? N0 / 16 : 0;
-  for (int jb = wave; jb < njb + ngb; jb += 4) {
+  for (int jb = jb0 + wave; jb < jb1; jb += 4) {
     floatx4 acc[4];
     zero_acc(acc, 4);
     if (jb >= njb) {
@@ -2298,17 +2308,29 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   const float2* w0f = w1t + (size_t)M * round_up(K, 16);
   const float2* w0i = w0f + (size_t)round_up(K, 16) * M;
   hipError_t e;
+  // split the next-stage tiles over two blocks per column tile when the
+  // launch would otherwise fill fewer than half of the compute units and
+  // every job has at least 8 such tiles
+  const int ktiles = round_up(d.K[0], 16) / 16;
+  int min_tiles = 1 << 30;
+  for (int i = 0; i < njobs; ++i) {
+    const ColJob& j = jobs.j[i];
+    const int t = j.nt1 * 2 * (round_up(d.M[0], 16) / 16) + (j.t1n ? d.N[0] / 16 : 0);
+    min_tiles = t < min_tiles ? t : min_tiles;
+  }
+  const int nparts = (d.Kh * njobs * ktiles <= 128 && min_tiles >= 8) ? 2 : 1;
+  const dim3 cgrid(d.Kh, njobs, ktiles * nparts);
   if (band_iso(d, 32, 48)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
-                       w0i, Lsym, Ksym, invG);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
+                 Ksym, invG, nparts);
     e = hipGetLastError();
   } else if (band_iso(d, 16, 24)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
-                       w0i, Lsym, Ksym, invG);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
+                 Ksym, invG, nparts);
     e = hipGetLastError();
   } else if (band_iso(d, 24, 36)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), dim3(d.Kh, njobs, round_up(d.K[0], 16) / 16), dim3(256), 0, st, jobs, w1t, w0f,
-                       w0i, Lsym, Ksym, invG);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
+                 Ksym, invG, nparts);
     e = hipGetLastError();
   } else {
     dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
