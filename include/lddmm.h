@@ -193,9 +193,39 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
                    int32_t gn_iters, int32_t pcg_iters, lddmm_stats* stats, int32_t stats_len,
                    void* ws, size_t ws_bytes, void* stream);
 
-/* Number of Hessian-vector products the last lddmm_register on this thread
- * evaluated (host only). */
+/* Number of Hessian-vector products the last lddmm_register (or, summed over
+ * its pairs, lddmm_register_batch) on this thread evaluated (host only). */
 int64_t lddmm_last_register_hvps(void);
+
+/* Bytes of device workspace for lddmm_register_batch on these n parameter
+ * sets: the sum over pairs of lddmm_workspace_bytes rounded up to 256.  Host
+ * only.  Returns LDDMM_OK or the first validation error (detail names the
+ * pair). */
+int lddmm_batch_workspace_bytes(int32_t n, const lddmm_params* p, size_t* bytes);
+
+/* Many independent registrations in one call (the atlas-serving form of the
+ * Gauss-Newton-Krylov loop of §2.7): pair i has its own parameters p[i]
+ * (sizes, band, state and Hessian mode may differ), images I0[i], I1[i] and
+ * iterate v0_inout[i], and runs exactly the loop of lddmm_register, so its
+ * results equal those of lddmm_register on the same inputs.  Up to
+ * `concurrency` pairs run at a time (0 selects 8), each from its own host
+ * thread on its own library streams, so that the launches of different pairs
+ * share the compute units.
+ *   n          1 <= n <= 4096
+ *   p, I0, I1, v0_inout   host arrays of n entries; the images and iterates are
+ *              device buffers laid out as for lddmm_register
+ *   stats      host array [n][stats_len] or NULL; status: host array [n] or
+ *              NULL (per-pair return code); hvps: host array [n] or NULL
+ *   ws         one device workspace of ws_bytes >= lddmm_batch_workspace_bytes();
+ *              pair i uses the slice that starts after the slices of pairs < i
+ * The pairs start after the work already enqueued on `stream`; the call is
+ * synchronous.  Returns LDDMM_OK, LDDMM_W_LINESEARCH if a pair stopped on a
+ * failed search, or the error of the lowest-numbered failing pair (every pair
+ * is still attempted; argument errors are found before anything runs). */
+int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I0, const float* const* I1,
+                         void* const* v0_inout, int32_t gn_iters, int32_t pcg_iters, int32_t concurrency,
+                         lddmm_stats* stats, int32_t stats_len, int32_t* status, int64_t* hvps, void* ws,
+                         size_t ws_bytes, void* stream);
 
 /* Launch timing of one kernel, for roofline accounting.  While enabled,
  * one launch in `every` (the first, then every `every`-th, counted over the

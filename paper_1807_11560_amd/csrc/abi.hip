@@ -4,6 +4,7 @@
 // kernel-family timer.
 #include "../../include/lddmm.h"
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -11,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.h"
@@ -346,6 +348,12 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
 enum GraphKind { GK_HESSVEC = 1, GK_GN_HEAD = 2, GK_PCG_ITER = 3, GK_TRIAL = 16 };
 
 // ------------------------------------------------------ register loop
+// batched registration: at most this many pairs per call, and by default
+// this many running at a time; each pair's workspace slice is 256-aligned
+constexpr int kMaxBatch = 4096;
+constexpr int kBatchConcurrency = 8;
+size_t batch_slice(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
 int run_register(Engine& e, const void* ws, const float* I0, const float* I1, void* v0_inout,
                  int gn_iters, int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
   const Dims& d = e.dims();
@@ -577,6 +585,111 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
 }
 
 int64_t lddmm_last_register_hvps(void) { return g_last_hvps; }
+
+int lddmm_batch_workspace_bytes(int32_t n, const lddmm_params* p, size_t* bytes) {
+  if (n < 1 || n > kMaxBatch) return fail(LDDMM_E_INVALID_ARG, "n must be in [1, 4096]");
+  if (!p || !bytes) return fail(LDDMM_E_INVALID_ARG, "params or bytes is NULL");
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    Dims d;
+    const int rc = validate(&p[i], &d);
+    if (rc) return fail(rc, "pair " + std::to_string(i) + ": " + g_last_error);
+    total += batch_slice(Engine::workspace_bytes(d));
+  }
+  *bytes = total;
+  return LDDMM_OK;
+}
+
+int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I0, const float* const* I1,
+                         void* const* v0_inout, int32_t gn_iters, int32_t pcg_iters, int32_t concurrency,
+                         lddmm_stats* stats, int32_t stats_len, int32_t* status, int64_t* hvps, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (n < 1 || n > kMaxBatch) return fail(LDDMM_E_INVALID_ARG, "n must be in [1, 4096]");
+  if (!p || !I0 || !I1 || !v0_inout || !ws) return fail(LDDMM_E_INVALID_ARG, "null argument");
+  if (gn_iters < 0 || pcg_iters < 1) return fail(LDDMM_E_INVALID_ARG, "bad iteration counts");
+  if (concurrency < 0 || concurrency > 64) return fail(LDDMM_E_INVALID_ARG, "concurrency must be in [0, 64]");
+  if (stats && stats_len < 0) return fail(LDDMM_E_INVALID_ARG, "negative stats_len");
+  std::vector<Dims> dims(n);
+  std::vector<size_t> off(n);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const int rc = validate(&p[i], &dims[i]);
+    if (rc) return fail(rc, "pair " + std::to_string(i) + ": " + g_last_error);
+    if (!I0[i] || !I1[i] || !v0_inout[i])
+      return fail(LDDMM_E_INVALID_ARG, "pair " + std::to_string(i) + ": null input or output");
+    off[i] = total;
+    total += batch_slice(Engine::workspace_bytes(dims[i]));
+  }
+  if (ws_bytes < total)
+    return fail(LDDMM_E_WORKSPACE, "workspace too small: need " + std::to_string(total) + " bytes");
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_fail(err, "device");
+  // the pairs start after the work already on the caller's stream
+  hipEvent_t start = nullptr;
+  if ((err = hipEventCreateWithFlags(&start, hipEventDisableTiming)) != hipSuccess) return hip_fail(err, "event");
+  if ((err = hipEventRecord(start, static_cast<hipStream_t>(stream))) != hipSuccess) {
+    (void)hipEventDestroy(start);
+    return hip_fail(err, "event record");
+  }
+  std::vector<int> rcs(n, LDDMM_OK);
+  std::vector<std::string> msgs(n);
+  std::vector<int64_t> counts(n, 0);
+  std::atomic<int> next{0};
+  // each worker thread owns one stream (and its engine's auxiliary stream)
+  // and takes pairs in index order until none is left
+  auto worker = [&]() {
+    hipStream_t s = nullptr;
+    hipError_t e = hipSetDevice(dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, start, 0);
+    for (int i; (i = next.fetch_add(1)) < n;) {
+      if (e != hipSuccess) {
+        rcs[i] = hip_fail(e, "worker stream");
+        msgs[i] = g_last_error;
+        continue;
+      }
+      void* w = static_cast<char*>(ws) + off[i];
+      set_prepared(w, false, dims[i]);
+      Engine eng(dims[i], w, s);
+      int rc = LDDMM_OK;
+      hipError_t fe = launch_fill(reinterpret_cast<float*>(eng.tmph), 6LL * dims[i].nb, 0.f, s);
+      if (fe != hipSuccess)
+        rc = hip_fail(fe, "fill");
+      else
+        rc = run_register(eng, w, I0[i], I1[i], v0_inout[i], gn_iters, pcg_iters,
+                          stats ? stats + (size_t)i * stats_len : nullptr, stats ? stats_len : 0, &counts[i]);
+      rcs[i] = rc;
+      if (rc < 0) msgs[i] = g_last_error;
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    release_thread_streams();
+  };
+  const int nw = std::min<int>(n, concurrency ? concurrency : kBatchConcurrency);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(start);
+  int result = LDDMM_OK;
+  int64_t sum = 0;
+  for (int i = 0; i < n; ++i) {
+    if (status) status[i] = rcs[i];
+    if (hvps) hvps[i] = counts[i];
+    sum += counts[i];
+    if (rcs[i] < 0 && result >= 0) {
+      result = rcs[i];
+      g_last_error = "pair " + std::to_string(i) + ": " + msgs[i];
+    } else if (rcs[i] == LDDMM_W_LINESEARCH && result == LDDMM_OK) {
+      result = LDDMM_W_LINESEARCH;
+    }
+  }
+  g_last_hvps = sum;
+  if (result >= 0) g_last_error.clear();
+  return result;
+}
 
 int lddmm_kernel_timer(int32_t family, int32_t every) {
   if (family < LDDMM_KF_NONE || family > KF_LAST) return fail(LDDMM_E_INVALID_ARG, "unknown kernel family");

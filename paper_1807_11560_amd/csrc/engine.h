@@ -24,6 +24,10 @@ struct Carver {
   }
 };
 
+// Destroys the auxiliary streams and events of the calling thread (worker
+// threads that end call it; the stream must be idle).
+void release_thread_streams();
+
 class Engine {
  public:
   Engine(const Dims& d, void* ws, hipStream_t st);

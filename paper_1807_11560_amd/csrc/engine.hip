@@ -56,6 +56,16 @@ hipError_t Engine::aux_init(int nevents) {
   return hipSuccess;
 }
 
+void release_thread_streams() {
+  for (auto& kv : t_aux) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != kv.first) (void)hipSetDevice(kv.first);
+    for (hipEvent_t e : kv.second.events) (void)hipEventDestroy(e);
+    if (kv.second.stream) (void)hipStreamDestroy(kv.second.stream);
+  }
+  t_aux.clear();
+}
+
 hipError_t Engine::record(hipStream_t s, int ev) { return hipEventRecord((*ev_)[ev], s); }
 hipError_t Engine::wait(hipStream_t s, int ev) { return hipStreamWaitEvent(s, (*ev_)[ev], 0); }
 

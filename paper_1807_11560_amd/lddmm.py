@@ -87,6 +87,11 @@ _SIGS = {
                                       ctypes.POINTER(LddmmStats), ctypes.c_int32, _vp,
                                       ctypes.c_size_t, _vp]),
     "lddmm_last_register_hvps": (ctypes.c_int64, []),
+    "lddmm_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "lddmm_register_batch": (ctypes.c_int, [ctypes.c_int32, _P, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.POINTER(LddmmStats), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                            _vp, ctypes.c_size_t, _vp]),
     "lddmm_kernel_timer": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "lddmm_kernel_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_double),
@@ -260,6 +265,67 @@ def register(problem: Problem, I0, I1, ws: Workspace, gn_iters=10, pcg_iters=20,
             break
         recs.append({f: getattr(s, f) for f, _ in LddmmStats._fields_ if f != "reserved"})
     return v0, recs, rc, int(_lib.lddmm_last_register_hvps())
+
+
+def batch_workspace_bytes(problems: Sequence[Problem]) -> int:
+    """Workspace bytes of register_batch over these problems (lddmm_batch_workspace_bytes)."""
+    arr = (LddmmParams * len(problems))(*[q.c_params() for q in problems])
+    n = ctypes.c_size_t(0)
+    _check(_lib.lddmm_batch_workspace_bytes(len(problems), arr, ctypes.byref(n)), "lddmm_batch_workspace_bytes")
+    return n.value
+
+
+class BatchWorkspace:
+    """One device workspace for register_batch over a list of problems."""
+
+    def __init__(self, problems: Sequence[Problem], device=None):
+        torch = _torch()
+        self.nbytes = batch_workspace_bytes(problems)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device or "cuda")
+
+    @property
+    def ptr(self):
+        return self.buf.data_ptr()
+
+
+def register_batch(problems: Sequence[Problem], I0s, I1s, ws: BatchWorkspace, gn_iters=10, pcg_iters=20,
+                   v0s=None, concurrency=0, stream=None):
+    """Independent registrations in one call (lddmm_register_batch).
+
+    Returns (v0s, stats, status, hvps, rc): per pair the result, one dict per GN
+    iteration, the return code and the number of Hessian-vector products."""
+    torch = _torch()
+    n = len(problems)
+    if not (len(I0s) == len(I1s) == n):
+        raise ValueError("one I0 and one I1 per problem")
+    for q, a, b in zip(problems, I0s, I1s):
+        _need(a, torch.float32, q.grid, "I0")
+        _need(b, torch.float32, q.grid, "I1")
+    if v0s is None:
+        v0s = [torch.zeros(q.band_shape, dtype=torch.complex64, device=a.device) for q, a in zip(problems, I0s)]
+    for q, v in zip(problems, v0s):
+        _need(v, torch.complex64, q.band_shape, "v0")
+    arr = (LddmmParams * n)(*[q.c_params() for q in problems])
+    p0 = (ctypes.c_void_p * n)(*[_ptr(a) for a in I0s])
+    p1 = (ctypes.c_void_p * n)(*[_ptr(b) for b in I1s])
+    pv = (ctypes.c_void_p * n)(*[_ptr(v) for v in v0s])
+    slen = max(gn_iters, 1)
+    stats = (LddmmStats * (n * slen))()
+    status = (ctypes.c_int32 * n)()
+    hv = (ctypes.c_int64 * n)()
+    rc = _check(_lib.lddmm_register_batch(n, arr, p0, p1, pv, int(gn_iters), int(pcg_iters), int(concurrency),
+                                          stats, slen, status, hv, ws.ptr, ws.nbytes, _stream(stream)),
+                "lddmm_register_batch")
+    recs = []
+    for i in range(n):
+        r = []
+        for k in range(gn_iters):
+            s_ = stats[i * slen + k]
+            if s_.trials == 0:
+                break
+            r.append({f: getattr(s_, f) for f, _ in LddmmStats._fields_ if f != "reserved"})
+        recs.append(r)
+    return v0s, recs, [int(x) for x in status], [int(x) for x in hv], rc
 
 
 def kernel_timer(family: int, every: int = 1):

@@ -14,8 +14,8 @@ Hermitian (v(-k) = conj v(k)), with the k = 0 mode zeroed (no translation).
 import numpy as np
 
 # ---------------------------------------------------------------- problem set
-# The five workloads: 2-D Gaussian blobs, 3-D nested ellipsoids, 3-D tissue
-# phantom (the measured workload), the autograd volume and the batch.
+# The workloads: 2-D Gaussian blobs, 3-D nested ellipsoids, 3-D tissue
+# phantom (the measured workload), the large volume; the batch is below.
 CONFIGS = {
     1: dict(grid=(64, 64), band=(16, 16), s=2, nt=10, dmax=4.0, gn=5, pcg=10),
     2: dict(grid=(64, 64, 64), band=(16, 16, 16), s=2, nt=10, dmax=5.0, gn=10, pcg=20),
@@ -185,6 +185,32 @@ def workload(config, pair=0, grid=None, band=None):
     params = dict(grid=c["grid"], band=c["band"], nt=c["nt"], alpha=ALPHA, s=c["s"],
                   sigma=SIGMA, gn=c["gn"], pcg=c["pcg"])
     return dict(I0=I0, v_star=v, params=params)
+
+
+# The batched serving workload: pairs warped from one atlas, each with a grid
+# and a band drawn from these sets and a maximal displacement in [4, 10] voxels.
+BATCH = dict(grids=((96, 96, 96), (128, 128, 128), (144, 176, 144), (160, 192, 160)),
+             bands=((24, 24, 24), (32, 32, 32)), dmax=(4.0, 10.0), s=3, nt=10, gn=10, pcg=20)
+BATCH_SEED = 5000
+
+
+def batch_workload(pairs=16, seed=BATCH_SEED):
+    """Source images and target velocities of `pairs` atlas registrations.
+    The atlas is one tissue phantom (its random series is drawn from the same
+    seed for every grid, so all sources are samplings of one image).  Returns a
+    list of dicts like ``workload``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(pairs):
+        grid = BATCH["grids"][int(rng.integers(len(BATCH["grids"])))]
+        band = BATCH["bands"][int(rng.integers(len(BATCH["bands"])))]
+        dmax = float(rng.uniform(*BATCH["dmax"]))
+        I0 = tissue_phantom(np.random.default_rng(seed + 1), grid)
+        v = scale_to_displacement(random_band_field(rng, band, ALPHA, BATCH["s"]), grid, dmax)
+        params = dict(grid=grid, band=band, nt=BATCH["nt"], alpha=ALPHA, s=BATCH["s"], sigma=SIGMA,
+                      gn=BATCH["gn"], pcg=BATCH["pcg"])
+        out.append(dict(I0=I0, v_star=v, params=params))
+    return out
 
 
 def random_direction(seed, band, s=2, alpha=ALPHA):

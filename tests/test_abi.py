@@ -36,14 +36,15 @@ def test_params_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lddmm.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu", sizeof(lddmm_params),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu", sizeof(lddmm_params),'
         ' offsetof(lddmm_params, alpha), offsetof(lddmm_params, hessian),'
+        ' offsetof(lddmm_params, state),'
         ' sizeof(lddmm_stats), offsetof(lddmm_stats, trials)); return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [ctypes.sizeof(L.LddmmParams), L.LddmmParams.alpha.offset,
-                   L.LddmmParams.hessian.offset, ctypes.sizeof(L.LddmmStats),
+                   L.LddmmParams.hessian.offset, L.LddmmParams.state.offset, ctypes.sizeof(L.LddmmStats),
                    L.LddmmStats.trials.offset]
 
 
@@ -64,6 +65,7 @@ def test_workspace_bytes_scales_with_problem():
     (dict(s=0), L.E_INVALID_ARG),
     (dict(time_steps=0), L.E_INVALID_ARG),
     (dict(hessian=7), L.E_INVALID_ARG),
+    (dict(state=2), L.E_INVALID_ARG),
 ])
 def test_validation_rejects(kw, code):
     base = dict(grid=(64, 64, 64), band=(16, 16, 16))
@@ -109,3 +111,40 @@ def test_switches_reject_bad_values():
     assert lib.lddmm_use_graphs(0) == L.OK
     assert lib.lddmm_kernel_timer(L.KF_SRC, 4) == L.OK
     assert lib.lddmm_kernel_timer(0, 1) == L.OK
+
+
+def test_deformation_state_needs_less_workspace():
+    """No per-step image, grid velocity or image-grid stage-0 buffer is kept
+    for the deformation state (paper §3.3: the lower-memory variant)."""
+    kw = dict(grid=(128, 128, 128), band=(32, 32, 32), s=3)
+    img = L.Problem(**kw).workspace_bytes()
+    dfm = L.Problem(state=L.STATE_DEFORMATION, **kw).workspace_bytes()
+    assert dfm < 0.8 * img
+
+
+def test_batch_workspace_is_the_sum_of_aligned_slices():
+    probs = [L.Problem(grid=(32, 32, 32), band=(8, 8, 8)),
+             L.Problem(grid=(40, 36, 32), band=(12, 16, 8), state=L.STATE_DEFORMATION),
+             L.Problem(grid=(64, 64, 64), band=(16, 16, 16), hessian=L.NEWTON)]
+    want = sum((q.workspace_bytes() + 255) // 256 * 256 for q in probs)
+    assert L.batch_workspace_bytes(probs) == want
+    bad = probs + [L.Problem(grid=(32, 32, 32), band=(9, 8, 8))]
+    with pytest.raises(L.LddmmError) as e:
+        L.batch_workspace_bytes(bad)
+    assert e.value.code == L.E_SHAPE and "pair 3" in str(e.value)
+
+
+def test_batch_validates_before_touching_the_device():
+    lib = L.raw()
+    probs = [L.Problem(grid=(32, 32, 32), band=(8, 8, 8))] * 2
+    arr = (L.LddmmParams * 2)(*[q.c_params() for q in probs])
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    nulls = (ctypes.c_void_p * 2)(0x1000, 0)
+    ws = ctypes.c_void_p(0x3000)
+    null = ctypes.c_void_p(0)
+    call = lib.lddmm_register_batch
+    assert call(0, arr, fake, fake, fake, 1, 1, 0, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
+    assert call(2, arr, fake, nulls, fake, 1, 1, 0, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
+    assert call(2, arr, fake, fake, fake, 1, 0, 0, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
+    assert call(2, arr, fake, fake, fake, 1, 1, 65, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
+    assert call(2, arr, fake, fake, fake, 1, 1, 0, None, 0, None, None, ws, 64, null) == L.E_WORKSPACE

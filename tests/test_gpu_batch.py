@@ -1,0 +1,99 @@
+"""lddmm_register_batch: independent registrations of different sizes, band,
+state and Hessian mode in one call give, pair by pair, exactly the results of
+lddmm_register on the same inputs (the single-pair loop is itself compared
+with the oracle in test_gpu_register.py), for any number of pairs running at
+a time; and the atlas-serving shapes run."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Params  # noqa: E402
+from oracle import deformation  # noqa: E402
+from oracle.jacobi import forward  # noqa: E402
+from paper_1807_11560_amd import synth  # noqa: E402
+
+
+def L():
+    from paper_1807_11560_amd import lddmm
+    return lddmm
+
+
+def small_pairs():
+    specs = [
+        dict(grid=(24, 20, 18), band=(8, 8, 6), nt=4, state=0, hessian=0),
+        dict(grid=(40, 36, 32), band=(12, 16, 8), nt=5, state=1, hessian=0),
+        dict(grid=(32, 32, 32), band=(8, 8, 8), nt=3, state=0, hessian=2),
+        dict(grid=(32, 32, 32), band=(8, 8, 8), nt=3, state=1, hessian=1),
+    ]
+    out = []
+    for i, c in enumerate(specs):
+        w = synth.workload(2, pair=i, grid=c["grid"], band=c["band"])
+        p = Params(grid=c["grid"], band=c["band"], nt=c["nt"], alpha=synth.ALPHA, s=2, sigma=synth.SIGMA)
+        vstar = synth.scale_to_displacement(w["v_star"], c["grid"], 1.5)
+        I1 = forward(vstar, w["I0"], p)[2][-1] if c["state"] == 0 else deformation.forward(vstar, w["I0"], p)[2]
+        prob = L().Problem(grid=c["grid"], band=c["band"], time_steps=c["nt"], alpha=synth.ALPHA, s=2,
+                           sigma=synth.SIGMA, state=c["state"], hessian=c["hessian"])
+        out.append((prob, torch.from_numpy(w["I0"]).float().cuda(), torch.from_numpy(I1).float().cuda()))
+    return out
+
+
+def singles(pairs, gn, pcg):
+    res = []
+    for prob, I0, I1 in pairs:
+        ws = L().Workspace(prob)
+        v, st, rc, hv = L().register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
+        torch.cuda.synchronize()
+        res.append((v.cpu().numpy(), st, rc, hv))
+    return res
+
+
+@pytest.mark.parametrize("concurrency", [1, 3])
+def test_batch_equals_single_registrations(concurrency):
+    pairs = small_pairs()
+    ref = singles(pairs, 3, 4)
+    probs = [q for q, _, _ in pairs]
+    ws = L().BatchWorkspace(probs)
+    vs, stats, status, hvps, rc = L().register_batch(probs, [a for _, a, _ in pairs], [b for _, _, b in pairs],
+                                                     ws, gn_iters=3, pcg_iters=4, concurrency=concurrency)
+    torch.cuda.synchronize()
+    assert rc == max(r[2] for r in ref)
+    for i, (v, st, s_, h) in enumerate(zip(vs, stats, status, hvps)):
+        rv, rst, rrc, rh = ref[i]
+        print(f"pair {i}: status {s_}/{rrc} hvps {h}/{rh} E {[round(x['energy'], 5) for x in st]}")
+        assert s_ == rrc and h == rh and len(st) == len(rst)
+        assert np.array_equal(v.cpu().numpy(), rv)
+        for a, b in zip(st, rst):
+            assert a == b
+
+
+def test_atlas_serving_shapes_run():
+    """Four atlas pairs, one per grid of the serving workload (96^3 to
+    160x192x160, bands 24^3 and 32^3), one Gauss-Newton iteration each:
+    every pair matches its single registration."""
+    work = synth.batch_workload(pairs=12)
+    chosen = {}
+    for w in work:
+        chosen.setdefault(w["params"]["grid"], w)
+    pairs = []
+    for w in chosen.values():
+        pp = w["params"]
+        prob = L().Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
+                           sigma=pp["sigma"])
+        I0 = torch.from_numpy(w["I0"]).float().cuda()
+        I1 = L().shoot(prob, I0, torch.from_numpy(w["v_star"]).to(torch.complex64).cuda(), L().Workspace(prob))
+        pairs.append((prob, I0, I1))
+    assert len(pairs) >= 3
+    ref = singles(pairs, 1, 3)
+    probs = [q for q, _, _ in pairs]
+    ws = L().BatchWorkspace(probs)
+    vs, stats, status, hvps, rc = L().register_batch(probs, [a for _, a, _ in pairs], [b for _, _, b in pairs],
+                                                     ws, gn_iters=1, pcg_iters=3, concurrency=4)
+    torch.cuda.synchronize()
+    for i in range(len(pairs)):
+        print(f"{probs[i].grid} {probs[i].band}: MSE_rel {stats[i][0]['mse_rel']:.2f} hvps {hvps[i]}")
+        assert status[i] == ref[i][2] and hvps[i] == ref[i][3]
+        assert np.array_equal(vs[i].cpu().numpy(), ref[i][0])
