@@ -12,6 +12,8 @@ the timed region.
 
 ``--state deformation`` registers the same images subject to the deformation
 state equation (paper §3.3) instead of the image state (paper §3.2).
+``--batch N`` measures instead the atlas-serving batch: N independent pairs of
+different sizes in one lddmm_register_batch call (aggregate HVP/s).
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -47,6 +49,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="measure the atlas-serving batch of this many pairs (lddmm_register_batch) instead")
+    ap.add_argument("--concurrency", type=int, default=0, help="pairs running at a time in --batch (0: default)")
     ap.add_argument("--state", choices=("image", "deformation"), default="image",
                     help="constraint of the registered problem: the image state (paper §3.2, the "
                          "default) or the deformation state (paper §3.3)")
@@ -119,6 +124,130 @@ def cpu_baseline(w, state="image"):
             "seconds": t}
 
 
+def dominant_family(L, run):
+    """The kernel family with the largest summed duration over one run."""
+    fam_ms = {}
+    for fam in L.KERNEL_FAMILIES:
+        L.kernel_timer(fam, 1)
+        run()
+        fam_ms[fam] = L.kernel_timer_read()[1]
+    L.kernel_timer(0)
+    log("ms per run by kernel: " + ", ".join(f"{L.KERNEL_FAMILIES[f]} {fam_ms[f]:.2f}" for f in fam_ms))
+    return max(fam_ms, key=fam_ms.get)
+
+
+def batch_main(args):
+    """The atlas-serving batch: independent registrations of different sizes
+    in one lddmm_register_batch call."""
+    import torch
+    from paper_1807_11560_amd import lddmm as L
+    from paper_1807_11560_amd import synth
+
+    dev = torch.device("cuda:0")
+    work = synth.batch_workload(pairs=args.batch)
+    probs, I0s, I1s = [], [], []
+    for w in work:
+        pp = w["params"]
+        prob = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
+                         sigma=pp["sigma"], hessian=L.GN_PAPER)
+        I0 = torch.from_numpy(w["I0"]).float().to(dev)
+        I1 = L.shoot(prob, I0, torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev), L.Workspace(prob, dev))
+        probs.append(prob)
+        I0s.append(I0)
+        I1s.append(I1)
+    gn, pcg = synth.BATCH["gn"], synth.BATCH["pcg"]
+    ws = L.BatchWorkspace(probs, dev)
+    torch.cuda.synchronize()
+    log(f"batch ready: {len(probs)} pairs, workspace {ws.nbytes / 2**30:.2f} GiB")
+
+    def run():
+        return L.register_batch(probs, I0s, I1s, ws, gn_iters=gn, pcg_iters=pcg, concurrency=args.concurrency)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    dominant = dominant_family(L, run)
+    L.kernel_timer(dominant, TIMER_EVERY)
+    hvps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, stats, status, hv, rc = run()
+        hvps += sum(hv)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    launches, kms, kfl, kby = L.kernel_timer_read()
+    L.kernel_timer(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hvps_u = 0
+    for _ in range(args.steps):
+        hvps_u += sum(run()[3])
+    torch.cuda.synchronize()
+    T_u = time.perf_counter() - t0
+    log(f"timed {args.steps} batches in {T:.3f} s, {hvps} HVPs; status {rc}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline_pair(work[0])
+        log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
+    name = L.KERNEL_FAMILIES[dominant]
+    res = {
+        "metric": METRIC,
+        "value": hvps / T,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"atlas serving batch: {len(probs)} tissue-phantom pairs, grids from 96^3 to "
+                        "160x192x160, bands 24^3 / 32^3, geodesics of 4-10 voxels, s=3, nt=10, "
+                        f"{gn} Gauss-Newton x {pcg} CG iterations each, lddmm_register_batch",
+            "pairs": [[list(q.grid), q.band[0]] for q in probs],
+            "concurrency": args.concurrency or 8,
+        },
+        "registrations_per_min": 60.0 * args.steps * len(probs) / T,
+        "value_without_timer_events": hvps_u / T_u,
+        "final_mse_rel_mean": float(np.mean([s[-1]["mse_rel"] for s in stats])),
+        "workspace_mib": ws.nbytes / 2**20,
+        "roofline": roofline(dominant, name, launches, kms, kfl, kby, None),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_pair(w):
+    """The FP64 oracle on the host: one Hessian-vector product of one pair of
+    the batch at v0 = v*/2, after an untimed oracle gradient."""
+    from oracle import Params
+    from oracle.jacobi import forward, gradient, hessvec
+    from paper_1807_11560_amd import synth
+    try:
+        import threadpoolctl
+        cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    pp = w["params"]
+    p = Params(grid=pp["grid"], band=pp["band"], nt=pp["nt"], alpha=pp["alpha"], s=pp["s"], sigma=pp["sigma"])
+    I0, vstar = w["I0"], w["v_star"]
+    I1 = forward(vstar, I0, p)[2][-1]
+    _, _, cache = gradient(0.5 * vstar, I0, I1, p)
+    d = synth.random_direction(4242, p.band, s=pp["s"])
+    t0 = time.perf_counter()
+    hessvec(cache, d, p, "R1")
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "HVP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one Hessian-vector product of the first pair ({'x'.join(map(str, pp['grid']))}, band "
+                      f"{pp['band'][0]}^3) at v0 = v*/2 (FP64 NumPy, after an untimed oracle gradient)",
+            "seconds": t}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +255,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         sys.exit(2)
+
+    if args.batch:
+        batch_main(args)
+        return
 
     import torch
     from paper_1807_11560_amd import lddmm as L
