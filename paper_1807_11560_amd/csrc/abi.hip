@@ -96,12 +96,10 @@ int validate(const lddmm_params* p, Dims* d) {
   o.sigma = p->sigma;
   o.hessian = p->hessian;
   o.state = p->state;
-  // the fused step kernel keeps a block's fields in LDS
-  // each block keeps its rows in LDS (at most 64 KiB per block)
-  if (synth_shared_bytes(o) > 64 * 1024 || prods_shared_bytes(o, 9) > 64 * 1024 ||
-      colstep_shared_bytes(o) > 64 * 1024)
+  // each block keeps its tile in LDS (at most the 160 KiB of a gfx950 workgroup)
+  if (synth_shared_bytes(o) > kMaxLds || prods_shared_bytes(o, 9) > kMaxLds || colstep_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
-  if (gridstep_shared_bytes(o) > 64 * 1024 || src_shared_bytes(o) > 64 * 1024)
+  if (gridstep_shared_bytes(o) > kMaxLds || src_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");
   return LDDMM_OK;
 }

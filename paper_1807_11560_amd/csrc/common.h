@@ -9,6 +9,7 @@
 namespace lddmm {
 
 constexpr int kMaxBand = 64;   // K_j upper bound
+constexpr size_t kMaxLds = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int kMaxJobs = 32;   // jobs per batched launch
 
 // Problem sizes.  Band fields are kept internally as the half spectrum

@@ -714,7 +714,8 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
 // variants, optionally of L~ out) for the same columns.
 template <int KG, class S>
 __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, const float* __restrict__ Lsym,
-                                                 const float* __restrict__ Ksym, S sh, float invG) {
+                                                 const float* __restrict__ Ksym, S sh, float invG, int xsz,
+                                                 int stage_w0) {
   extern __shared__ float2 shc[];
   const int M0 = sh.M0(), M1 = sh.M1(), K0 = sh.K0(), K1 = sh.K1(), Kh = sh.Kh();
   const ColJob job = jobs.j[blockIdx.z];
@@ -722,37 +723,35 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
   const int kb = blockIdx.x * KG;
   const int C = K1 * Kh;
   const int nterm = job.b ? 2 : 1;
-  // region X: S1 slices (and later the inverse twiddles); region Y: the rest
-  const int xsz = max(2 * M0 * M1, 2 * M0 * K0);
-  float2* sx = shc;                       // [nterm][M0][M1]
-  float2* w0s = shc;                      // [2][M0][K0] (phase 3)
+  // region X: one S1 slice at a time (and later the inverse twiddles, when
+  // they fit; else phase 3 reads them from global memory); region Y: the rest
+  float2* sx = shc;                       // [M0][M1]
+  float2* w0s = shc;                      // [2][M0][K0] (phase 3, when staged)
   float2* wf1 = shc + xsz;                // [KG][M1]
   float2* s2 = wf1 + KG * M1;             // [2][M0][KG]
   float2* wf0 = s2 + 2 * M0 * KG;         // [K0][M0]
   float2* bnd = wf0 + K0 * M0;            // [2][K0][KG]  (out, L~ out)
 
-  {
-    const float2* sa = job.a + (size_t)kh * M0 * M1;
-    const float2* sb = job.b ? job.b + (size_t)kh * M0 * M1 : sa;
-    const int n1 = M0 * M1;
-    batched_fill<float2>(nterm * n1, [&](int i) { return i < n1 ? sa[i] : sb[i - n1]; },
-                         [&](int i, float2 v) { sx[i] = v; });
-  }
   batched_fill<float2>(KG * M1, [&](int i) {
     int kk = i / M1, x = i % M1;
     int k1 = kb + kk;
     return (k1 < K1) ? tw.fwd1[(size_t)k1 * M1 + x] : make_float2(0.f, 0.f);
   }, [&](int i, float2 v) { wf1[i] = v; });
   batched_fill<float2>(K0 * M0, [&](int i) { return tw.fwd0[i]; }, [&](int i, float2 v) { wf0[i] = v; });
-  __syncthreads();
-  // stage 1': s2[t][x0][kk] = sum_x1 wf1[kk][x1] S[t][x0][x1]
-  for (int i = threadIdx.x; i < nterm * M0 * KG; i += blockDim.x) {
-    int t = i / (M0 * KG), x0 = (i / KG) % M0, kk = i % KG;
-    const float2* row = sx + ((size_t)t * M0 + x0) * M1;
-    const float2* w = wf1 + (size_t)kk * M1;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int x = 0; x < M1; ++x) cmac(acc, w[x], row[x]);
-    s2[i] = acc;
+  // stage 1', one term at a time: s2[t][x0][kk] = sum_x1 wf1[kk][x1] S[t][x0][x1]
+  for (int t = 0; t < nterm; ++t) {
+    const float2* src = (t ? job.b : job.a) + (size_t)kh * M0 * M1;
+    if (t) __syncthreads();  // the previous slice has been consumed
+    batched_fill<float2>(M0 * M1, [&](int i) { return src[i]; }, [&](int i, float2 v) { sx[i] = v; });
+    __syncthreads();
+    for (int i = threadIdx.x; i < M0 * KG; i += blockDim.x) {
+      int x0 = i / KG, kk = i % KG;
+      const float2* row = sx + (size_t)x0 * M1;
+      const float2* w = wf1 + (size_t)kk * M1;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int x = 0; x < M1; ++x) cmac(acc, w[x], row[x]);
+      s2[(size_t)t * M0 * KG + i] = acc;
+    }
   }
   __syncthreads();
   // stage 0' + band update
@@ -803,7 +802,11 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
     }
   }
   if (job.nt1 == 0) return;
-  batched_fill<float2>(2 * M0 * K0, [&](int i) { return tw.inv0[i]; }, [&](int i, float2 v) { w0s[i] = v; });
+  const float2* w0t = tw.inv0;
+  if (stage_w0) {
+    batched_fill<float2>(2 * M0 * K0, [&](int i) { return tw.inv0[i]; }, [&](int i, float2 v) { w0s[i] = v; });
+    w0t = w0s;
+  }
   __syncthreads();
   // next inverse stage 0: t1[v][x0][k1][kh] = sum_k0 w0[v][x0][k0] b[k0]
 #pragma unroll
@@ -815,7 +818,7 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
       int v = i / (M0 * KG), x0 = (i / KG) % M0, kk = i % KG;
       int k1 = kb + kk;
       if (k1 >= K1) continue;
-      const float2* w = w0s + ((size_t)v * M0 + x0) * K0;
+      const float2* w = w0t + ((size_t)v * M0 + x0) * K0;
       float2 acc = make_float2(0.f, 0.f);
       for (int k0 = 0; k0 < K0; ++k0) cmac(acc, w[k0], bsrc[(size_t)k0 * KG + kk]);
       dst[((size_t)v * M0 + x0) * C + (size_t)kh * K1 + k1] = acc;
@@ -2243,11 +2246,25 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
 
 constexpr int kColGroup = 8;
 
-size_t colstep_shared_bytes(const Dims& d) {
+// LDS plan of the generic column kernel: region X holds one S1 slice and,
+// when the total stays within the LDS of a workgroup, the inverse twiddles
+// of phase 3.
+static void colstep_lds_plan(const Dims& d, int* xsz, int* stage_w0, size_t* bytes) {
   const int M0 = d.M[0], M1 = d.M[1], K0 = d.K[0];
-  size_t xsz = (size_t)std::max(2 * M0 * M1, 2 * M0 * K0);
-  return (xsz + (size_t)kColGroup * M1 + 2 * (size_t)M0 * kColGroup + (size_t)K0 * M0 +
-          2 * (size_t)K0 * kColGroup) * sizeof(float2);
+  const size_t rest = (size_t)kColGroup * M1 + 2 * (size_t)M0 * kColGroup + (size_t)K0 * M0 +
+                      2 * (size_t)K0 * kColGroup;
+  const size_t staged = (size_t)std::max(M0 * M1, 2 * M0 * K0);
+  const bool st = (staged + rest) * sizeof(float2) <= kMaxLds;
+  *xsz = st ? (int)staged : M0 * M1;
+  *stage_w0 = st ? 1 : 0;
+  *bytes = ((size_t)*xsz + rest) * sizeof(float2);
+}
+
+size_t colstep_shared_bytes(const Dims& d) {
+  int xsz, sw;
+  size_t b;
+  colstep_lds_plan(d, &xsz, &sw, &b);
+  return b;
 }
 
 size_t col_table_count(const Dims& d) {
@@ -2334,9 +2351,12 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
     e = hipGetLastError();
   } else {
     dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
-    size_t shm = colstep_shared_bytes(d);
+    int xsz, stage_w0;
+    size_t shm;
+    colstep_lds_plan(d, &xsz, &stage_w0, &shm);
     BandDyn sh{d.K[0], d.K[1], d.Kh, d.M[0], d.M[1], d.M[2]};
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep<kColGroup, BandDyn>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh, invG);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep<kColGroup, BandDyn>), grid, dim3(256), shm, st, jobs, tw, Lsym, Ksym, sh, invG,
+                 xsz, stage_w0);
     e = hipGetLastError();
   }
   return e;

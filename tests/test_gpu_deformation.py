@@ -47,6 +47,9 @@ CASES = {
     "one_step": dict(grid=(32, 32, 32), band=(8, 8, 8), nt=1, s=2, dmax=1.5, cfg=2),
     "cfg2": dict(grid=(64, 64, 64), band=(16, 16, 16), nt=10, s=2, dmax=5.0, cfg=2),
     "cfg3": dict(grid=(128, 128, 128), band=(32, 32, 32), nt=10, s=3, dmax=8.0, cfg=3),
+    # large bands on the generic kernels (LDS tiles up to the 160 KiB of a workgroup)
+    "wide_aniso": dict(grid=(64, 56, 64), band=(48, 40, 56), nt=3, s=2, dmax=3.0, cfg=2),
+    "band64": dict(grid=(64, 64, 64), band=(64, 64, 64), nt=2, s=2, dmax=3.0, cfg=2),
 }
 
 
