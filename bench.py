@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=0,
                     help="measure the atlas-serving batch of this many pairs (lddmm_register_batch) instead")
     ap.add_argument("--concurrency", type=int, default=0, help="pairs running at a time in --batch (0: default)")
+    ap.add_argument("--band", type=int, default=0,
+                    help="register with this band size instead of 32 (the band sweep of the paper's experiment; "
+                         "the target stays the one made with band 32)")
     ap.add_argument("--state", choices=("image", "deformation"), default="image",
                     help="constraint of the registered problem: the image state (paper §3.2, the "
                          "default) or the deformation state (paper §3.3)")
@@ -94,7 +97,7 @@ def stored_traffic(kernel_name):
     return None
 
 
-def cpu_baseline(w, state="image"):
+def cpu_baseline(w, state="image", band=None):
     """The FP64 oracle on the host: one Hessian-vector product of the same
     problem at v0 = v*/2, after an untimed oracle gradient."""
     from oracle import Params
@@ -113,14 +116,20 @@ def cpu_baseline(w, state="image"):
     p = Params(grid=pp["grid"], band=pp["band"], nt=pp["nt"], alpha=pp["alpha"], s=pp["s"], sigma=pp["sigma"])
     I0, vstar = w["I0"], w["v_star"]
     I1 = forward(vstar, I0, p)[2][-1]
+    at = "v0 = v*/2"
+    if band and tuple(band) != tuple(pp["band"]):
+        # register with another band: the same target, v0 = 0
+        p = dataclasses.replace(p, band=tuple(band), spectral=None)
+        vstar = np.zeros((3,) + tuple(band), dtype=np.complex128)
+        at = "v0 = 0"
     _, _, cache = gradient(0.5 * vstar, I0, I1, p)
     d = synth.random_direction(4242, p.band, s=pp["s"])
     t0 = time.perf_counter()
     hessvec(cache, d, p, "R1")
     t = time.perf_counter() - t0
     return {"value": 1.0 / t, "unit": "HVP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one Hessian-vector product of the 128^3 / band 32^3 problem ({state} state) "
-                      "at v0 = v*/2 (FP64 NumPy, after an untimed oracle gradient)",
+            "sample": f"one Hessian-vector product of the 128^3 / band {p.band[0]}^3 problem ({state} state) "
+                      f"at {at} (FP64 NumPy, after an untimed oracle gradient)",
             "seconds": t}
 
 
@@ -269,13 +278,15 @@ def main():
     # the target is the phantom warped by the image-state model in both cases
     prob_img = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
                          sigma=pp["sigma"], hessian=L.GN_PAPER)
-    prob = dataclasses.replace(prob_img, state=L.STATE_IMAGE if args.state == "image" else L.STATE_DEFORMATION)
+    band = (args.band,) * 3 if args.band else tuple(pp["band"])
+    prob = dataclasses.replace(prob_img, band=band,
+                               state=L.STATE_IMAGE if args.state == "image" else L.STATE_DEFORMATION)
     gn, pcg = pp["gn"], pp["pcg"]
     dev = torch.device("cuda:0")
     ws = L.Workspace(prob, dev)
     I0 = torch.from_numpy(w["I0"]).float().to(dev)
     vstar = torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev)
-    I1 = L.shoot(prob_img, I0, vstar, L.Workspace(prob_img, dev) if args.state != "image" else ws)
+    I1 = L.shoot(prob_img, I0, vstar, ws if prob == prob_img else L.Workspace(prob_img, dev))
     torch.cuda.synchronize()
     log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
 
@@ -348,7 +359,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(w, args.state)
+        cpu = cpu_baseline(w, args.state, band)
         log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
 
     name = L.KERNEL_FAMILIES[dominant]
@@ -369,7 +380,9 @@ def main():
             "workload": "tissue phantom 128^3 registered to its warp by a random band-limited geodesic "
                         "(8 voxels), band 32^3, padded grid 48^3, s=3, alpha=0.0025, sigma=0.03, nt=10, "
                         "10 Gauss-Newton x 20 CG iterations, paper Gauss-Newton reading"
-                        + ("" if args.state == "image" else ", subject to the deformation state equation"),
+                        + ("" if args.state == "image" else ", subject to the deformation state equation")
+                        + ("" if band == tuple(pp["band"]) else f", registered with band {band[0]}^3 "
+                           f"(padded grid {3 * band[0] // 2}^3)"),
             "state": args.state,
             "grid": list(prob.grid), "band": list(prob.band), "time_steps": prob.time_steps,
             "gn_iters": gn, "pcg_iters": pcg,
@@ -379,6 +392,7 @@ def main():
         "value_without_timer_events": hvps_u / T_u,
         "hvp_only_per_s": hvp_only,
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
+        "final_grad_inf_rel": stats[-1]["grad_inf_rel"] if stats else None,
         "workspace_mib": ws.nbytes / 2**20,
         "roofline": roofline(dominant, name, launches, kms, kfl, kby, stored_traffic(name)),
         "cpu_baseline": cpu,
