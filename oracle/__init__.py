@@ -19,6 +19,7 @@ Modules
              Hessian-vector product (paper §3.2)
   deformation  the same problem subject to the deformation state equation,
              phi = id + u carried in the band, m(1) = I0 o phi(1) (paper §3.3)
+  highorder  shooting by RK4 and transport with midpoint departure points
   gn         CG in the V metric and the Gauss-Newton-Krylov loop (paper §2.7)
 
 Every function cites the passage it restates.  Readings of passages where the
