@@ -69,6 +69,8 @@ enum { LDDMM_FP32 = 0 };                              /* arithmetic of the bulk 
 enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2 };
 /* State that carries the deformation, see lddmm_params */
 enum { LDDMM_STATE_IMAGE = 0, LDDMM_STATE_DEFORMATION = 1 };
+/* Time integration of shooting and transport, see lddmm_params */
+enum { LDDMM_EULER = 0, LDDMM_RK4 = 1 };
 
 typedef struct lddmm_params {
   int32_t ndim;         /* spatial dimension; this library computes ndim == 3 */
@@ -115,6 +117,15 @@ typedef struct lddmm_params {
                            trilinearly at phi(1).  The plus signs are the derivative of U(1)
                            (the paper prints a minus before D~phi(1) * drho~(1)).  No per-step
                            image or grid velocity is kept, so the workspace is smaller. */
+  int32_t integrator;   /* LDDMM_EULER: nt explicit Euler steps everywhere (as documented above).
+                           LDDMM_RK4 (lddmm_shoot and lddmm_geodesic_energy only, image state):
+                           the band EPDiff by classical fourth-order Runge-Kutta steps, which
+                           conserve the geodesic energy <L~ v_t, v_t> of §2.2 to O(dt^4), and the
+                           image transport with midpoint departure points
+                           X_h = x - dt/2 v_h(x), X = x - dt v_h(X_h), v_h = iota((v_n + v_{n+1})/2)
+                           interpolated trilinearly at X_h (second order in dt).  The gradient,
+                           Hessian-vector product and registration integrate the adjoint sweeps
+                           as transposes of Euler steps and reject LDDMM_RK4. */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */
@@ -142,6 +153,30 @@ int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes);
  *   v1  [3][K0][K1][K2] complex64 (device, written) or NULL: v_nt */
 int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
                 void* ws, size_t ws_bytes, void* stream);
+
+/* Band symbols of lddmm_apply_symbol */
+enum { LDDMM_SYMBOL_L = 0, LDDMM_SYMBOL_K = 1 };
+
+/* out = L~ in (which = LDDMM_SYMBOL_L) or K~ in (LDDMM_SYMBOL_K) on a band field
+ * (paper §3.1: the band symbols of L = (Id - alpha Laplacian)^s and K = L^-1).
+ * Converts a V-metric gradient g_V into the l2 gradient L~ g_V that is the
+ * derivative of the energy with respect to the real and imaginary parts of
+ * v0 (and back).  in and out: [3][K0][K1][K2] complex64 (device); in is
+ * projected onto Hermitian fields on the effective band; out may alias in.
+ * Overwrites the workspace's scratch fields (not the trajectories that
+ * lddmm_hessvec uses). */
+int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, void* out, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Geodesic energies E_n = <L~ v_n, v_n>_l2, n = 0..nt, in FP64, along the band
+ * trajectory that lddmm_shoot would follow from v0 with the same parameters
+ * (paper §2.2: constant along the exact geodesic; an Euler step changes it by
+ * dt^2 <a_n, K~ a_n>, a_n = ad~*_{v_n}(L~ v_n), an RK4 step by O(dt^5)).  The
+ * conservation check of the shooting; no image is involved.
+ *   v0        [3][K0][K1][K2] complex64 (device, read)
+ *   energies  nt + 1 doubles (device, written) */
+int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energies, void* ws,
+                          size_t ws_bytes, void* stream);
 
 /* Energy and gradient in the V metric (paper §3.2: energy, the reduced
  * adjoint Jacobi equations in the band with U(1) = K~ pi(lambda(1) grad

@@ -46,7 +46,7 @@ bool same_dims(const Dims& a, const Dims& b) {
   for (int j = 0; j < 3; ++j)
     if (a.N[j] != b.N[j] || a.K[j] != b.K[j] || a.M[j] != b.M[j]) return false;
   return a.nt == b.nt && a.s == b.s && a.alpha == b.alpha && a.sigma == b.sigma &&
-         a.hessian == b.hessian && a.state == b.state;
+         a.hessian == b.hessian && a.state == b.state && a.integrator == b.integrator;
 }
 
 void set_prepared(const void* ws, bool prepared, const Dims& d) {
@@ -71,6 +71,10 @@ int validate(const lddmm_params* p, Dims* d) {
     return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
   if (p->state != LDDMM_STATE_IMAGE && p->state != LDDMM_STATE_DEFORMATION)
     return fail(LDDMM_E_INVALID_ARG, "unknown state");
+  if (p->integrator != LDDMM_EULER && p->integrator != LDDMM_RK4)
+    return fail(LDDMM_E_INVALID_ARG, "unknown integrator");
+  if (p->integrator == LDDMM_RK4 && p->state != LDDMM_STATE_IMAGE)
+    return fail(LDDMM_E_INVALID_ARG, "LDDMM_RK4 integrates the image state only");
   Dims& o = *d;
   o = Dims{};
   for (int j = 0; j < 3; ++j) {
@@ -96,11 +100,19 @@ int validate(const lddmm_params* p, Dims* d) {
   o.sigma = p->sigma;
   o.hessian = p->hessian;
   o.state = p->state;
+  o.integrator = p->integrator;
   // each block keeps its tile in LDS (at most the 160 KiB of a gfx950 workgroup)
   if (synth_shared_bytes(o) > kMaxLds || prods_shared_bytes(o, 9) > kMaxLds || colstep_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
   if (gridstep_shared_bytes(o) > kMaxLds || src_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");
+  return LDDMM_OK;
+}
+
+// The adjoint sweeps are transposes of Euler steps: only shooting takes RK4.
+int euler_only(const Dims& d) {
+  if (d.integrator != LDDMM_EULER)
+    return fail(LDDMM_E_INVALID_ARG, "LDDMM_RK4 is for lddmm_shoot and lddmm_geodesic_energy only");
   return LDDMM_OK;
 }
 
@@ -514,11 +526,47 @@ int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m
   return LDDMM_OK;
 }
 
+int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, void* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (which != LDDMM_SYMBOL_L && which != LDDMM_SYMBOL_K) return fail(LDDMM_E_INVALID_ARG, "unknown symbol");
+  if (!in || !out) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(in, e.tmph)) != hipSuccess) return hip_fail(err, "load");
+  if ((err = e.store_band(e.tmph, nullptr, 0.f, out, which == LDDMM_SYMBOL_L ? e.Lsym : e.Ksym)) != hipSuccess)
+    return hip_fail(err, "store");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energies, void* ws,
+                          size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!v0 || !energies) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  if ((err = e.geodesic_energies(energies)) != hipSuccess) return hip_fail(err, "geodesic energies");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
 int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
                    void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream) {
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = euler_only(d))) return rc;
   if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
   set_prepared(ws, false, d);
@@ -542,6 +590,7 @@ int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, s
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = euler_only(d))) return rc;
   if (!dv0 || !Hdv) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if (dv0 == Hdv) return fail(LDDMM_E_INVALID_ARG, "Hdv may not alias dv0");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
@@ -568,6 +617,7 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = euler_only(d))) return rc;
   if (!I0 || !I1 || !v0_inout) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if (gn_iters < 0 || pcg_iters < 1) return fail(LDDMM_E_INVALID_ARG, "bad iteration counts");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
@@ -611,7 +661,8 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
   std::vector<size_t> off(n);
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
-    const int rc = validate(&p[i], &dims[i]);
+    int rc = validate(&p[i], &dims[i]);
+    if (!rc) rc = euler_only(dims[i]);
     if (rc) return fail(rc, "pair " + std::to_string(i) + ": " + g_last_error);
     if (!I0[i] || !I1[i] || !v0_inout[i])
       return fail(LDDMM_E_INVALID_ARG, "pair " + std::to_string(i) + ": null input or output");

@@ -26,6 +26,7 @@ struct Dims {
   double alpha, sigma;
   int hessian;      // 0: couplings kept (paper reading), 1: dropped, 2: full Newton
   int state;        // 0: image state on the grid; 1: deformation state in the band
+  int integrator;   // 0: Euler; 1: RK4 shooting with midpoint transport (shooting only)
 };
 
 // ---------------------------------------------------------------- tables
@@ -137,8 +138,9 @@ struct GridStepArgs {
 hipError_t launch_twiddles(float2* dst, int K, int G, int mode, hipStream_t st);
 hipError_t launch_symbols(float* Lsym, float* Ksym, const Dims& d, hipStream_t st);
 hipError_t launch_full_to_half(const float2* full, float2* half, const Dims& d, hipStream_t st);
+// full = expand(a + cb b), times the band symbol sym when given
 hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float2* full,
-                               const Dims& d, hipStream_t st);
+                               const Dims& d, hipStream_t st, const float* sym = nullptr);
 // Inverse stage 0; `trans` writes the padded-grid layout [v][x0][kh][k1]
 // instead of [v][x0][k1][kh].
 // Output [nvar][G0][Kh][K1]; image_grid selects the timer family of the launch.
@@ -166,6 +168,10 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
 hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st);
+// One transport step with midpoint departure points: vel is the mid-step
+// velocity [3][nN]; dst(x) = src(x - dt vel(x - dt/2 vel(x))).
+hipError_t launch_sl_rk2(const float* src, const float* vel, float* dst, float dt, const Dims& d,
+                         hipStream_t st);
 // Fused t = 1 tail on the tuned shapes: image-matching source (with the
 // r d_j a term of the full Newton product when r is given), forward
 // stages 2 and 1 (partial over 64-row chunks of x1) into P

@@ -36,7 +36,7 @@ class Engine {
   hipError_t init_tables();
   // band I/O in the caller's full layout
   hipError_t load_band(const void* full, float2* half);
-  hipError_t store_band(const float2* a, const float2* b, float cb, void* full);
+  hipError_t store_band(const float2* a, const float2* b, float cb, void* full, const float* sym = nullptr);
 
   // Called after the band step that produces v_n has been enqueued.
   using StepHook = std::function<hipError_t(int)>;
@@ -47,6 +47,11 @@ class Engine {
   hipError_t forward(const float* I0);
   // Shooting and transport without caches; *m_out = m_nt.
   hipError_t forward_light(const float* I0, const float** m_out);
+  // Band shooting by classical RK4 steps from V[0] (no caches).
+  hipError_t shoot_band_rk4();
+  // <L~ v_n, v_n> (FP64) for n = 0..nt into out[0..nt] (device), after shooting
+  // with the integrator of the parameters.
+  hipError_t geodesic_energies(double* out);
   // E, E_reg, E_data of (V[0], m_nt) into scal[0..2] (device).
   hipError_t energy(const float* mnt, const float* I1);
   // U, W sweeps from m_nt; g_V = V[0] + W[0] into g_out (half) if non-null.
@@ -109,6 +114,7 @@ class Engine {
   hipError_t grid_source(int n, const float* dmn, hipStream_t s);
   // deformation state (paper §3.3)
   hipError_t forward_def(const float* I0);
+  hipError_t forward_rk(const float* I0, const float** m_out);
   hipError_t tail_def(const float* I1);
   hipError_t hessvec_def(const float2* dvh, float2* out);
   hipError_t hessvec_sweep(float2* out);

@@ -191,8 +191,8 @@ hipError_t Engine::load_band(const void* full, float2* half) {
   return launch_full_to_half(static_cast<const float2*>(full), half, d_, st_);
 }
 
-hipError_t Engine::store_band(const float2* a, const float2* b, float cb, void* full) {
-  return launch_half_to_full(a, b, cb, static_cast<float2*>(full), d_, st_);
+hipError_t Engine::store_band(const float2* a, const float2* b, float cb, void* full, const float* sym) {
+  return launch_half_to_full(a, b, cb, static_cast<float2*>(full), d_, st_, sym);
 }
 
 float2* Engine::t1(int g, int c) const {
@@ -418,6 +418,7 @@ hipError_t Engine::forward(const float* I0) {
 
 // Shooting and transport without the caches; returns m_nt in *m_out.
 hipError_t Engine::forward_light(const float* I0, const float** m_out) {
+  if (d_.integrator == 1) return forward_rk(I0, m_out);
   if (d_.state) {
     // the displacement chain reads the cached trajectory fields, so the
     // deformation state always runs the caching forward
@@ -444,6 +445,77 @@ hipError_t Engine::forward_light(const float* I0, const float** m_out) {
   TRY(record(aux_, nt + 1));
   TRY(wait(st_, nt + 1));
   *m_out = cur;
+  return hipSuccess;
+}
+
+// Classical RK4 steps of the band EPDiff, f(v) = -K~ F(ad*_v(L~ v)): each stage
+// is the usual synthesis and products launch pair and one column launch;
+// the column launches of stages 1-3 form the next stage value (with its
+// stage-0 groups) and the running sum v_n + dt/6 k1 + dt/3 k2 + dt/3 k3,
+// that of stage 4 adds dt/6 k4 into V[n+1] and forms the next step's groups.
+hipError_t Engine::shoot_band_rk4() {
+  const float dt = 1.0f / d_.nt;
+  const float cst[3] = {0.5f * dt, 0.5f * dt, dt};                // stage value = v_n + c k
+  const float wsum[4] = {dt / 6.0f, dt / 3.0f, dt / 3.0f, dt / 6.0f};  // weights of the sum
+  float2* va = dU[0];
+  float2* acc[2] = {dU[1], dW[0]};
+  TRY(inv0_groups(V[0], 0, V[0], 1));
+  for (int n = 0; n < d_.nt; ++n) {
+    const bool next = n + 1 < d_.nt;
+    int cur = 0;
+    for (int stg = 0; stg < 4; ++stg) {
+      TRY(mstep(PROG_SHOOT, 3, nullptr, nullptr, nullptr));
+      ColJob jobs[6];
+      int nj = 0;
+      if (stg < 3) {
+        for (int c = 0; c < 3; ++c)
+          jobs[nj++] = col_job(c, c, -cst[stg], 1, -1, 0.f, 0, V[n], nullptr, 0.f, va, 0, 0, 1, 1);
+        const float2* base = stg == 0 ? V[n] : acc[cur];
+        for (int c = 0; c < 3; ++c)
+          jobs[nj++] = col_job(c, c, -wsum[stg], 1, -1, 0.f, 0, base, nullptr, 0.f, acc[1 - cur], -1, 0, -1, 0);
+        cur = 1 - cur;
+      } else {
+        for (int c = 0; c < 3; ++c)
+          jobs[nj++] = col_job(c, c, -wsum[3], 1, -1, 0.f, 0, acc[cur], nullptr, 0.f, V[n + 1], next ? 0 : -1, 0,
+                               next ? 1 : -1, 1);
+      }
+      TRY(colstep(jobs, nj));
+    }
+  }
+  return hipSuccess;
+}
+
+// RK4 shooting, then the image transport with midpoint departure points
+// whose mid-step velocity is iota of the band average of v_n and v_{n+1}.
+hipError_t Engine::forward_rk(const float* I0, const float** m_out) {
+  const float dt = 1.0f / d_.nt;
+  TRY(shoot_band_rk4());
+  float2* diff = dW[1];
+  float2* vmid = dV[0];
+  const float* cur = I0;
+  for (int n = 0; n < d_.nt; ++n) {
+    TRY(launch_axpy_band(V[n + 1], V[n], -1.f, diff, 3 * d_.nb, st_));
+    TRY(launch_axpy_band(V[n], diff, 0.5f, vmid, 3 * d_.nb, st_));
+    TRY(grid_stage0(vmid, T1N[0], st_));
+    GridStepArgs a{};
+    a.t1 = T1N[0];
+    a.op = 0;
+    a.vout = vg[0];
+    TRY(launch_gridstep(a, d_, twN_, st_));
+    float* dst = mlight[n & 1];
+    TRY(launch_sl_rk2(cur, vg[0], dst, dt, d_, st_));
+    cur = dst;
+  }
+  *m_out = cur;
+  return hipSuccess;
+}
+
+hipError_t Engine::geodesic_energies(double* out) {
+  if (d_.integrator == 1)
+    TRY(shoot_band_rk4());
+  else
+    TRY(shoot_band(false));
+  for (int n = 0; n <= d_.nt; ++n) TRY(launch_band_dot(V[n], V[n], Lsym, d_, partial, out + n, 1.0, st_));
   return hipSuccess;
 }
 

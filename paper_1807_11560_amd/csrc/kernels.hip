@@ -193,7 +193,8 @@ __global__ void k_full_to_half(const float2* __restrict__ full, float2* __restri
 
 // full = expand(a + cb*b)
 __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __restrict__ b, float cb,
-                               float2* __restrict__ full, int K0, int K1, int K2) {
+                               const float* __restrict__ sym, float2* __restrict__ full, int K0, int K1,
+                               int K2) {
   const int Kh = K2 / 2;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * K0 * K1 * K2) return;
@@ -205,6 +206,11 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
   size_t j = (size_t)c * K0 * K1 * Kh + ((size_t)s0 * K1 + s1) * Kh + s2;
   float2 v = a[j];
   if (b) { v.x += cb * b[j].x; v.y += cb * b[j].y; }
+  if (sym) {
+    const float w = sym[((size_t)s0 * K1 + s1) * Kh + s2];
+    v.x *= w;
+    v.y *= w;
+  }
   if (conj) v.y = -v.y;
   full[i] = v;
 }
@@ -1420,6 +1426,53 @@ __global__ void __launch_bounds__(256) k_sl(const float* __restrict__ src,
   dst[gi] = c0 + w0 * (c1 - c0);
 }
 
+// Periodic trilinear interpolation of f at voxel coordinates X (floor cell).
+template <class G>
+__device__ __forceinline__ float trilinear(const float* __restrict__ f, float X0, float X1, float X2, int i0,
+                                           int i1, int i2, G gs) {
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2();
+  // a non-finite coordinate must not turn into an out-of-range index
+  if (!isfinite(X0)) X0 = (float)i0;
+  if (!isfinite(X1)) X1 = (float)i1;
+  if (!isfinite(X2)) X2 = (float)i2;
+  const float f0 = floorf(X0), f1 = floorf(X1), f2 = floorf(X2);
+  const float w0 = X0 - f0, w1 = X1 - f1, w2 = X2 - f2;
+  int a0 = (int)f0 % N0; if (a0 < 0) a0 += N0;
+  int a1 = (int)f1 % N1; if (a1 < 0) a1 += N1;
+  int a2 = (int)f2 % N2; if (a2 < 0) a2 += N2;
+  const int b0 = (a0 + 1 == N0) ? 0 : a0 + 1;
+  const int b1 = (a1 + 1 == N1) ? 0 : a1 + 1;
+  const int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
+  auto at = [&](int u, int v, int w) { return f[((long long)u * N1 + v) * N2 + w]; };
+  const float c00 = at(a0, a1, a2) + w2 * (at(a0, a1, b2) - at(a0, a1, a2));
+  const float c01 = at(a0, b1, a2) + w2 * (at(a0, b1, b2) - at(a0, b1, a2));
+  const float c10 = at(b0, a1, a2) + w2 * (at(b0, a1, b2) - at(b0, a1, a2));
+  const float c11 = at(b0, b1, a2) + w2 * (at(b0, b1, b2) - at(b0, b1, a2));
+  const float c0 = c00 + w1 * (c01 - c00);
+  const float c1 = c10 + w1 * (c11 - c10);
+  return c0 + w0 * (c1 - c0);
+}
+
+// One transport step with midpoint departure points: X_h = x - dt/2 v(x),
+// X = x - dt v(X_h) (v trilinear at X_h), dst = src(X).
+template <class G>
+__global__ void __launch_bounds__(256) k_sl_rk2(const float* __restrict__ src, const float* __restrict__ vel,
+                                                float* __restrict__ dst, float dt, G gs) {
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2();
+  const long long nN = (long long)N0 * N1 * N2;
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= nN) return;
+  const int i2 = (int)(gi % N2), i1 = (int)((gi / N2) % N1), i0 = (int)(gi / ((long long)N1 * N2));
+  const float h0 = (float)i0 - 0.5f * dt * vel[gi] * (float)N0;
+  const float h1 = (float)i1 - 0.5f * dt * vel[nN + gi] * (float)N1;
+  const float h2 = (float)i2 - 0.5f * dt * vel[2 * nN + gi] * (float)N2;
+  const float v0 = trilinear(vel, h0, h1, h2, i0, i1, i2, gs);
+  const float v1 = trilinear(vel + nN, h0, h1, h2, i0, i1, i2, gs);
+  const float v2 = trilinear(vel + 2 * nN, h0, h1, h2, i0, i1, i2, gs);
+  dst[gi] = trilinear(src, (float)i0 - dt * v0 * (float)N0, (float)i1 - dt * v1 * (float)N1,
+                      (float)i2 - dt * v2 * (float)N2, i0, i1, i2, gs);
+}
+
 // ------------------- image-term source and forward stage 2 (N grid)
 // s_j = coef * [(a - b) * d_j m + res * d_j a] (periodic central
 // differences; b and res may be null) at the points of 16 x1 rows of plane x0, contracted
@@ -2112,9 +2165,9 @@ hipError_t launch_full_to_half(const float2* full, float2* half, const Dims& d, 
 }
 
 hipError_t launch_half_to_full(const float2* a, const float2* b, float cb, float2* full,
-                               const Dims& d, hipStream_t st) {
+                               const Dims& d, hipStream_t st, const float* sym) {
   long long n = 3LL * d.K[0] * d.K[1] * d.K[2];
-  hipLaunchKernelGGL(k_half_to_full, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, cb, full, d.K[0],
+  hipLaunchKernelGGL(k_half_to_full, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, cb, sym, full, d.K[0],
                      d.K[1], d.K[2]);
   return hipGetLastError();
 }
@@ -2447,6 +2500,15 @@ hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, c
     return hipGetLastError();
   });
   return e;
+}
+
+hipError_t launch_sl_rk2(const float* src, const float* vel, float* dst, float dt, const Dims& d,
+                         hipStream_t st) {
+  timer_work(KF_SL, 140.0 * (double)d.nN, 20.0 * (double)d.nN);
+  return with_grid(d, [&](auto gs) {
+    LAUNCH_TIMED(KF_SL, (k_sl_rk2<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, gs);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,

@@ -38,6 +38,10 @@ GN_CLASSICAL = 1
 NEWTON = 2
 STATE_IMAGE = 0
 STATE_DEFORMATION = 1
+EULER = 0
+RK4 = 1
+SYMBOL_L = 0
+SYMBOL_K = 1
 KF_SYNTH, KF_GRID, KF_SL, KF_INV0, KF_COLUMN, KF_PRODS = 1, 2, 3, 4, 5, 6
 KF_INV0_GRID, KF_FWD1_GRID, KF_FWD0_GRID, KF_SRC = 7, 8, 9, 10
 KERNEL_FAMILIES = {KF_SYNTH: "k_synth", KF_GRID: "k_gridstep", KF_SL: "k_sl", KF_INV0: "k_inv0 (padded grid)",
@@ -58,6 +62,7 @@ class LddmmParams(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("hessian", ctypes.c_int32),
         ("state", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -82,6 +87,8 @@ _SIGS = {
     "lddmm_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "lddmm_shoot": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_gradient": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_geodesic_energy": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_apply_symbol": (ctypes.c_int, [_P, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_hessvec": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_register": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(LddmmStats), ctypes.c_int32, _vp,
@@ -134,6 +141,7 @@ class Problem:
     spectral: Tuple[int, int, int] = (0, 0, 0)
     hessian: int = GN_PAPER
     state: int = STATE_IMAGE
+    integrator: int = EULER
 
     def c_params(self) -> LddmmParams:
         p = LddmmParams()
@@ -149,6 +157,7 @@ class Problem:
         p.precision = FP32
         p.hessian = int(self.hessian)
         p.state = int(self.state)
+        p.integrator = int(self.integrator)
         return p
 
     def workspace_bytes(self) -> int:
@@ -213,6 +222,28 @@ def shoot(problem: Problem, I0, v0, ws: Workspace, want_v1=False, stream=None):
     _check(_lib.lddmm_shoot(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(v0), _ptr(m1), _ptr(v1),
                             ws.ptr, ws.nbytes, _stream(stream)), "lddmm_shoot")
     return (m1, v1) if want_v1 else m1
+
+
+def apply_symbol(problem: Problem, which: int, x, ws: Workspace, out=None, stream=None):
+    """L~ x (which = SYMBOL_L) or K~ x (SYMBOL_K) on a band field (lddmm_apply_symbol)."""
+    torch = _torch()
+    _need(x, torch.complex64, problem.band_shape, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(_lib.lddmm_apply_symbol(ctypes.byref(problem.c_params()), int(which), _ptr(x), _ptr(out), ws.ptr,
+                                   ws.nbytes, _stream(stream)), "lddmm_apply_symbol")
+    return out
+
+
+def geodesic_energy(problem: Problem, v0, ws: Workspace, stream=None):
+    """<L~ v_n, v_n> for n = 0..nt along the shot trajectory (lddmm_geodesic_energy):
+    a float64 device tensor of nt + 1 values."""
+    torch = _torch()
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    out = torch.empty(problem.time_steps + 1, dtype=torch.float64, device=v0.device)
+    _check(_lib.lddmm_geodesic_energy(ctypes.byref(problem.c_params()), _ptr(v0), _ptr(out), ws.ptr, ws.nbytes,
+                                      _stream(stream)), "lddmm_geodesic_energy")
+    return out
 
 
 def gradient(problem: Problem, I0, I1, v0, ws: Workspace, stream=None):

@@ -36,15 +36,16 @@ def test_params_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lddmm.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu", sizeof(lddmm_params),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu", sizeof(lddmm_params),'
         ' offsetof(lddmm_params, alpha), offsetof(lddmm_params, hessian),'
-        ' offsetof(lddmm_params, state),'
+        ' offsetof(lddmm_params, state), offsetof(lddmm_params, integrator),'
         ' sizeof(lddmm_stats), offsetof(lddmm_stats, trials)); return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [ctypes.sizeof(L.LddmmParams), L.LddmmParams.alpha.offset,
-                   L.LddmmParams.hessian.offset, L.LddmmParams.state.offset, ctypes.sizeof(L.LddmmStats),
+                   L.LddmmParams.hessian.offset, L.LddmmParams.state.offset, L.LddmmParams.integrator.offset,
+                   ctypes.sizeof(L.LddmmStats),
                    L.LddmmStats.trials.offset]
 
 
@@ -66,6 +67,8 @@ def test_workspace_bytes_scales_with_problem():
     (dict(time_steps=0), L.E_INVALID_ARG),
     (dict(hessian=7), L.E_INVALID_ARG),
     (dict(state=2), L.E_INVALID_ARG),
+    (dict(integrator=2), L.E_INVALID_ARG),
+    (dict(integrator=1, state=1), L.E_INVALID_ARG),   # RK4 integrates the image state only
 ])
 def test_validation_rejects(kw, code):
     base = dict(grid=(64, 64, 64), band=(16, 16, 16))
@@ -148,3 +151,25 @@ def test_batch_validates_before_touching_the_device():
     assert call(2, arr, fake, fake, fake, 1, 0, 0, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
     assert call(2, arr, fake, fake, fake, 1, 1, 65, None, 0, None, None, ws, 1 << 40, null) == L.E_INVALID_ARG
     assert call(2, arr, fake, fake, fake, 1, 1, 0, None, 0, None, None, ws, 64, null) == L.E_WORKSPACE
+
+
+def test_rk4_is_for_shooting_only():
+    """The adjoint sweeps are transposes of Euler steps: gradient, hessvec,
+    register and the batch reject LDDMM_RK4 on the host; the workspace query
+    and the shooting entry points accept it."""
+    lib = L.raw()
+    prob = L.Problem(grid=(32, 32, 32), band=(8, 8, 8), integrator=L.RK4)
+    assert prob.workspace_bytes() > 0
+    p = prob.c_params()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    big = 1 << 40
+    assert lib.lddmm_gradient(ctypes.byref(p), fake, fake, fake, fake, null, fake, big, null) == L.E_INVALID_ARG
+    assert lib.lddmm_hessvec(ctypes.byref(p), fake, ctypes.c_void_p(0x2000), fake, big, null) == L.E_INVALID_ARG
+    assert lib.lddmm_register(ctypes.byref(p), fake, fake, fake, 1, 1, None, 0, fake, big, null) == L.E_INVALID_ARG
+    assert "lddmm_shoot" in lib.lddmm_last_error().decode()
+    arr = (L.LddmmParams * 1)(p)
+    ptrs = (ctypes.c_void_p * 1)(0x1000)
+    assert lib.lddmm_register_batch(1, arr, ptrs, ptrs, ptrs, 1, 1, 0, None, 0, None, None, fake, big,
+                                    null) == L.E_INVALID_ARG
+    assert lib.lddmm_geodesic_energy(ctypes.byref(p), null, fake, fake, big, null) == L.E_INVALID_ARG
