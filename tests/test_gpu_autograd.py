@@ -55,7 +55,7 @@ def test_backward_is_the_l2_gradient():
     e.backward()
     torch.cuda.synchronize()
     got = v0.grad.detach().cpu().numpy().astype(np.complex128)
-    eg, eE = rel(got, ref), abs(float(e) - E[0]) / E[0]
+    eg, eE = rel(got, ref), abs(float(e.detach()) - E[0]) / E[0]
     print(f"autograd l2 gradient rel {eg:.2e}, energy rel {eE:.2e}")
     assert eg < 1e-4 and eE < 1e-5
     # the chain rule through a scalar factor

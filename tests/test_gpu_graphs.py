@@ -111,7 +111,7 @@ def test_timer_samples_one_launch_in_every(setup):
     lib.gradient(prob, I0, I1, v0, ws)
     counts = {}
     for every in (1, 4):
-        lib.kernel_timer(lib.KF_PRODS, every)
+        lib.kernel_timer(lib.KF_SL, every)  # ten identical launches per product
         for _ in range(3):
             lib.hessvec(prob, dirs[1], ws)
         torch.cuda.synchronize()
