@@ -566,7 +566,9 @@ __global__ void k_synth_tables(const float2* inv1, const float2* inv2, float* w1
 // ------------------------------------------------ Lie products on the padded grid
 // One block per (x0, R rows), one thread per point (R*M2 threads).  Reads
 // the new and cached groups, forms the products of the program and
-// contracts them over x2 (forward stage 2) into s1[o][kh][x0][x1].
+// contracts them over x2 (forward stage 2) into s1[o][kh][x0][x1]: on the
+// matrix cores when M2 % 4 == 0 (rows (o, r) x columns (kh re | kh im), depth
+// x2), else one thread per output.
 template <class S>
 __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
   extern __shared__ float smp[];
@@ -576,9 +578,10 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
   const int x1b = blockIdx.x * R;
   const int rv = min(R, M1 - x1b);
   const int P = R * M2;
+  const int LV = M2 + 2;  // product rows: 2 mod 4 floats, an MFMA A operand read along rows
   const long long nM = (long long)M0 * M1 * M2;
   float2* wfx = (float2*)smp;                  // [M2][Kh]
-  float* outv = (float*)(wfx + M2 * Kh);       // [nout][R][M2]
+  float* outv = (float*)(wfx + M2 * Kh);       // [nout][R][LV]
   // the stage-2 table goes to LDS after the products (its loads overlap theirs)
   const int nw = M2 * Kh;
   const bool wreg = nw <= 256 * 4;
@@ -690,7 +693,8 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
           break;
       }
     }
-    for (int i = 0; i < a.nout; ++i) outv[(size_t)i * P + p] = o[i];
+    if (p < P)
+      for (int i = 0; i < a.nout; ++i) outv[((size_t)i * R + p / M2) * LV + p % M2] = o[i];
   }
   if (wreg)
     rw.store(nw, [&](int i, float2 v) { wfx[i] = v; });
@@ -698,10 +702,39 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
     batched_fill<float2>(nw, [&](int i) { return tw.fwd2[(size_t)(i % Kh) * M2 + i / Kh]; },
                          [&](int i, float2 v) { wfx[i] = v; });
   __syncthreads();
+  if (M2 % 4 == 0) {
+    // forward stage 2 on the matrix cores: D[row][kh] = sum_x2 outv[row][x2] fwd2[kh][x2],
+    // row = o R + r, one 16-row tile (re and im columns of 16 kh) per wave and step
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int rows = a.nout * R, trow = (rows + 15) / 16, tcol = (Kh + 15) / 16;
+    for (int t = wave; t < trow * tcol; t += (int)(blockDim.x >> 6)) {
+      const int ti = t / tcol, tj = t % tcol;
+      const int arow = ti * 16 + li, kh = tj * 16 + li;
+      const float* A = outv + (size_t)(arow < rows ? arow : 0) * LV + lk;
+      const float2* B = wfx + (size_t)lk * Kh + (kh < Kh ? kh : 0);
+      floatx4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < M2 / 4; ++ks) {
+        const float av = (arow < rows) ? A[4 * ks] : 0.f;
+        const float2 bv = (kh < Kh) ? B[(size_t)4 * ks * Kh] : make_float2(0.f, 0.f);
+        dre = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.x, dre, 0, 0, 0);
+        dim = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.y, dim, 0, 0, 0);
+      }
+      if (kh < Kh) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = ti * 16 + 4 * lk + rr;
+          const int o = row / R, r = row % R;
+          if (row < rows && r < rv)
+            a.s1[(((size_t)o * Kh + kh) * M0 + x0) * M1 + x1b + r] = make_float2(dre[rr], dim[rr]);
+        }
+      }
+    }
+    return;
+  }
   // forward stage 2: one thread per (o, r, kh)
   for (int i = threadIdx.x; i < a.nout * rv * Kh; i += blockDim.x) {
     const int o = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
-    const float* row = outv + (size_t)o * P + r * M2;
+    const float* row = outv + ((size_t)o * R + r) * LV;
     float2 acc = make_float2(0.f, 0.f);
     for (int x2 = 0; x2 < M2; ++x2) {
       const float2 w = wfx[(size_t)x2 * Kh + kh];
@@ -2273,7 +2306,7 @@ static int prod_rows(const Dims& d) {
 }
 
 size_t prods_shared_bytes(const Dims& d, int nout) {
-  return (size_t)d.M[2] * d.Kh * sizeof(float2) + (size_t)nout * prod_rows(d) * d.M[2] * sizeof(float);
+  return (size_t)d.M[2] * d.Kh * sizeof(float2) + (size_t)nout * prod_rows(d) * (d.M[2] + 2) * sizeof(float);
 }
 
 hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hipStream_t st) {
