@@ -159,18 +159,26 @@ __global__ void k_twiddles(float2* dst, int K, int G, int mode) {
   dst[i] = make_float2((float)re, (float)im);
 }
 
+// L~ and K~ = 1 / L~ at the band slot (q0, q1, k2) (FP64, rounded once);
+// kernels that need a few symbols per thread form them here instead of
+// loading them from the tables at a stride of Kh.
+__device__ __forceinline__ float2 band_symbols(int q0, int q1, int k2, int K0, int K1, int s, double alpha) {
+  const int k0 = q0 < K0 / 2 ? q0 : q0 - K0;
+  const int k1 = q1 < K1 / 2 ? q1 : q1 - K1;
+  const double tp = 2.0 * M_PI;
+  const double lap = tp * tp * ((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
+  const double base = 1.0 + alpha * lap;
+  double L = 1.0;
+  for (int e = 0; e < s; ++e) L *= base;
+  return make_float2((float)L, (float)(1.0 / L));
+}
+
 __global__ void k_symbols(float* Lsym, float* Ksym, int K0, int K1, int Kh, int s, double alpha) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K0 * K1 * Kh) return;
-  int q0 = i / (K1 * Kh), q1 = (i / Kh) % K1, k2 = i % Kh;
-  int k0 = q0 < K0 / 2 ? q0 : q0 - K0;
-  int k1 = q1 < K1 / 2 ? q1 : q1 - K1;
-  const double tp = 2.0 * M_PI;
-  double lap = tp * tp * ((double)k0 * k0 + (double)k1 * k1 + (double)k2 * k2);
-  double base = 1.0 + alpha * lap, L = 1.0;
-  for (int e = 0; e < s; ++e) L *= base;
-  Lsym[i] = (float)L;
-  Ksym[i] = (float)(1.0 / L);
+  const float2 lk = band_symbols(i / (K1 * Kh), (i / Kh) % K1, i % Kh, K0, K1, s, alpha);
+  Lsym[i] = lk.x;
+  Ksym[i] = lk.y;
 }
 
 // ------------------------------------------------------- layout changes
@@ -935,8 +943,7 @@ template <class S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
                                                       const float2* __restrict__ w0f,
                                                       const float2* __restrict__ w0i,
-                                                      const float* __restrict__ Lsym,
-                                                      const float* __restrict__ Ksym, float invG,
+                                                      double alpha, int spow, float invG,
                                                       int nparts) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
@@ -1001,8 +1008,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
       pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
       pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
-      pks[r] = ok ? Ksym[idx] : 0.f;
-      pls[r] = ok ? Lsym[idx] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = wave * 16 + 4 * lk + r;
+      const bool ok = k0 < K && k1 < K;
+      const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
+      pks[r] = ok ? sym.y : 0.f;
+      pls[r] = ok ? sym.x : 0.f;
     }
   }
   // ---- stores
@@ -1871,9 +1884,8 @@ struct TailJobs {
 };
 template <class S, int NG0, int NP>
 __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __restrict__ w0n,
-                                                   const float2* __restrict__ w0i,
-                                                   const float* __restrict__ Lsym,
-                                                   const float* __restrict__ Ksym, float invG) {
+                                                   const float2* __restrict__ w0i, double alpha,
+                                                   int spow, float invG) {
   constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
   constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15, C = K * Kh;
   constexpr int LB = 18, LA = NG0 + 1, LW0I = K + 1, LOB = 18;  // A operands: odd complex strides
@@ -1909,9 +1921,9 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     for (int r = 0; r < 4; ++r) {
       const int k0 = wave * 16 + 4 * lk + r;
       const bool ok = k0 < K && k1 < K;
-      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
-      pks[r] = ok ? Ksym[idx] : 0.f;
-      pls[r] = ok ? Lsym[idx] : 0.f;
+      const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
+      pks[r] = ok ? sym.y : 0.f;
+      pls[r] = ok ? sym.x : 0.f;
     }
   }
   rb.store(DEPTH * 8, [&](int i, float4 v) { st4(&bs[i / 8][2 * (i % 8)], v); });
@@ -2400,7 +2412,7 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
       const double N0 = j.t1n ? d.N[0] : 0.0;
       fl += terms * (M0 * M1 * K1 + K0 * K1 * M0) * Kh * 8.0 + j.nt1 * 2.0 * M0 * K0 * K1 * Kh * 8.0 +
             N0 * K0 * K1 * Kh * 8.0;
-      by += terms * M0 * M1 * Kh * 8.0 + K0 * K1 * Kh * 8.0 * (2 + (j.base != nullptr) + (j.extra != nullptr)) +
+      by += terms * M0 * M1 * Kh * 8.0 + K0 * K1 * Kh * 8.0 * (1 + (j.base != nullptr) + (j.extra != nullptr)) +
             j.nt1 * 2.0 * M0 * K1 * Kh * 8.0 + N0 * K1 * Kh * 8.0;
     }
     timer_work(KF_COLUMN, fl, by);
@@ -2424,16 +2436,16 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   const int nparts = (d.Kh * njobs * ktiles <= 128 && min_tiles >= 8) ? 2 : 1;
   const dim3 cgrid(d.Kh, njobs, ktiles * nparts);
   if (band_iso(d, 32, 48)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
-                 Ksym, invG, nparts);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                 d.s, invG, nparts);
     e = hipGetLastError();
   } else if (band_iso(d, 16, 24)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
-                 Ksym, invG, nparts);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                 d.s, invG, nparts);
     e = hipGetLastError();
   } else if (band_iso(d, 24, 36)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, Lsym,
-                 Ksym, invG, nparts);
+    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                 d.s, invG, nparts);
     e = hipGetLastError();
   } else {
     dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
@@ -2633,14 +2645,14 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
   const float2* w0i = coltab + (size_t)M * round_up(K, 16) + (size_t)round_up(K, 16) * M;
   const float invG = (float)(1.0 / d.nN);
   timer_work(KF_FWD0_GRID, 3.0 * K * C * N * np * 8.0 + 3.0 * 2.0 * M * K * C * 8.0,
-             np * 3.0 * N * C * 8.0 + 3.0 * K * C * 8.0 + 3.0 * 2.0 * 2.0 * M * C * 8.0 + 8.0 * 3.0 * K * C);
+             np * 3.0 * N * C * 8.0 + 3.0 * K * C * 8.0 + 3.0 * 2.0 * 2.0 * M * C * 8.0);
   const dim3 grid(Kh, 3, round_up(K, 16) / 16);
   if (N == 128)
     LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<32, 48>, 128, 2>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
-                 Lsym, Ksym, invG);
+                 d.alpha, d.s, invG);
   else
     LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<16, 24>, 64, 1>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
-                 Lsym, Ksym, invG);
+                 d.alpha, d.s, invG);
   return hipGetLastError();
 }
 
