@@ -440,16 +440,18 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   }
   __syncthreads();
   // GEMM1 on this tile's 16 rows: var 0 = pp (plain stage 0, plain stage 1),
-  // 1 = p1 (d1), 2 = 0p (d0 input).  A wave runs kSynthT tiles at once, their
-  // matrix instructions interleaved, operands fetched four k-steps ahead.
+  // 1 = p1 (d1), 2 = 0p (d0 input).  Wave w takes tiles w, w + 4, w + 8, ...
+  // and runs up to kSynthT of them at once, their matrix instructions
+  // interleaved, operands fetched four k-steps ahead.
   const int tj1 = N1 / 16, nj1 = 3 * tj1;
-  for (int j0 = wave; j0 < nj1; j0 += 4 * kSynthT) {
-    const float* A[kSynthT];
-    const float* B[kSynthT];
-    floatx4 acc[kSynthT];
+  auto gemm1 = [&](auto TT, int j0) {
+    constexpr int T = decltype(TT)::value;
+    const float* A[T];
+    const float* B[T];
+    floatx4 acc[T];
 #pragma unroll
-    for (int t = 0; t < kSynthT; ++t) {
-      const int job = min(j0 + 4 * t, nj1 - 1);  // a missing tile recomputes the last one, unstored
+    for (int t = 0; t < T; ++t) {
+      const int job = j0 + 4 * t;
       const int var = job / tj1, tj = job % tj1;
       const int vs = (var == 2), vt = (var == 1);
       A[t] = w1s + ((size_t)vt * 16 + li) * lda1 + lk;
@@ -457,9 +459,9 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < K2r / 4; k0 += 4) {
-      float av[kSynthT][4], bv[kSynthT][4];
+      float av[T][4], bv[T][4];
 #pragma unroll
-      for (int t = 0; t < kSynthT; ++t)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ks = k0 + u;
@@ -469,18 +471,27 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int t = 0; t < kSynthT; ++t)
+        for (int t = 0; t < T; ++t)
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < kSynthT; ++t) {
+    for (int t = 0; t < T; ++t) {
       const int job = j0 + 4 * t;
-      if (job >= nj1) break;
       const int var = job / tj1, tj = job % tj1;
-      float* T = t2s + ((size_t)var * 16 + 4 * lk) * ldt2 + tj * 16 + li;
+      float* Tp = t2s + ((size_t)var * 16 + 4 * lk) * ldt2 + tj * 16 + li;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) T[(size_t)r * ldt2] = acc[t][r];
+      for (int r = 0; r < 4; ++r) Tp[(size_t)r * ldt2] = acc[t][r];
     }
+  };
+  static_assert(kSynthT == 3, "tile groups of one to three");
+  for (int j0 = wave; j0 < nj1; j0 += 4 * kSynthT) {
+    const int cnt = min(kSynthT, (nj1 - j0 + 3) / 4);
+    if (cnt == 3)
+      gemm1(std::integral_constant<int, 3>{}, j0);
+    else if (cnt == 2)
+      gemm1(std::integral_constant<int, 2>{}, j0);
+    else
+      gemm1(std::integral_constant<int, 1>{}, j0);
   }
   __syncthreads();
   const float* w2src = a.w2b;
@@ -498,13 +509,14 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const long long nM = (long long)M0 * M1 * M2;
   float* out = a.dst[g];
   const int nj2 = 4 * tj2;
-  for (int j0 = wave; j0 < nj2; j0 += 4 * kSynthT) {
-    const float* A[kSynthT];
-    const float* B[kSynthT];
-    floatx4 acc[kSynthT];
+  auto gemm2 = [&](auto TT, int j0) {
+    constexpr int T = decltype(TT)::value;
+    const float* A[T];
+    const float* B[T];
+    floatx4 acc[T];
 #pragma unroll
-    for (int t = 0; t < kSynthT; ++t) {
-      const int job = min(j0 + 4 * t, nj2 - 1);
+    for (int t = 0; t < T; ++t) {
+      const int job = j0 + 4 * t;
       const int ov = job / tj2, tj = job % tj2;
       const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
       const int wv = (ov == 1);
@@ -513,9 +525,9 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < N1 / 4; k0 += 4) {
-      float av[kSynthT][4], bv[kSynthT][4];
+      float av[T][4], bv[T][4];
 #pragma unroll
-      for (int t = 0; t < kSynthT; ++t)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ks = k0 + u;
@@ -525,13 +537,12 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int t = 0; t < kSynthT; ++t)
+        for (int t = 0; t < T; ++t)
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < kSynthT; ++t) {
+    for (int t = 0; t < T; ++t) {
       const int job = j0 + 4 * t;
-      if (job >= nj2) break;
       const int ov = job / tj2, tj = job % tj2;
       const int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
       const int x2 = tj * 16 + li;
@@ -541,6 +552,15 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
         if (x1 < M1 && x2 < M2) out[(size_t)f * nM + ((long long)x0 * M1 + x1) * M2 + x2] = acc[t][r];
       }
     }
+  };
+  for (int j0 = wave; j0 < nj2; j0 += 4 * kSynthT) {
+    const int cnt = min(kSynthT, (nj2 - j0 + 3) / 4);
+    if (cnt == 3)
+      gemm2(std::integral_constant<int, 3>{}, j0);
+    else if (cnt == 2)
+      gemm2(std::integral_constant<int, 2>{}, j0);
+    else
+      gemm2(std::integral_constant<int, 1>{}, j0);
   }
 }
 
