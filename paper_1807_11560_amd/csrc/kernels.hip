@@ -1064,14 +1064,46 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   }
   __syncthreads();
   rg.store(ng, [&](int i, float4 v) { st22(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
-  // stage 0' and the band update (one k0 tile per wave)
+  // stage 0' and the band update (one k0 tile per wave).  With two k0 tiles
+  // the other two waves take half of the products: the second term, or with
+  // one term the second half of the x0 depth, and hand their sums over
+  // through the LDS of the stage-1 table (unused after stage 1').
+  constexpr bool kSplit0 = (T0 == 2);
+  [[maybe_unused]] float2 own[4], other[4];
+  if constexpr (kSplit0) {
+    const int ti = wave & 1, h = wave >> 1;
+    constexpr int SD = M / 4, S1 = SD / 2;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    if (nterm == 2)
+      ctile<SD>(&w0fs[ti * 16][0], LW0F, &s2[h][0][0], LS2, acc);
+    else if (h == 0)
+      ctile<S1>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, acc);
+    else
+      ctile<SD - S1>(&w0fs[ti * 16][4 * S1], LW0F, &s2[0][4 * S1][0], LS2, acc);
+    static_assert(M * LW1 >= 2 * 4 * 64, "hand-over buffer fits the stage-1 table");
+    float2* red = &w1s[0][0];  // [tile][r][lane]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) own[r] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+    if (h == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(ti * 4 + r) * 64 + lane] = own[r];
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) other[r] = red[(ti * 4 + r) * 64 + lane];
+    }
+  }
   if (wave < T0) {
     const int ti = wave;
     floatx4 aa[4], bb[4];
-    zero_acc(aa, 4);
-    zero_acc(bb, 4);
-    ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, aa);
-    if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][0], LS2, bb);
+    if constexpr (!kSplit0) {
+      zero_acc(aa, 4);
+      zero_acc(bb, 4);
+      ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, aa);
+      if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][0], LS2, bb);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k0 = ti * 16 + 4 * lk + r;
@@ -1081,12 +1113,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       if (k0 != K / 2 && k1 != K / 2) {
         res = pbase[r];
         const float sa_ = job.ca * invG * (job.syma ? pks[r] : 1.f);
-        res.x = fmaf(sa_, aa[0][r] - aa[1][r], res.x);
-        res.y = fmaf(sa_, aa[2][r] + aa[3][r], res.y);
-        if (nterm == 2) {
-          const float sb_ = job.cb * invG * (job.symb ? pks[r] : 1.f);
-          res.x = fmaf(sb_, bb[0][r] - bb[1][r], res.x);
-          res.y = fmaf(sb_, bb[2][r] + bb[3][r], res.y);
+        if constexpr (kSplit0) {
+          const float2 ta = (nterm == 2) ? own[r] : make_float2(own[r].x + other[r].x, own[r].y + other[r].y);
+          res.x = fmaf(sa_, ta.x, res.x);
+          res.y = fmaf(sa_, ta.y, res.y);
+          if (nterm == 2) {
+            const float sb_ = job.cb * invG * (job.symb ? pks[r] : 1.f);
+            res.x = fmaf(sb_, other[r].x, res.x);
+            res.y = fmaf(sb_, other[r].y, res.y);
+          }
+        } else {
+          res.x = fmaf(sa_, aa[0][r] - aa[1][r], res.x);
+          res.y = fmaf(sa_, aa[2][r] + aa[3][r], res.y);
+          if (nterm == 2) {
+            const float sb_ = job.cb * invG * (job.symb ? pks[r] : 1.f);
+            res.x = fmaf(sb_, bb[0][r] - bb[1][r], res.x);
+            res.y = fmaf(sb_, bb[2][r] + bb[3][r], res.y);
+          }
         }
         res.x = fmaf(job.ce, pextra[r].x, res.x);
         res.y = fmaf(job.ce, pextra[r].y, res.y);

@@ -47,6 +47,8 @@ CASES = {
     "aniso": dict(grid=(40, 36, 32), band=(12, 16, 8), nt=5, s=2, dmax=2.0, cfg=2),
     # the 64^3, band 16^3 problem
     "cfg2": dict(grid=(64, 64, 64), band=(16, 16, 16), nt=10, s=2, dmax=5.0, cfg=2),
+    # band 24^3 on the tuned 36^3 padded-grid kernels (odd depth halves in the column step)
+    "band24": dict(grid=(48, 48, 48), band=(24, 24, 24), nt=3, s=2, dmax=3.0, cfg=2),
     # large bands on the generic kernels (LDS tiles up to the 160 KiB of a workgroup)
     "wide_aniso": dict(grid=(64, 56, 64), band=(48, 40, 56), nt=3, s=2, dmax=3.0, cfg=2),
     "band64": dict(grid=(64, 64, 64), band=(64, 64, 64), nt=2, s=2, dmax=3.0, cfg=2),
