@@ -74,8 +74,9 @@ enum MProg {
   // fields are read, of one that enters through its values only the three values.
 };
 
-// Lie products on the padded grid (k_prods): group pointers [12][nM] in
-// the order the program names them (see MProg).
+// Lie products on the padded grid (k_prods): group pointers ([3][nM][4]:
+// per component and point the value and its three derivatives) in the
+// order the program names them (see MProg).
 struct ProdArgs {
   const float* g[8];
   float2* s1;  // [nout][Kh][M0][M1]

@@ -339,12 +339,13 @@ __device__ __forceinline__ void jact_acc(float* o, const float* ja, const float*
 //   f  = [T2r | T2i] [[w2r], [-w2i]]                   rows x1, cols x2
 // for the variants value, d/dx2 (pp with the derivative stage-2 table), d/dx1
 // (stage-1 derivative table) and d/dx0 (stage-0 derivative input).  The
-// four results go to the group's [12][nM] field array.
+// four results go to the group's field array [3][nM][4]: per component and
+// padded-grid point (value, d/dx0, d/dx1, d/dx2).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct SynthArgs {
   const float2* t1[2];  // stage-0 output of group g: [3][2][M0][K1*Kh]
-  float* dst[2];        // fields of group g: [12][nM]
+  float* dst[2];        // fields of group g: [3][nM][4] (value, d0, d1, d2)
   const float* w1a;     // [2][M1p][2K1]    real block form of the stage-1 twiddles
   const float* w2b;     // [2][2Khp][M2p]   real block form of the stage-2 twiddles
 };
@@ -504,63 +505,48 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     w2src = bt1;
     w2ld = ldw2;
   }
-  // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p)
+  // GEMM2: ov 0 = value (pp, plain), 1 = d2 (pp, derivative table), 2 = d1 (p1), 3 = d0 (0p).
+  // A wave forms all four for one 16-column tile, so that each point's
+  // (value, d0, d1, d2) leaves as one 16-byte store.
   const int tj2 = M2p / 16;
   const long long nM = (long long)M0 * M1 * M2;
-  float* out = a.dst[g];
-  const int nj2 = 4 * tj2;
-  auto gemm2 = [&](auto TT, int j0) {
-    constexpr int T = decltype(TT)::value;
-    const float* A[T];
-    const float* B[T];
-    floatx4 acc[T];
+  float* out = a.dst[g] + (size_t)c * nM * 4;
+  for (int tj = wave; tj < tj2; tj += 4) {
+    const float* A[4];
+    const float* B[4];
+    floatx4 acc[4];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int job = j0 + 4 * t;
-      const int ov = job / tj2, tj = job % tj2;
+    for (int ov = 0; ov < 4; ++ov) {
       const int srcv = (ov <= 1) ? 0 : (ov == 2 ? 1 : 2);
       const int wv = (ov == 1);
-      A[t] = t2s + ((size_t)srcv * 16 + li) * ldt2 + lk;
-      B[t] = w2src + ((size_t)wv * N1 + lk) * w2ld + tj * 16 + li;
-      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      A[ov] = t2s + ((size_t)srcv * 16 + li) * ldt2 + lk;
+      B[ov] = w2src + ((size_t)wv * N1 + lk) * w2ld + tj * 16 + li;
+      acc[ov] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < N1 / 4; k0 += 4) {
-      float av[T][4], bv[T][4];
+      float av[4][4], bv[4][4];
 #pragma unroll
-      for (int t = 0; t < T; ++t)
+      for (int ov = 0; ov < 4; ++ov)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ks = k0 + u;
-          bv[t][u] = (ks < N1 / 4) ? B[t][(size_t)4 * ks * w2ld] : 0.f;
-          av[t][u] = (ks < N1 / 4) ? A[t][4 * ks] : 0.f;
+          bv[ov][u] = (ks < N1 / 4) ? B[ov][(size_t)4 * ks * w2ld] : 0.f;
+          av[ov][u] = (ks < N1 / 4) ? A[ov][4 * ks] : 0.f;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int t = 0; t < T; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
+        for (int ov = 0; ov < 4; ++ov)
+          acc[ov] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ov][u], bv[ov][u], acc[ov], 0, 0, 0);
     }
+    const int x2 = tj * 16 + li;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int job = j0 + 4 * t;
-      const int ov = job / tj2, tj = job % tj2;
-      const int f = (ov == 0) ? c : 3 + 3 * c + (ov == 1 ? 2 : (ov == 2 ? 1 : 0));
-      const int x2 = tj * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x1 = rt * 16 + 4 * lk + r;
-        if (x1 < M1 && x2 < M2) out[(size_t)f * nM + ((long long)x0 * M1 + x1) * M2 + x2] = acc[t][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int x1 = rt * 16 + 4 * lk + r;
+      if (x1 < M1 && x2 < M2)
+        *reinterpret_cast<float4*>(out + 4 * (((long long)x0 * M1 + x1) * M2 + x2)) =
+            make_float4(acc[0][r], acc[3][r], acc[2][r], acc[1][r]);
     }
-  };
-  for (int j0 = wave; j0 < nj2; j0 += 4 * kSynthT) {
-    const int cnt = min(kSynthT, (nj2 - j0 + 3) / 4);
-    if (cnt == 3)
-      gemm2(std::integral_constant<int, 3>{}, j0);
-    else if (cnt == 2)
-      gemm2(std::integral_constant<int, 2>{}, j0);
-    else
-      gemm2(std::integral_constant<int, 1>{}, j0);
   }
 }
 
@@ -622,17 +608,29 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
     for (int i = 0; i < 9; ++i) o[i] = 0.f;
     if (r < rv) {
       const long long gp = ((long long)x0 * M1 + x1b) * M2 + p;
-      auto get = [&](const float* base, float* dst) {
+      // a group is [3][nM][4]: per component i and point (a_i, d_0 a_i, d_1 a_i, d_2 a_i)
+      auto get = [&](const float* base, float* dst) {  // dst[i] = a_i, dst[3 + 3 i + j] = d_j a_i
 #pragma unroll
-        for (int f = 0; f < 12; ++f) dst[f] = base[(size_t)f * nM + gp];
+        for (int i = 0; i < 3; ++i) {
+          const float4 v = *reinterpret_cast<const float4*>(base + ((size_t)i * nM + gp) * 4);
+          dst[i] = v.x;
+          dst[3 + 3 * i] = v.y;
+          dst[4 + 3 * i] = v.z;
+          dst[5 + 3 * i] = v.w;
+        }
       };
       auto get_jac = [&](const float* base, float* dst) {  // dst[3 i + j] = d_j a_i
 #pragma unroll
-        for (int f = 0; f < 9; ++f) dst[f] = base[(size_t)(3 + f) * nM + gp];
+        for (int i = 0; i < 3; ++i) {
+          const float4 v = *reinterpret_cast<const float4*>(base + ((size_t)i * nM + gp) * 4);
+          dst[3 * i] = v.y;
+          dst[3 * i + 1] = v.z;
+          dst[3 * i + 2] = v.w;
+        }
       };
       auto get_val = [&](const float* base, float* dst) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) dst[f] = base[(size_t)f * nM + gp];
+        for (int i = 0; i < 3; ++i) dst[i] = base[((size_t)i * nM + gp) * 4];
       };
       // every group the program needs is loaded before any product is formed
       switch (a.prog) {
