@@ -355,7 +355,7 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
   return hipSuccess;
 }
 
-enum GraphKind { GK_HESSVEC = 1, GK_GN_HEAD = 2, GK_PCG_ITER = 3, GK_TRIAL = 16 };
+enum GraphKind { GK_HESSVEC = 1, GK_GN_HEAD = 2, GK_PCG_ITER = 3, GK_GN_HEAD_KEPT = 4, GK_TRIAL = 16 };
 
 // ------------------------------------------------------ register loop
 // batched registration: at most this many pairs per call, and by default
@@ -386,16 +386,24 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
   HTRY(hipStreamSynchronize(st));
   double g0_inf = -1.0;
   int status = LDDMM_OK;
+  // the accepted line-search trial of the previous iteration ran the caching
+  // forward at the new v0 and left its energy in scal[0..2]
+  bool kept = false;
   for (int it = 0; it < gn_iters; ++it) {
     // energy and gradient at v0 (and max |g|)
-    HTRY(run_graph(e, graph_key(e, ws, GK_GN_HEAD, {I0, I1}), [&]() -> hipError_t {
+    HTRY(run_graph(e, graph_key(e, ws, kept ? GK_GN_HEAD_KEPT : GK_GN_HEAD, {I0, I1}), [&]() -> hipError_t {
       hipError_t r;
       const hipStream_t s = e.stream();
-      if ((r = launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n, s)))
-        return r;
-      if ((r = e.forward(I0)) || (r = e.energy(e.final_state(), I1)) || (r = e.backward(I1, e.gh))) return r;
+      if (!kept) {
+        if ((r = launch_copy(reinterpret_cast<const float*>(e.v0h), reinterpret_cast<float*>(e.V[0]), 2LL * n,
+                             s)))
+          return r;
+        if ((r = e.forward(I0)) || (r = e.energy(e.final_state(), I1))) return r;
+      }
+      if ((r = e.backward(I1, e.gh))) return r;
       return launch_band_maxabs(e.gh, d, e.partial, e.scal + 3, s);
     }));
+    kept = false;
     double sc[4];
     HTRY(hipMemcpyAsync(sc, e.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HTRY(hipStreamSynchronize(st));
@@ -448,16 +456,17 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     int trials = 0;
     for (int t = 0; t < max_trials; ++t) {
       ++trials;
-      // E(v0 + eps p)
+      // E(v0 + eps p), by the caching forward (it costs what the light one
+      // does: the same fields are written, to their cache slots), so that an
+      // accepted trial leaves the trajectories of the next gradient
       HTRY(run_graph(e, graph_key(e, ws, GK_TRIAL + t, {I0, I1}), [&]() -> hipError_t {
         hipError_t r;
         const hipStream_t s = e.stream();
-        const float* mnt = nullptr;
         if ((r = launch_axpy_band(e.v0h, e.ph, (float)eps, e.vtry, n, s))) return r;
         if ((r = launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.V[0]), 2LL * n, s)))
           return r;
-        if ((r = e.forward_light(I0, &mnt))) return r;
-        return e.energy(mnt, I1);
+        if ((r = e.forward(I0))) return r;
+        return e.energy(e.final_state(), I1);
       }));
       HTRY(hipMemcpyAsync(&Etry, e.scal, sizeof(double), hipMemcpyDeviceToHost, st));
       HTRY(hipStreamSynchronize(st));
@@ -485,6 +494,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
       break;
     }
     HTRY(launch_copy(reinterpret_cast<const float*>(e.vtry), reinterpret_cast<float*>(e.v0h), 2LL * n, st));
+    kept = true;
   }
   HTRY(e.store_band(e.v0h, nullptr, 0.f, v0_inout));
   HTRY(hipStreamSynchronize(st));
