@@ -133,6 +133,25 @@ def cpu_baseline(w, state="image", band=None):
             "seconds": t}
 
 
+def separable_flops(K, G):
+    """Flops of one band <-> grid transform of a scalar field by separable
+    partial DFTs: two complex stages, then a real last stage (full K2)."""
+    return 8.0 * (G[0] * K[0] * K[1] * K[2] + G[0] * G[1] * K[1] * K[2]) + 4.0 * G[0] * G[1] * G[2] * K[2]
+
+
+def hvp_ceiling(prob, res_value, hvp_only):
+    """The whole-HVP FP32 compute ceiling: 60 padded-grid and 3.3 image-grid
+    transforms per time step (600 and 33 at nt = 10) against 157.3 TFLOP/s,
+    and the measured rates as fractions of it."""
+    K = prob.band
+    M = tuple(3 * k // 2 for k in K)
+    nt = prob.time_steps
+    flops = 60.0 * nt * separable_flops(K, M) + 3.3 * nt * separable_flops(K, prob.grid)
+    ceiling = PEAK_TFLOPS_FP32 * 1e12 / flops
+    return {"flops_per_hvp": flops, "ceiling_hvp_per_s": ceiling, "frac_registration": res_value / ceiling,
+            "frac_back_to_back": (hvp_only / ceiling) if hvp_only else None}
+
+
 def dominant_family(L, run):
     """The kernel family with the largest summed duration over one run."""
     fam_ms = {}
@@ -335,7 +354,7 @@ def main():
     T_u = time.perf_counter() - t0
 
     # pure Hessian-vector product rate (same problem, last iterate)
-    hvp_only = None
+    hvp_only = hvp_med = cold_ms = None
     if args.hvp_loop > 0:
         L.gradient(prob, I0, I1, v, ws)
         d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
@@ -348,6 +367,21 @@ def main():
             L.hessvec(prob, d, ws, out=out)
         torch.cuda.synchronize()
         hvp_only = args.hvp_loop / (time.perf_counter() - t1)
+        # per-call durations (events on the stream the library runs on) and the cold product
+        # (gradient with its trajectories recomputed, then the product)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        for e0, e1 in evs:
+            e0.record()
+            L.hessvec(prob, d, ws, out=out)
+            e1.record()
+        torch.cuda.synchronize()
+        hvp_med = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+        t1 = time.perf_counter()
+        for _ in range(5):
+            L.gradient(prob, I0, I1, v, ws)
+            L.hessvec(prob, d, ws, out=out)
+        torch.cuda.synchronize()
+        cold_ms = 1e3 * (time.perf_counter() - t1) / 5
 
     # plain copy of known size: the calibration for the FETCH_SIZE / WRITE_SIZE counters
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -391,6 +425,9 @@ def main():
         "hvps_per_registration": hvps / args.steps,
         "value_without_timer_events": hvps_u / T_u,
         "hvp_only_per_s": hvp_only,
+        "hvp_ms_median": hvp_med,
+        "cold_hvp_ms": cold_ms,
+        "hvp_roofline": hvp_ceiling(prob, res_value=hvps / T, hvp_only=hvp_only),
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
         "final_grad_inf_rel": stats[-1]["grad_inf_rel"] if stats else None,
         "workspace_mib": ws.nbytes / 2**20,
