@@ -119,6 +119,7 @@ struct Fwd0Job {
   const float2* base;
   const float2* extra;
   float2* out;
+  float2* out2;  // optional (a alone, syma = 0): ca K~ F(a) / |N| beside out
   float ca, cb, ce;
   int syma, symb;
 };

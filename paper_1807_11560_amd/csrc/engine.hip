@@ -674,17 +674,17 @@ hipError_t Engine::grid_field(const float2* band, bool have_t1n, float* out, hip
 // Forward stages 1 and 0 of the three fields in S1N: pi(s) into `plain` and
 // K~ pi(s) into `smooth`.
 hipError_t Engine::band_pair(float2* plain, float2* smooth, hipStream_t s) {
-  Fwd0Job fj[6];
-  for (int c = 0; c < 3; ++c)
-    for (int k = 0; k < 2; ++k) {
-      Fwd0Job& j = fj[2 * c + k];
-      j = Fwd0Job{};
-      j.a = s2n(c);
-      j.ca = 1.f;
-      j.syma = k;
-      j.out = (k ? smooth : plain) + (size_t)c * d_.nb;
-    }
-  return fwd_grid(fj, 6, s);
+  Fwd0Job fj[3];
+  for (int c = 0; c < 3; ++c) {
+    Fwd0Job& j = fj[c];
+    j = Fwd0Job{};
+    j.a = s2n(c);
+    j.ca = 1.f;
+    j.syma = 0;
+    j.out = plain + (size_t)c * d_.nb;
+    j.out2 = smooth + (size_t)c * d_.nb;
+  }
+  return fwd_grid(fj, 3, s);
 }
 
 // out = base + K~ F(products of the program) on the caller's stream, with the

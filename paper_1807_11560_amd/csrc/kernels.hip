@@ -1258,6 +1258,15 @@ __global__ void __launch_bounds__(128) k_fwd0(Fwd0Jobs jobs, const float2* __res
       }
     }
     job.out[idx] = r;
+    if (job.out2) {
+      float2 r2 = make_float2(0.f, 0.f);
+      if (q0 != K0 / 2 && q1 != K1 / 2) {
+        const float s2 = job.ca * invG * Ksym[idx];
+        r2.x = fmaf(s2, aa[t].x, 0.f);
+        r2.y = fmaf(s2, aa[t].y, 0.f);
+      }
+      job.out2[idx] = r2;
+    }
   }
 }
 
@@ -1694,6 +1703,8 @@ __global__ void __launch_bounds__(256) k_rho_fwd2(RhoArgs a, float2* __restrict_
     int x2 = i / Kh, kh = i % Kh;
     return tw.fwd2[(size_t)kh * N2 + x2];
   }, [&](int i, float2 v) { wfx[i] = v; });
+  // two points per iteration, so that two chains of dependent loads are in flight
+#pragma unroll 2
   for (int p = threadIdx.x; p < R * N2; p += blockDim.x) {
     const int r = p / N2, x2 = p % N2;
     const int x1 = x1b + r;
@@ -2546,7 +2557,8 @@ hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const 
       const Fwd0Job& j = jobs.j[i];
       int terms = 1 + (j.b != nullptr);
       fl += terms * 8.0 * K0 * C * G0;
-      by += terms * 8.0 * G0 * C + 8.0 * K0 * C * (1 + (j.base != nullptr) + (j.extra != nullptr)) + 4.0 * K0 * C;
+      by += terms * 8.0 * G0 * C +
+            8.0 * K0 * C * (1 + (j.base != nullptr) + (j.extra != nullptr) + (j.out2 != nullptr)) + 4.0 * K0 * C;
     }
     timer_work(KF_FWD0_GRID, fl, by);
   }
