@@ -4,6 +4,7 @@
 // kernel-family timer.
 #include "../../include/lddmm.h"
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -694,15 +695,22 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
   std::vector<int> rcs(n, LDDMM_OK);
   std::vector<std::string> msgs(n);
   std::vector<int64_t> counts(n, 0);
+  // largest pairs first (workspace size as the measure of work), so that the
+  // last pairs to finish are small ones and the tail of the batch is short
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return Engine::workspace_bytes(dims[a]) > Engine::workspace_bytes(dims[b]); });
   std::atomic<int> next{0};
   // each worker thread owns one stream (and its engine's auxiliary stream)
-  // and takes pairs in index order until none is left
+  // and takes the next pair of that order until none is left
   auto worker = [&]() {
     hipStream_t s = nullptr;
     hipError_t e = hipSetDevice(dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, start, 0);
-    for (int i; (i = next.fetch_add(1)) < n;) {
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      const int i = order[k];
       if (e != hipSuccess) {
         rcs[i] = hip_fail(e, "worker stream");
         msgs[i] = g_last_error;
