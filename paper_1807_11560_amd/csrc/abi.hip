@@ -719,6 +719,7 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
       void* w = static_cast<char*>(ws) + off[i];
       set_prepared(w, false, dims[i]);
       Engine eng(dims[i], w, s);
+      eng.set_one_stream(true);
       int rc = LDDMM_OK;
       hipError_t fe = launch_fill(reinterpret_cast<float*>(eng.tmph), 6LL * dims[i].nb, 0.f, s);
       if (fe != hipSuccess)

@@ -68,6 +68,9 @@ class Engine {
   hipStream_t stream() const { return st_; }
   // Redirects all further work (used while capturing a graph).
   void set_stream(hipStream_t s) { st_ = s; }
+  // Runs the grid chain on the caller's stream too (the host enqueues every
+  // step after the work it depends on, so one stream keeps the order).
+  void set_one_stream(bool on) { one_stream_ = on; }
 
   // buffers
   std::vector<float2*> V, U, W, dV;
@@ -128,6 +131,7 @@ class Engine {
   Dims d_;
   hipStream_t st_;
   hipStream_t aux_ = nullptr;
+  bool one_stream_ = false;
   std::vector<hipEvent_t>* ev_ = nullptr;
   Twiddles twM_{}, twN_{};
   float2* twbuf_ = nullptr;

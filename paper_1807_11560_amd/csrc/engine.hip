@@ -40,7 +40,7 @@ hipError_t Engine::aux_init(int nevents) {
   int dev = 0;
   TRY(hipGetDevice(&dev));
   AuxRes& r = t_aux[dev];
-  if (!r.stream) TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
+  if (!r.stream && !one_stream_) TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
   // The events only order the two streams of one device: a device-scope
   // release suffices (runtimes without that flag get the default).
   while ((int)r.events.size() < nevents) {
@@ -51,7 +51,7 @@ hipError_t Engine::aux_init(int nevents) {
     }
     r.events.push_back(e);
   }
-  aux_ = r.stream;
+  aux_ = one_stream_ ? st_ : r.stream;
   ev_ = &r.events;
   return hipSuccess;
 }
