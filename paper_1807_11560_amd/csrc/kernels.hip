@@ -1389,6 +1389,11 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
   __shared__ __align__(16) float2 w1s[R][LW1];
   __shared__ __align__(16) float2 t2s[3][R][LT2];
   __shared__ __align__(16) float2 w2t[Khp][LW2];
+  // source: rows x1b - 1 .. x1b + R of m in plane x0 (periodic), for the x1
+  // and x2 differences; the x0 differences are read directly
+  constexpr int LM = N2 + 4;
+  __shared__ __align__(16) float mrow[R + 2][LM];
+  static_assert(N1 % R == 0, "whole row tiles");
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -1408,8 +1413,13 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     return (x1 < N1) ? ld4(tw.inv1 + (size_t)x1 * K1 + 2 * (i % KP)) : z4;
   });
   rw2.load(N2 * KHP, [&](int i) { return ld4(tw.inv2 + (size_t)(i / KHP) * Kh + 2 * (i % KHP)); });
-  constexpr int NTJ = N2 / 16, TPW = (NTJ + 3) / 4;
-  float nb[TPW][4][6], dmv[TPW][4];
+  constexpr int NTJ = N2 / 16, TPW = (NTJ + 3) / 4, NM4 = (R + 2) * N2 / 4;
+  RegStage<(NM4 + 255) / 256, float4> rm;
+  if (a.op == 1) rm.load(NM4, [&](int i) {
+    const int x1 = (x1b - 1 + i / (N2 / 4) + N1) % N1;
+    return *reinterpret_cast<const float4*>(a.m + ((size_t)x0 * N1 + x1) * N2 + 4 * (i % (N2 / 4)));
+  });
+  float nb[TPW][4][2], dmv[TPW][4];
   if (a.op == 1) {
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
@@ -1419,15 +1429,9 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
         const int x1 = x1b + 4 * lk + r, x2 = tj * 16 + li;
         if (tj >= NTJ || x1 >= N1) continue;
         const int xp0 = (x0 + 1 == N0) ? 0 : x0 + 1, xm0 = (x0 == 0) ? N0 - 1 : x0 - 1;
-        const int xp1 = (x1 + 1 == N1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? N1 - 1 : x1 - 1;
-        const int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
         auto at = [&](int i0, int i1, int i2) { return a.m[((long long)i0 * N1 + i1) * N2 + i2]; };
         nb[q][r][0] = at(xp0, x1, x2);
         nb[q][r][1] = at(xm0, x1, x2);
-        nb[q][r][2] = at(x0, xp1, x2);
-        nb[q][r][3] = at(x0, xm1, x2);
-        nb[q][r][4] = at(x0, x1, xp2);
-        nb[q][r][5] = at(x0, x1, xm2);
         dmv[q][r] = a.dm ? a.dm[((long long)x0 * N1 + x1) * N2 + x2] : 0.f;
       }
     }
@@ -1443,6 +1447,9 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     const int x2 = i / KHP, kh = 2 * (i % KHP);
     w2t[kh][x2] = make_float2(v.x, v.y);
     w2t[kh + 1][x2] = make_float2(v.z, v.w);
+  });
+  if (a.op == 1) rm.store(NM4, [&](int i, float4 v) {
+    *reinterpret_cast<float4*>(&mrow[i / (N2 / 4)][4 * (i % (N2 / 4))]) = v;
   });
   if constexpr (Khp > Kh) {  // zero padding columns of the half spectrum
     for (int i = threadIdx.x; i < 3 * K1 * (Khp - Kh); i += 256)
@@ -1493,9 +1500,11 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.vout[(size_t)c * nN + gi] = vel[c][r];
       } else {
+        const int lr = 4 * lk + r + 1;  // row of x1 in mrow
+        const int xp2 = (x2 + 1 == N2) ? 0 : x2 + 1, xm2 = (x2 == 0) ? N2 - 1 : x2 - 1;
         const float g0 = (nb[q][r][0] - nb[q][r][1]) * (0.5f * N0);
-        const float g1 = (nb[q][r][2] - nb[q][r][3]) * (0.5f * N1);
-        const float g2 = (nb[q][r][4] - nb[q][r][5]) * (0.5f * N2);
+        const float g1 = (mrow[lr + 1][x2] - mrow[lr - 1][x2]) * (0.5f * N1);
+        const float g2 = (mrow[lr][xp2] - mrow[lr][xm2]) * (0.5f * N2);
         const float dot = g0 * vel[0][r] + g1 * vel[1][r] + g2 * vel[2][r];
         a.q[gi] = fmaf(-a.dt, dot, dmv[q][r]);
       }
