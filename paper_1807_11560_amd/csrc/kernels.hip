@@ -2318,16 +2318,16 @@ hipError_t launch_inv0(const Inv0Jobs& jobs, int njobs, int nvar, const float2* 
   };
   using I2 = std::integral_constant<int, 2>;
   using I1 = std::integral_constant<int, 1>;
+  using X2 = std::integral_constant<int, 2>;
   using X4 = std::integral_constant<int, 4>;
-  using X8 = std::integral_constant<int, 8>;
   if (nvar == 2) {
-    if (K0 == 32) go(I2{}, X4{}, std::integral_constant<int, 32>{});
-    else if (K0 == 16) go(I2{}, X4{}, std::integral_constant<int, 16>{});
-    else go(I2{}, X4{}, std::integral_constant<int, 0>{});
+    if (K0 == 32) go(I2{}, X2{}, std::integral_constant<int, 32>{});
+    else if (K0 == 16) go(I2{}, X2{}, std::integral_constant<int, 16>{});
+    else go(I2{}, X2{}, std::integral_constant<int, 0>{});
   } else {
-    if (K0 == 32) go(I1{}, X8{}, std::integral_constant<int, 32>{});
-    else if (K0 == 16) go(I1{}, X8{}, std::integral_constant<int, 16>{});
-    else go(I1{}, X8{}, std::integral_constant<int, 0>{});
+    if (K0 == 32) go(I1{}, X4{}, std::integral_constant<int, 32>{});
+    else if (K0 == 16) go(I1{}, X4{}, std::integral_constant<int, 16>{});
+    else go(I1{}, X4{}, std::integral_constant<int, 0>{});
   }
   return hipGetLastError();
 }
