@@ -2543,7 +2543,7 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
 
 hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0, int G1, int K1,
                        int Kh, hipStream_t st) {
-  constexpr int QT = 8;
+  constexpr int QT = 2;
   const int T = 128;
   dim3 grid(nblk((long long)G0 * Kh, T), nblk(K1, QT), njobs);
   size_t shm = QT * G1 * sizeof(float2);
@@ -2555,7 +2555,7 @@ hipError_t launch_fwd1(const Fwd1Jobs& jobs, int njobs, const float2* tw, int G0
 
 hipError_t launch_fwd0(const Fwd0Jobs& jobs, int njobs, const float2* tw, const float* Ksym, int G0,
                        int K0, int K1, int Kh, float invG, hipStream_t st) {
-  constexpr int QT = 8;
+  constexpr int QT = 2;
   const int T = 128;
   dim3 grid(nblk((long long)K1 * Kh, T), nblk(K0, QT), njobs);
   size_t shm = QT * G0 * sizeof(float2);
