@@ -194,8 +194,8 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const
 // phi(1) = id + u and its forward stage 2 into s1 [3][N0][N1][Kh].
 struct RhoArgs {
   const float* I0;
-  const float* G;     // [3][nN] central-difference gradient of I0
-  const float* H;     // [6][nN] its Hessian (00, 01, 02, 11, 12, 22), full Newton only
+  const float* G;     // [nN][4]: I0 and its central-difference gradient per point
+  const float* H;     // [nN][8]: its Hessian (00, 01, 02, 11, 12, 22, 0, 0), full Newton only
   const float* u;     // [3][nN] displacement iota(u_nt)
   const float* I1;    // op 0
   const float* du;    // op 1: [3][nN] iota(du_nt)
@@ -203,7 +203,8 @@ struct RhoArgs {
   float coef;
   int op;
 };
-// Central differences of I0: G [3][nN] and, when H is set, H [6][nN].
+// I0 with its central differences, G [nN][4] = (I0, d0, d1, d2), and, when H
+// is set, H [nN][8] = (d00, d01, d02, d11, d12, d22, 0, 0).
 hipError_t launch_image_derivs(const float* I0, float* G, float* H, const Dims& d, hipStream_t st);
 hipError_t launch_rho_fwd2(const RhoArgs& a, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);

@@ -89,7 +89,7 @@ class Engine {
   std::vector<float*> PG;
   float* RG;
   float2 *R, *KR, *dR, *KdR;
-  float *ug, *dug, *m1, *I0c, *IG, *IH;  // IG, IH: central-difference gradient / Hessian of I0
+  float *ug, *dug, *m1, *I0c, *IG, *IH;  // IG [nN][4]: I0 and its central differences; IH [nN][8]: Hessian
   float *mlight[2];
   double *partial, *scal, *pcg;
   float *Lsym, *Ksym;

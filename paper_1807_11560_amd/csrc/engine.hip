@@ -141,8 +141,8 @@ void Engine::layout(Carver& c) {
     dug = c.take<float>(3 * (size_t)d.nN);
     m1 = c.take<float>((size_t)d.nN);
     I0c = c.take<float>((size_t)d.nN);
-    IG = c.take<float>(3 * (size_t)d.nN);
-    if (d.hessian == 2) IH = c.take<float>(6 * (size_t)d.nN);
+    IG = c.take<float>(4 * (size_t)d.nN);
+    if (d.hessian == 2) IH = c.take<float>(8 * (size_t)d.nN);
   }
 }
 

@@ -1677,17 +1677,20 @@ __global__ void __launch_bounds__(256) k_image_derivs(const float* __restrict__ 
     return I0[((long long)i * N1 + j) * N2 + k];
   };
   (void)x;
-  Gr[gi] = (at(1, 0, 0) - at(-1, 0, 0)) * (0.5f * N0);
-  Gr[nN + gi] = (at(0, 1, 0) - at(0, -1, 0)) * (0.5f * N1);
-  Gr[2 * nN + gi] = (at(0, 0, 1) - at(0, 0, -1)) * (0.5f * N2);
-  if (!H) return;
+  (void)nN;
   const float c = at(0, 0, 0);
-  H[gi] = (at(2, 0, 0) - 2.f * c + at(-2, 0, 0)) * (0.25f * n[0] * n[0]);
-  H[nN + gi] = (at(1, 1, 0) - at(1, -1, 0) - at(-1, 1, 0) + at(-1, -1, 0)) * (0.25f * n[0] * n[1]);
-  H[2 * nN + gi] = (at(1, 0, 1) - at(1, 0, -1) - at(-1, 0, 1) + at(-1, 0, -1)) * (0.25f * n[0] * n[2]);
-  H[3 * nN + gi] = (at(0, 2, 0) - 2.f * c + at(0, -2, 0)) * (0.25f * n[1] * n[1]);
-  H[4 * nN + gi] = (at(0, 1, 1) - at(0, 1, -1) - at(0, -1, 1) + at(0, -1, -1)) * (0.25f * n[1] * n[2]);
-  H[5 * nN + gi] = (at(0, 0, 2) - 2.f * c + at(0, 0, -2)) * (0.25f * n[2] * n[2]);
+  reinterpret_cast<float4*>(Gr)[gi] =
+      make_float4(c, (at(1, 0, 0) - at(-1, 0, 0)) * (0.5f * N0), (at(0, 1, 0) - at(0, -1, 0)) * (0.5f * N1),
+                  (at(0, 0, 1) - at(0, 0, -1)) * (0.5f * N2));
+  if (!H) return;
+  reinterpret_cast<float4*>(H)[2 * gi] =
+      make_float4((at(2, 0, 0) - 2.f * c + at(-2, 0, 0)) * (0.25f * n[0] * n[0]),
+                  (at(1, 1, 0) - at(1, -1, 0) - at(-1, 1, 0) + at(-1, -1, 0)) * (0.25f * n[0] * n[1]),
+                  (at(1, 0, 1) - at(1, 0, -1) - at(-1, 0, 1) + at(-1, 0, -1)) * (0.25f * n[0] * n[2]),
+                  (at(0, 2, 0) - 2.f * c + at(0, -2, 0)) * (0.25f * n[1] * n[1]));
+  reinterpret_cast<float4*>(H)[2 * gi + 1] =
+      make_float4((at(0, 1, 1) - at(0, 1, -1) - at(0, -1, 1) + at(0, -1, -1)) * (0.25f * n[1] * n[2]),
+                  (at(0, 0, 2) - 2.f * c + at(0, 0, -2)) * (0.25f * n[2] * n[2]), 0.f, 0.f);
 }
 
 // At phi(x) = x + u(x) (voxel coordinates x_j + N_j u_j) the periodic
@@ -1737,18 +1740,22 @@ __global__ void __launch_bounds__(256) k_rho_fwd2(RhoArgs a, float2* __restrict_
       const int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
       const long long r00 = ((long long)a0 * N1 + a1) * N2, r01 = ((long long)a0 * N1 + b1) * N2;
       const long long r10 = ((long long)b0 * N1 + a1) * N2, r11 = ((long long)b0 * N1 + b1) * N2;
-      auto interp = [&](const float* f) {
-        const float c00 = f[r00 + a2] + w2 * (f[r00 + b2] - f[r00 + a2]);
-        const float c01 = f[r01 + a2] + w2 * (f[r01 + b2] - f[r01 + a2]);
-        const float c10 = f[r10 + a2] + w2 * (f[r10 + b2] - f[r10 + a2]);
-        const float c11 = f[r11 + a2] + w2 * (f[r11 + b2] - f[r11 + a2]);
-        const float c0 = c00 + w1 * (c01 - c00);
-        const float c1 = c10 + w1 * (c11 - c10);
-        return c0 + w0 * (c1 - c0);
+      // the four (or eight) channels of a point are one 16-byte load per corner
+      auto lerp4 = [](float4 p, float4 q, float w) {
+        return make_float4(p.x + w * (q.x - p.x), p.y + w * (q.y - p.y), p.z + w * (q.z - p.z),
+                           p.w + w * (q.w - p.w));
       };
-      const float g0 = interp(a.G), g1 = interp(a.G + nN), g2 = interp(a.G + 2 * nN);
+      auto interp4 = [&](const float4* f, int stride) {
+        const float4 c00 = lerp4(f[stride * (r00 + a2)], f[stride * (r00 + b2)], w2);
+        const float4 c01 = lerp4(f[stride * (r01 + a2)], f[stride * (r01 + b2)], w2);
+        const float4 c10 = lerp4(f[stride * (r10 + a2)], f[stride * (r10 + b2)], w2);
+        const float4 c11 = lerp4(f[stride * (r11 + a2)], f[stride * (r11 + b2)], w2);
+        return lerp4(lerp4(c00, c01, w1), lerp4(c10, c11, w1), w0);
+      };
+      const float4 ig = interp4(reinterpret_cast<const float4*>(a.G), 1);  // (I0, d0, d1, d2)
+      const float g0 = ig.y, g1 = ig.z, g2 = ig.w;
       if (a.op == 0) {
-        const float l = a.coef * (interp(a.I0) - a.I1[gi]);
+        const float l = a.coef * (ig.x - a.I1[gi]);
         v0 = l * g0;
         v1 = l * g1;
         v2 = l * g2;
@@ -1759,8 +1766,9 @@ __global__ void __launch_bounds__(256) k_rho_fwd2(RhoArgs a, float2* __restrict_
         v1 = l * g1;
         v2 = l * g2;
         if (a.res) {
-          const float h00 = interp(a.H), h01 = interp(a.H + nN), h02 = interp(a.H + 2 * nN);
-          const float h11 = interp(a.H + 3 * nN), h12 = interp(a.H + 4 * nN), h22 = interp(a.H + 5 * nN);
+          const float4 ha = interp4(reinterpret_cast<const float4*>(a.H), 2);      // (00, 01, 02, 11)
+          const float4 hb = interp4(reinterpret_cast<const float4*>(a.H) + 1, 2);  // (12, 22, -, -)
+          const float h00 = ha.x, h01 = ha.y, h02 = ha.z, h11 = ha.w, h12 = hb.x, h22 = hb.y;
           const float t = a.coef * a.res[gi];
           v0 = fmaf(t, h00 * du0 + h01 * du1 + h02 * du2, v0);
           v1 = fmaf(t, h01 * du0 + h11 * du1 + h12 * du2, v1);
