@@ -244,8 +244,9 @@ int lddmm_batch_workspace_bytes(int32_t n, const lddmm_params* p, size_t* bytes)
  * iterate v0_inout[i], and runs exactly the loop of lddmm_register, so its
  * results equal those of lddmm_register on the same inputs.  Up to
  * `concurrency` pairs run at a time (0 selects 8), each from its own host
- * thread on its own library streams, so that the launches of different pairs
- * share the compute units; pairs start largest first (by workspace size).
+ * thread on one library stream of its own (a pair's grid chain follows its
+ * band chain on that stream), so that the launches of different pairs share
+ * the compute units; pairs start largest first (by workspace size).
  *   n          1 <= n <= 4096
  *   p, I0, I1, v0_inout   host arrays of n entries; the images and iterates are
  *              device buffers laid out as for lddmm_register
