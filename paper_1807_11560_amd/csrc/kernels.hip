@@ -1169,6 +1169,190 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   }
 }
 
+// Lean form of k_colstep_mfma for the launches of the forward sweeps (one
+// product field per job, the image-grid stage 0 fused, two parts per column
+// tile), which run beside the grid chain: part 0 forms the next padded-grid
+// stage 0 and stores the band update, part 1 the image-grid stage 0.  One LDS
+// region holds in turn the stage-1 input, the stage-0 table and the part's
+// next-stage table, so the block needs about half the LDS of k_colstep_mfma
+// and can share a compute unit with grid-step blocks.  The tables wait in
+// registers until their turn.
+template <class S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_lean(
+    ColJobs jobs, const float2* __restrict__ w1t, const float2* __restrict__ w0f, const float2* __restrict__ w0i,
+    double alpha, int spow, float invG) {
+  constexpr int K = S::K0(), M = S::M0(), Kh = S::Kh();
+  constexpr int Mp = (M + 15) & ~15, Kp = (K + 15) & ~15;
+  constexpr int LS1 = M + 1, LS2 = 18, LOB = 18;
+  constexpr int C = K * Kh;
+  constexpr int LW1 = 18, LW0F = M + 1, LW0I = K + 1, LG = K + 1;
+  constexpr int T0 = Kp / 16, TIR = Mp / 16;
+  constexpr int NG0MAX = 256 * kGrid0Pre / K;  // image-grid rows the table may hold
+  constexpr int NA1 = Mp * LS1, NA2 = Kp * LW0F, NA3 = 2 * Mp * LW0I, NA4 = NG0MAX * LG;
+  constexpr int NA = NA1 > NA2 ? (NA1 > NA3 ? (NA1 > NA4 ? NA1 : NA4) : (NA3 > NA4 ? NA3 : NA4))
+                               : (NA2 > NA3 ? (NA2 > NA4 ? NA2 : NA4) : (NA3 > NA4 ? NA3 : NA4));
+  static_assert(M % 2 == 0 && K % 2 == 0 && T0 == 2, "pairs of complex values per load, two k0 tiles");
+  __shared__ __align__(16) float2 ra[NA];          // s1 | w0fs | w0is or g0s
+  __shared__ __align__(16) float2 s2[M][LS2];
+  __shared__ __align__(16) float2 ob[2][K][LOB];
+  __shared__ __align__(16) float2 w1s[M][LW1];      // stage-1 table; then the stage-0' hand-over
+  float2(*s1)[LS1] = reinterpret_cast<float2(*)[LS1]>(ra);
+  float2(*w0fs)[LW0F] = reinterpret_cast<float2(*)[LW0F]>(ra);
+  float2(*w0is)[Mp][LW0I] = reinterpret_cast<float2(*)[Mp][LW0I]>(ra);
+  float2* g0s = ra;
+  const ColJob& job = jobs.j[blockIdx.y];
+  const int kh = blockIdx.x;
+  const int kc = (blockIdx.z % T0) * 16;
+  const int part = blockIdx.z / T0;  // 0: padded-grid stage 0 and the store; 1: image-grid stage 0
+  const int N0 = jobs.N0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int k1 = kc + li;
+  constexpr int H = M / 2, KH2 = K / 2;
+  const float2* sa = job.a + (size_t)kh * M * M;
+  RegStage<(Mp * H + 255) / 256, float4> rs1;
+  RegStage<(M * 8 + 255) / 256, float4> rw1;
+  RegStage<(Kp * H + 255) / 256, float4> rw0f;
+  constexpr int NT_I = 2 * Mp * KH2, NT_G = NG0MAX * KH2;
+  RegStage<((NT_I > NT_G ? NT_I : NT_G) + 255) / 256, float4> rt;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  rs1.load(Mp * H, [&](int i) {
+    const int x0 = i / H, x1 = 2 * (i % H);
+    return (x0 < M) ? ld4(sa + x0 * M + x1) : z4;
+  });
+  rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
+  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
+  const int nt_tab = part == 0 ? NT_I : N0 * KH2;
+  if (part == 0)
+    rt.load(nt_tab, [&](int i) { return ld4(w0i + 2 * i); });
+  else
+    rt.load(nt_tab, [&](int i) { return ld4(jobs.w0n + 2 * i); });
+  float2 pbase[4], pextra[4];
+  float pks[4], pls[4];
+  if (wave < T0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = wave * 16 + 4 * lk + r;
+      const bool ok = k0 < K && k1 < K;
+      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
+      pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
+      pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = wave * 16 + 4 * lk + r;
+      const bool ok = k0 < K && k1 < K;
+      const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
+      pks[r] = ok ? sym.y : 0.f;
+      pls[r] = ok ? sym.x : 0.f;
+    }
+  }
+  rs1.store(Mp * H, [&](int i, float4 v) { st22(&s1[i / H][2 * (i % H)], v); });
+  rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
+  __syncthreads();
+  // stage 1': s2[x0][j] = sum_x1 s1[x0][x1] w1t[x1][kc + j]
+  for (int ti = wave; ti < TIR; ti += 4) {
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    ctile<M / 4>(&s1[ti * 16][0], LS1, &w1s[0][0], LW1, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x0 = ti * 16 + 4 * lk + r;
+      if (x0 < M) s2[x0][li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+    }
+  }
+  __syncthreads();
+  rw0f.store(Kp * H, [&](int i, float4 v) { st22(&w0fs[i / H][2 * (i % H)], v); });
+  __syncthreads();
+  // stage 0' on all four waves: waves 2-3 take the second half of the x0
+  // depth and hand their sums over through w1s; waves 0-1 form the update
+  float2 own[4], other[4];
+  {
+    const int ti = wave & 1, h = wave >> 1;
+    constexpr int SD = M / 4, S1 = SD / 2;
+    floatx4 acc[4];
+    zero_acc(acc, 4);
+    if (h == 0)
+      ctile<S1>(&w0fs[ti * 16][0], LW0F, &s2[0][0], LS2, acc);
+    else
+      ctile<SD - S1>(&w0fs[ti * 16][4 * S1], LW0F, &s2[4 * S1][0], LS2, acc);
+    static_assert(M * LW1 >= 2 * 4 * 64, "hand-over buffer fits the stage-1 table");
+    float2* red = &w1s[0][0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) own[r] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+    if (h == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(ti * 4 + r) * 64 + lane] = own[r];
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) other[r] = red[(ti * 4 + r) * 64 + lane];
+    }
+  }
+  if (wave < T0) {
+    const int ti = wave;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k0 = ti * 16 + 4 * lk + r;
+      if (k0 >= K || k1 >= K) continue;
+      const size_t idx = ((size_t)k0 * K + k1) * Kh + kh;
+      float2 res = make_float2(0.f, 0.f);
+      if (k0 != K / 2 && k1 != K / 2) {
+        res = pbase[r];
+        const float sa_ = job.ca * invG * (job.syma ? pks[r] : 1.f);
+        res.x = fmaf(sa_, own[r].x + other[r].x, res.x);
+        res.y = fmaf(sa_, own[r].y + other[r].y, res.y);
+        res.x = fmaf(job.ce, pextra[r].x, res.x);
+        res.y = fmaf(job.ce, pextra[r].y, res.y);
+      }
+      if (part == 0) job.out[idx] = res;
+      ob[0][k0][li] = res;
+      ob[1][k0][li] = make_float2(pls[r] * res.x, pls[r] * res.y);
+    }
+  }
+  __syncthreads();
+  if (part == 0)
+    rt.store(nt_tab, [&](int i, float4 v) {
+      st22(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
+    });
+  else
+    rt.store(nt_tab, [&](int i, float4 v) { st22(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
+  __syncthreads();
+  if (part == 0) {
+    // next inverse stage 0 on the padded grid: t1[v][x0][kh][k1] = sum_k0 w0i[v][x0][k0] ob[L][k0][k1]
+    const int njb = job.nt1 * 2 * TIR;
+    for (int jb = wave; jb < njb; jb += 4) {
+      floatx4 acc[4];
+      zero_acc(acc, 4);
+      const int u = jb / (2 * TIR), v = (jb / TIR) % 2, ti = jb % TIR;
+      const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
+      float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
+      ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
+      if (k1 >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x0 = ti * 16 + 4 * lk + r;
+        if (x0 < M)
+          dst[((size_t)v * M + x0) * C + (size_t)kh * K + k1] =
+              make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+      }
+    }
+  } else {
+    // image grid: t1n[x0][kh][k1] = sum_k0 w0n[x0][k0] ob[0][k0][k1]
+    for (int ti = wave; ti < N0 / 16; ti += 4) {
+      floatx4 acc[4];
+      zero_acc(acc, 4);
+      ctile<K / 4>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
+      if (k1 >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x0 = ti * 16 + 4 * lk + r;
+        job.t1n[((size_t)x0 * Kh + kh) * K + k1] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
+      }
+    }
+  }
+}
+
 // ----------------------------------------------- forward stage 1 (x1)
 template <int QT>
 __global__ void __launch_bounds__(128) k_fwd1(Fwd1Jobs jobs, const float2* __restrict__ tw, int G0,
@@ -2524,6 +2708,19 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   }
   const int nparts = (d.Kh * njobs * ktiles <= 128 && min_tiles >= 8) ? 2 : 1;
   const dim3 cgrid(d.Kh, njobs, ktiles * nparts);
+  // the forward sweeps' launches (one product field per job, image-grid stage
+  // 0 fused, two parts) take the lean kernel
+  bool lean = nparts == 2 && (band_iso(d, 32, 48) || band_iso(d, 24, 36));
+  for (int i = 0; i < njobs && lean; ++i) lean = jobs.j[i].b == nullptr && jobs.j[i].t1n != nullptr;
+  if (lean) {
+    if (band_iso(d, 32, 48))
+      LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                   d.alpha, d.s, invG);
+    else
+      LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                   d.alpha, d.s, invG);
+    return hipGetLastError();
+  }
   if (band_iso(d, 32, 48)) {
     LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
                  d.s, invG, nparts);
