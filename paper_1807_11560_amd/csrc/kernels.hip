@@ -956,6 +956,31 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
 // image-grid stage-0 table and the band values of the update) are issued at
 // the start, two complex values per load; the image-grid table waits in
 // registers until the LDS of the stage-1 input is free.
+// Band values of the column step's update at (k0 = 16 tile + 4 lk + r, k1):
+// the base and extra terms (read at a stride of Kh) and the L~ / K~ symbols
+// (formed in FP64); zero outside the band.
+template <int K, int Kh>
+__device__ __forceinline__ void update_values(const ColJob& job, int tile, int lk, int k1, int kh, int spow,
+                                              double alpha, float2 (&pbase)[4], float2 (&pextra)[4],
+                                              float (&pks)[4], float (&pls)[4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k0 = tile * 16 + 4 * lk + r;
+    const bool ok = k0 < K && k1 < K;
+    const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
+    pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
+    pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k0 = tile * 16 + 4 * lk + r;
+    const bool ok = k0 < K && k1 < K;
+    const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
+    pks[r] = ok ? sym.y : 0.f;
+    pls[r] = ok ? sym.x : 0.f;
+  }
+}
+
 constexpr int kGrid0Pre = 16;  // image-grid stage-0 table: complex values per thread
 template <class S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
@@ -1018,24 +1043,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   // band values of the update at (k0 = 16 wave + 4 lk + r, k1)
   float2 pbase[4], pextra[4];
   float pks[4], pls[4];
-  if (wave < T0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k0 = wave * 16 + 4 * lk + r;
-      const bool ok = k0 < K && k1 < K;
-      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
-      pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
-      pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k0 = wave * 16 + 4 * lk + r;
-      const bool ok = k0 < K && k1 < K;
-      const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
-      pks[r] = ok ? sym.y : 0.f;
-      pls[r] = ok ? sym.x : 0.f;
-    }
-  }
+  if (wave < T0) update_values<K, Kh>(job, wave, lk, k1, kh, spow, alpha, pbase, pextra, pks, pls);
   // ---- stores
   rs1.store(ns1, [&](int i, float4 v) {
     const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
@@ -1228,24 +1236,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     rt.load(nt_tab, [&](int i) { return ld4(jobs.w0n + 2 * i); });
   float2 pbase[4], pextra[4];
   float pks[4], pls[4];
-  if (wave < T0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k0 = wave * 16 + 4 * lk + r;
-      const bool ok = k0 < K && k1 < K;
-      const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
-      pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
-      pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k0 = wave * 16 + 4 * lk + r;
-      const bool ok = k0 < K && k1 < K;
-      const float2 sym = band_symbols(ok ? k0 : 0, ok ? k1 : 0, kh, K, K, spow, alpha);
-      pks[r] = ok ? sym.y : 0.f;
-      pls[r] = ok ? sym.x : 0.f;
-    }
-  }
+  if (wave < T0) update_values<K, Kh>(job, wave, lk, k1, kh, spow, alpha, pbase, pextra, pks, pls);
   rs1.store(Mp * H, [&](int i, float4 v) { st22(&s1[i / H][2 * (i % H)], v); });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
   __syncthreads();
