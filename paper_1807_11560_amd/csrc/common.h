@@ -215,8 +215,11 @@ hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* o
 // Reductions, deterministic two-pass; results in double on the device.
 hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* partial, double* out,
                          double scale, hipStream_t st);
+// With `count` (a zero counter of the caller, left zero), one launch: the
+// last block to finish sums the partials in the same order as the second pass.
 hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
-                           double* partial, double* out, double scale, hipStream_t st);
+                           double* partial, double* out, double scale, hipStream_t st,
+                           unsigned* count = nullptr);
 hipError_t launch_band_maxabs(const float2* a, const Dims& d, double* partial, double* out,
                               hipStream_t st);
 hipError_t launch_scalar_copy(const double* src, double* dst, int n, hipStream_t st);

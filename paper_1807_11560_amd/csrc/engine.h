@@ -92,6 +92,7 @@ class Engine {
   float *ug, *dug, *m1, *I0c, *IG, *IH;  // IG [nN][4]: I0 and its central differences; IH [nN][8]: Hessian
   float *mlight[2];
   double *partial, *scal, *pcg;
+  unsigned* count;  // zero counter of the one-launch reductions (zeroed with the tables)
   float *Lsym, *Ksym;
 
  private:

@@ -104,6 +104,7 @@ void Engine::layout(Carver& c) {
   }
   resid = c.take<float>(d.hessian == 2 ? (size_t)d.nN : 1);
   partial = c.take<double>(1024);
+  count = c.take<unsigned>(64);
   scal = c.take<double>(64);
   pcg = c.take<double>(SC_COUNT);
   Lsym = c.take<float>((size_t)d.nb);
@@ -182,6 +183,7 @@ hipError_t Engine::init_tables() {
     TRY(launch_twiddles(const_cast<float2*>(tw.fwd1), d_.K[1], G[1], 2, st_));
     TRY(launch_twiddles(const_cast<float2*>(tw.fwd2), d_.K[2], G[2], 3, st_));
   }
+  TRY(launch_fill(reinterpret_cast<float*>(count), 64, 0.f, st_));
   TRY(launch_synth_tables(twM_, synth_tab_, d_, st_));
   TRY(launch_col_tables(twM_, col_tab_, d_, st_));
   return launch_symbols(Lsym, Ksym, d_, st_);

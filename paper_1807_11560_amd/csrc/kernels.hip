@@ -2313,6 +2313,45 @@ __global__ void __launch_bounds__(kRedThreads) k_band_dot(const float2* a, const
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
+// k_band_dot and k_final in one launch: each block stores its partial sum,
+// and the block that finishes last (by a device-wide counter) adds the
+// partials in k_final's order and resets the counter.
+__global__ void __launch_bounds__(kRedThreads) k_band_dot_once(const float2* a, const float2* b,
+                                                               const float* Lsym, int nb, int Kh, double* partial,
+                                                               unsigned* count, double* out, double scale) {
+  __shared__ double sh[kRedThreads];
+  __shared__ bool last;
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nb; i += gridDim.x * blockDim.x) {
+    int e = i % nb;
+    double w = (e % Kh == 0) ? 1.0 : 2.0;
+    if (Lsym) w *= (double)Lsym[e];
+    s += w * ((double)a[i].x * b[i].x + (double)a[i].y * b[i].y);
+  }
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = r;
+    __threadfence();
+    last = atomicAdd(count, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vp = partial;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v = v + vp[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out = scale * sh[0];
+    *count = 0u;
+  }
+}
+
 __global__ void __launch_bounds__(kRedThreads) k_band_maxabs(const float2* a, int n,
                                                              double* partial) {
   __shared__ double sh[kRedThreads];
@@ -2963,8 +3002,13 @@ hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* pa
 }
 
 hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
-                           double* partial, double* out, double scale, hipStream_t st) {
+                           double* partial, double* out, double scale, hipStream_t st, unsigned* count) {
   const int blocks = 64;
+  if (count) {
+    hipLaunchKernelGGL(k_band_dot_once, dim3(blocks), dim3(kRedThreads), 0, st, a, b, Lsym, d.nb, d.Kh, partial,
+                       count, out, scale);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_band_dot, dim3(blocks), dim3(kRedThreads), 0, st, a, b, Lsym, d.nb, d.Kh,
                      partial);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, st, partial, blocks, out, scale, 0);
