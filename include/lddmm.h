@@ -222,8 +222,12 @@ int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, s
  *   v0_inout  [3][K0][K1][K2] complex64 (device, read and written): the start
  *             iterate (zero for a fresh registration) and the result
  *   stats     host array of `stats_len` entries (one per iteration) or NULL
- * Synchronous.  Returns LDDMM_OK, LDDMM_W_LINESEARCH (stopped early on a
- * failed search; v0 holds the last accepted iterate) or an error. */
+ * Synchronous: the host takes the loop's decisions from scalars that a
+ * kernel writes to 512 bytes of pinned host memory held per calling host
+ * thread until the process ends (copies and stream synchronisation instead
+ * if that memory cannot be allocated).  Returns LDDMM_OK, LDDMM_W_LINESEARCH
+ * (stopped early on a failed search; v0 holds the last accepted iterate) or
+ * an error. */
 int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void* v0_inout,
                    int32_t gn_iters, int32_t pcg_iters, lddmm_stats* stats, int32_t stats_len,
                    void* ws, size_t ws_bytes, void* stream);

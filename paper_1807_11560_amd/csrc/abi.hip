@@ -365,6 +365,58 @@ constexpr int kMaxBatch = 4096;
 constexpr int kBatchConcurrency = 8;
 size_t batch_slice(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 
+// 64 doubles of pinned, coherent host memory per host thread (held until the
+// process ends; null if they cannot be had), through which the registration
+// loop reads its scalars without a copy command: a kernel at the end of the
+// work writes the values to words 1.. and then 1 to word 0, which the host
+// cleared before enqueueing it and spins on.
+constexpr int kHostWords = 64;
+double* host_flag_pair() {
+  thread_local double* p = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), kHostWords * sizeof(double),
+                      hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  return p;
+}
+
+// Waits until the stream's kernel has set hf[0] (spinning on the host
+// memory), or the stream has finished or failed.
+hipError_t wait_host_flag(double* hf, hipStream_t st) {
+  volatile double* f = hf;
+  for (;;) {
+    for (int i = 0; i < 2048; ++i)
+      if (f[0] != 0.0) return hipSuccess;
+    const hipError_t q = hipStreamQuery(st);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return q;
+    return f[0] != 0.0 ? hipSuccess : hipErrorUnknown;
+  }
+}
+
+// out[0 .. na + nb) = a[0 .. na), b[0 .. nb) (device memory, na + nb < 64),
+// read once the work enqueued on st so far has finished.
+hipError_t read_back(double* out, const double* a, int na, const double* b, int nb, hipStream_t st) {
+  hipError_t r;
+  double* hf = host_flag_pair();
+  if (!hf) {
+    if ((r = hipMemcpyAsync(out, a, na * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
+    if (nb && (r = hipMemcpyAsync(out + na, b, nb * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
+    return hipStreamSynchronize(st);
+  }
+  volatile double* f = hf;
+  f[0] = 0.0;
+  if ((r = launch_host_copy(a, na, b, nb, hf, st))) return r;
+  if ((r = wait_host_flag(hf, st))) return r;
+  for (int i = 0; i < na + nb; ++i) out[i] = f[1 + i];
+  return hipSuccess;
+}
+
 int run_register(Engine& e, const void* ws, const float* I0, const float* I1, void* v0_inout,
                  int gn_iters, int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
   const Dims& d = e.dims();
@@ -406,8 +458,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     }));
     kept = false;
     double sc[4];
-    HTRY(hipMemcpyAsync(sc, e.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HTRY(hipStreamSynchronize(st));
+    HTRY(read_back(sc, e.scal, 4, nullptr, 0, st));
     if (!std::isfinite(sc[0]) || !std::isfinite(sc[3]))
       return fail(LDDMM_E_NONFINITE, "energy or gradient is not finite");
     if (g0_inf < 0) g0_inf = sc[3];
@@ -416,8 +467,10 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
     HTRY(launch_pcg_reset(e.pcg, st));
     int used = 0;
-    const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {});
+    double* hf = host_flag_pair();
+    const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {hf});
     for (int k = 0; k < pcg_iters; ++k) {
+      if (hf) static_cast<volatile double*>(hf)[0] = 0.0;
       // H d, then the CG updates (decisions taken on the device)
       HTRY(run_graph(e, iter_key, [&]() -> hipError_t {
         hipError_t r;
@@ -427,29 +480,32 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
         if ((r = launch_pcg_phase_a(e.pcg, s))) return r;
         if ((r = launch_pcg_update_pr(e.pcg, e.dh, e.Hdh, e.ph, e.rh, n, s))) return r;
         if ((r = launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, s, e.count))) return r;
-        if ((r = launch_pcg_phase_b(e.pcg, s))) return r;
+        if ((r = launch_pcg_phase_b(e.pcg, s, hf))) return r;
         return launch_pcg_update_d(e.pcg, e.rh, e.dh, n, s);
       }));
       ++*hvps;
       double stopped = 0.0;
-      HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
-      HTRY(hipStreamSynchronize(st));
+      if (hf) {
+        HTRY(wait_host_flag(hf, st));
+        stopped = static_cast<volatile double*>(hf)[1];
+      } else {
+        HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
+        HTRY(hipStreamSynchronize(st));
+      }
       used = k + 1;
       if (stopped != 0.0) break;
     }
     (void)used;
-    double pc[SC_COUNT];
-    HTRY(hipMemcpyAsync(pc, e.pcg, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-    // slope <g, p>_V; fall back to -g if p is not a descent direction
+    // the CG scalars and the slope <g, p>_V; fall back to -g if p is not a
+    // descent direction
+    double pc[SC_COUNT + 1];
     HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
-    double slope = 0.0;
-    HTRY(hipMemcpyAsync(&slope, e.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-    HTRY(hipStreamSynchronize(st));
+    HTRY(read_back(pc, e.pcg, SC_COUNT, e.scal + 4, 1, st));
+    double slope = pc[SC_COUNT];
     if (!(slope < 0.0)) {
       HTRY(launch_axpy_band(e.tmph, e.gh, -1.f, e.ph, n, st));  // tmph is zero-filled below
       HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
-      HTRY(hipMemcpyAsync(&slope, e.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-      HTRY(hipStreamSynchronize(st));
+      HTRY(read_back(&slope, e.scal + 4, 1, nullptr, 0, st));
     }
     // Armijo backtracking
     double eps = 1.0, Etry = 0.0;
@@ -469,8 +525,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
         if ((r = e.forward(I0))) return r;
         return e.energy(e.final_state(), I1);
       }));
-      HTRY(hipMemcpyAsync(&Etry, e.scal, sizeof(double), hipMemcpyDeviceToHost, st));
-      HTRY(hipStreamSynchronize(st));
+      HTRY(read_back(&Etry, e.scal, 1, nullptr, 0, st));
       if (std::isfinite(Etry) && Etry <= sc[0] + c1 * eps * slope) {
         ok = true;
         break;

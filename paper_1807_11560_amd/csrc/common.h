@@ -233,7 +233,11 @@ hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dvec, 
 hipError_t launch_pcg_phase_a(double* sc, hipStream_t st);
 hipError_t launch_pcg_update_pr(const double* sc, const float2* dvec, const float2* Hd, float2* p,
                                 float2* r, int n, hipStream_t st);
-hipError_t launch_pcg_phase_b(double* sc, hipStream_t st);
+// host: optional pinned host pair that receives {1, stop flag} (see k_pcg_phase_b)
+hipError_t launch_pcg_phase_b(double* sc, hipStream_t st, double* host = nullptr);
+// Copies a[0 .. na) and b[0 .. nb) (na + nb <= 63) of device memory to
+// host[1 ..] of pinned host memory, then sets host[0] = 1.
+hipError_t launch_host_copy(const double* a, int na, const double* b, int nb, double* host, hipStream_t st);
 hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dvec, int n,
                                hipStream_t st);
 

@@ -2437,8 +2437,15 @@ __global__ void k_pcg_update_pr(const double* sc, const float2* dv, const float2
   r[i] = make_float2(fmaf(-al, hd.x, rv.x), fmaf(-al, hd.y, rv.y));
 }
 
-__global__ void k_pcg_phase_b(double* sc) {
+// host (optional, pinned host memory): host[1] = the stop flag of this
+// iteration, then host[0] = 1, both visible system-wide
+__global__ void k_pcg_phase_b(double* sc, double* host) {
   if (threadIdx.x != 0) return;
+  if (host) {
+    host[1] = sc[SC_STOPPED];
+    __threadfence_system();
+    __hip_atomic_store(host, 1.0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   if (sc[SC_DOUPD] == 0.0) return;
   sc[SC_BETA] = sc[SC_RRNEW] / sc[SC_RR];
   sc[SC_RR] = sc[SC_RRNEW];
@@ -3050,8 +3057,25 @@ hipError_t launch_pcg_update_pr(const double* sc, const float2* dv, const float2
   hipLaunchKernelGGL(k_pcg_update_pr, dim3(nblk(n, 256)), dim3(256), 0, st, sc, dv, Hd, p, r, n);
   return hipGetLastError();
 }
-hipError_t launch_pcg_phase_b(double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_phase_b, dim3(1), dim3(64), 0, st, sc);
+// host[1 .. na] = a, host[1 + na .. na + nb] = b, then host[0] = 1, visible
+// system-wide (host: pinned host memory)
+__global__ void k_host_copy(const double* a, int na, const double* b, int nb, double* host) {
+  const int i = threadIdx.x;
+  if (i < na) host[1 + i] = a[i];
+  if (i < nb) host[1 + na + i] = b[i];
+  __threadfence_system();
+  __syncthreads();
+  if (i == 0) __hip_atomic_store(host, 1.0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_host_copy(const double* a, int na, const double* b, int nb, double* host, hipStream_t st) {
+  if (na < 0 || nb < 0 || na + nb > 63) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_host_copy, dim3(1), dim3(64), 0, st, a, na, b, nb, host);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_phase_b(double* sc, hipStream_t st, double* host) {
+  hipLaunchKernelGGL(k_pcg_phase_b, dim3(1), dim3(64), 0, st, sc, host);
   return hipGetLastError();
 }
 hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dv, int n, hipStream_t st) {
