@@ -268,8 +268,10 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
                          size_t ws_bytes, void* stream);
 
 /* Launch timing of one kernel, for roofline accounting.  While enabled,
- * one launch in `every` (the first, then every `every`-th, counted over the
- * launches of that kernel this process makes) of kernel family `family`
+ * one launch in `every` on average (all of them for every = 1; otherwise
+ * those whose sequence number among the launches of that kernel this
+ * process makes hashes to a multiple of `every`, so that the sample does not
+ * follow a period of the launch sequence) of kernel family `family`
  * (LDDMM_KF_*) is bracketed by HIP events on its stream, and the
  * algorithmic work of those launches (flops of the partial DFT contractions,
  * Lie products and interpolation; HBM bytes of their inputs and outputs, each

@@ -130,7 +130,7 @@ using EventPair = std::pair<hipEvent_t, hipEvent_t>;
 struct Timer {
   std::mutex mu;
   int family = 0;
-  int every = 1;        // time one launch of the family in `every`
+  int every = 1;        // time one launch of the family in `every` (on average)
   int64_t seen = 0;     // launches of the family enqueued or captured
   bool take = false;    // whether the current launch is sampled
   bool error = false;
@@ -200,7 +200,14 @@ namespace lddmm {
 void timer_work(int family, double flops, double bytes) {
   if (g_timer.family == 0 || family != g_timer.family) return;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  g_timer.take = g_timer.seen++ % g_timer.every == 0;
+  // a launch is sampled when a mix of its sequence number (SplitMix64's
+  // finaliser) is divisible by `every`, so that the sample does not lock onto
+  // a period of the launch sequence
+  uint64_t z = (uint64_t)g_timer.seen++ + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  g_timer.take = z % (uint64_t)g_timer.every == 0;
   if (!g_timer.take) return;
   double& f = t_capturing ? t_capturing->flops : g_timer.flops;
   double& b = t_capturing ? t_capturing->bytes : g_timer.bytes;
