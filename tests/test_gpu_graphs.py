@@ -103,6 +103,24 @@ def test_timer_counts_the_same_launches_with_graphs(setup):
     assert 0.0 < ms1 < 3.0 * ms0 and 0.0 < ms0 < 3.0 * ms1
 
 
+def splitmix64(i):
+    m = (1 << 64) - 1
+    z = (i + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_published_values():
+    """The first outputs of SplitMix64 seeded with 0 (the generator adds the
+    gamma before mixing, so output k mixes k * gamma): 0xE220A8397B1DCDAF,
+    0x6E789E6AA1B965F4, 0x06C45D188009454F."""
+    m = (1 << 64) - 1
+    g = 0x9E3779B97F4A7C15
+    outs = [splitmix64(((k * g) - g) & m) for k in (1, 2, 3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
 def test_timer_samples_one_launch_in_every(setup):
     prob, I0, I1, v0, dirs = setup
     lib = L()
@@ -118,6 +136,9 @@ def test_timer_samples_one_launch_in_every(setup):
         counts[every] = lib.kernel_timer_read()
     lib.kernel_timer(0)
     n1, n4 = counts[1][0], counts[4][0]
-    assert n4 == (n1 + 3) // 4
+    # launch i (counted from the enabling call) is sampled when the SplitMix64
+    # finaliser of i + golden gamma is divisible by `every`
+    assert n4 == sum(1 for i in range(n1) if splitmix64(i) % 4 == 0)
+    assert 0 < n4 < n1
     # the sampled work is the work of the sampled launches
     assert counts[4][2] == pytest.approx(counts[1][2] * n4 / n1, rel=0.2)
