@@ -473,7 +473,6 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     HTRY(launch_pcg_init(e.gh, e.ph, e.rh, e.dh, n, st));
     HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
     HTRY(launch_pcg_reset(e.pcg, st));
-    int used = 0;
     double* hf = host_flag_pair();
     const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {hf});
     for (int k = 0; k < pcg_iters; ++k) {
@@ -499,10 +498,8 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
         HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
         HTRY(hipStreamSynchronize(st));
       }
-      used = k + 1;
       if (stopped != 0.0) break;
     }
-    (void)used;
     // the CG scalars and the slope <g, p>_V; fall back to -g if p is not a
     // descent direction
     double pc[SC_COUNT + 1];
