@@ -173,8 +173,10 @@ bool take_pair(EventPair* ev) {
     g_timer.pool.pop_back();
     return true;
   }
-  if (hipEventCreate(&ev->first) != hipSuccess) return false;
-  if (hipEventCreate(&ev->second) != hipSuccess) return false;
+  // device-scope release: recording the pair writes back no caches for the
+  // host, so the interval holds the kernel and not a system-wide fence
+  if (hipEventCreateWithFlags(&ev->first, hipEventReleaseToDevice) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&ev->second, hipEventReleaseToDevice) != hipSuccess) return false;
   return true;
 }
 
