@@ -380,7 +380,7 @@ size_t batch_slice(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 // work writes the values to words 1.. and then 1 to word 0, which the host
 // cleared before enqueueing it and spins on.
 constexpr int kHostWords = 64;
-double* host_flag_pair() {
+double* host_words() {
   thread_local double* p = nullptr;
   thread_local bool tried = false;
   if (!tried) {
@@ -412,7 +412,7 @@ hipError_t wait_host_flag(double* hf, hipStream_t st) {
 // read once the work enqueued on st so far has finished.
 hipError_t read_back(double* out, const double* a, int na, const double* b, int nb, hipStream_t st) {
   hipError_t r;
-  double* hf = host_flag_pair();
+  double* hf = host_words();
   if (!hf) {
     if ((r = hipMemcpyAsync(out, a, na * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
     if (nb && (r = hipMemcpyAsync(out + na, b, nb * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
@@ -475,7 +475,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     HTRY(launch_pcg_init(e.gh, e.ph, e.rh, e.dh, n, st));
     HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
     HTRY(launch_pcg_reset(e.pcg, st));
-    double* hf = host_flag_pair();
+    double* hf = host_words();
     const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {hf});
     for (int k = 0; k < pcg_iters; ++k) {
       if (hf) static_cast<volatile double*>(hf)[0] = 0.0;
