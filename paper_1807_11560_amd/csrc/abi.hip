@@ -484,11 +484,13 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
         hipError_t r;
         const hipStream_t s = e.stream();
         if ((r = e.hessvec(e.dh, e.Hdh))) return r;
-        if ((r = launch_band_dot(e.dh, e.Hdh, e.Lsym, d, e.partial, e.pcg + SC_DHD, 1.0, s, e.count))) return r;
-        if ((r = launch_pcg_phase_a(e.pcg, s))) return r;
+        // <d, H d>_V, then phase a; <r, r>_V, then phase b (in the reductions' last blocks)
+        if ((r = launch_band_dot(e.dh, e.Hdh, e.Lsym, d, e.partial, e.pcg + SC_DHD, 1.0, s, e.count, e.pcg, 1)))
+          return r;
         if ((r = launch_pcg_update_pr(e.pcg, e.dh, e.Hdh, e.ph, e.rh, n, s))) return r;
-        if ((r = launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, s, e.count))) return r;
-        if ((r = launch_pcg_phase_b(e.pcg, s, hf))) return r;
+        if ((r = launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RRNEW, 1.0, s, e.count, e.pcg, 2,
+                                 hf)))
+          return r;
         return launch_pcg_update_d(e.pcg, e.rh, e.dh, n, s);
       }));
       ++*hvps;

@@ -216,10 +216,13 @@ hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* o
 hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* partial, double* out,
                          double scale, hipStream_t st);
 // With `count` (a zero counter of the caller, left zero), one launch: the
-// last block to finish sums the partials in the same order as the second pass.
+// last block to finish sums the partials in the same order as the second pass
+// and then, for post = 1 or 2, runs CG scalar phase a or b on `pcg` (phase b
+// with the optional pinned host pair `host`).
 hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
                            double* partial, double* out, double scale, hipStream_t st,
-                           unsigned* count = nullptr);
+                           unsigned* count = nullptr, double* pcg = nullptr, int post = 0,
+                           double* host = nullptr);
 hipError_t launch_band_maxabs(const float2* a, const Dims& d, double* partial, double* out,
                               hipStream_t st);
 hipError_t launch_scalar_copy(const double* src, double* dst, int n, hipStream_t st);
@@ -230,11 +233,8 @@ size_t src_shared_bytes(const Dims& d);
 hipError_t launch_pcg_reset(double* sc, hipStream_t st);
 hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dvec, int n,
                            hipStream_t st);
-hipError_t launch_pcg_phase_a(double* sc, hipStream_t st);
 hipError_t launch_pcg_update_pr(const double* sc, const float2* dvec, const float2* Hd, float2* p,
                                 float2* r, int n, hipStream_t st);
-// host: optional pinned host pair that receives {1, stop flag} (see k_pcg_phase_b)
-hipError_t launch_pcg_phase_b(double* sc, hipStream_t st, double* host = nullptr);
 // Copies a[0 .. na) and b[0 .. nb) (na + nb <= 63) of device memory to
 // host[1 ..] of pinned host memory, then sets host[0] = 1.
 hipError_t launch_host_copy(const double* a, int na, const double* b, int nb, double* host, hipStream_t st);

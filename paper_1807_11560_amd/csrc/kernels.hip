@@ -2316,9 +2316,15 @@ __global__ void __launch_bounds__(kRedThreads) k_band_dot(const float2* a, const
 // k_band_dot and k_final in one launch: each block stores its partial sum,
 // and the block that finishes last (by a device-wide counter) adds the
 // partials in k_final's order and resets the counter.
+__device__ void pcg_phase_a_body(double* sc);
+__device__ void pcg_phase_b_body(double* sc, double* host);
+
+// post: 0, or the CG scalar phase that follows the sum (1: phase a, 2: phase
+// b with the optional host pair), run by the last block once the sum is in *out
 __global__ void __launch_bounds__(kRedThreads) k_band_dot_once(const float2* a, const float2* b,
                                                                const float* Lsym, int nb, int Kh, double* partial,
-                                                               unsigned* count, double* out, double scale) {
+                                                               unsigned* count, double* out, double scale,
+                                                               double* pcg, int post, double* host) {
   __shared__ double sh[kRedThreads];
   __shared__ bool last;
   double s = 0.0;
@@ -2349,6 +2355,8 @@ __global__ void __launch_bounds__(kRedThreads) k_band_dot_once(const float2* a, 
   if (threadIdx.x == 0) {
     *out = scale * sh[0];
     *count = 0u;
+    if (post == 1) pcg_phase_a_body(pcg);
+    if (post == 2) pcg_phase_b_body(pcg, host);
   }
 }
 
@@ -2409,8 +2417,7 @@ __global__ void k_pcg_init(const float2* g, float2* p, float2* r, float2* dv, in
 
 // After <d, H d>_V: decide whether this iteration updates.  The first
 // iteration is the one before any update (SC_ITERS == 0 and not stopped).
-__global__ void k_pcg_phase_a(double* sc) {
-  if (threadIdx.x != 0) return;
+__device__ void pcg_phase_a_body(double* sc) {
   sc[SC_DOUPD] = 0.0;
   sc[SC_NEGG] = 0.0;
   if (sc[SC_STOPPED] != 0.0) return;
@@ -2437,10 +2444,10 @@ __global__ void k_pcg_update_pr(const double* sc, const float2* dv, const float2
   r[i] = make_float2(fmaf(-al, hd.x, rv.x), fmaf(-al, hd.y, rv.y));
 }
 
-// host (optional, pinned host memory): host[1] = the stop flag of this
-// iteration, then host[0] = 1, both visible system-wide
-__global__ void k_pcg_phase_b(double* sc, double* host) {
-  if (threadIdx.x != 0) return;
+// After <r, r>_V: beta = <r, r>_new / <r, r>_old for an iteration that
+// updated.  host (optional, pinned host memory): host[1] = the stop flag of
+// this iteration, then host[0] = 1, both visible system-wide.
+__device__ void pcg_phase_b_body(double* sc, double* host) {
   if (host) {
     host[1] = sc[SC_STOPPED];
     __threadfence_system();
@@ -3009,11 +3016,13 @@ hipError_t launch_sqdiff(const float* a, const float* b, long long n, double* pa
 }
 
 hipError_t launch_band_dot(const float2* a, const float2* b, const float* Lsym, const Dims& d,
-                           double* partial, double* out, double scale, hipStream_t st, unsigned* count) {
+                           double* partial, double* out, double scale, hipStream_t st, unsigned* count,
+                           double* pcg, int post, double* host) {
+  if (post && (!count || !pcg)) return hipErrorInvalidValue;
   const int blocks = 64;
   if (count) {
     hipLaunchKernelGGL(k_band_dot_once, dim3(blocks), dim3(kRedThreads), 0, st, a, b, Lsym, d.nb, d.Kh, partial,
-                       count, out, scale);
+                       count, out, scale, pcg, post, host);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_band_dot, dim3(blocks), dim3(kRedThreads), 0, st, a, b, Lsym, d.nb, d.Kh,
@@ -3048,10 +3057,6 @@ hipError_t launch_pcg_init(const float2* g, float2* p, float2* r, float2* dv, in
   hipLaunchKernelGGL(k_pcg_init, dim3(nblk(n, 256)), dim3(256), 0, st, g, p, r, dv, n);
   return hipGetLastError();
 }
-hipError_t launch_pcg_phase_a(double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_phase_a, dim3(1), dim3(64), 0, st, sc);
-  return hipGetLastError();
-}
 hipError_t launch_pcg_update_pr(const double* sc, const float2* dv, const float2* Hd, float2* p,
                                 float2* r, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_update_pr, dim3(nblk(n, 256)), dim3(256), 0, st, sc, dv, Hd, p, r, n);
@@ -3074,10 +3079,6 @@ hipError_t launch_host_copy(const double* a, int na, const double* b, int nb, do
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_phase_b(double* sc, hipStream_t st, double* host) {
-  hipLaunchKernelGGL(k_pcg_phase_b, dim3(1), dim3(64), 0, st, sc, host);
-  return hipGetLastError();
-}
 hipError_t launch_pcg_update_d(const double* sc, const float2* r, float2* dv, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_update_d, dim3(nblk(n, 256)), dim3(256), 0, st, sc, r, dv, n);
   return hipGetLastError();
