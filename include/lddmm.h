@@ -306,7 +306,10 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, 
  * the first time they run for a given device, workspace, problem, external
  * input pointers and timed kernel family, and replayed on the caller's
  * stream afterwards; the kernels and their order are the same as without.
- * The captured graphs hold workspace addresses: a workspace that is freed
+ * Captures run one at a time across host threads (the pairs of
+ * lddmm_register_batch capture their own graphs in turn).  The CG iteration's
+ * graph also holds the calling thread's pinned host words (see
+ * lddmm_register), so each thread has its own.  The captured graphs hold workspace addresses: a workspace that is freed
  * and reallocated at the same address with the same problem reuses them,
  * which is correct because all of its buffers are recomputed.  Graphs live
  * until the process ends.  `enable` must be 0 or 1 (else

@@ -163,6 +163,7 @@ struct GraphEntry {
 };
 bool g_use_graphs = false;
 std::mutex g_graph_mu;
+std::mutex g_capture_mu;
 std::map<std::string, GraphEntry> g_graphs;  // entries live until the process ends
 std::map<int, hipStream_t> g_cap_streams;
 thread_local GraphEntry* t_capturing = nullptr;
@@ -323,6 +324,15 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
   }
   const hipStream_t st = e.stream();
   hipError_t err;
+  // captures run one at a time (the capture stream of a device is shared by
+  // the host threads of a batch)
+  std::unique_lock<std::mutex> cl(g_capture_mu, std::defer_lock);
+  if (!g) {
+    cl.lock();
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) g = &it->second;
+  }
   if (!g) {
     hipStream_t cap = nullptr;
     if ((err = capture_stream(&cap)) != hipSuccess) return err;
@@ -351,6 +361,7 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
     std::lock_guard<std::mutex> lk(g_graph_mu);
     g = &(g_graphs[key] = std::move(ne));
   }
+  if (cl.owns_lock()) cl.unlock();
   if (!g->pairs.empty()) {
     std::lock_guard<std::mutex> lk(g_timer.mu);
     harvest(*g);

@@ -97,3 +97,29 @@ def test_atlas_serving_shapes_run():
         print(f"{probs[i].grid} {probs[i].band}: MSE_rel {stats[i][0]['mse_rel']:.2f} hvps {hvps[i]}")
         assert status[i] == ref[i][2] and hvps[i] == ref[i][3]
         assert np.array_equal(vs[i].cpu().numpy(), ref[i][0])
+
+
+def test_batch_with_graph_replay():
+    """With graph replay on, the pairs' host threads capture their sequences
+    one at a time and then replay them: two batches in a row give, pair by
+    pair, exactly the results of the batch without graphs."""
+    pairs = small_pairs()
+    probs = [q for q, _, _ in pairs]
+    I0s, I1s = [a for _, a, _ in pairs], [b for _, _, b in pairs]
+    ws = L().BatchWorkspace(probs)
+    ref = L().register_batch(probs, I0s, I1s, ws, gn_iters=2, pcg_iters=4, concurrency=4)
+    torch.cuda.synchronize()
+    ref_v = [v.cpu().numpy() for v in ref[0]]
+    L().use_graphs(True)
+    try:
+        for rep in range(2):
+            vs, stats, status, hvps, rc = L().register_batch(probs, I0s, I1s, ws, gn_iters=2, pcg_iters=4,
+                                                             concurrency=4)
+            torch.cuda.synchronize()
+            print(f"replay {rep}: status {status} hvps {hvps}")
+            assert rc == ref[4] and list(status) == list(ref[2]) and list(hvps) == list(ref[3])
+            for i in range(len(pairs)):
+                assert np.array_equal(vs[i].cpu().numpy(), ref_v[i])
+                assert [s["energy"] for s in stats[i]] == [s["energy"] for s in ref[1][i]]
+    finally:
+        L().use_graphs(False)
