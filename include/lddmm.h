@@ -223,8 +223,9 @@ int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, s
  *             iterate (zero for a fresh registration) and the result
  *   stats     host array of `stats_len` entries (one per iteration) or NULL
  * Synchronous: the host takes the loop's decisions from scalars that a
- * kernel writes to 512 bytes of pinned host memory held per calling host
- * thread until the process ends (copies and stream synchronisation instead
+ * kernel writes to 512 bytes of pinned host memory that the calling host
+ * thread holds until it exits (the block then serves a later thread; blocks
+ * are kept until the process ends; copies and stream synchronisation instead
  * if that memory cannot be allocated).  Returns LDDMM_OK, LDDMM_W_LINESEARCH
  * (stopped early on a failed search; v0 holds the last accepted iterate) or
  * an error. */
@@ -309,7 +310,10 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, 
  * Captures run one at a time across host threads (the pairs of
  * lddmm_register_batch capture their own graphs in turn).  The CG iteration's
  * graph also holds the calling thread's pinned host words (see
- * lddmm_register), so each thread has its own.  The captured graphs hold workspace addresses: a workspace that is freed
+ * lddmm_register), so each block of words has its own; the worker threads of
+ * successive batched calls reuse the blocks and therefore the graphs.  The
+ * graphs are keyed by the state and integrator too, so calls on one
+ * workspace that differ only in those never share a graph.  The captured graphs hold workspace addresses: a workspace that is freed
  * and reallocated at the same address with the same problem reuses them,
  * which is correct because all of its buffers are recomputed.  Graphs live
  * until the process ends.  `enable` must be 0 or 1 (else

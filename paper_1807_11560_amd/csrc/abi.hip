@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "sampler.h"
 
 using namespace lddmm;
 
@@ -128,11 +129,8 @@ int check_ws(const Dims& d, const void* ws, size_t ws_bytes) {
 // ---------------------------------------------------------------- timer
 using EventPair = std::pair<hipEvent_t, hipEvent_t>;
 struct Timer {
-  std::mutex mu;
-  int family = 0;
-  int every = 1;        // time one launch of the family in `every` (on average)
-  int64_t seen = 0;     // launches of the family enqueued or captured
-  bool take = false;    // whether the current launch is sampled
+  LaunchSampler smp;    // family, one launch in `every`, the per-thread decision
+  std::mutex& mu = smp.mu;
   bool error = false;
   std::vector<EventPair> pending;
   std::vector<EventPair> pool;
@@ -201,26 +199,16 @@ void harvest(GraphEntry& g) {
 
 namespace lddmm {
 void timer_work(int family, double flops, double bytes) {
-  if (g_timer.family == 0 || family != g_timer.family) return;
-  std::lock_guard<std::mutex> lk(g_timer.mu);
-  // a launch is sampled when a mix of its sequence number (SplitMix64's
-  // finaliser) is divisible by `every`, so that the sample does not lock onto
-  // a period of the launch sequence
-  uint64_t z = (uint64_t)g_timer.seen++ + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  g_timer.take = z % (uint64_t)g_timer.every == 0;
-  if (!g_timer.take) return;
-  double& f = t_capturing ? t_capturing->flops : g_timer.flops;
-  double& b = t_capturing ? t_capturing->bytes : g_timer.bytes;
-  f += flops;
-  b += bytes;
+  g_timer.smp.account(family, [&] {
+    double& f = t_capturing ? t_capturing->flops : g_timer.flops;
+    double& b = t_capturing ? t_capturing->bytes : g_timer.bytes;
+    f += flops;
+    b += bytes;
+  });
 }
 bool timer_events(int family, hipEvent_t* start, hipEvent_t* stop) {
-  if (g_timer.family == 0 || family != g_timer.family || t_capturing) return false;
+  if (t_capturing || !g_timer.smp.sampled(family)) return false;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  if (!g_timer.take) return false;
   EventPair ev;
   if (!take_pair(&ev)) {
     g_timer.error = true;
@@ -232,9 +220,8 @@ bool timer_events(int family, hipEvent_t* start, hipEvent_t* stop) {
   return true;
 }
 void timer_captured(int family, hipStream_t st) {
-  if (g_timer.family == 0 || family != g_timer.family || !t_capturing) return;
+  if (!t_capturing || !g_timer.smp.sampled(family)) return;
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  if (!g_timer.take) return;
   // the node the next captured operation would depend on: the kernel just launched
   hipStreamCaptureStatus cs;
   const hipGraphNode_t* deps = nullptr;
@@ -253,7 +240,8 @@ std::string graph_key(const Engine& e, const void* ws, int kind, std::initialize
   int dev = -1;
   (void)hipGetDevice(&dev);
   // a timed graph samples the launches the timer picked while it was captured
-  const int fam = g_timer.family ? g_timer.family + 256 * g_timer.every : 0;
+  const int tf = g_timer.smp.family.load();
+  const int fam = tf ? tf + 256 * g_timer.smp.every.load() : 0;
   std::string k;
   auto put = [&k](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
   put(&dev, sizeof dev);
@@ -268,6 +256,8 @@ std::string graph_key(const Engine& e, const void* ws, int kind, std::initialize
   put(&d.alpha, sizeof d.alpha);
   put(&d.sigma, sizeof d.sigma);
   put(&d.hessian, sizeof d.hessian);
+  put(&d.state, sizeof d.state);
+  put(&d.integrator, sizeof d.integrator);
   for (const void* p : ext) put(&p, sizeof p);
   return k;
 }
@@ -338,7 +328,7 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
     if ((err = capture_stream(&cap)) != hipSuccess) return err;
     if ((err = e.aux_init(e.dims().nt + 2)) != hipSuccess) return err;
     GraphEntry ne;
-    ne.family = g_timer.family;
+    ne.family = g_timer.smp.family.load();
     e.set_stream(cap);
     t_capturing = &ne;
     err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -367,7 +357,7 @@ hipError_t run_graph(Engine& e, const std::string& key, const std::function<hipE
     harvest(*g);
   }
   if ((err = hipGraphLaunch(g->exec, st)) != hipSuccess) return err;
-  if (g->family != 0 && g->family == g_timer.family) {
+  if (g->family != 0 && g->family == g_timer.smp.family.load()) {
     std::lock_guard<std::mutex> lk(g_timer.mu);
     g_timer.flops += g->flops;
     g_timer.bytes += g->bytes;
@@ -385,24 +375,48 @@ constexpr int kMaxBatch = 4096;
 constexpr int kBatchConcurrency = 8;
 size_t batch_slice(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 
-// 64 doubles of pinned, coherent host memory per host thread (held until the
-// process ends; null if they cannot be had), through which the registration
-// loop reads its scalars without a copy command: a kernel at the end of the
-// work writes the values to words 1.. and then 1 to word 0, which the host
-// cleared before enqueueing it and spins on.
+// 64 doubles of pinned, coherent host memory per host thread, through which
+// the registration loop reads its scalars without a copy command: a kernel
+// at the end of the work writes the values to words 1.. and then 1 to word
+// 0, which the host cleared before enqueueing it and spins on.  A thread
+// holds its block from its first use until it exits; the block then returns
+// to a pool that later threads draw from, so the worker threads of
+// successive batched calls reuse the same blocks (and the CG graphs captured
+// with them).  Blocks are never freed; null if none can be had.
 constexpr int kHostWords = 64;
+struct HostWordsPool {
+  std::mutex mu;
+  std::vector<double*> free;
+};
+HostWordsPool g_host_words;
+struct HostWordsLease {
+  double* p = nullptr;
+  bool tried = false;
+  ~HostWordsLease() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_host_words.mu);
+    g_host_words.free.push_back(p);
+  }
+};
 double* host_words() {
-  thread_local double* p = nullptr;
-  thread_local bool tried = false;
-  if (!tried) {
-    tried = true;
-    if (hipHostMalloc(reinterpret_cast<void**>(&p), kHostWords * sizeof(double),
-                      hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+  thread_local HostWordsLease lease;
+  if (!lease.tried) {
+    lease.tried = true;
+    {
+      std::lock_guard<std::mutex> lk(g_host_words.mu);
+      if (!g_host_words.free.empty()) {
+        lease.p = g_host_words.free.back();
+        g_host_words.free.pop_back();
+      }
+    }
+    if (!lease.p && hipHostMalloc(reinterpret_cast<void**>(&lease.p), kHostWords * sizeof(double),
+                                  hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) !=
+                        hipSuccess) {
       (void)hipGetLastError();
-      p = nullptr;
+      lease.p = nullptr;
     }
   }
-  return p;
+  return lease.p;
 }
 
 // Waits until the stream's kernel has set hf[0] (spinning on the host
@@ -842,10 +856,9 @@ int lddmm_kernel_timer(int32_t family, int32_t every) {
   g_timer.pending.clear();
   for (auto& kv : g_graphs) kv.second.unharvested = false;
   g_timer.error = false;
-  g_timer.family = family;
-  g_timer.every = every;
-  g_timer.seen = 0;
-  g_timer.take = false;
+  g_timer.smp.family.store(family);
+  g_timer.smp.every.store(every);
+  g_timer.smp.seen = 0;
   g_timer.launches = 0;
   g_timer.ms = 0.0;
   g_timer.flops = 0.0;
