@@ -59,6 +59,11 @@ def parse():
                     help="constraint of the registered problem: the image state (paper §3.2, the "
                          "default) or the deformation state (paper §3.3)")
     ap.add_argument("--hvp-loop", type=int, default=50, help="extra pure hessvec calls timed")
+    ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
+                    help="arithmetic of the matrix-core contractions of the timed registrations: FP32, or "
+                         "compensated BF16 (hi/lo split, three products, FP32 accumulation)")
+    ap.add_argument("--no-second-precision", action="store_true",
+                    help="skip the shorter measurement of the other precision mode")
     return ap.parse_args()
 
 
@@ -97,59 +102,178 @@ def stored_traffic(kernel_name):
     return None
 
 
-def cpu_baseline(w, state="image", band=None):
-    """The FP64 oracle on the host: one Hessian-vector product of the same
-    problem at v0 = v*/2, after an untimed oracle gradient."""
+def _cpu_model():
+    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # pragma: no cover
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
+def _blas_threads():
+    try:
+        import threadpoolctl
+        return max(i["num_threads"] for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def _timed(fn, reps):
+    """Median wall-clock seconds of `reps` calls of fn (and the last result)."""
+    ts, out = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
+
+
+def cpu_baseline(w, state="image", band=None, counts=None):
+    """The FP64 oracle on the host cores, on a bounded sample of the measured
+    workload: one Euler step of the band EPDiff, one gradient, one
+    Hessian-vector product and one line-search trial (a forward shooting and
+    transport plus the energy) at v0 = v*/2, medians of 3 where the sample
+    allows, on all BLAS threads and (one step and one product) on one thread;
+    and the registration time these give, n_grad t_grad + n_hvp t_hvp +
+    n_trial t_trial with the counts of the GPU registration.  Also returns the
+    oracle results the GPU is checked against."""
+    import threadpoolctl
     from oracle import Params
-    from oracle.jacobi import forward
+    from oracle.epdiff import shoot
+    from oracle.jacobi import energy, forward
     from paper_1807_11560_amd import synth
     if state == "image":
         from oracle.jacobi import gradient, hessvec
+        fwd = forward
     else:
-        from oracle.deformation import gradient, hessvec
-    try:
-        import threadpoolctl
-        cores = max(i["num_threads"] for i in threadpoolctl.threadpool_info()) or os.cpu_count()
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
+        from oracle import deformation as D
+        gradient, hessvec, fwd = D.gradient, D.hessvec, D.forward
+    cores = int(_blas_threads())
     pp = w["params"]
     p = Params(grid=pp["grid"], band=pp["band"], nt=pp["nt"], alpha=pp["alpha"], s=pp["s"], sigma=pp["sigma"])
     I0, vstar = w["I0"], w["v_star"]
+    # the target is the phantom warped by the image-state model in both cases
     I1 = forward(vstar, I0, p)[2][-1]
     at = "v0 = v*/2"
+    v0 = 0.5 * vstar
     if band and tuple(band) != tuple(pp["band"]):
         # register with another band: the same target, v0 = 0
         p = dataclasses.replace(p, band=tuple(band), spectral=None)
-        vstar = np.zeros((3,) + tuple(band), dtype=np.complex128)
+        v0 = np.zeros((3,) + tuple(band), dtype=np.complex128)
         at = "v0 = 0"
-    _, _, cache = gradient(0.5 * vstar, I0, I1, p)
     d = synth.random_direction(4242, p.band, s=pp["s"])
-    t0 = time.perf_counter()
-    hessvec(cache, d, p, "R1")
-    t = time.perf_counter() - t0
-    return {"value": 1.0 / t, "unit": "HVP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one Hessian-vector product of the 128^3 / band {p.band[0]}^3 problem ({state} state) "
-                      f"at {at} (FP64 NumPy, after an untimed oracle gradient)",
-            "seconds": t}
+    p1 = dataclasses.replace(p, nt=1)
+    t_step, _ = _timed(lambda: shoot(p.dt * v0, p1), 3)
+    t_grad, (g, E, cache) = _timed(lambda: gradient(v0, I0, I1, p), 1)
+    t_hvp, h = _timed(lambda: hessvec(cache, d, p, "R1"), 3)
+
+    def trial():
+        m1 = fwd(v0, I0, p)[2]
+        return energy(v0, m1[-1] if state == "image" else m1, I1, p)
+
+    t_trial, _ = _timed(trial, 1)
+    with threadpoolctl.threadpool_limits(1):
+        t_step1, _ = _timed(lambda: shoot(p.dt * v0, p1), 1)
+        t_hvp1, _ = _timed(lambda: hessvec(cache, d, p, "R1"), 1)
+    out = {"value": 1.0 / t_hvp, "unit": "HVP/s", "cores": cores, "kind": "oracle",
+           "sample": f"128^3 / band {p.band[0]}^3 problem ({state} state) at {at}, FP64 NumPy: one Euler step "
+                     f"of the band EPDiff (median of 3), one gradient, one Hessian-vector product (median of "
+                     f"3), one line-search trial on {cores} threads; one step and one product on 1 thread",
+           "cpu_model": _cpu_model(), "numpy": np.__version__,
+           "seconds": {"euler_step": t_step, "gradient": t_grad, "hvp": t_hvp, "line_search_trial": t_trial,
+                       "euler_step_1_thread": t_step1, "hvp_1_thread": t_hvp1},
+           "hvp_per_s_1_thread": 1.0 / t_hvp1}
+    if counts:
+        t_reg = counts["gradients"] * t_grad + counts["hvps"] * t_hvp + counts["trials"] * t_trial
+        out["registration_seconds_extrapolated"] = t_reg
+        out["registrations_per_min_extrapolated"] = 60.0 / t_reg
+        out["extrapolation"] = (f"{counts['gradients']} gradients x {t_grad:.2f} s + {counts['hvps']} products x "
+                                f"{t_hvp:.2f} s + {counts['trials']} trials x {t_trial:.2f} s (counts of the GPU "
+                                "registration; the oracle registration itself is not run)")
+    refs = {"I1": I1, "v0": v0, "direction": d, "gradient": g, "energy": E, "hvp": h, "params": p}
+    return out, refs
+
+
+def gpu_accuracy(L, prob, refs, dev):
+    """Relative errors of the library against the FP64 oracle on the sample
+    of cpu_baseline: energy, gradient and the Hessian-vector product (the
+    timed operation) at the same v0 and direction, on the oracle's target."""
+    import torch
+    ws = L.Workspace(prob, dev)
+    I0 = refs["I0"]
+    g, e3 = L.gradient(prob, I0, torch.from_numpy(refs["I1"]).float().to(dev),
+                       torch.from_numpy(refs["v0"]).to(torch.complex64).to(dev), ws)
+    h = L.hessvec(prob, torch.from_numpy(refs["direction"]).to(torch.complex64).to(dev), ws)
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    e3 = e3.cpu().numpy()
+    return {"hvp_rel_l2": rel(h.cpu().numpy().astype(np.complex128), refs["hvp"]),
+            "gradient_rel_l2": rel(g.cpu().numpy().astype(np.complex128), refs["gradient"]),
+            "energy_rel": float(abs(e3[0] - refs["energy"][0]) / abs(refs["energy"][0])),
+            "against": "FP64 oracle, same inputs (v0 = v*/2 or 0, one random direction)"}
 
 
 def separable_flops(K, G):
     """Flops of one band <-> grid transform of a scalar field by separable
-    partial DFTs: two complex stages, then a real last stage (full K2)."""
+    partial DFTs over the full spectrum: two complex stages, then a real
+    last stage (the count of the method's separable algorithm before any
+    Hermitian saving)."""
     return 8.0 * (G[0] * K[0] * K[1] * K[2] + G[0] * G[1] * K[1] * K[2]) + 4.0 * G[0] * G[1] * G[2] * K[2]
 
 
-def hvp_ceiling(prob, res_value, hvp_only):
-    """The whole-HVP FP32 compute ceiling: 60 padded-grid and 3.3 image-grid
-    transforms per time step (600 and 33 at nt = 10) against 157.3 TFLOP/s,
-    and the measured rates as fractions of it."""
+def hvp_work(L, prob, ws, d):
+    """Flops and HBM bytes one Hessian-vector product performs: the library's
+    per-launch work counts (the half-spectrum contractions, products,
+    interpolation and every launch's inputs and outputs, each read or written
+    once) summed over every kernel family, one family timed per product."""
+    import torch
+    fl = by = 0.0
+    per = {}
+    for fam in L.KERNEL_FAMILIES:
+        L.kernel_timer(fam, 1)
+        L.hessvec(prob, d, ws)
+        torch.cuda.synchronize()
+        _, _, f, b = L.kernel_timer_read()
+        per[L.KERNEL_FAMILIES[fam]] = {"gflop": f / 1e9, "mb": b / 1e6}
+        fl += f
+        by += b
+    L.kernel_timer(0)
+    return fl, by, per
+
+
+def hvp_ceiling(prob, work, res_value, hvp_only):
+    """The whole-HVP roofline: the performed flops against the FP32 matrix
+    peak and the performed kernel traffic against HBM, whichever is longer;
+    the measured rates as fractions of it.  The full-spectrum count of the
+    separable algorithm (60 padded-grid and 3.3 image-grid transforms per time
+    step) is given beside it."""
+    flops, nbytes, per = work
     K = prob.band
     M = tuple(3 * k // 2 for k in K)
     nt = prob.time_steps
-    flops = 60.0 * nt * separable_flops(K, M) + 3.3 * nt * separable_flops(K, prob.grid)
-    ceiling = PEAK_TFLOPS_FP32 * 1e12 / flops
-    return {"flops_per_hvp": flops, "ceiling_hvp_per_s": ceiling, "frac_registration": res_value / ceiling,
-            "frac_back_to_back": (hvp_only / ceiling) if hvp_only else None}
+    full = 60.0 * nt * separable_flops(K, M) + 3.3 * nt * separable_flops(K, prob.grid)
+    t_cmp = flops / (PEAK_TFLOPS_FP32 * 1e12)
+    t_mem = nbytes / (PEAK_GBS_HBM * 1e9)
+    ceiling = 1.0 / max(t_cmp, t_mem)
+    return {"flops_per_hvp": flops, "kernel_bytes_per_hvp": nbytes,
+            "bound": "mfma" if t_cmp >= t_mem else "hbm",
+            "ceiling_hvp_per_s": ceiling, "frac_registration": res_value / ceiling,
+            "frac_back_to_back": (hvp_only / ceiling) if hvp_only else None,
+            "full_spectrum_flops_per_hvp": full, "per_kernel": per}
 
 
 def dominant_family(L, run):
@@ -298,14 +422,16 @@ def main():
     prob_img = L.Problem(grid=pp["grid"], band=pp["band"], time_steps=pp["nt"], alpha=pp["alpha"], s=pp["s"],
                          sigma=pp["sigma"], hessian=L.GN_PAPER)
     band = (args.band,) * 3 if args.band else tuple(pp["band"])
-    prob = dataclasses.replace(prob_img, band=band,
+    prec = L.FP32 if args.precision == "fp32" else L.FP32_BF16X3
+    prob = dataclasses.replace(prob_img, band=band, precision=prec,
                                state=L.STATE_IMAGE if args.state == "image" else L.STATE_DEFORMATION)
     gn, pcg = pp["gn"], pp["pcg"]
     dev = torch.device("cuda:0")
     ws = L.Workspace(prob, dev)
     I0 = torch.from_numpy(w["I0"]).float().to(dev)
     vstar = torch.from_numpy(w["v_star"]).to(torch.complex64).to(dev)
-    I1 = L.shoot(prob_img, I0, vstar, ws if prob == prob_img else L.Workspace(prob_img, dev))
+    # the target is made by the FP32 image-state shooting in every mode
+    I1 = L.shoot(prob_img, I0, vstar, L.Workspace(prob_img, dev))
     torch.cuda.synchronize()
     log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
 
@@ -354,7 +480,7 @@ def main():
     T_u = time.perf_counter() - t0
 
     # pure Hessian-vector product rate (same problem, last iterate)
-    hvp_only = hvp_med = cold_ms = None
+    hvp_only = hvp_med = cold_ms = work = None
     if args.hvp_loop > 0:
         L.gradient(prob, I0, I1, v, ws)
         d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
@@ -382,6 +508,7 @@ def main():
             L.hessvec(prob, d, ws, out=out)
         torch.cuda.synchronize()
         cold_ms = 1e3 * (time.perf_counter() - t1) / 5
+        work = hvp_work(L, prob, ws, d)
 
     # plain copy of known size: the calibration for the FETCH_SIZE / WRITE_SIZE counters
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -390,11 +517,63 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
-    cpu = None
+    # the configured 20 CG iterations: classical Gauss-Newton (definite), whose
+    # CG is not cut short by the curvature guard
+    prob_cl = dataclasses.replace(prob, hessian=L.GN_CLASSICAL)
+    ws_cl = L.Workspace(prob_cl, dev)
+    L.register(prob_cl, I0, I1, ws_cl, gn_iters=gn, pcg_iters=pcg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st_cl, _, n_cl = L.register(prob_cl, I0, I1, ws_cl, gn_iters=gn, pcg_iters=pcg)
+    torch.cuda.synchronize()
+    T_cl = time.perf_counter() - t0
+    del ws_cl
+    classical = {"registrations_per_min": 60.0 / T_cl, "hvps_per_registration": n_cl, "hvp_per_s": n_cl / T_cl,
+                 "final_mse_rel": st_cl[-1]["mse_rel"] if st_cl else None,
+                 "what": "one registration with classical Gauss-Newton (coupling terms dropped)"}
+
+    # the other precision mode, shorter: one registration and back-to-back products
+    other = None
+    if not args.no_second_precision:
+        prob_o = dataclasses.replace(prob, precision=L.FP32_BF16X3 if prec == L.FP32 else L.FP32)
+        ws_o = L.Workspace(prob_o, dev)
+        L.register(prob_o, I0, I1, ws_o, gn_iters=gn, pcg_iters=pcg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v_o, st_o, _, n_o = L.register(prob_o, I0, I1, ws_o, gn_iters=gn, pcg_iters=pcg)
+        torch.cuda.synchronize()
+        T_o = time.perf_counter() - t0
+        L.gradient(prob_o, I0, I1, v_o, ws_o)
+        d_o = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
+        out_o = torch.empty_like(d_o)
+        for _ in range(3):
+            L.hessvec(prob_o, d_o, ws_o, out=out_o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.hvp_loop or 20):
+            L.hessvec(prob_o, d_o, ws_o, out=out_o)
+        torch.cuda.synchronize()
+        other = {"dtype": "bf16x3" if prob_o.precision == L.FP32_BF16X3 else "f32",
+                 "value": n_o / T_o, "unit": "HVP/s", "registrations_per_min": 60.0 / T_o,
+                 "hvps_per_registration": n_o,
+                 "hvp_only_per_s": (args.hvp_loop or 20) / (time.perf_counter() - t1),
+                 "final_mse_rel": st_o[-1]["mse_rel"] if st_o else None,
+                 "what": "one registration and back-to-back products of the same workload"}
+        del ws_o
+
+    cpu = accuracy = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(w, args.state, band)
-        log(f"oracle: {cpu['seconds']:.1f} s per HVP on {cpu['cores']} threads")
+        counts = {"gradients": len(stats), "hvps": int(round(hvps / args.steps)),
+                  "trials": int(sum(s["trials"] for s in stats))}
+        cpu, refs = cpu_baseline(w, args.state, band, counts)
+        log(f"oracle: {cpu['seconds']}")
+        refs["I0"] = I0
+        accuracy = gpu_accuracy(L, prob, refs, dev)
+        log(f"accuracy against the oracle: {accuracy}")
+        if other is not None:
+            other["accuracy_vs_fp64"] = gpu_accuracy(L, prob_o, refs, dev)
+            log(f"{other['dtype']} accuracy against the oracle: {other['accuracy_vs_fp64']}")
 
     name = L.KERNEL_FAMILIES[dominant]
     res = {
@@ -408,7 +587,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == L.FP32 else "bf16x3",
         "data": "synthetic",
         "config": {
             "workload": "tissue phantom 128^3 registered to its warp by a random band-limited geodesic "
@@ -417,7 +596,7 @@ def main():
                         + ("" if args.state == "image" else ", subject to the deformation state equation")
                         + ("" if band == tuple(pp["band"]) else f", registered with band {band[0]}^3 "
                            f"(padded grid {3 * band[0] // 2}^3)"),
-            "state": args.state,
+            "state": args.state, "precision": args.precision,
             "grid": list(prob.grid), "band": list(prob.band), "time_steps": prob.time_steps,
             "gn_iters": gn, "pcg_iters": pcg,
         },
@@ -427,7 +606,10 @@ def main():
         "hvp_only_per_s": hvp_only,
         "hvp_ms_median": hvp_med,
         "cold_hvp_ms": cold_ms,
-        "hvp_roofline": hvp_ceiling(prob, res_value=hvps / T, hvp_only=hvp_only),
+        "hvp_roofline": hvp_ceiling(prob, work, res_value=hvps / T, hvp_only=hvp_only) if work else None,
+        "gn_classical": classical,
+        "other_precision": other,
+        "accuracy_vs_fp64": accuracy,
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
         "final_grad_inf_rel": stats[-1]["grad_inf_rel"] if stats else None,
         "workspace_mib": ws.nbytes / 2**20,

@@ -64,7 +64,19 @@ enum {
   LDDMM_E_NONFINITE = -6      /* register: energy or gradient is not finite */
 };
 
-enum { LDDMM_FP32 = 0 };                              /* arithmetic of the bulk path */
+/* Arithmetic of the partial-DFT contractions on the matrix cores (paper §3.1: the
+ * band <-> grid transforms iota and pi and the truncated convolution, evaluated as
+ * separable partial DFTs).  LDDMM_FP32: FP32 operands and accumulation.
+ * LDDMM_FP32_BF16X3: each FP32 operand x is split into hi = bf16(x) and
+ * lo = bf16(x - hi) (round to nearest even), every product a*b is formed as
+ * ah*bh + ah*bl + al*bh on BF16 matrix instructions with FP32 accumulation (the
+ * dropped al*bl is about 2^-16 of a*b), so each contraction carries a relative
+ * error of about 2^-16 instead of 2^-24.  Everything else (pointwise Lie products,
+ * interpolation, symbols, updates) stays FP32, and all inner products, energies
+ * and line-search reductions are FP64 in both modes.  Shapes that run on the
+ * shape-generic (non-matrix-core) kernels compute those stages in FP32 in both
+ * modes. */
+enum { LDDMM_FP32 = 0, LDDMM_FP32_BF16X3 = 1 };
 /* Hessian of the Krylov solves, see lddmm_params */
 enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2 };
 /* State that carries the deformation, see lddmm_params */
@@ -84,7 +96,7 @@ typedef struct lddmm_params {
   int32_t s;            /* exponent of L, 1 <= s <= 8 */
   double alpha;         /* > 0 */
   double sigma;         /* > 0, weight of the image term */
-  int32_t precision;    /* LDDMM_FP32 */
+  int32_t precision;    /* LDDMM_FP32 or LDDMM_FP32_BF16X3 */
   int32_t hessian;      /* LDDMM_GN_PAPER: Gauss-Newton drops only the -lambda(1) grad dm(1) term
                            of dU(1) and keeps every coupling term of the incremental adjoint
                            Jacobi equations; LDDMM_GN_CLASSICAL also drops the coupling terms

@@ -48,7 +48,7 @@ bool same_dims(const Dims& a, const Dims& b) {
   for (int j = 0; j < 3; ++j)
     if (a.N[j] != b.N[j] || a.K[j] != b.K[j] || a.M[j] != b.M[j]) return false;
   return a.nt == b.nt && a.s == b.s && a.alpha == b.alpha && a.sigma == b.sigma &&
-         a.hessian == b.hessian && a.state == b.state && a.integrator == b.integrator;
+         a.hessian == b.hessian && a.state == b.state && a.integrator == b.integrator && a.prec == b.prec;
 }
 
 void set_prepared(const void* ws, bool prepared, const Dims& d) {
@@ -68,7 +68,8 @@ int validate(const lddmm_params* p, Dims* d) {
   if (p->s < 1 || p->s > 8) return fail(LDDMM_E_INVALID_ARG, "s must be in [1, 8]");
   if (p->time_steps < 1 || p->time_steps > 1000)
     return fail(LDDMM_E_INVALID_ARG, "time_steps must be in [1, 1000]");
-  if (p->precision != LDDMM_FP32) return fail(LDDMM_E_INVALID_ARG, "unknown precision");
+  if (p->precision != LDDMM_FP32 && p->precision != LDDMM_FP32_BF16X3)
+    return fail(LDDMM_E_INVALID_ARG, "unknown precision");
   if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL && p->hessian != LDDMM_NEWTON)
     return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
   if (p->state != LDDMM_STATE_IMAGE && p->state != LDDMM_STATE_DEFORMATION)
@@ -103,6 +104,7 @@ int validate(const lddmm_params* p, Dims* d) {
   o.hessian = p->hessian;
   o.state = p->state;
   o.integrator = p->integrator;
+  o.prec = p->precision == LDDMM_FP32_BF16X3 ? 1 : 0;
   // each block keeps its tile in LDS (at most the 160 KiB of a gfx950 workgroup)
   if (synth_shared_bytes(o) > kMaxLds || prods_shared_bytes(o, 9) > kMaxLds || colstep_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
@@ -258,6 +260,7 @@ std::string graph_key(const Engine& e, const void* ws, int kind, std::initialize
   put(&d.hessian, sizeof d.hessian);
   put(&d.state, sizeof d.state);
   put(&d.integrator, sizeof d.integrator);
+  put(&d.prec, sizeof d.prec);
   for (const void* p : ext) put(&p, sizeof p);
   return k;
 }

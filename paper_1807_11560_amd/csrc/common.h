@@ -27,6 +27,7 @@ struct Dims {
   int hessian;      // 0: couplings kept (paper reading), 1: dropped, 2: full Newton
   int state;        // 0: image state on the grid; 1: deformation state in the band
   int integrator;   // 0: Euler; 1: RK4 shooting with midpoint transport (shooting only)
+  int prec;         // 0: FP32 matrix-core products; 1: compensated BF16 (three products)
 };
 
 // ---------------------------------------------------------------- tables

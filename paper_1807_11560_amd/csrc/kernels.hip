@@ -211,13 +211,23 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
   if (q0 == K0 / 2 || q1 == K1 / 2 || q2 == K2 / 2) { full[i] = make_float2(0.f, 0.f); return; }
   bool conj = q2 > Kh;
   int s0 = conj ? (K0 - q0) % K0 : q0, s1 = conj ? (K1 - q1) % K1 : q1, s2 = conj ? K2 - q2 : q2;
-  size_t j = (size_t)c * K0 * K1 * Kh + ((size_t)s0 * K1 + s1) * Kh + s2;
-  float2 v = a[j];
-  if (b) { v.x += cb * b[j].x; v.y += cb * b[j].y; }
-  if (sym) {
-    const float w = sym[((size_t)s0 * K1 + s1) * Kh + s2];
-    v.x *= w;
-    v.y *= w;
+  auto value = [&](int t0, int t1, int t2) {
+    const size_t j = (size_t)c * K0 * K1 * Kh + ((size_t)t0 * K1 + t1) * Kh + t2;
+    float2 v = a[j];
+    if (b) { v.x += cb * b[j].x; v.y += cb * b[j].y; }
+    if (sym) {
+      const float w = sym[((size_t)t0 * K1 + t1) * Kh + t2];
+      v.x *= w;
+      v.y *= w;
+    }
+    return v;
+  };
+  float2 v = value(s0, s1, s2);
+  if (q2 == 0) {
+    // the k2 = 0 plane holds both v(k0, k1, 0) and v(-k0, -k1, 0): its
+    // Hermitian part, formed so that the two results are exact conjugates
+    const float2 w = value((K0 - q0) % K0, (K1 - q1) % K1, 0);
+    v = make_float2(0.5f * (v.x + w.x), 0.5f * (v.y - w.y));
   }
   if (conj) v.y = -v.y;
   full[i] = v;
@@ -342,6 +352,41 @@ __device__ __forceinline__ void jact_acc(float* o, const float* ja, const float*
 // four results go to the group's field array [3][nM][4]: per component and
 // padded-grid point (value, d/dx0, d/dx1, d/dx2).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// Compensated BF16 products on the matrix cores (precision LDDMM_FP32_BF16X3):
+// each FP32 operand x is split as hi = bf16(x), lo = bf16(x - hi) (round to
+// nearest even both times), and a b is formed as ah bh + ah bl + al bh with
+// FP32 accumulation; the dropped al bl is about 2^-16 of a b.  One FP32
+// k-step of v_mfma_f32_16x16x4f32 becomes one v_mfma_f32_16x16x16_bf16 whose
+// four k slots per lane hold the three terms and a zero: the A operand
+// (ah, ah, al, 0), the B operand (bh, bl, bh, 0).  Both operands index k
+// by (lane / 16, slot) alike, so the slot order only has to pair the terms.
+__device__ __forceinline__ shortx4 bf3_a(float x) {
+  const __bf16 h = (__bf16)x;
+  const __bf16 l = (__bf16)(x - (float)h);
+  const bf16x4 v = {h, h, l, (__bf16)0.f};
+  return __builtin_bit_cast(shortx4, v);
+}
+__device__ __forceinline__ shortx4 bf3_b(float x) {
+  const __bf16 h = (__bf16)x;
+  const __bf16 l = (__bf16)(x - (float)h);
+  const bf16x4 v = {h, l, h, (__bf16)0.f};
+  return __builtin_bit_cast(shortx4, v);
+}
+__device__ __forceinline__ floatx4 mma_bf3(shortx4 a, shortx4 b, floatx4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+}
+// acc += a b over one k-step of a 16x16 tile (lane layout of
+// v_mfma_f32_16x16x4f32: A[row = lane % 16][k = lane / 16], B[k][col = lane % 16]).
+template <bool BF3>
+__device__ __forceinline__ floatx4 mma(float a, float b, floatx4 acc) {
+  if constexpr (BF3)
+    return mma_bf3(bf3_a(a), bf3_b(b), acc);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
 
 struct SynthArgs {
   const float2* t1[2];  // stage-0 output of group g: [3][2][M0][K1*Kh]
@@ -352,7 +397,7 @@ struct SynthArgs {
 
 constexpr int kSynthW2Pre = 16;
 constexpr int kSynthT = 3;  // tiles a wave computes together
-template <class S>
+template <class S, bool BF3>
 __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   extern __shared__ float sms[];
   const int M0 = sh.M0(), M1 = sh.M1(), M2 = sh.M2(), K1 = sh.K1(), Kh = sh.Kh();
@@ -473,7 +518,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int t = 0; t < T; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], bv[t][u], acc[t], 0, 0, 0);
+          acc[t] = mma<BF3>(av[t][u], bv[t][u], acc[t]);
     }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -537,7 +582,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int ov = 0; ov < 4; ++ov)
-          acc[ov] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ov][u], bv[ov][u], acc[ov], 0, 0, 0);
+          acc[ov] = mma<BF3>(av[ov][u], bv[ov][u], acc[ov]);
     }
     const int x2 = tj * 16 + li;
 #pragma unroll
@@ -583,7 +628,7 @@ __global__ void k_synth_tables(const float2* inv1, const float2* inv2, float* w1
 // contracts them over x2 (forward stage 2) into s1[o][kh][x0][x1]: on the
 // matrix cores when M2 % 4 == 0 (rows (o, r) x columns (kh re | kh im), depth
 // x2), else one thread per output.
-template <class S>
+template <class S, bool BF3>
 __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
   extern __shared__ float smp[];
   const int M0 = sh.M0(), M1 = sh.M1(), M2 = sh.M2(), Kh = sh.Kh();
@@ -742,8 +787,8 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
       for (int ks = 0; ks < M2 / 4; ++ks) {
         const float av = (arow < rows) ? A[4 * ks] : 0.f;
         const float2 bv = (kh < Kh) ? B[(size_t)4 * ks * Kh] : make_float2(0.f, 0.f);
-        dre = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.x, dre, 0, 0, 0);
-        dim = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.y, dim, 0, 0, 0);
+        dre = mma<BF3>(av, bv.x, dre);
+        dim = mma<BF3>(av, bv.y, dim);
       }
       if (kh < Kh) {
 #pragma unroll
@@ -896,7 +941,7 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
 // acc0 += Ar Br, acc1 += Ai Bi, acc2 += Ar Bi, acc3 += Ai Br, so the tile is
 // (acc0 - acc1) + i (acc2 + acc3).  A(row, k) = A[row * lda + k] and
 // B(k, col) = B[k * ldb + col] for the tile's 16 rows / 16 columns.
-template <int KSTEPS>
+template <int KSTEPS, bool BF3>
 __device__ __forceinline__ void ctile(const float2* __restrict__ A, int lda, const float2* __restrict__ B,
                                       int ldb, floatx4* acc) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -914,10 +959,18 @@ __device__ __forceinline__ void ctile(const float2* __restrict__ A, int lda, con
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (k0 + u < KSTEPS) {
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].x, bv[u].x, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].y, bv[u].y, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].x, bv[u].y, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].y, bv[u].x, acc[3], 0, 0, 0);
+        if constexpr (BF3) {  // each operand split once for its two products
+          const shortx4 ar = bf3_a(av[u].x), ai = bf3_a(av[u].y), br = bf3_b(bv[u].x), bi = bf3_b(bv[u].y);
+          acc[0] = mma_bf3(ar, br, acc[0]);
+          acc[1] = mma_bf3(ai, bi, acc[1]);
+          acc[2] = mma_bf3(ar, bi, acc[2]);
+          acc[3] = mma_bf3(ai, br, acc[3]);
+        } else {
+          acc[0] = mma<BF3>(av[u].x, bv[u].x, acc[0]);
+          acc[1] = mma<BF3>(av[u].y, bv[u].y, acc[1]);
+          acc[2] = mma<BF3>(av[u].x, bv[u].y, acc[2]);
+          acc[3] = mma<BF3>(av[u].y, bv[u].x, acc[3]);
+        }
       }
   }
 }
@@ -982,7 +1035,7 @@ __device__ __forceinline__ void update_values(const ColJob& job, int tile, int l
 }
 
 constexpr int kGrid0Pre = 16;  // image-grid stage-0 table: complex values per thread
-template <class S>
+template <class S, bool BF3>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_mfma(ColJobs jobs, const float2* __restrict__ w1t,
                                                       const float2* __restrict__ w0f,
                                                       const float2* __restrict__ w0i,
@@ -1061,7 +1114,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     const int t = jb / T1R, ti = jb % T1R;
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<M / 4>(&s1[t][ti * 16][0], LS1, &w1s[0][0], LW1, acc);
+    ctile<M / 4, BF3>(&s1[t][ti * 16][0], LS1, &w1s[0][0], LW1, acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int x0 = ti * 16 + 4 * lk + r;
@@ -1082,11 +1135,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     floatx4 acc[4];
     zero_acc(acc, 4);
     if (nterm == 2)
-      ctile<SD>(&w0fs[ti * 16][0], LW0F, &s2[h][0][0], LS2, acc);
+      ctile<SD, BF3>(&w0fs[ti * 16][0], LW0F, &s2[h][0][0], LS2, acc);
     else if (h == 0)
-      ctile<S1>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, acc);
+      ctile<S1, BF3>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, acc);
     else
-      ctile<SD - S1>(&w0fs[ti * 16][4 * S1], LW0F, &s2[0][4 * S1][0], LS2, acc);
+      ctile<SD - S1, BF3>(&w0fs[ti * 16][4 * S1], LW0F, &s2[0][4 * S1][0], LS2, acc);
     static_assert(M * LW1 >= 2 * 4 * 64, "hand-over buffer fits the stage-1 table");
     float2* red = &w1s[0][0];  // [tile][r][lane]
 #pragma unroll
@@ -1107,8 +1160,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     if constexpr (!kSplit0) {
       zero_acc(aa, 4);
       zero_acc(bb, 4);
-      ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, aa);
-      if (nterm == 2) ctile<M / 4>(&w0fs[ti * 16][0], LW0F, &s2[1][0][0], LS2, bb);
+      ctile<M / 4, BF3>(&w0fs[ti * 16][0], LW0F, &s2[0][0][0], LS2, aa);
+      if (nterm == 2) ctile<M / 4, BF3>(&w0fs[ti * 16][0], LW0F, &s2[1][0][0], LS2, bb);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1154,7 +1207,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     zero_acc(acc, 4);
     if (jb >= njb) {
       const int ti = jb - njb;
-      ctile<K / 4>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
+      ctile<K / 4, BF3>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
       if (k1 >= K) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1166,7 +1219,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     const int u = jb / (2 * TIR), v = (jb / TIR) % 2, ti = jb % TIR;
     const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
     float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
-    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
+    ctile<K / 4, BF3>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
     if (k1 >= K) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1185,7 +1238,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 // next-stage table, so the block needs about half the LDS of k_colstep_mfma
 // and can share a compute unit with grid-step blocks.  The tables wait in
 // registers until their turn.
-template <class S>
+template <class S, bool BF3>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_lean(
     ColJobs jobs, const float2* __restrict__ w1t, const float2* __restrict__ w0f, const float2* __restrict__ w0i,
     double alpha, int spow, float invG) {
@@ -1244,7 +1297,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   for (int ti = wave; ti < TIR; ti += 4) {
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<M / 4>(&s1[ti * 16][0], LS1, &w1s[0][0], LW1, acc);
+    ctile<M / 4, BF3>(&s1[ti * 16][0], LS1, &w1s[0][0], LW1, acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int x0 = ti * 16 + 4 * lk + r;
@@ -1263,9 +1316,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     floatx4 acc[4];
     zero_acc(acc, 4);
     if (h == 0)
-      ctile<S1>(&w0fs[ti * 16][0], LW0F, &s2[0][0], LS2, acc);
+      ctile<S1, BF3>(&w0fs[ti * 16][0], LW0F, &s2[0][0], LS2, acc);
     else
-      ctile<SD - S1>(&w0fs[ti * 16][4 * S1], LW0F, &s2[4 * S1][0], LS2, acc);
+      ctile<SD - S1, BF3>(&w0fs[ti * 16][4 * S1], LW0F, &s2[4 * S1][0], LS2, acc);
     static_assert(M * LW1 >= 2 * 4 * 64, "hand-over buffer fits the stage-1 table");
     float2* red = &w1s[0][0];
 #pragma unroll
@@ -1318,7 +1371,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const int u = jb / (2 * TIR), v = (jb / TIR) % 2, ti = jb % TIR;
       const int lsel = (u == 0) ? job.t1l[0] : job.t1l[1];
       float2* dst = (u == 0) ? job.t1[0] : job.t1[1];
-      ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
+      ctile<K / 4, BF3>(&w0is[v][ti * 16][0], LW0I, &ob[lsel][0][0], LOB, acc);
       if (k1 >= K) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1333,7 +1386,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     for (int ti = wave; ti < N0 / 16; ti += 4) {
       floatx4 acc[4];
       zero_acc(acc, 4);
-      ctile<K / 4>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
+      ctile<K / 4, BF3>(g0s + ti * 16 * LG, LG, &ob[0][0][0], LOB, acc);
       if (k1 >= K) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1552,7 +1605,7 @@ __global__ void __launch_bounds__(256) k_gridstep(GridStepArgs a, Twiddles tw, G
 // stage 2 the real part of a complex GEMM per (component, 16-column tile);
 // a wave owns the three components of its column tiles, so the source
 // term is formed in registers.
-template <class G>
+template <class G, bool BF3>
 __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles tw) {
   constexpr int N0 = G::N0(), N1 = G::N1(), N2 = G::N2(), K1 = G::K1(), Kh = G::Kh();
   constexpr int R = kGridRows;
@@ -1637,7 +1690,7 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     const int c = jb % 3, tj = jb / 3;
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<K1 / 4>(&w1s[0][0], LW1, &t1s[c][0][tj * 16], LT1, acc);
+    ctile<K1 / 4, BF3>(&w1s[0][0], LW1, &t1s[c][0][tj * 16], LT1, acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       t2s[c][4 * lk + r][tj * 16 + li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
@@ -1660,8 +1713,8 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
 #pragma unroll
       for (int ks = 0; ks < Khp / 4; ++ks) {
         const float2 av = A[4 * ks], bv = B[4 * ks * LW2];
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[1], 0, 0, 0);
+        acc[0] = mma<BF3>(av.x, bv.x, acc[0]);
+        acc[1] = mma<BF3>(av.y, bv.y, acc[1]);
       }
       vel[c] = acc[0] - acc[1];
     }
@@ -1977,7 +2030,7 @@ __global__ void __launch_bounds__(256) k_rho_fwd2(RhoArgs a, float2* __restrict_
 // the chunk's part of forward stage 1 (x1 -> k1), accumulated in the matrix
 // accumulators over the sub-chunks: P[part][j][kh][x0][k1].
 constexpr int kTailRows = 64, kTailSub = 32;
-template <class G, bool FULL>
+template <class G, bool FULL, bool BF3>
 __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, const float* __restrict__ b,
                                                 const float* __restrict__ res, const float* __restrict__ m,
                                                 float coef, float2* __restrict__ P, Twiddles tw) {
@@ -2097,8 +2150,7 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
       const float* B = &w2r[0][0] + lk * LW2 + tj * 16;
 #pragma unroll 8
       for (int ks = 0; ks < N2 / 4; ++ks)  // row 4 ks + lk, swizzle (2 ks + lk / 2) % 16
-        a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 * ks], B[4 * ks * LW2 + (li ^ ((2 * ks + (lk >> 1)) & 15))],
-                                                  a2, 0, 0, 0);
+        a2 = mma<BF3>(A[4 * ks], B[4 * ks * LW2 + (li ^ ((2 * ks + (lk >> 1)) & 15))], a2);
       const int j = tj * 16 + li;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
@@ -2114,7 +2166,7 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
       const int t = wave + 4 * q;
       if (t >= NT1) break;
       const int c = t / (TK1 * TKH), ti = (t / TKH) % TK1, tj = t % TKH;
-      ctile<SR / 4>(&w1f[ti * 16][sub * SR], LW1, &o2[c][0][tj * 16], LO, acc[q]);
+      ctile<SR / 4, BF3>(&w1f[ti * 16][sub * SR], LW1, &o2[c][0][tj * 16], LO, acc[q]);
     }
     __syncthreads();
   }
@@ -2146,7 +2198,7 @@ struct TailJobs {
   float2* t1z[3];
   float ca;
 };
-template <class S, int NG0, int NP>
+template <class S, int NG0, int NP, bool BF3>
 __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __restrict__ w0n,
                                                    const float2* __restrict__ w0i, double alpha,
                                                    int spow, float invG) {
@@ -2200,7 +2252,7 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     const int ti = wave % T0, h = wave / T0, d0 = h * LEN;
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<LEN / 4>(&as[ti * 16][d0 % NG0], LA, &bs[d0][0], LB, acc);
+    ctile<LEN / 4, BF3>(&as[ti * 16][d0 % NG0], LA, &bs[d0][0], LB, acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) red[wave][i][lane] = acc[i];
   }
@@ -2235,7 +2287,7 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     const int v = jb / TIR, ti = jb % TIR;
     floatx4 acc[4];
     zero_acc(acc, 4);
-    ctile<K / 4>(&w0is[v][ti * 16][0], LW0I, &ob[1][0][0], LOB, acc);
+    ctile<K / 4, BF3>(&w0is[v][ti * 16][0], LW0I, &ob[1][0][0], LOB, acc);
     if (k1 >= K) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -2620,8 +2672,14 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
   (void)Khp;
   (void)M2p;
   hipError_t e = with_band(d, [&](auto sh) {
-    LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh)>), dim3(d.M[0], nf, M1p / 16), dim3(256), synth_shared_bytes(d), st,
-                 a, sh);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh), true>), dim3(d.M[0], nf, M1p / 16), dim3(256), synth_shared_bytes(d), st,
+                   a, sh);
+      else
+        LAUNCH_TIMED(KF_SYNTH, (k_synth<decltype(sh), false>), dim3(d.M[0], nf, M1p / 16), dim3(256), synth_shared_bytes(d), st,
+                   a, sh);
+    } while (0);
     return hipGetLastError();
   });
   return e;
@@ -2653,7 +2711,12 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
   int threads = ((R * d.M[2] + 63) / 64) * 64;
   if (threads > 256) threads = 256;
   hipError_t e = with_band(d, [&](auto sh) {
-    LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh)>), grid, dim3(threads), shm, st, a, tw, sh);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), true>), grid, dim3(threads), shm, st, a, tw, sh);
+      else
+        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), false>), grid, dim3(threads), shm, st, a, tw, sh);
+    } while (0);
     return hipGetLastError();
   });
   return e;
@@ -2758,24 +2821,54 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
   for (int i = 0; i < njobs && lean; ++i) lean = jobs.j[i].b == nullptr && jobs.j[i].t1n != nullptr;
   if (lean) {
     if (band_iso(d, 32, 48))
-      LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
-                   d.alpha, d.s, invG);
+      do {
+        if (d.prec)
+          LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<32, 48>, true>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                     d.alpha, d.s, invG);
+        else
+          LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<32, 48>, false>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                     d.alpha, d.s, invG);
+      } while (0);
     else
-      LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
-                   d.alpha, d.s, invG);
+      do {
+        if (d.prec)
+          LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<24, 36>, true>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                     d.alpha, d.s, invG);
+        else
+          LAUNCH_TIMED(KF_COLUMN, (k_colstep_lean<BandIso<24, 36>, false>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i,
+                     d.alpha, d.s, invG);
+      } while (0);
     return hipGetLastError();
   }
   if (band_iso(d, 32, 48)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
-                 d.s, invG, nparts);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>, true>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+      else
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<32, 48>, false>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+    } while (0);
     e = hipGetLastError();
   } else if (band_iso(d, 16, 24)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
-                 d.s, invG, nparts);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>, true>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+      else
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<16, 24>, false>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+    } while (0);
     e = hipGetLastError();
   } else if (band_iso(d, 24, 36)) {
-    LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
-                 d.s, invG, nparts);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>, true>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+      else
+        LAUNCH_TIMED(KF_COLUMN, (k_colstep_mfma<BandIso<24, 36>, false>), cgrid, dim3(256), 0, st, jobs, w1t, w0f, w0i, d.alpha,
+                   d.s, invG, nparts);
+    } while (0);
     e = hipGetLastError();
   } else {
     dim3 grid(nblk(d.K[1], kColGroup), d.Kh, njobs);
@@ -2847,10 +2940,20 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
   }
   hipError_t e;
   if (grid_iso(d, 128, 32)) {
-    LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>>), grid, dim3(256), 0, st, a, tw);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>, true>), grid, dim3(256), 0, st, a, tw);
+      else
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>, false>), grid, dim3(256), 0, st, a, tw);
+    } while (0);
     e = hipGetLastError();
   } else if (grid_iso(d, 64, 16)) {
-    LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>>), grid, dim3(256), 0, st, a, tw);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>, true>), grid, dim3(256), 0, st, a, tw);
+      else
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>, false>), grid, dim3(256), 0, st, a, tw);
+    } while (0);
     e = hipGetLastError();
   } else {
     const int jn = (d.N[2] + 15) / 16;
@@ -2957,13 +3060,33 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
   hipError_t e;
   const dim3 g1(N > kTailRows ? N / kTailRows : 1, N);
   if (N == 128 && r)
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, true, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+      else
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, true, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    } while (0);
   else if (N == 128)
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, false, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+      else
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<128, 32>, false, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    } while (0);
   else if (r)
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, true, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+      else
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, true, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    } while (0);
   else
-    LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, false, true>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+      else
+        LAUNCH_TIMED(KF_SRC, (k_srcfwd<GridIso<64, 16>, false, false>), g1, dim3(256), 0, st, a, b, r, m, coef, P, twN);
+    } while (0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   TailJobs tj{};
   tj.P = P;
@@ -2979,11 +3102,23 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
              np * 3.0 * N * C * 8.0 + 3.0 * K * C * 8.0 + 3.0 * 2.0 * 2.0 * M * C * 8.0);
   const dim3 grid(Kh, 3, round_up(K, 16) / 16);
   if (N == 128)
-    LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<32, 48>, 128, 2>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
-                 d.alpha, d.s, invG);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<32, 48>, 128, 2, true>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                   d.alpha, d.s, invG);
+      else
+        LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<32, 48>, 128, 2, false>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                   d.alpha, d.s, invG);
+    } while (0);
   else
-    LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<16, 24>, 64, 1>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
-                 d.alpha, d.s, invG);
+    do {
+      if (d.prec)
+        LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<16, 24>, 64, 1, true>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                   d.alpha, d.s, invG);
+      else
+        LAUNCH_TIMED(KF_FWD0_GRID, (k_fwd0_mfma<BandIso<16, 24>, 64, 1, false>), grid, dim3(256), 0, st, tj, twN.fwd0, w0i,
+                   d.alpha, d.s, invG);
+    } while (0);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ E_HIP = -4
 E_NOT_PREPARED = -5
 E_NONFINITE = -6
 FP32 = 0
+FP32_BF16X3 = 1
 GN_PAPER = 0
 GN_CLASSICAL = 1
 NEWTON = 2
@@ -142,6 +143,7 @@ class Problem:
     hessian: int = GN_PAPER
     state: int = STATE_IMAGE
     integrator: int = EULER
+    precision: int = FP32
 
     def c_params(self) -> LddmmParams:
         p = LddmmParams()
@@ -154,7 +156,7 @@ class Problem:
         p.s = int(self.s)
         p.alpha = float(self.alpha)
         p.sigma = float(self.sigma)
-        p.precision = FP32
+        p.precision = int(self.precision)
         p.hessian = int(self.hessian)
         p.state = int(self.state)
         p.integrator = int(self.integrator)

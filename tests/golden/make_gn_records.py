@@ -1,0 +1,146 @@
+"""Writes the oracle's Gauss-Newton records that the GPU loop is compared
+with (paper §2.7, the Newton-Krylov update with Armijo search), calling only
+the FP64 oracle and the seeded input generators:
+
+  gn_config3.npz / gn_config3.json
+      The measured workload (128^3 tissue phantom, band 32^3, s = 3, 10 Euler
+      steps, a random geodesic of 8 voxels, Gauss-Newton as printed: mode R1,
+      20 CG iterations).  Iteration 0 from v0 = 0 and iteration 1 from the
+      oracle's iterate after iteration 0 rounded to complex64 (the input the
+      library will be given); for each, the record of the iteration and the
+      resulting iterate (complex64, half spectrum k2 >= 0: the other half is
+      the Hermitian image).  The quantities each decision compares (the
+      curvature of every CG iteration, the Armijo margin of every trial) are
+      stored too, to show how far each decision is from its threshold.
+  gn_config2.npz / gn_config2.json
+      The 64^3 nested-ellipsoid workload (band 16^3, s = 2, 10 Euler steps, a
+      geodesic of 5 voxels): the whole registration, 10 Gauss-Newton x 20 CG
+      iterations from v0 = 0, with every iteration's record and the final
+      iterate.
+
+Usage: python tests/golden/make_gn_records.py [config3|config2|all]
+(the config-3 records take tens of minutes on eight cores).
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import Params  # noqa: E402
+from oracle import gn as GN  # noqa: E402
+from oracle.band import inner  # noqa: E402
+from oracle.jacobi import forward  # noqa: E402
+from paper_1807_11560_amd import synth  # noqa: E402
+
+
+def half(v):
+    """complex64 half spectrum (last axis k2 = 0 .. K2/2 - 1)."""
+    K2 = v.shape[-1]
+    return np.ascontiguousarray(v[..., : K2 // 2]).astype(np.complex64)
+
+
+def problem(config):
+    w = synth.workload(config)
+    pp = w["params"]
+    p = Params(grid=pp["grid"], band=pp["band"], nt=pp["nt"], alpha=pp["alpha"], s=pp["s"], sigma=pp["sigma"])
+    I0, vstar = w["I0"], w["v_star"]
+    I1 = forward(vstar, I0, p)[2][-1]
+    return p, pp, I0, I1
+
+
+class DecisionLog:
+    """Wraps the oracle's CG and line search so that the quantities its
+    decisions compare are kept: each CG iteration's <d, H d>_V / <d, d>_V
+    (the curvature guard stops at a value <= 0), and each Armijo trial's
+    (E(v0 + eps p) - E0 - c1 eps slope) / E0 (accepted at a value <= 0)."""
+
+    def __init__(self, p):
+        self.log = []
+        self.armijo = []
+        self._pcg = GN.pcg
+        self._ls = GN.line_search
+        self._energy = GN.energy
+
+    def __enter__(self):
+        def pcg(apply_H, g, Lsym, iters):
+            def H(d):
+                Hd = apply_H(d)
+                self.log[-1].append(inner(Lsym * d, Hd) / inner(Lsym * d, d))
+                return Hd
+            self.log.append([])
+            return self._pcg(H, g, Lsym, iters)
+
+        def line_search(v0, p_dir, E0, slope, *a, **kw):
+            trials = []
+            self.armijo.append(trials)
+
+            def energy(v, m1, I1, p):
+                E = self._energy(v, m1, I1, p)
+                eps = 0.5 ** len(trials)
+                trials.append((E[0] - E0 - 1e-4 * eps * slope) / E0)
+                return E
+            GN.energy = energy
+            try:
+                return self._ls(v0, p_dir, E0, slope, *a, **kw)
+            finally:
+                GN.energy = self._energy
+
+        GN.pcg = pcg
+        GN.line_search = line_search
+        return self
+
+    def __exit__(self, *a):
+        GN.pcg = self._pcg
+        GN.line_search = self._ls
+        GN.energy = self._energy
+
+
+def config3():
+    t0 = time.time()
+    p, pp, I0, I1 = problem(3)
+    print(f"config 3 inputs {time.time() - t0:.0f} s", flush=True)
+    recs, curv, armijo, iterates = [], [], [], []
+    v = None
+    for k in range(2):
+        with DecisionLog(p) as cl:
+            vk, st, status = GN.register(I0, I1, p, gn_iters=1, pcg_iters=pp["pcg"], v0=v, mode="R1")
+        assert status == 0, "the search failed"
+        recs.append(st[0])
+        curv.append(cl.log[0])
+        armijo.append(cl.armijo[0])
+        vc = vk.astype(np.complex64)
+        iterates.append(half(vc))
+        v = vc.astype(np.complex128)
+        print(f"config 3 iteration {k}: {st[0]}  {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "gn_config3.npz"), v1=iterates[0], v2=iterates[1])
+    with open(os.path.join(HERE, "gn_config3.json"), "w") as f:
+        json.dump({"workload": "128^3 tissue phantom, band 32^3, s = 3, nt = 10, dmax 8, mode R1, 20 CG",
+                   "records": recs, "curvature": curv, "armijo": armijo}, f, indent=1, default=float)
+
+
+def config2():
+    t0 = time.time()
+    p, pp, I0, I1 = problem(2)
+    with DecisionLog(p) as cl:
+        v, st, status = GN.register(I0, I1, p, gn_iters=pp["gn"], pcg_iters=pp["pcg"], mode="R1")
+    print(f"config 2: status {status}, {len(st)} iterations, {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "gn_config2.npz"), v_final=half(v))
+    with open(os.path.join(HERE, "gn_config2.json"), "w") as f:
+        json.dump({"workload": "64^3 nested ellipsoids, band 16^3, s = 2, nt = 10, dmax 5, mode R1, 10 GN x 20 CG",
+                   "status": status, "records": st, "curvature": cl.log, "armijo": cl.armijo}, f, indent=1,
+                  default=float)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if which in ("config2", "all"):
+        config2()
+    if which in ("config3", "all"):
+        config3()

@@ -33,15 +33,25 @@ def test_separable_transform_counts():
 
 
 def test_whole_hvp_ceiling():
-    """600 padded-grid and 33 image-grid transforms per HVP at nt = 10:
-    41.8 GFLOP, 3767 HVP/s at 157.3 TFLOP/s; fractions are rate / ceiling."""
+    """The ceiling is priced at the work the kernels perform (the library's
+    per-launch counts summed over one product) against 157.3 TFLOP/s, or its
+    kernels' traffic against 8 TB/s when that takes longer (19.8 GFLOP is
+    126 us, 1.9 GB is 238 us: traffic-bound); the full-spectrum count of the
+    separable algorithm (600 padded-grid and 33 image-grid transforms at
+    nt = 10, 41.8 GFLOP) is reported beside it."""
     prob = types.SimpleNamespace(band=(32, 32, 32), grid=(128, 128, 128), time_steps=10)
-    c = bench.hvp_ceiling(prob, res_value=900.0, hvp_only=1200.0)
-    assert abs(c["flops_per_hvp"] - 41.76e9) < 0.01e9
-    assert abs(c["ceiling_hvp_per_s"] - 3766.5) < 1.0
+    work = (19.8e9, 1.9e9, {})
+    c = bench.hvp_ceiling(prob, work, res_value=900.0, hvp_only=1200.0)
+    assert c["flops_per_hvp"] == 19.8e9 and c["kernel_bytes_per_hvp"] == 1.9e9
+    assert c["bound"] == "hbm"
+    t_cmp, t_mem = 19.8e9 / 157.3e12, 1.9e9 / 8000e9
+    assert abs(c["ceiling_hvp_per_s"] - 1.0 / max(t_cmp, t_mem)) < 1e-6
+    assert abs(c["full_spectrum_flops_per_hvp"] - 41.76e9) < 0.01e9
     assert abs(c["frac_registration"] - 900.0 / c["ceiling_hvp_per_s"]) < 1e-12
     assert abs(c["frac_back_to_back"] - 1200.0 / c["ceiling_hvp_per_s"]) < 1e-12
-    assert bench.hvp_ceiling(prob, 900.0, None)["frac_back_to_back"] is None
+    assert bench.hvp_ceiling(prob, work, 900.0, None)["frac_back_to_back"] is None
+    # compute-bound when the flops take longer than the bytes
+    assert bench.hvp_ceiling(prob, (19.8e9, 0.5e9, {}), 900.0, None)["bound"] == "mfma"
 
 
 def test_roofline_record_picks_the_binding_fraction():
