@@ -166,6 +166,24 @@ int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes);
 int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of the library's own device array that lddmm_shoot_static works in. */
+#define LDDMM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* lddmm_shoot without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same computation, arguments and outputs as
+ * lddmm_shoot, working in LDDMM_STATIC_SCRATCH_BYTES of device memory that
+ * the library holds as a fixed array, one copy per GPU, from its first use
+ * on that GPU until the process ends (problems whose lddmm_workspace_bytes
+ * exceeds that size, e.g. beyond 64^3 / band 16^3 / 10 steps, return
+ * LDDMM_E_WORKSPACE before anything is enqueued).  It allocates nothing and
+ * creates no stream or event: all work is enqueued on `stream`.  Every call
+ * on one GPU uses that GPU's array and leaves its contents behind; nothing
+ * in it needs to start at zero, and calls that overlap on one GPU (from
+ * several host threads or streams) race. */
+int lddmm_shoot_static(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
+                       void* stream);
+
 /* Band symbols of lddmm_apply_symbol */
 enum { LDDMM_SYMBOL_L = 0, LDDMM_SYMBOL_K = 1 };
 

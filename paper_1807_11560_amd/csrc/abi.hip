@@ -120,6 +120,34 @@ int euler_only(const Dims& d) {
   return LDDMM_OK;
 }
 
+// ------------------------------------------- the workspace of lddmm_shoot_static
+// For callers that cannot allocate device memory: a fixed array in the
+// library's device code, one copy per GPU, held until the process ends.  In
+// host code the name `scratch` only stands for the symbol; its device address
+// on the current GPU comes from hipGetSymbolAddress, taken once per device
+// and kept.  Every lddmm_shoot_static call on one GPU uses that GPU's copy,
+// so such calls that overlap on one GPU race.
+static __device__ __align__(256) unsigned char scratch[LDDMM_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> its copy of scratch
+
+// Address of the current GPU's copy of `scratch`.
+hipError_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    it = g_scratch_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
 int check_ws(const Dims& d, const void* ws, size_t ws_bytes) {
   if (!ws) return fail(LDDMM_E_INVALID_ARG, "workspace is NULL");
   size_t need = Engine::workspace_bytes(d);
@@ -624,6 +652,33 @@ int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m
   if ((err = launch_copy(mnt, m1, d.nN, e.stream())) != hipSuccess) return hip_fail(err, "copy m1");
   if (v1 && (err = e.store_band(e.V[d.nt], nullptr, 0.f, v1)) != hipSuccess)
     return hip_fail(err, "store v1");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_shoot_static(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
+                       void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!I0 || !v0 || !m1) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  const size_t need = Engine::workspace_bytes(d);
+  if (need > LDDMM_STATIC_SCRATCH_BYTES)
+    return fail(LDDMM_E_WORKSPACE, "problem needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                       std::to_string((size_t)LDDMM_STATIC_SCRATCH_BYTES) +
+                                       " of lddmm_shoot_static; use lddmm_shoot with a caller workspace");
+  void* ws = nullptr;
+  hipError_t err;
+  if ((err = static_scratch(&ws)) != hipSuccess) return hip_fail(err, "static workspace");
+  // the caller's stream only: no auxiliary stream or event is created
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  e.set_one_stream(true);
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  const float* mnt = nullptr;
+  if ((err = e.forward_light(I0, &mnt)) != hipSuccess) return hip_fail(err, "shoot");
+  if ((err = launch_copy(mnt, m1, d.nN, e.stream())) != hipSuccess) return hip_fail(err, "copy m1");
+  if (v1 && (err = e.store_band(e.V[d.nt], nullptr, 0.f, v1)) != hipSuccess) return hip_fail(err, "store v1");
   g_last_error.clear();
   return LDDMM_OK;
 }

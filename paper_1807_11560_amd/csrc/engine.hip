@@ -37,6 +37,11 @@ struct AuxRes {
 static thread_local std::map<int, AuxRes> t_aux;
 
 hipError_t Engine::aux_init(int nevents) {
+  if (one_stream_) {  // everything on the caller's stream: nothing to order, nothing to create
+    aux_ = st_;
+    ev_ = nullptr;
+    return hipSuccess;
+  }
   int dev = 0;
   TRY(hipGetDevice(&dev));
   AuxRes& r = t_aux[dev];
@@ -66,8 +71,8 @@ void release_thread_streams() {
   t_aux.clear();
 }
 
-hipError_t Engine::record(hipStream_t s, int ev) { return hipEventRecord((*ev_)[ev], s); }
-hipError_t Engine::wait(hipStream_t s, int ev) { return hipStreamWaitEvent(s, (*ev_)[ev], 0); }
+hipError_t Engine::record(hipStream_t s, int ev) { return one_stream_ ? hipSuccess : hipEventRecord((*ev_)[ev], s); }
+hipError_t Engine::wait(hipStream_t s, int ev) { return one_stream_ ? hipSuccess : hipStreamWaitEvent(s, (*ev_)[ev], 0); }
 
 void Engine::layout(Carver& c) {
   const Dims& d = d_;

@@ -87,6 +87,7 @@ _P = ctypes.POINTER(LddmmParams)
 _SIGS = {
     "lddmm_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "lddmm_shoot": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_shoot_static": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp]),
     "lddmm_gradient": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_geodesic_energy": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_apply_symbol": (ctypes.c_int, [_P, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -223,6 +224,23 @@ def shoot(problem: Problem, I0, v0, ws: Workspace, want_v1=False, stream=None):
     v1 = torch.empty_like(v0) if want_v1 else None
     _check(_lib.lddmm_shoot(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(v0), _ptr(m1), _ptr(v1),
                             ws.ptr, ws.nbytes, _stream(stream)), "lddmm_shoot")
+    return (m1, v1) if want_v1 else m1
+
+
+STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def shoot_static(problem: Problem, I0, v0, want_v1=False, stream=None):
+    """lddmm_shoot in the library's own device array (lddmm_shoot_static):
+    no workspace, nothing allocated by the library (the outputs here are
+    torch tensors)."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    m1 = torch.empty_like(I0)
+    v1 = torch.empty_like(v0) if want_v1 else None
+    _check(_lib.lddmm_shoot_static(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(v0), _ptr(m1), _ptr(v1),
+                                   _stream(stream)), "lddmm_shoot_static")
     return (m1, v1) if want_v1 else m1
 
 

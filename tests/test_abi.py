@@ -99,6 +99,11 @@ def test_entry_points_validate_before_touching_the_device():
     assert lib.lddmm_register(ctypes.byref(p), fake, fake, fake, 1, 0, None, 0, fake, 1 << 40,
                               null) == L.E_INVALID_ARG
     assert b"grid" in lib.lddmm_status_string(L.E_SHAPE) or lib.lddmm_status_string(L.E_SHAPE)
+    # the entry point without a workspace: null pointers, and problems larger than its fixed array
+    assert lib.lddmm_shoot_static(ctypes.byref(p), null, fake, fake, null, null) == L.E_INVALID_ARG
+    big = L.Problem(grid=(128, 128, 128), band=(32, 32, 32)).c_params()
+    assert lib.lddmm_shoot_static(ctypes.byref(big), fake, fake, fake, null, null) == L.E_WORKSPACE
+    assert b"lddmm_shoot_static" in lib.lddmm_last_error()
 
 
 def test_switches_reject_bad_values():
