@@ -21,6 +21,9 @@ Modules
              phi = id + u carried in the band, m(1) = I0 o phi(1) (paper §3.3)
   highorder  shooting by RK4 and transport with midpoint departure points
   gn         CG in the V metric and the Gauss-Newton-Krylov loop (paper §2.7)
+  exact      the exact derivative of the discrete energy (reverse sweep of
+             every Euler and semi-Lagrangian step) and its Gauss-Newton
+             product, beside the paper's adjoint Jacobi gradient
 
 Every function cites the passage it restates.  Readings of passages where the
 paper is silent or ambiguous are stated where they are used.
