@@ -138,6 +138,14 @@ typedef struct lddmm_params {
                            interpolated trilinearly at X_h (second order in dt).  The gradient,
                            Hessian-vector product and registration integrate the adjoint sweeps
                            as transposes of Euler steps and reject LDDMM_RK4. */
+  int32_t checkpoint;   /* 0: the forward keeps every state m_n and grid velocity (the workspace
+                           layout of every entry point).  c >= 1 (lddmm_gradient_exact and
+                           lddmm_workspace_bytes only; image state, Euler): only the states
+                           m_0, m_c, m_2c, ... and m_nt are kept; the backward sweep transports
+                           each segment of c steps again from its first state and synthesises
+                           the grid velocities again from the band trajectory, so the workspace
+                           holds about nt/c + c states instead of 4 nt + 1 grid fields (states and
+                           grid velocities) and no sweep caches beyond the shooting's. */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */
@@ -222,6 +230,34 @@ int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energie
  * Leaves in `ws` the trajectories lddmm_hessvec needs (prepares it). */
 int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
                    void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream);
+
+/* Energy only (paper §3.2, band-limited energy): E, E_reg, E_data of v0,
+ * by shooting and transport without the caches of the gradient (the
+ * forward pass of the autograd form, whose backward is
+ * lddmm_gradient_exact).  Arguments as for lddmm_gradient; energy3 (device,
+ * 3 doubles) is required. */
+int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const void* v0, double* energy3,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Energy and the exact derivative of the discrete energy in the V metric
+ * (paper §3.2 energy and constraints as discretised here: explicit Euler
+ * steps of the band EPDiff, one semi-Lagrangian transport step per time
+ * step): every step is differentiated in reverse order,
+ *   state adjoint     lam_nt = 2/(sigma^2 |N|) (m_nt - I1), lam_n = I^T[lam_{n+1}]
+ *                     (transpose of the trilinear interpolation at X_n = x - dt v_n(x)),
+ *   velocity source   S_n = K~ |N| pi(-dt N_j lam_{n+1} (d_j I[m_n])(X_n)), the exact
+ *                     slope of the interpolant in the cell of X_n,
+ *   band adjoint      w_n = w_{n+1} + dt [-ad~_{v_n} w_{n+1} + K~ ad~*_{w_{n+1}}(L~ v_n)] + S_n,
+ *                     w_nt = 0, g_V = v0 + w_0.
+ * This is the derivative that finite differences of the energy see (the
+ * gradient of lddmm_gradient is the paper's adjoint Jacobi gradient, which
+ * discretises the continuous adjoint instead; the two differ by the band
+ * truncation of the coadjoint transport and by O(dt) and O(h)).  The
+ * scatter uses FP32 atomic additions, so the last bits vary between runs.
+ * Honours params->checkpoint (see lddmm_params).  Arguments as for
+ * lddmm_gradient; does not prepare the workspace for lddmm_hessvec. */
+int lddmm_gradient_exact(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
+                         void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream);
 
 /* Hessian-vector product in the V metric at the v0 of the last
  * lddmm_gradient on this workspace with equal parameters (paper §3.2: the

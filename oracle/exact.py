@@ -88,14 +88,15 @@ def interpolate_transpose(lam, X):
     with its interpolation weights (the transpose of ``interpolate``)."""
     d = lam.ndim
     idx0, frac = _cells(X, lam.shape)
-    out = np.zeros(lam.shape)
+    out = np.zeros(lam.size)
     for corner in itertools.product((0, 1), repeat=d):
         w = np.ones(X.shape[1:])
         for i in range(d):
             w = w * (frac[i] if corner[i] else 1.0 - frac[i])
         ind = tuple((idx0[i] + corner[i]) % lam.shape[i] for i in range(d))
-        np.add.at(out, ind, w * lam)
-    return out
+        out += np.bincount(np.ravel_multi_index(ind, lam.shape).ravel(), weights=(w * lam).ravel(),
+                           minlength=lam.size)
+    return out.reshape(lam.shape)
 
 
 def adjoint_sweep(vs, vgrid, ms, lam_nt, p):

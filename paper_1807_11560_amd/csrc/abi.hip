@@ -48,7 +48,8 @@ bool same_dims(const Dims& a, const Dims& b) {
   for (int j = 0; j < 3; ++j)
     if (a.N[j] != b.N[j] || a.K[j] != b.K[j] || a.M[j] != b.M[j]) return false;
   return a.nt == b.nt && a.s == b.s && a.alpha == b.alpha && a.sigma == b.sigma &&
-         a.hessian == b.hessian && a.state == b.state && a.integrator == b.integrator && a.prec == b.prec;
+         a.hessian == b.hessian && a.state == b.state && a.integrator == b.integrator && a.prec == b.prec &&
+         a.ckpt == b.ckpt;
 }
 
 void set_prepared(const void* ws, bool prepared, const Dims& d) {
@@ -105,11 +106,22 @@ int validate(const lddmm_params* p, Dims* d) {
   o.state = p->state;
   o.integrator = p->integrator;
   o.prec = p->precision == LDDMM_FP32_BF16X3 ? 1 : 0;
+  if (p->checkpoint < 0 || p->checkpoint > o.nt)
+    return fail(LDDMM_E_INVALID_ARG, "checkpoint must be in [0, time_steps]");
+  if (p->checkpoint > 0 && (p->state != LDDMM_STATE_IMAGE || p->integrator != LDDMM_EULER))
+    return fail(LDDMM_E_INVALID_ARG, "checkpoints need the image state and Euler steps");
+  o.ckpt = p->checkpoint;
   // each block keeps its tile in LDS (at most the 160 KiB of a gfx950 workgroup)
   if (synth_shared_bytes(o) > kMaxLds || prods_shared_bytes(o, 9) > kMaxLds || colstep_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
   if (gridstep_shared_bytes(o) > kMaxLds || src_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");
+  return LDDMM_OK;
+}
+
+// Only lddmm_gradient_exact (and the workspace size) take checkpoints.
+int no_checkpoint(const Dims& d) {
+  if (d.ckpt) return fail(LDDMM_E_INVALID_ARG, "checkpoint is for lddmm_gradient_exact only");
   return LDDMM_OK;
 }
 
@@ -289,6 +301,7 @@ std::string graph_key(const Engine& e, const void* ws, int kind, std::initialize
   put(&d.state, sizeof d.state);
   put(&d.integrator, sizeof d.integrator);
   put(&d.prec, sizeof d.prec);
+  put(&d.ckpt, sizeof d.ckpt);
   for (const void* p : ext) put(&p, sizeof p);
   return k;
 }
@@ -640,6 +653,7 @@ int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if (!I0 || !v0 || !m1) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
   set_prepared(ws, false, d);
@@ -661,6 +675,7 @@ int lddmm_shoot_static(const lddmm_params* p, const float* I0, const void* v0, f
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if (!I0 || !v0 || !m1) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   const size_t need = Engine::workspace_bytes(d);
   if (need > LDDMM_STATIC_SCRATCH_BYTES)
@@ -688,6 +703,7 @@ int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, voi
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if (which != LDDMM_SYMBOL_L && which != LDDMM_SYMBOL_K) return fail(LDDMM_E_INVALID_ARG, "unknown symbol");
   if (!in || !out) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
@@ -706,6 +722,7 @@ int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energie
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if (!v0 || !energies) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
   set_prepared(ws, false, d);
@@ -723,6 +740,7 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if ((rc = euler_only(d))) return rc;
   if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
@@ -742,11 +760,57 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
   return LDDMM_OK;
 }
 
+int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const void* v0, double* energy3,
+                 void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
+  if (!I0 || !I1 || !v0 || !energy3) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  const float* mnt = nullptr;
+  if ((err = e.forward_light(I0, &mnt)) != hipSuccess) return hip_fail(err, "shoot");
+  if ((err = e.energy(mnt, I1)) != hipSuccess) return hip_fail(err, "energy");
+  if ((err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess) return hip_fail(err, "energy copy");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
+int lddmm_gradient_exact(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
+                         void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if ((rc = euler_only(d))) return rc;
+  if (d.state != LDDMM_STATE_IMAGE) return fail(LDDMM_E_INVALID_ARG, "the exact gradient is for the image state");
+  if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  set_prepared(ws, false, d);
+  Engine e(d, ws, static_cast<hipStream_t>(stream));
+  hipError_t err;
+  if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
+  if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
+  if ((err = e.forward_ckpt(I0)) != hipSuccess) return hip_fail(err, "forward");
+  if ((err = e.energy(e.final_state(), I1)) != hipSuccess) return hip_fail(err, "energy");
+  if ((err = e.backward_exact(I1, e.gh)) != hipSuccess) return hip_fail(err, "backward");
+  if ((err = e.store_band(e.gh, nullptr, 0.f, grad)) != hipSuccess) return hip_fail(err, "store");
+  if (energy3 && (err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess)
+    return hip_fail(err, "energy copy");
+  g_last_error.clear();
+  return LDDMM_OK;
+}
+
 int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, size_t ws_bytes,
                   void* stream) {
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if ((rc = euler_only(d))) return rc;
   if (!dv0 || !Hdv) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if (dv0 == Hdv) return fail(LDDMM_E_INVALID_ARG, "Hdv may not alias dv0");
@@ -774,6 +838,7 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
   if ((rc = euler_only(d))) return rc;
   if (!I0 || !I1 || !v0_inout) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if (gn_iters < 0 || pcg_iters < 1) return fail(LDDMM_E_INVALID_ARG, "bad iteration counts");
@@ -797,7 +862,8 @@ int lddmm_batch_workspace_bytes(int32_t n, const lddmm_params* p, size_t* bytes)
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
     Dims d;
-    const int rc = validate(&p[i], &d);
+    int rc = validate(&p[i], &d);
+    if (!rc) rc = no_checkpoint(d);
     if (rc) return fail(rc, "pair " + std::to_string(i) + ": " + g_last_error);
     total += batch_slice(Engine::workspace_bytes(d));
   }
@@ -820,6 +886,7 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
   for (int i = 0; i < n; ++i) {
     int rc = validate(&p[i], &dims[i]);
     if (!rc) rc = euler_only(dims[i]);
+    if (!rc) rc = no_checkpoint(dims[i]);
     if (rc) return fail(rc, "pair " + std::to_string(i) + ": " + g_last_error);
     if (!I0[i] || !I1[i] || !v0_inout[i])
       return fail(LDDMM_E_INVALID_ARG, "pair " + std::to_string(i) + ": null input or output");

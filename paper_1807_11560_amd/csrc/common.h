@@ -28,6 +28,7 @@ struct Dims {
   int state;        // 0: image state on the grid; 1: deformation state in the band
   int integrator;   // 0: Euler; 1: RK4 shooting with midpoint transport (shooting only)
   int prec;         // 0: FP32 matrix-core products; 1: compensated BF16 (three products)
+  int ckpt;         // 0: every state kept; c > 0: states every c steps (exact gradient only)
 };
 
 // ---------------------------------------------------------------- tables
@@ -67,7 +68,9 @@ enum MProg {
   PROG_DEF_FWD = 6,     // out0 = D~Phi * V                             new: Phi; cached: V
   PROG_DEF_H = 7,       // out0 = D~dPhi * V + D~Phi * dV               new: dPhi; cached: V, Phi, dV
   PROG_DEF_TAIL = 8,    // out0 = (D~A)^T * R                           new: A and/or R
-  PROG_DEF_HTAIL = 9    // out0 = (D~dPhi)^T * R + (D~Phi)^T * dR       new: dPhi, dR; cached: Phi, R
+  PROG_DEF_HTAIL = 9,   // out0 = (D~dPhi)^T * R + (D~Phi)^T * dR       new: dPhi, dR; cached: Phi, R
+  // exact adjoint sweep (no U recursion):
+  PROG_ADJ = 10         // out0 = ad_V(W), out1 = ad*_W(LV)              new: W; cached: V, LV
   // k_prods group order: SHOOT (V, LV); H1 (dV, LdV, V, LV); GRAD (LU, W, V, LV);
   // H5 (LdU, dW, V, LV, LU, W, dV, LdV); H5_NOCOUPLE (LdU, dW, V, LV);
   // DEF_FWD (Phi, V); DEF_H (dPhi, V, Phi, dV); DEF_TAIL (A, R); DEF_HTAIL (dPhi, dR, Phi, R).
@@ -191,6 +194,11 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,
                            float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st);
+// Exact adjoint of one transport step (see k_adj_src_fwd2): lam_out += I^T
+// [lam] (lam_out zeroed by the caller), and forward stage 2 of
+// s_j = -dt N_j coef lam (d_j I[m])(x - dt vel(x)) into s1 [3][N0][N1][Kh].
+hipError_t launch_adj_src_fwd2(const float* lam, const float* m, const float* vel, float* lam_out, float coef,
+                               float dt, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st);
 // Deformation state at t = 1 (see k_rho_fwd2): the image-term source at
 // phi(1) = id + u and its forward stage 2 into s1 [3][N0][N1][Kh].
 struct RhoArgs {

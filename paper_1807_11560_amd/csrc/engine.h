@@ -58,9 +58,16 @@ class Engine {
   hipError_t backward(const float* I1, float2* g_out);
   // Hessian-vector product on half-spectrum vectors.
   hipError_t hessvec(const float2* dvh, float2* out);
+  // Exact derivative of the discrete energy (reverse sweep of every Euler and
+  // transport step) after `forward` (or `forward_ckpt` with checkpoints):
+  // g_V = V[0] + W[0] into g_out (half); the per-step band sources go to U[n].
+  hipError_t backward_exact(const float* I1, float2* g_out);
+  // Shooting with caches; with checkpoints only the states m_{kc} and m_nt
+  // are kept (final_state() is m_nt).
+  hipError_t forward_ckpt(const float* I0);
 
   // m(1) of the last forward: m_nt (image state) or I0 o phi(1) (deformation state).
-  const float* final_state() const { return d_.state ? m1 : m[d_.nt]; }
+  const float* final_state() const { return d_.state ? m1 : (d_.ckpt ? mfin_ : m[d_.nt]); }
 
   const Dims& dims() const { return d_; }
   // Second stream of this thread and device for the grid chain, and events.
@@ -142,6 +149,13 @@ class Engine {
   std::vector<float2*> T1N;     // image-grid stage-0 output of each time step [3][N0][Kh][K1]
   bool fuse_grid0_ = false;     // the column kernel forms T1N[n + 1]
   float* NG_ = nullptr;         // scratch for new groups that are not cached
+  // with checkpoints (d_.ckpt = c > 0): m[k] = m_{kc}; mseg_[i] = m_{sc+i} of the
+  // segment being recomputed; mfin_ = m_nt
+  std::vector<float*> mseg_;
+  float* mfin_ = nullptr;
+  // where state n lives in the checkpointed layout (nullptr: not kept now)
+  float* ckpt_state(int n) const;
+  hipError_t grid_velocity_ckpt(int n, float* out, hipStream_t s);
   float* synth_tab_ = nullptr;  // MFMA-form stage-1/2 twiddles of the padded grid
   float2* col_tab_ = nullptr;   // MFMA-form twiddles of the column step
 };

@@ -78,7 +78,8 @@ void Engine::layout(Carver& c) {
   const Dims& d = d_;
   const size_t nbv = 3 * (size_t)d.nb;
   const int nt = d.nt;
-  V.resize(nt + 1); U.resize(nt + 1); W.resize(nt + 1); dV.resize(nt);
+  const bool ck = d.ckpt > 0 && d.state == 0;
+  V.resize(nt + 1); U.resize(nt + 1); W.resize(nt + 1); dV.resize(ck ? 0 : nt);
   for (auto& p : V) p = c.take<float2>(nbv);
   for (auto& p : U) p = c.take<float2>(nbv);
   for (auto& p : W) p = c.take<float2>(nbv);
@@ -87,7 +88,8 @@ void Engine::layout(Carver& c) {
   gh = c.take<float2>(nbv); ph = c.take<float2>(nbv); rh = c.take<float2>(nbv);
   dh = c.take<float2>(nbv); Hdh = c.take<float2>(nbv); v0h = c.take<float2>(nbv);
   vtry = c.take<float2>(nbv); tmph = c.take<float2>(nbv);
-  VG.resize(nt); UG.resize(nt); WG.resize(nt); dVG.resize(nt);
+  // with checkpoints only the exact gradient runs: no sweep caches but VG
+  VG.resize(nt); UG.resize(ck ? 0 : nt); WG.resize(ck ? 0 : nt); dVG.resize(ck ? 0 : nt);
   for (auto& p : VG) p = c.take<float>(24 * (size_t)d.nM);
   for (auto& p : UG) p = c.take<float>(12 * (size_t)d.nM);
   for (auto& p : WG) p = c.take<float>(12 * (size_t)d.nM);
@@ -95,17 +97,30 @@ void Engine::layout(Carver& c) {
   // the image state keeps m_n and the grid velocities of every step; the
   // deformation state needs neither
   const bool def = d.state == 1;
-  m.assign(def ? 0 : nt + 1, nullptr);
-  vg.assign(def ? 0 : nt, nullptr);
+  if (ck) {
+    // states m_0, m_c, m_2c, ... < nt; one segment of c recomputed states;
+    // m_nt; one grid velocity, recomputed when needed
+    m.assign((nt + d.ckpt - 1) / d.ckpt, nullptr);
+    mseg_.assign(d.ckpt, nullptr);
+    vg.assign(1, nullptr);
+  } else {
+    m.assign(def ? 0 : nt + 1, nullptr);
+    mseg_.clear();
+    vg.assign(def ? 0 : nt, nullptr);
+  }
   for (auto& p : m) p = c.take<float>((size_t)d.nN);
+  for (auto& p : mseg_) p = c.take<float>((size_t)d.nN);
+  mfin_ = ck ? c.take<float>((size_t)d.nN) : nullptr;
   for (auto& p : vg) p = c.take<float>(3 * (size_t)d.nN);
   dm[0] = dm[1] = q = mlight[0] = mlight[1] = nullptr;
   if (!def) {
-    dm[0] = c.take<float>((size_t)d.nN);
+    dm[0] = c.take<float>((size_t)d.nN);  // also the state adjoint of the exact gradient
     dm[1] = c.take<float>((size_t)d.nN);
-    q = c.take<float>((size_t)d.nN);
-    mlight[0] = c.take<float>((size_t)d.nN);
-    mlight[1] = c.take<float>((size_t)d.nN);
+    if (!ck) {
+      q = c.take<float>((size_t)d.nN);
+      mlight[0] = c.take<float>((size_t)d.nN);
+      mlight[1] = c.take<float>((size_t)d.nN);
+    }
   }
   resid = c.take<float>(d.hessian == 2 ? (size_t)d.nN : 1);
   partial = c.take<double>(1024);
@@ -121,7 +136,7 @@ void Engine::layout(Carver& c) {
   synth_tab_ = c.take<float>(synth_table_floats(d));
   col_tab_ = c.take<float2>(col_table_count(d));
   S1_ = c.take<float2>(9 * (size_t)d.M[0] * d.M[1] * d.Kh);
-  T1N.assign(def ? 0 : nt, nullptr);
+  T1N.assign(def ? 0 : (ck ? 1 : nt), nullptr);
   for (auto& p : T1N) p = c.take<float2>(3 * (size_t)d.N[0] * C);
   S1N_ = c.take<float2>(3 * (size_t)d.N[0] * d.N[1] * d.Kh);
   S2N_ = c.take<float2>(3 * (size_t)d.N[0] * C);
@@ -152,7 +167,8 @@ void Engine::layout(Carver& c) {
   }
 }
 
-Engine::Engine(const Dims& d, void* ws, hipStream_t st) : d_(d), st_(st), fuse_grid0_(colstep_fuses_grid0(d)) {
+Engine::Engine(const Dims& d, void* ws, hipStream_t st)
+    : d_(d), st_(st), fuse_grid0_(colstep_fuses_grid0(d) && d.ckpt == 0) {
   Carver c{static_cast<char*>(ws)};
   layout(c);
   // twiddle table views
@@ -641,6 +657,116 @@ hipError_t Engine::hessvec_sweep(float2* out) {
     cur = 1 - cur;
   }
   return launch_axpy_band(dV[0], dW[cur], 1.f, out, 3 * d_.nb, st_);
+}
+
+// ------------------------------------- exact derivative of the discrete energy
+// The reverse of every step of `forward`: the state adjoint lam (held as
+// lam / coef, lam_nt / coef = m_nt - I1, coef = 2 / sigma^2 with the 1/|N| of
+// the energy's mean folded into pi) is carried back through the transpose
+// of each transport step, and each step's velocity sensitivity goes to the
+// band as S_n = K~ pi(s_n) (k_adj_src_fwd2, then forward stages 1 and 0);
+// then the transpose of each Euler step of the band EPDiff in the V metric,
+// w_n = w_{n+1} - dt ad~_{v_n} w_{n+1} + dt K~ ad~*_{w_{n+1}}(L~ v_n) + S_n,
+// w_nt = 0, g_V = v_0 + w_0.  With checkpoints the states of each segment of
+// c steps are transported again from its first state, and the grid
+// velocities are synthesised again from the band trajectory.
+
+float* Engine::ckpt_state(int n) const {
+  const int c = d_.ckpt;
+  if (n == d_.nt) return mfin_;
+  if (n % c == 0) return m[n / c];
+  return mseg_[n % c];
+}
+
+hipError_t Engine::grid_velocity_ckpt(int n, float* out, hipStream_t s) {
+  TRY(grid_stage0(V[n], T1N[0], s));
+  GridStepArgs a{};
+  a.t1 = T1N[0];
+  a.op = 0;
+  a.vout = out;
+  return launch_gridstep(a, d_, twN_, s);
+}
+
+hipError_t Engine::forward_ckpt(const float* I0) {
+  if (d_.ckpt == 0) return forward(I0);
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  TRY(aux_init(nt + 2));
+  TRY(record(st_, 0));
+  auto grid_step = [&](int n) -> hipError_t {
+    if (n >= nt) return hipSuccess;
+    TRY(wait(aux_, n));
+    if (n == 0) TRY(launch_copy(I0, m[0], d_.nN, aux_));
+    TRY(grid_velocity_ckpt(n, vg[0], aux_));
+    return launch_sl(ckpt_state(n), vg[0], ckpt_state(n + 1), dt, d_, aux_);
+  };
+  TRY(grid_step(0));
+  TRY(shoot_band(true, grid_step));
+  TRY(record(aux_, nt + 1));
+  return wait(st_, nt + 1);
+}
+
+hipError_t Engine::backward_exact(const float* I1, float2* g_out) {
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  const int c = d_.ckpt;
+  const size_t nM = (size_t)d_.nM;
+  const float coef = (float)(2.0 / (d_.sigma * d_.sigma));
+  // grid chain, backward: S_n into U[n]
+  int cur = 0;
+  TRY(launch_diff(final_state(), I1, dm[cur], d_.nN, st_));
+  for (int n = nt - 1; n >= 0; --n) {
+    const float* mn;
+    const float* vn;
+    if (c == 0) {
+      mn = m[n];
+      vn = vg[n];
+    } else {
+      // entering a segment from its end: transport its states again
+      const int s0 = (n / c) * c;
+      if (n == nt - 1 || n % c == c - 1)
+        for (int k = s0; k < n; ++k) {
+          TRY(grid_velocity_ckpt(k, vg[0], st_));
+          TRY(launch_sl(ckpt_state(k), vg[0], mseg_[(k + 1) - s0], dt, d_, st_));
+        }
+      mn = ckpt_state(n);
+      TRY(grid_velocity_ckpt(n, vg[0], st_));
+      vn = vg[0];
+    }
+    TRY(launch_fill(dm[1 - cur], d_.nN, 0.f, st_));
+    TRY(launch_adj_src_fwd2(dm[cur], mn, vn, dm[1 - cur], coef, dt, S1N_, d_, twN_, st_));
+    Fwd0Job fj[3];
+    for (int k = 0; k < 3; ++k) {
+      fj[k] = Fwd0Job{};
+      fj[k].a = s2n(k);
+      fj[k].ca = 1.f;
+      fj[k].syma = 1;
+      fj[k].out = U[n] + (size_t)k * d_.nb;
+    }
+    TRY(fwd_grid(fj, 3, st_));
+    cur = 1 - cur;
+  }
+  // band sweep, backward from w_nt = 0
+  TRY(launch_fill(reinterpret_cast<float*>(W[nt]), 6LL * d_.nb, 0.f, st_));
+  TRY(inv0_group(W[nt], 0, 0, st_));
+  for (int n = nt - 1; n >= 0; --n) {
+    TRY(launch_synth(t1(0, 0), nullptr, NG_, nullptr, synth_tab_, d_, st_));
+    ProdArgs a{};
+    a.g[0] = NG_;
+    a.g[1] = VG[n];
+    a.g[2] = VG[n] + 12 * nM;
+    a.s1 = S1_;
+    a.nout = 6;
+    a.prog = PROG_ADJ;
+    TRY(launch_prods(a, d_, twM_, st_));
+    const bool next = n > 0;
+    ColJob jobs[3];
+    for (int k = 0; k < 3; ++k)
+      jobs[k] = col_job(k, k, -dt, 0, 3 + k, dt, 1, W[n + 1], U[n], 1.f, W[n], next ? 0 : -1, 0, -1, 0);
+    TRY(colstep(jobs, 3));
+  }
+  if (g_out) TRY(launch_axpy_band(V[0], W[0], 1.f, g_out, 3 * d_.nb, st_));
+  return hipSuccess;
 }
 
 // ------------------------------------------------ deformation state (§3.3)

@@ -708,6 +708,15 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
           adstar_acc(o + 6, gW, gLV, 1.f); // ad*_W(LV)
           break;
         }
+        case PROG_ADJ: {  // g: W, V, LV
+          float gW[12], gV[12], gLV[12];
+          get(a.g[0], gW);
+          get(a.g[1], gV);
+          get(a.g[2], gLV);
+          ad_acc(o, gV, gW, 1.f);          // ad_V(W)
+          adstar_acc(o + 3, gW, gLV, 1.f); // ad*_W(LV)
+          break;
+        }
         case PROG_H5: {  // g: LdU, dW, V, LV, LU, W, dV, LdV
           float gLdU[12], gdW[12], gV[12], gLV[12], gLU[12], gW[12], gdV[12], gLdV[12];
           get(a.g[0], gLdU);
@@ -1884,6 +1893,103 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
   }
 }
 
+// ----------- exact adjoint of one semi-Lagrangian step, forward stage 2
+// The reverse of m_{n+1}(x) = I[m_n](X(x)), X(x) = x - dt v(x) (voxels per
+// axis, the departure point k_sl computes).  For the state adjoint lam of
+// m_{n+1} (held as lam / coef): the transpose of the interpolation scatters
+// lam(x) with the trilinear weights onto the eight corners of X(x) in
+// lam_out (zero on entry; atomic adds), and the derivative with respect to
+// the grid velocity, s_j(x) = -dt N_j coef lam(x) (d_j I[m_n])(X(x)) with the
+// interpolant's exact slope in the cell of X, is contracted over x2 as in
+// k_src_fwd2: s1[j][x0][x1][kh].
+template <class G>
+__global__ void __launch_bounds__(256) k_adj_src_fwd2(const float* __restrict__ lam,
+                                                      const float* __restrict__ m,
+                                                      const float* __restrict__ vel,
+                                                      float* __restrict__ lam_out, float coef, float dt,
+                                                      float2* __restrict__ s1, Twiddles tw, G gs) {
+  extern __shared__ float shs[];
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2(), Kh = gs.Kh();
+  const long long nN = (long long)N0 * N1 * N2;
+  constexpr int R = kGridRows;
+  const int x0 = blockIdx.y;
+  const int x1b = blockIdx.x * R;
+  const int rv = min(R, N1 - x1b);
+  const int P = R * N2;
+  float* vals = shs;                                   // [3][R][N2]
+  float2* wfx = (float2*)(vals + ((3 * P + 3) & ~3));  // [N2][Kh]
+  batched_fill<float2>(Kh * N2, [&](int i) {
+    int x2 = i / Kh, kh = i % Kh;
+    return tw.fwd2[(size_t)kh * N2 + x2];
+  }, [&](int i, float2 v) { wfx[i] = v; });
+  for (int p = threadIdx.x; p < R * N2; p += blockDim.x) {
+    const int r = p / N2, x2 = p % N2;
+    const int x1 = x1b + r;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (r < rv) {
+      const long long gi = ((long long)x0 * N1 + x1) * N2 + x2;
+      float X0 = (float)x0 - dt * vel[gi] * (float)N0;
+      float X1 = (float)x1 - dt * vel[nN + gi] * (float)N1;
+      float X2 = (float)x2 - dt * vel[2 * nN + gi] * (float)N2;
+      if (!isfinite(X0)) X0 = (float)x0;
+      if (!isfinite(X1)) X1 = (float)x1;
+      if (!isfinite(X2)) X2 = (float)x2;
+      const float f0 = floorf(X0), f1 = floorf(X1), f2 = floorf(X2);
+      const float w0 = X0 - f0, w1 = X1 - f1, w2 = X2 - f2;
+      int a0 = (int)f0 % N0; if (a0 < 0) a0 += N0;
+      int a1 = (int)f1 % N1; if (a1 < 0) a1 += N1;
+      int a2 = (int)f2 % N2; if (a2 < 0) a2 += N2;
+      const int b0 = (a0 + 1 == N0) ? 0 : a0 + 1;
+      const int b1 = (a1 + 1 == N1) ? 0 : a1 + 1;
+      const int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
+      auto idx = [&](int u, int v, int w) { return ((long long)u * N1 + v) * N2 + w; };
+      const float m000 = m[idx(a0, a1, a2)], m001 = m[idx(a0, a1, b2)];
+      const float m010 = m[idx(a0, b1, a2)], m011 = m[idx(a0, b1, b2)];
+      const float m100 = m[idx(b0, a1, a2)], m101 = m[idx(b0, a1, b2)];
+      const float m110 = m[idx(b0, b1, a2)], m111 = m[idx(b0, b1, b2)];
+      // the interpolant's slopes in the cell (lerps of the edge differences)
+      const float c00 = m000 + w2 * (m001 - m000), c01 = m010 + w2 * (m011 - m010);
+      const float c10 = m100 + w2 * (m101 - m100), c11 = m110 + w2 * (m111 - m110);
+      const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
+      const float d0 = c1 - c0;
+      const float d1 = (c01 - c00) + w0 * ((c11 - c10) - (c01 - c00));
+      const float e00 = m001 - m000, e01 = m011 - m010, e10 = m101 - m100, e11 = m111 - m110;
+      const float e0 = e00 + w1 * (e01 - e00), e1 = e10 + w1 * (e11 - e10);
+      const float d2 = e0 + w0 * (e1 - e0);
+      const float l = lam[gi];
+      const float s = -dt * coef * l;
+      g0 = s * (float)N0 * d0;
+      g1 = s * (float)N1 * d1;
+      g2 = s * (float)N2 * d2;
+      // transpose of the interpolation
+      const float u0 = 1.f - w0, u1 = 1.f - w1, u2 = 1.f - w2;
+      atomicAdd(lam_out + idx(a0, a1, a2), l * u0 * u1 * u2);
+      atomicAdd(lam_out + idx(a0, a1, b2), l * u0 * u1 * w2);
+      atomicAdd(lam_out + idx(a0, b1, a2), l * u0 * w1 * u2);
+      atomicAdd(lam_out + idx(a0, b1, b2), l * u0 * w1 * w2);
+      atomicAdd(lam_out + idx(b0, a1, a2), l * w0 * u1 * u2);
+      atomicAdd(lam_out + idx(b0, a1, b2), l * w0 * u1 * w2);
+      atomicAdd(lam_out + idx(b0, b1, a2), l * w0 * w1 * u2);
+      atomicAdd(lam_out + idx(b0, b1, b2), l * w0 * w1 * w2);
+    }
+    vals[p] = g0;
+    vals[P + p] = g1;
+    vals[2 * P + p] = g2;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * rv * Kh; i += blockDim.x) {
+    int j = i / (rv * Kh), r = (i / Kh) % rv, kh = i % Kh;
+    const float* row = vals + (size_t)j * P + r * N2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int x2 = 0; x2 < N2; ++x2) {
+      float2 w = wfx[(size_t)x2 * Kh + kh];
+      acc.x = fmaf(row[x2], w.x, acc.x);
+      acc.y = fmaf(row[x2], w.y, acc.y);
+    }
+    s1[(((size_t)j * N0 + x0) * N1 + x1b + r) * Kh + kh] = acc;
+  }
+}
+
 // ------------- deformation-state image term and forward stage 2 (N grid)
 // Central differences of I0 at every node: G_a = d_a I0 and, when H is set,
 // H = (d0d0, d0d1, d0d2, d1d1, d1d2, d2d2) I0 (the same central difference
@@ -2701,8 +2807,8 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
   dim3 grid(nblk(d.M[1], R), d.M[0]);
   size_t shm = prods_shared_bytes(d, a.nout);
   {
-    static const double prog_flops[10] = {0, 47, 94, 136, 272, 136, 18, 36, 18, 36};
-    static const int prog_fields[10] = {0, 24, 48, 48, 96, 48, 12, 24, 12, 24};
+    static const double prog_flops[11] = {0, 47, 94, 136, 272, 136, 18, 36, 18, 36, 89};
+    static const int prog_fields[11] = {0, 24, 48, 48, 96, 48, 12, 24, 12, 24, 36};
     const double nM = (double)d.nM;
     double fl = prog_flops[a.prog] * nM + a.nout * nM * d.Kh * 4.0;
     double by = prog_fields[a.prog] * nM * 4.0 + a.nout * (double)d.M[0] * d.M[1] * d.Kh * 8.0;
@@ -3002,6 +3108,24 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const
   }
   hipError_t e = with_grid(d, [&](auto gs) {
     LAUNCH_TIMED(KF_SRC, (k_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, a, b, r, m, coef, s1, tw, gs);
+    return hipGetLastError();
+  });
+  return e;
+}
+
+hipError_t launch_adj_src_fwd2(const float* lam, const float* m, const float* vel, float* lam_out, float coef,
+                               float dt, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st) {
+  dim3 grid(nblk(d.N[1], kGridRows), d.N[0]);
+  size_t shm = src_shared_bytes(d);
+  {
+    // departure point, 8 gathers, slopes, 8 scattered weights, forward stage 2 of 3 fields
+    const double nN = (double)d.nN;
+    timer_work(KF_SRC, 3.0 * nN * d.Kh * 4.0 + 80.0 * nN,
+               (4.0 + 12.0 + 4.0 + 8.0 * 4.0) * nN + 3.0 * d.N[0] * (double)d.N[1] * d.Kh * 8.0);
+  }
+  hipError_t e = with_grid(d, [&](auto gs) {
+    LAUNCH_TIMED(KF_SRC, (k_adj_src_fwd2<decltype(gs)>), grid, dim3(256), shm, st, lam, m, vel, lam_out, coef, dt,
+                 s1, tw, gs);
     return hipGetLastError();
   });
   return e;

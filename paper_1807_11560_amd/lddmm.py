@@ -64,6 +64,7 @@ class LddmmParams(ctypes.Structure):
         ("hessian", ctypes.c_int32),
         ("state", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("checkpoint", ctypes.c_int32),
     ]
 
 
@@ -92,6 +93,8 @@ _SIGS = {
     "lddmm_geodesic_energy": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_apply_symbol": (ctypes.c_int, [_P, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_hessvec": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_gradient_exact": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lddmm_energy": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lddmm_register": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(LddmmStats), ctypes.c_int32, _vp,
                                       ctypes.c_size_t, _vp]),
@@ -145,6 +148,7 @@ class Problem:
     state: int = STATE_IMAGE
     integrator: int = EULER
     precision: int = FP32
+    checkpoint: int = 0
 
     def c_params(self) -> LddmmParams:
         p = LddmmParams()
@@ -158,6 +162,7 @@ class Problem:
         p.alpha = float(self.alpha)
         p.sigma = float(self.sigma)
         p.precision = int(self.precision)
+        p.checkpoint = int(self.checkpoint)
         p.hessian = int(self.hessian)
         p.state = int(self.state)
         p.integrator = int(self.integrator)
@@ -276,6 +281,32 @@ def gradient(problem: Problem, I0, I1, v0, ws: Workspace, stream=None):
     e3 = torch.empty(3, dtype=torch.float64, device=v0.device)
     _check(_lib.lddmm_gradient(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0), _ptr(g),
                                _ptr(e3), ws.ptr, ws.nbytes, _stream(stream)), "lddmm_gradient")
+    return g, e3
+
+
+def energy(problem: Problem, I0, I1, v0, ws: Workspace, stream=None):
+    """energy[3] (E, E_reg, E_data; float64 on the device) at v0 (lddmm_energy)."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(I1, torch.float32, problem.grid, "I1")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    e3 = torch.empty(3, dtype=torch.float64, device=v0.device)
+    _check(_lib.lddmm_energy(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0), _ptr(e3), ws.ptr,
+                             ws.nbytes, _stream(stream)), "lddmm_energy")
+    return e3
+
+
+def gradient_exact(problem: Problem, I0, I1, v0, ws: Workspace, stream=None):
+    """(g_V, energy[3] float64 on the device): the exact derivative of the
+    discrete energy at v0 (lddmm_gradient_exact; honours problem.checkpoint)."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(I1, torch.float32, problem.grid, "I1")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    g = torch.empty_like(v0)
+    e3 = torch.empty(3, dtype=torch.float64, device=v0.device)
+    _check(_lib.lddmm_gradient_exact(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0), _ptr(g),
+                                     _ptr(e3), ws.ptr, ws.nbytes, _stream(stream)), "lddmm_gradient_exact")
     return g, e3
 
 
