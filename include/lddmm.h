@@ -78,7 +78,7 @@ enum {
  * modes. */
 enum { LDDMM_FP32 = 0, LDDMM_FP32_BF16X3 = 1 };
 /* Hessian of the Krylov solves, see lddmm_params */
-enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2 };
+enum { LDDMM_GN_PAPER = 0, LDDMM_GN_CLASSICAL = 1, LDDMM_NEWTON = 2, LDDMM_GN_EXACT = 3 };
 /* State that carries the deformation, see lddmm_params */
 enum { LDDMM_STATE_IMAGE = 0, LDDMM_STATE_DEFORMATION = 1 };
 /* Time integration of shooting and transport, see lddmm_params */
@@ -106,7 +106,16 @@ typedef struct lddmm_params {
                            derivative of the gradient's U(1) (the paper prints a minus before
                            lambda(1) grad dm(1) in §2.3/§3.2; the plus sign is the derivative,
                            see the oracle's pins).  This Hessian need not be positive definite:
-                           the CG of lddmm_register stops on non-positive curvature. */
+                           the CG of lddmm_register stops on non-positive curvature.
+                           LDDMM_GN_EXACT (image state, Euler): the exact derivative of the
+                           discrete energy instead of the paper's adjoint Jacobi one, for
+                           lddmm_gradient, lddmm_hessvec and lddmm_register alike: the gradient
+                           of lddmm_gradient_exact and the Gauss-Newton product J^T W J + Id
+                           (V metric) of that energy, J the derivative of m_nt (the linearised
+                           Euler steps and the tangent of every transport step,
+                           dm_{n+1} = I[dm_n](X_n) - dt sum_j N_j (d_j I[m_n])(X_n) dv_n,j),
+                           W = 2/(sigma^2 |N|); symmetric positive definite, so CG runs its
+                           iterations to the end. */
   int32_t state;        /* LDDMM_STATE_IMAGE: the image is transported on the grid (paper §3.2,
                            everything documented above).  LDDMM_STATE_DEFORMATION: the
                            deformation phi = id + u is transported in the band and the image
@@ -139,13 +148,15 @@ typedef struct lddmm_params {
                            Hessian-vector product and registration integrate the adjoint sweeps
                            as transposes of Euler steps and reject LDDMM_RK4. */
   int32_t checkpoint;   /* 0: the forward keeps every state m_n and grid velocity (the workspace
-                           layout of every entry point).  c >= 1 (lddmm_gradient_exact and
-                           lddmm_workspace_bytes only; image state, Euler): only the states
+                           layout of every entry point).  c >= 1 (lddmm_gradient_exact,
+                           lddmm_energy, lddmm_apply_symbol and lddmm_workspace_bytes only;
+                           image state, Euler): only the states
                            m_0, m_c, m_2c, ... and m_nt are kept; the backward sweep transports
                            each segment of c steps again from its first state and synthesises
                            the grid velocities again from the band trajectory, so the workspace
                            holds about nt/c + c states instead of 4 nt + 1 grid fields (states and
-                           grid velocities) and no sweep caches beyond the shooting's. */
+                           grid velocities) and no sweep caches beyond the shooting's.
+                           lddmm_energy accepts it too (the forward pass of the same layout). */
 } lddmm_params;
 
 /* One Gauss-Newton iteration of lddmm_register (host memory). */
@@ -235,7 +246,8 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
  * by shooting and transport without the caches of the gradient (the
  * forward pass of the autograd form, whose backward is
  * lddmm_gradient_exact).  Arguments as for lddmm_gradient; energy3 (device,
- * 3 doubles) is required. */
+ * 3 doubles) is required.  Accepts params->checkpoint, so that one
+ * checkpointed workspace serves both passes. */
 int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const void* v0, double* energy3,
                  void* ws, size_t ws_bytes, void* stream);
 

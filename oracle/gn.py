@@ -22,7 +22,7 @@ Readings:
 
 import numpy as np
 
-from . import deformation, jacobi
+from . import deformation, exact, jacobi
 from .band import inner, symbol_L
 from .jacobi import energy
 
@@ -79,10 +79,20 @@ def line_search(v0, p_dir, E0, slope, I0, I1, p, c1=1e-4, max_trials=10, state="
 
 def register(I0, I1, p, gn_iters, pcg_iters, v0=None, mode="R1", max_trials=10, state="image"):
     """Gauss-Newton-Krylov registration from v0 (zero by default) for the
-    problem subject to the image state (§3.2) or the deformation state (§3.3)."""
+    problem subject to the image state (§3.2) or the deformation state (§3.3).
+    mode: the Hessian of the paper's method ("R1", "R2", "FULL"), or "EXACT":
+    the exact derivative of the discrete energy and its Gauss-Newton product
+    (oracle/exact.py)."""
     if state not in STATES:
         raise ValueError("state must be 'image' or 'deformation'")
     model = jacobi if state == "image" else deformation
+    if mode == "EXACT":
+        # the exact derivative of the discrete energy and its Gauss-Newton product
+        if state != "image":
+            raise ValueError("mode 'EXACT' is for the image state")
+        grad_fn, hess_fn = exact.gradient, (lambda cache, d: exact.gauss_newton_hessvec(cache, d, p))
+    else:
+        grad_fn, hess_fn = model.gradient, (lambda cache, d: model.hessvec(cache, d, p, mode))
     Lsym = symbol_L(p.band, p.alpha, p.s)
     if v0 is None:
         v0 = np.zeros((p.d,) + tuple(p.band), dtype=np.complex128)
@@ -91,12 +101,12 @@ def register(I0, I1, p, gn_iters, pcg_iters, v0=None, mode="R1", max_trials=10, 
     g0_inf = None
     status = 0
     for it in range(gn_iters):
-        g, E, cache = model.gradient(v0, I0, I1, p)
+        g, E, cache = grad_fn(v0, I0, I1, p)
         m1 = cache["ms"][-1] if state == "image" else cache["m1"]
         g_inf = float(np.max(np.abs(g)))
         if g0_inf is None:
             g0_inf = g_inf
-        p_dir, info = pcg(lambda dvec: model.hessvec(cache, dvec, p, mode), g, Lsym, pcg_iters)
+        p_dir, info = pcg(lambda dvec: hess_fn(cache, dvec), g, Lsym, pcg_iters)
         slope = inner(Lsym * g, p_dir)
         if slope >= 0.0:
             p_dir = -g

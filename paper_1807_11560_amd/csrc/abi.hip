@@ -71,8 +71,11 @@ int validate(const lddmm_params* p, Dims* d) {
     return fail(LDDMM_E_INVALID_ARG, "time_steps must be in [1, 1000]");
   if (p->precision != LDDMM_FP32 && p->precision != LDDMM_FP32_BF16X3)
     return fail(LDDMM_E_INVALID_ARG, "unknown precision");
-  if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL && p->hessian != LDDMM_NEWTON)
+  if (p->hessian != LDDMM_GN_PAPER && p->hessian != LDDMM_GN_CLASSICAL && p->hessian != LDDMM_NEWTON &&
+      p->hessian != LDDMM_GN_EXACT)
     return fail(LDDMM_E_INVALID_ARG, "unknown hessian mode");
+  if (p->hessian == LDDMM_GN_EXACT && (p->state != LDDMM_STATE_IMAGE || p->integrator != LDDMM_EULER))
+    return fail(LDDMM_E_INVALID_ARG, "LDDMM_GN_EXACT needs the image state and Euler steps");
   if (p->state != LDDMM_STATE_IMAGE && p->state != LDDMM_STATE_DEFORMATION)
     return fail(LDDMM_E_INVALID_ARG, "unknown state");
   if (p->integrator != LDDMM_EULER && p->integrator != LDDMM_RK4)
@@ -703,7 +706,6 @@ int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, voi
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
-  if ((rc = no_checkpoint(d))) return rc;
   if (which != LDDMM_SYMBOL_L && which != LDDMM_SYMBOL_K) return fail(LDDMM_E_INVALID_ARG, "unknown symbol");
   if (!in || !out) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
@@ -765,7 +767,8 @@ int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const 
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
-  if ((rc = no_checkpoint(d))) return rc;
+  if (d.ckpt && (d.state != LDDMM_STATE_IMAGE || d.integrator != LDDMM_EULER))
+    return fail(LDDMM_E_INVALID_ARG, "checkpoints need the image state and Euler steps");
   if (!I0 || !I1 || !v0 || !energy3) return fail(LDDMM_E_INVALID_ARG, "null input or output");
   if ((rc = check_ws(d, ws, ws_bytes))) return rc;
   set_prepared(ws, false, d);
@@ -774,7 +777,12 @@ int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const 
   if ((err = e.init_tables()) != hipSuccess) return hip_fail(err, "tables");
   if ((err = e.load_band(v0, e.V[0])) != hipSuccess) return hip_fail(err, "load v0");
   const float* mnt = nullptr;
-  if ((err = e.forward_light(I0, &mnt)) != hipSuccess) return hip_fail(err, "shoot");
+  if (d.ckpt) {  // the checkpointed layout has no light-forward buffers
+    if ((err = e.forward_ckpt(I0)) != hipSuccess) return hip_fail(err, "shoot");
+    mnt = e.final_state();
+  } else if ((err = e.forward_light(I0, &mnt)) != hipSuccess) {
+    return hip_fail(err, "shoot");
+  }
   if ((err = e.energy(mnt, I1)) != hipSuccess) return hip_fail(err, "energy");
   if ((err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess) return hip_fail(err, "energy copy");
   g_last_error.clear();
@@ -801,6 +809,8 @@ int lddmm_gradient_exact(const lddmm_params* p, const float* I0, const float* I1
   if ((err = e.store_band(e.gh, nullptr, 0.f, grad)) != hipSuccess) return hip_fail(err, "store");
   if (energy3 && (err = launch_scalar_copy(e.scal, energy3, 3, e.stream())) != hipSuccess)
     return hip_fail(err, "energy copy");
+  // the exact Gauss-Newton product may follow on an unchecked workspace
+  if (d.hessian == LDDMM_GN_EXACT && d.ckpt == 0) set_prepared(ws, true, d);
   g_last_error.clear();
   return LDDMM_OK;
 }

@@ -194,6 +194,10 @@ hipError_t launch_tail(const float* a, const float* b, const float* r, const flo
 hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const float* m, float coef,
                            float2* s1,
                            const Dims& d, const Twiddles& tw, hipStream_t st);
+// Tangent of one transport step (see k_sl_tangent): out = I[dm](X) -
+// dt sum_j N_j (d_j I[m])(X) dvel_j, X = x - dt vel(x); dm may be null (zero).
+hipError_t launch_sl_tangent(const float* dm, const float* m, const float* vel, const float* dvel, float* out,
+                             float dt, const Dims& d, hipStream_t st);
 // Exact adjoint of one transport step (see k_adj_src_fwd2): lam_out += I^T
 // [lam] (lam_out zeroed by the caller), and forward stage 2 of
 // s_j = -dt N_j coef lam (d_j I[m])(x - dt vel(x)) into s1 [3][N0][N1][Kh].

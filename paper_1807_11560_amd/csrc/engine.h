@@ -62,6 +62,11 @@ class Engine {
   // transport step) after `forward` (or `forward_ckpt` with checkpoints):
   // g_V = V[0] + W[0] into g_out (half); the per-step band sources go to U[n].
   hipError_t backward_exact(const float* I1, float2* g_out);
+  // Gauss-Newton product of the exact discrete energy, (J^T W J + Id) dv in
+  // the V metric, at the v0 of the last forward (no checkpoints): the
+  // linearised Euler steps and the tangent of every transport step, then the
+  // reverse sweep of backward_exact from the state adjoint W dm_nt.
+  hipError_t hessvec_exact(const float2* dvh, float2* out);
   // Shooting with caches; with checkpoints only the states m_{kc} and m_nt
   // are kept (final_state() is m_nt).
   hipError_t forward_ckpt(const float* I0);
@@ -156,6 +161,9 @@ class Engine {
   // where state n lives in the checkpointed layout (nullptr: not kept now)
   float* ckpt_state(int n) const;
   hipError_t grid_velocity_ckpt(int n, float* out, hipStream_t s);
+  // reverse sweep of backward_exact from the state adjoint (over coef) in dm[cur]
+  hipError_t adjoint_exact(int cur);
+  float* dvg_ = nullptr;  // grid velocity increment of one step [3][nN] (exact product)
   float* synth_tab_ = nullptr;  // MFMA-form stage-1/2 twiddles of the padded grid
   float2* col_tab_ = nullptr;   // MFMA-form twiddles of the column step
 };

@@ -117,6 +117,7 @@ void Engine::layout(Carver& c) {
     dm[0] = c.take<float>((size_t)d.nN);  // also the state adjoint of the exact gradient
     dm[1] = c.take<float>((size_t)d.nN);
     if (!ck) {
+      dvg_ = c.take<float>(3 * (size_t)d.nN);
       q = c.take<float>((size_t)d.nN);
       mlight[0] = c.take<float>((size_t)d.nN);
       mlight[1] = c.take<float>((size_t)d.nN);
@@ -550,6 +551,7 @@ hipError_t Engine::energy(const float* mnt, const float* I1) {
 }
 
 hipError_t Engine::backward(const float* I1, float2* g_out) {
+  if (d_.hessian == 3) return backward_exact(I1, g_out);
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   const float coef = (float)(-2.0 / (d_.sigma * d_.sigma));
@@ -581,6 +583,7 @@ hipError_t Engine::backward(const float* I1, float2* g_out) {
 
 hipError_t Engine::hessvec(const float2* dvh, float2* out) {
   if (d_.state) return hessvec_def(dvh, out);
+  if (d_.hessian == 3) return hessvec_exact(dvh, out);
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   const bool coupled = d_.hessian != 1;  // paper reading and full Newton keep the coupling terms
@@ -707,14 +710,52 @@ hipError_t Engine::forward_ckpt(const float* I0) {
 }
 
 hipError_t Engine::backward_exact(const float* I1, float2* g_out) {
+  TRY(launch_diff(final_state(), I1, dm[0], d_.nN, st_));
+  TRY(adjoint_exact(0));
+  if (g_out) TRY(launch_axpy_band(V[0], W[0], 1.f, g_out, 3 * d_.nb, st_));
+  return hipSuccess;
+}
+
+hipError_t Engine::hessvec_exact(const float2* dvh, float2* out) {
+  const float dt = 1.0f / d_.nt;
+  const int nt = d_.nt;
+  const size_t nM = (size_t)d_.nM;
+  if (dvh != dV[0])
+    TRY(launch_copy(reinterpret_cast<const float*>(dvh), reinterpret_cast<float*>(dV[0]), 6LL * d_.nb, st_));
+  // the linearised Euler steps dv_{n+1} = dv_n - dt K~[ad*_{dv_n}(L~ v_n) + ad*_{v_n}(L~ dv_n)],
+  // each step's grid increment iota(dv_n) and the tangent of transport step n
+  TRY(inv0_groups(dV[0], 0, dV[0], 1));
+  int cur = 0;
+  for (int n = 0; n < nt; ++n) {
+    TRY(grid_t1(n, dV[n], st_));
+    GridStepArgs ga{};
+    ga.t1 = T1N[n];
+    ga.op = 0;
+    ga.vout = dvg_;
+    TRY(launch_gridstep(ga, d_, twN_, st_));
+    TRY(launch_sl_tangent(n == 0 ? nullptr : dm[cur], m[n], vg[n], dvg_, dm[1 - cur], dt, d_, st_));
+    cur = 1 - cur;
+    if (n == nt - 1) break;
+    const float* cached[6] = {VG[n], VG[n] + 12 * nM, nullptr, nullptr, nullptr, nullptr};
+    TRY(mstep(PROG_H1, 3, nullptr, nullptr, cached));
+    ColJob jobs[3];
+    for (int c = 0; c < 3; ++c)
+      jobs[c] = col_job(c, c, -dt, 1, -1, 0.f, 0, dV[n], nullptr, 0.f, dV[n + 1], 0, 0, 1, 1,
+                        fuse_grid0_ ? T1N[n + 1] : nullptr);
+    TRY(colstep(jobs, 3));
+  }
+  // lam_nt / coef = dm_nt (W = 2 / (sigma^2 |N|), the 1/|N| folded into pi)
+  TRY(adjoint_exact(cur));
+  return launch_axpy_band(dV[0], W[0], 1.f, out, 3 * d_.nb, st_);
+}
+
+hipError_t Engine::adjoint_exact(int cur) {
   const float dt = 1.0f / d_.nt;
   const int nt = d_.nt;
   const int c = d_.ckpt;
   const size_t nM = (size_t)d_.nM;
   const float coef = (float)(2.0 / (d_.sigma * d_.sigma));
   // grid chain, backward: S_n into U[n]
-  int cur = 0;
-  TRY(launch_diff(final_state(), I1, dm[cur], d_.nN, st_));
   for (int n = nt - 1; n >= 0; --n) {
     const float* mn;
     const float* vn;
@@ -765,7 +806,6 @@ hipError_t Engine::backward_exact(const float* I1, float2* g_out) {
       jobs[k] = col_job(k, k, -dt, 0, 3 + k, dt, 1, W[n + 1], U[n], 1.f, W[n], next ? 0 : -1, 0, -1, 0);
     TRY(colstep(jobs, 3));
   }
-  if (g_out) TRY(launch_axpy_band(V[0], W[0], 1.f, g_out, 3 * d_.nb, st_));
   return hipSuccess;
 }
 

@@ -1893,6 +1893,60 @@ __global__ void __launch_bounds__(256) k_src_fwd2(const float* __restrict__ a,
   }
 }
 
+// ------------------------------ tangent of one semi-Lagrangian step (N)
+// The derivative of m_{n+1}(x) = I[m_n](X(x)), X(x) = x - dt v(x), in the
+// direction (dm_n, dv): dm_{n+1}(x) = I[dm_n](X) - dt sum_j N_j
+// (d_j I[m_n])(X) dv_j(x), with the interpolant's exact slope in the cell of
+// X (dm_n null: zero).
+template <class G>
+__global__ void __launch_bounds__(256) k_sl_tangent(const float* __restrict__ dm, const float* __restrict__ m,
+                                                    const float* __restrict__ vel,
+                                                    const float* __restrict__ dvel, float* __restrict__ out,
+                                                    float dt, G gs) {
+  const int N0 = gs.N0(), N1 = gs.N1(), N2 = gs.N2();
+  const long long nN = (long long)N0 * N1 * N2;
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= nN) return;
+  const int i2 = (int)(gi % N2), i1 = (int)((gi / N2) % N1), i0 = (int)(gi / ((long long)N1 * N2));
+  float X0 = (float)i0 - dt * vel[gi] * (float)N0;
+  float X1 = (float)i1 - dt * vel[nN + gi] * (float)N1;
+  float X2 = (float)i2 - dt * vel[2 * nN + gi] * (float)N2;
+  if (!isfinite(X0)) X0 = (float)i0;
+  if (!isfinite(X1)) X1 = (float)i1;
+  if (!isfinite(X2)) X2 = (float)i2;
+  const float f0 = floorf(X0), f1 = floorf(X1), f2 = floorf(X2);
+  const float w0 = X0 - f0, w1 = X1 - f1, w2 = X2 - f2;
+  int a0 = (int)f0 % N0; if (a0 < 0) a0 += N0;
+  int a1 = (int)f1 % N1; if (a1 < 0) a1 += N1;
+  int a2 = (int)f2 % N2; if (a2 < 0) a2 += N2;
+  const int b0 = (a0 + 1 == N0) ? 0 : a0 + 1;
+  const int b1 = (a1 + 1 == N1) ? 0 : a1 + 1;
+  const int b2 = (a2 + 1 == N2) ? 0 : a2 + 1;
+  auto idx = [&](int u, int v, int w) { return ((long long)u * N1 + v) * N2 + w; };
+  const float m000 = m[idx(a0, a1, a2)], m001 = m[idx(a0, a1, b2)];
+  const float m010 = m[idx(a0, b1, a2)], m011 = m[idx(a0, b1, b2)];
+  const float m100 = m[idx(b0, a1, a2)], m101 = m[idx(b0, a1, b2)];
+  const float m110 = m[idx(b0, b1, a2)], m111 = m[idx(b0, b1, b2)];
+  const float c00 = m000 + w2 * (m001 - m000), c01 = m010 + w2 * (m011 - m010);
+  const float c10 = m100 + w2 * (m101 - m100), c11 = m110 + w2 * (m111 - m110);
+  const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
+  const float d0 = c1 - c0;
+  const float d1 = (c01 - c00) + w0 * ((c11 - c10) - (c01 - c00));
+  const float e00 = m001 - m000, e01 = m011 - m010, e10 = m101 - m100, e11 = m111 - m110;
+  const float e0 = e00 + w1 * (e01 - e00), e1 = e10 + w1 * (e11 - e10);
+  const float d2 = e0 + w0 * (e1 - e0);
+  float r = -dt * ((float)N0 * d0 * dvel[gi] + (float)N1 * d1 * dvel[nN + gi] + (float)N2 * d2 * dvel[2 * nN + gi]);
+  if (dm) {
+    const float q00 = dm[idx(a0, a1, a2)] + w2 * (dm[idx(a0, a1, b2)] - dm[idx(a0, a1, a2)]);
+    const float q01 = dm[idx(a0, b1, a2)] + w2 * (dm[idx(a0, b1, b2)] - dm[idx(a0, b1, a2)]);
+    const float q10 = dm[idx(b0, a1, a2)] + w2 * (dm[idx(b0, a1, b2)] - dm[idx(b0, a1, a2)]);
+    const float q11 = dm[idx(b0, b1, a2)] + w2 * (dm[idx(b0, b1, b2)] - dm[idx(b0, b1, a2)]);
+    const float q0 = q00 + w1 * (q01 - q00), q1 = q10 + w1 * (q11 - q10);
+    r += q0 + w0 * (q1 - q0);
+  }
+  out[gi] = r;
+}
+
 // ----------- exact adjoint of one semi-Lagrangian step, forward stage 2
 // The reverse of m_{n+1}(x) = I[m_n](X(x)), X(x) = x - dt v(x) (voxels per
 // axis, the departure point k_sl computes).  For the state adjoint lam of
@@ -3111,6 +3165,16 @@ hipError_t launch_src_fwd2(const float* a, const float* b, const float* r, const
     return hipGetLastError();
   });
   return e;
+}
+
+hipError_t launch_sl_tangent(const float* dm, const float* m, const float* vel, const float* dvel, float* out,
+                             float dt, const Dims& d, hipStream_t st) {
+  timer_work(KF_SL, 90.0 * (double)d.nN, ((dm ? 8.0 : 4.0) + 12.0 + 12.0 + 4.0) * (double)d.nN);
+  return with_grid(d, [&](auto gs) {
+    LAUNCH_TIMED(KF_SL, (k_sl_tangent<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, dm, m, vel, dvel,
+                 out, dt, gs);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_adj_src_fwd2(const float* lam, const float* m, const float* vel, float* lam_out, float coef,

@@ -37,6 +37,7 @@ FP32_BF16X3 = 1
 GN_PAPER = 0
 GN_CLASSICAL = 1
 NEWTON = 2
+GN_EXACT = 3
 STATE_IMAGE = 0
 STATE_DEFORMATION = 1
 EULER = 0

@@ -64,7 +64,7 @@ def case(request):
     prob = L().Problem(grid=c["grid"], band=c["band"], time_steps=c["nt"], alpha=synth.ALPHA, s=c["s"],
                        sigma=synth.SIGMA)
     args = (dev(I0, torch.float32), dev(I1, torch.float32), dev(v0, torch.complex64))
-    return dict(name=name, c=c, p=p, g=g, E=E, prob=prob, args=args)
+    return dict(name=name, c=c, p=p, g=g, E=E, prob=prob, args=args, vstar=vstar, I0=I0, I1=I1)
 
 
 def test_exact_gradient_matches_oracle(case):
@@ -90,3 +90,80 @@ def test_checkpointed_equals_plain(case):
           f"{ws_c.nbytes / 2**20:.1f} MiB instead of {ws.nbytes / 2**20:.1f} MiB")
     assert e < 1e-5
     assert ws_c.nbytes < ws.nbytes
+
+
+def test_exact_gauss_newton_product_matches_oracle_and_is_symmetric(case):
+    """LDDMM_GN_EXACT: (J^T W J + Id) dv against the oracle (1e-4), and
+    <a, H b>_V = <b, H a>_V on random pairs (relative to sqrt(<a,Ha><b,Hb>),
+    1e-5: the product is symmetric up to FP32 rounding)."""
+    from oracle.band import inner, symbol_L
+    p = case["p"]
+    _, _, cache = exact.gradient(0.6 * case["vstar"], case["I0"], case["I1"], p)
+    prob = dataclasses.replace(case["prob"], hessian=L().GN_EXACT)
+    ws = L().Workspace(prob)
+    L().gradient(prob, *case["args"], ws)
+    Lsym = symbol_L(p.band, p.alpha, p.s)
+    dirs = [synth.random_direction(500 + k, p.band, s=p.s) for k in range(4)]
+    H = [host(L().hessvec(prob, dev(d, torch.complex64), ws)) for d in dirs]
+    ref = exact.gauss_newton_hessvec(cache, dirs[0], p)
+    e = rel(H[0], ref)
+    sym = []
+    for i, j in ((0, 1), (2, 3), (0, 3)):
+        ab, ba = inner(Lsym * dirs[i], H[j]), inner(Lsym * dirs[j], H[i])
+        sym.append(abs(ab - ba) / np.sqrt(inner(Lsym * dirs[i], H[i]) * inner(Lsym * dirs[j], H[j])))
+    print(f"{case['name']}: exact Gauss-Newton product rel {e:.2e}, symmetry {['%.1e' % x for x in sym]}")
+    assert e < 1e-4 and max(sym) < 1e-5
+
+
+def test_exact_registration_loop_matches_oracle():
+    """The Gauss-Newton-Krylov loop in LDDMM_GN_EXACT against the oracle's
+    mode "EXACT" (decisions exact, energies 1e-4, final iterate 1e-3)."""
+    from oracle.gn import register as oracle_register
+    print("\n[exact Gauss-Newton loop]", flush=True)
+    grid, band, nt = (24, 20, 18), (8, 8, 6), 4
+    w = synth.workload(2, grid=grid, band=band)
+    p = Params(grid=grid, band=band, nt=nt, alpha=synth.ALPHA, s=2, sigma=synth.SIGMA)
+    vstar = synth.scale_to_displacement(w["v_star"], grid, 1.5)
+    I0 = w["I0"]
+    I1 = forward(vstar, I0, p)[2][-1]
+    v_ref, st_ref, status_ref = oracle_register(I0, I1, p, 3, 4, mode="EXACT")
+    prob = L().Problem(grid=grid, band=band, time_steps=nt, alpha=synth.ALPHA, s=2, sigma=synth.SIGMA,
+                       hessian=L().GN_EXACT)
+    ws = L().Workspace(prob)
+    v, st, rc, hv = L().register(prob, dev(I0, torch.float32), dev(I1, torch.float32), ws, gn_iters=3, pcg_iters=4)
+    assert rc == status_ref and len(st) == len(st_ref)
+    for a, b in zip(st, st_ref):
+        print(f"library pcg {a['pcg_iters']} guard {a['pcg_guard']} step {a['step']} E {a['energy']:.6f} | "
+              f"oracle pcg {b['pcg_iters']} guard {b['pcg_guard']} step {b['eps']} E {b['E']:.6f}")
+        assert a["pcg_iters"] == b["pcg_iters"] and bool(a["pcg_guard"]) == bool(b["pcg_guard"])
+        assert a["trials"] == b["trials"] and a["step"] == b["eps"]
+        assert abs(a["energy"] - b["E"]) <= 1e-4 * abs(b["E"])
+    ev = rel(host(v), v_ref)
+    print(f"exact loop: final v0 rel {ev:.2e}")
+    assert ev < 1e-3
+
+
+def test_exact_product_symmetry_at_the_autograd_volume():
+    """160x192x160 / band 32^3 / 20 steps at a random v0 of 5 voxels: the
+    exact Gauss-Newton product on random pairs (relative asymmetry 1e-5)."""
+    from oracle.band import inner, symbol_L
+    print("\n[exact product 160x192x160]", flush=True)
+    grid, band, nt = (160, 192, 160), (32, 32, 32), 20
+    w = synth.workload(4)
+    vstar = w["v_star"]
+    prob = L().Problem(grid=grid, band=band, time_steps=nt, alpha=synth.ALPHA, s=3, sigma=synth.SIGMA,
+                       hessian=L().GN_EXACT)
+    ws = L().Workspace(prob)
+    tI0 = dev(w["I0"], torch.float32)
+    tI1 = L().shoot(dataclasses.replace(prob, hessian=L().GN_PAPER), tI0, dev(vstar, torch.complex64),
+                    L().Workspace(dataclasses.replace(prob, hessian=L().GN_PAPER)))
+    L().gradient(prob, tI0, tI1, dev(0.6 * vstar, torch.complex64), ws)
+    Lsym = symbol_L(band, synth.ALPHA, 3)
+    dirs = [synth.random_direction(600 + k, band, s=3) for k in range(4)]
+    H = [host(L().hessvec(prob, dev(d, torch.complex64), ws)) for d in dirs]
+    sym = []
+    for i, j in ((0, 1), (2, 3), (1, 2)):
+        ab, ba = inner(Lsym * dirs[i], H[j]), inner(Lsym * dirs[j], H[i])
+        sym.append(abs(ab - ba) / np.sqrt(inner(Lsym * dirs[i], H[i]) * inner(Lsym * dirs[j], H[j])))
+    print("asymmetry on random pairs", ["%.1e" % x for x in sym])
+    assert max(sym) < 1e-5

@@ -119,3 +119,15 @@ def test_paper_gradient_gap_is_reported():
     gap = np.linalg.norm(gA - gB) / np.linalg.norm(gB)
     print(f"paper gradient vs exact: relative gap {gap:.3f}")
     assert np.isfinite(gap)
+
+
+def test_exact_gauss_newton_loop_decreases_energy():
+    """The Gauss-Newton-Krylov loop with the exact gradient and its
+    (positive definite) Gauss-Newton product: CG is never stopped by the
+    curvature guard and the energy decreases at every iteration."""
+    from oracle.gn import register
+    p, I0, I1, v0, rng = problem("2d")
+    v, stats, status = register(I0, I1, p, gn_iters=4, pcg_iters=5, mode="EXACT")
+    assert status == 0
+    assert not any(s["pcg_guard"] for s in stats)
+    assert all(stats[k + 1]["E"] < stats[k]["E"] for k in range(len(stats) - 1))
