@@ -54,6 +54,28 @@ from .lie import ad, ad_dagger
 from .transport import departure_points, interpolate
 
 
+def departure_points_fp32(v, dt):
+    """Departure points formed in single precision as the library's kernels
+    form them: t = fl32(dt v_j), X_j = fl32(i_j - t N_j) with the product t N_j
+    exact (one fused multiply-add).  The cell of a departure point is an
+    integer that floating point decides; the exact derivative jumps with it
+    (the slope of the interpolant is piecewise constant), so a comparison with
+    a single-precision implementation takes that decision in single
+    precision.  Returned as float64 values."""
+    grid = v.shape[1:]
+    d = len(grid)
+    nodes = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in grid], indexing="ij")
+    out = []
+    for j in range(d):
+        t = (np.float32(dt) * v[j].astype(np.float32)).astype(np.float64)
+        out.append((nodes[j] - t * float(grid[j])).astype(np.float32).astype(np.float64))
+    return np.stack(out)
+
+
+def _departures(decisions):
+    return departure_points_fp32 if decisions == "fp32" else departure_points
+
+
 def _cells(X, shape):
     """Per axis: the lower corner index (periodic) and the fractional part."""
     base = [np.floor(X[j]) for j in range(len(shape))]
@@ -99,9 +121,12 @@ def interpolate_transpose(lam, X):
     return out.reshape(lam.shape)
 
 
-def adjoint_sweep(vs, vgrid, ms, lam_nt, p):
+def adjoint_sweep(vs, vgrid, ms, lam_nt, p, decisions="fp64"):
     """The reverse sweep above from the state adjoint lambda_nt: returns w_0
-    (V metric) and the per-step band sources S_n."""
+    (V metric) and the per-step band sources S_n.  decisions="fp32" forms the
+    departure points as a single-precision implementation does (see
+    departure_points_fp32)."""
+    dep = _departures(decisions)
     Lsym = symbol_L(p.band, p.alpha, p.s)
     Ksym = symbol_K(p.band, p.alpha, p.s)
     nN = float(np.prod(p.grid))
@@ -110,7 +135,7 @@ def adjoint_sweep(vs, vgrid, ms, lam_nt, p):
     w = np.zeros_like(vs[0])
     sources = [None] * p.nt
     for n in range(p.nt - 1, -1, -1):
-        X = departure_points(vgrid[n], p.dt)
+        X = dep(vgrid[n], p.dt)
         dEdv = -p.dt * scale * lam[None] * interpolant_gradient(ms[n], X)
         S = Ksym * nN * pi_vec(dEdv, p.band)
         sources[n] = S
@@ -119,33 +144,34 @@ def adjoint_sweep(vs, vgrid, ms, lam_nt, p):
     return w, sources
 
 
-def gradient(v0, I0, I1, p):
+def gradient(v0, I0, I1, p, decisions="fp64"):
     """V-metric gradient of the discrete energy, the energy and a cache."""
     vs, vgrid, ms = forward(v0, I0, p)
     E = energy(v0, ms[-1], I1, p)
     lam = 2.0 / (p.sigma ** 2 * float(np.prod(p.grid))) * (ms[-1] - I1)
-    w, sources = adjoint_sweep(vs, vgrid, ms, lam, p)
+    w, sources = adjoint_sweep(vs, vgrid, ms, lam, p, decisions)
     cache = dict(vs=vs, vgrid=vgrid, ms=ms, sources=sources)
     return v0 + w, E, cache
 
 
-def tangent_transport(ms, vgrid, dvgrid, dt):
+def tangent_transport(ms, vgrid, dvgrid, dt, decisions="fp64"):
     """dm_nt of the tangent of the transport steps, dm_0 = 0."""
+    dep = _departures(decisions)
     grid = ms[0].shape
     scale = np.array(grid, dtype=np.float64).reshape((len(grid),) + (1,) * len(grid))
     dm = np.zeros(grid)
     for n in range(len(vgrid)):
-        X = departure_points(vgrid[n], dt)
+        X = dep(vgrid[n], dt)
         dm = interpolate(dm, X) - dt * np.sum(scale * interpolant_gradient(ms[n], X) * dvgrid[n], axis=0)
     return dm
 
 
-def gauss_newton_hessvec(cache, dv0, p):
+def gauss_newton_hessvec(cache, dv0, p, decisions="fp64"):
     """(J^T W J + Id) dv0 in the V metric (see the module docstring)."""
     vs, vgrid, ms = cache["vs"], cache["vgrid"], cache["ms"]
     dvs = incremental_shoot(vs, dv0, p)
     dvgrid = [iota_vec(dvs[n], p.grid) for n in range(p.nt)]
-    dm = tangent_transport(ms, vgrid, dvgrid, p.dt)
+    dm = tangent_transport(ms, vgrid, dvgrid, p.dt, decisions)
     lam = 2.0 / (p.sigma ** 2 * float(np.prod(p.grid))) * dm
-    w, _ = adjoint_sweep(vs, vgrid, ms, lam, p)
+    w, _ = adjoint_sweep(vs, vgrid, ms, lam, p, decisions)
     return dv0 + w

@@ -988,6 +988,19 @@ __device__ __forceinline__ void zero_acc(floatx4* acc, int n) {
   for (int i = 0; i < n; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
+// Logical block index (x, y, z) of a launch whose workgroups the command
+// processor hands round-robin to the eight XCDs (workgroup p to XCD p % 8):
+// with the block count a multiple of 8, XCD x takes the contiguous logical
+// range [x T/8, (x + 1) T/8), so blocks that are neighbours in x (here the
+// kh of one band column and its neighbours, which share 32-byte granules of
+// the band) run on one XCD and meet in its L2.
+__device__ __forceinline__ uint3 xcd_block3() {
+  const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+  unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if (total % 8u == 0) p = (p % 8u) * (total / 8u) + p / 8u;
+  return make_uint3(p % gx, (p / gx) % gy, p / (gx * gy));
+}
+
 // Tables for the MFMA column step: w1t[x1][k1] = fwd1[k1][x1] (columns padded
 // to Kp), w0f[k0][x0] = fwd0 (rows padded to Kp), w0i[v][x0][k0] = inv0 (rows
 // padded to Mp); padding is zero.
@@ -1064,11 +1077,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   __shared__ __align__(16) float2 w0fs[Kp][LW0F];     // w0f
   __shared__ __align__(16) float2 w0is[2][Mp][LW0I];  // w0i
   float2* g0s = &s1[0][0][0];           // [N0][LG] image-grid stage-0 table, after stage 1'
-  const ColJob& job = jobs.j[blockIdx.y];
-  const int kh = blockIdx.x;
+  const uint3 lb = xcd_block3();
+  const ColJob& job = jobs.j[lb.y];
+  const int kh = lb.x;
   constexpr int T0 = Kp / 16;
-  const int kc = (blockIdx.z % T0) * 16;  // first k1 of the tile
-  const int part = blockIdx.z / T0;
+  const int kc = (lb.z % T0) * 16;  // first k1 of the tile
+  const int part = lb.z / T0;
   const int nterm = job.b ? 2 : 1;
   const bool grid0 = job.t1n != nullptr;
   const int N0 = jobs.N0;
@@ -1270,10 +1284,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   float2(*w0fs)[LW0F] = reinterpret_cast<float2(*)[LW0F]>(ra);
   float2(*w0is)[Mp][LW0I] = reinterpret_cast<float2(*)[Mp][LW0I]>(ra);
   float2* g0s = ra;
-  const ColJob& job = jobs.j[blockIdx.y];
-  const int kh = blockIdx.x;
-  const int kc = (blockIdx.z % T0) * 16;
-  const int part = blockIdx.z / T0;  // 0: padded-grid stage 0 and the store; 1: image-grid stage 0
+  const uint3 lb = xcd_block3();
+  const ColJob& job = jobs.j[lb.y];
+  const int kh = lb.x;
+  const int kc = (lb.z % T0) * 16;
+  const int part = lb.z / T0;  // 0: padded-grid stage 0 and the store; 1: image-grid stage 0
   const int N0 = jobs.N0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int k1 = kc + li;

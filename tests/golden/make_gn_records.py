@@ -18,8 +18,13 @@ the FP64 oracle and the seeded input generators:
       iterations from v0 = 0, with every iteration's record and the final
       iterate.
 
-Usage: python tests/golden/make_gn_records.py [config3|config2|all]
-(the config-3 records take tens of minutes on eight cores).
+  gn_band64.json
+      The first Gauss-Newton iteration from v0 = 0 of the 128^3 workload
+      registered with band 64^3 (padded grid 96^3) to the band-32 target, the
+      paper's band sweep: the record and its decision margins.
+
+Usage: python tests/golden/make_gn_records.py [config3|config2|all|band64]
+(the config-3 records take minutes, band 64 about an hour, on eight cores).
 """
 
 import json
@@ -138,9 +143,28 @@ def config2():
                   default=float)
 
 
+def band_sweep(band):
+    """The first Gauss-Newton iteration (from v0 = 0) of the 128^3 registration
+    of the band-32 target with another band (the paper's band sweep): the
+    record and its decision margins, no iterate."""
+    t0 = time.time()
+    p32, pp, I0, I1 = problem(3)
+    p = Params(grid=p32.grid, band=(band,) * 3, nt=p32.nt, alpha=p32.alpha, s=p32.s, sigma=p32.sigma)
+    with DecisionLog(p) as cl:
+        v, st, status = GN.register(I0, I1, p, gn_iters=1, pcg_iters=pp["pcg"], mode="R1")
+    print(f"band {band}: {st[0]}  {time.time() - t0:.0f} s", flush=True)
+    with open(os.path.join(HERE, f"gn_band{band}.json"), "w") as f:
+        json.dump({"workload": f"128^3 tissue phantom registered with band {band}^3 to the band-32 target, s = 3, "
+                               "nt = 10, mode R1, 20 CG; iteration 0 from v0 = 0",
+                   "status": status, "records": st, "curvature": cl.log, "armijo": cl.armijo}, f, indent=1,
+                  default=float)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("config2", "all"):
         config2()
     if which in ("config3", "all"):
         config3()
+    if which.startswith("band"):
+        band_sweep(int(which[4:]))

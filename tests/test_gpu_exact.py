@@ -6,7 +6,21 @@ lddmm_energy against the gradient's energy.
 
 Tolerances: gradient relative L2 1e-4 and energy 1e-5 against FP64, as for
 the paper's gradient; checkpointed against plain 1e-5 (the same arithmetic,
-except that the scatter of the state adjoint adds in a different order)."""
+except that the scatter of the state adjoint adds in a different order).
+
+The exact derivative holds the slope of the interpolant's cell at each
+departure point, and the cell is an integer that floating point decides: the
+kernels form X = i - (dt v) N in single precision.  Where a departure point
+lies within rounding of a cell face, single and double precision pick
+different cells and the exact derivative differs by a whole slope jump there.
+So the library is compared with the oracle taking its cell decisions in single
+precision as the kernels do (exact.departure_points_fp32) at 1e-5 (measured
+2e-7 to 1.3e-6: FP32 arithmetic and the order of the scatter's additions
+only), and with the all-FP64 oracle at a bar that allows
+for those decisions: the gradient 1e-4 still, the Gauss-Newton product 5e-4
+(at 64^3 / band 16^3 / 10 steps the oracle's own product moves by 1.6e-4 when
+only its cell decisions are made in single precision, the gradient by
+2.9e-5)."""
 
 import dataclasses
 
@@ -60,21 +74,27 @@ def case(request):
     I0 = w["I0"]
     I1 = forward(vstar, I0, p)[2][-1]
     v0 = 0.6 * vstar
-    g, E, _ = exact.gradient(v0, I0, I1, p)
+    g, E, cache = exact.gradient(v0, I0, I1, p)
+    g32 = v0 + exact.adjoint_sweep(cache["vs"], cache["vgrid"], cache["ms"],
+                                   2.0 / (p.sigma ** 2 * float(np.prod(p.grid))) * (cache["ms"][-1] - I1), p,
+                                   decisions="fp32")[0]
     prob = L().Problem(grid=c["grid"], band=c["band"], time_steps=c["nt"], alpha=synth.ALPHA, s=c["s"],
                        sigma=synth.SIGMA)
     args = (dev(I0, torch.float32), dev(I1, torch.float32), dev(v0, torch.complex64))
-    return dict(name=name, c=c, p=p, g=g, E=E, prob=prob, args=args, vstar=vstar, I0=I0, I1=I1)
+    return dict(name=name, c=c, p=p, g=g, g32=g32, E=E, cache=cache, prob=prob, args=args, vstar=vstar,
+                I0=I0, I1=I1)
 
 
 def test_exact_gradient_matches_oracle(case):
     ws = L().Workspace(case["prob"])
     gg, e3 = L().gradient_exact(case["prob"], *case["args"], ws)
-    eg = rel(host(gg), case["g"])
+    gh = host(gg)
+    eg, eg32 = rel(gh, case["g"]), rel(gh, case["g32"])
     e3 = host(e3)
     eE = max(abs(e3[i] - case["E"][i]) / abs(case["E"][i]) for i in range(3))
-    print(f"{case['name']}: exact gradient rel {eg:.2e}, energy rel {eE:.1e}")
-    assert eg < 1e-4 and eE < 1e-5
+    print(f"{case['name']}: exact gradient rel {eg32:.2e} (single-precision cell decisions), "
+          f"{eg:.2e} (FP64), energy rel {eE:.1e}")
+    assert eg32 < 1e-5 and eg < 1e-4 and eE < 1e-5
     e_only = host(L().energy(case["prob"], *case["args"], ws))
     assert np.max(np.abs(e_only - e3) / np.abs(e3)) < 1e-12
 
@@ -93,26 +113,29 @@ def test_checkpointed_equals_plain(case):
 
 
 def test_exact_gauss_newton_product_matches_oracle_and_is_symmetric(case):
-    """LDDMM_GN_EXACT: (J^T W J + Id) dv against the oracle (1e-4), and
-    <a, H b>_V = <b, H a>_V on random pairs (relative to sqrt(<a,Ha><b,Hb>),
-    1e-5: the product is symmetric up to FP32 rounding)."""
+    """LDDMM_GN_EXACT: (J^T W J + Id) dv against the oracle (1e-5 with the
+    cell decisions in single precision, 5e-4 all FP64; see the module doc),
+    and <a, H b>_V = <b, H a>_V on random pairs (relative to
+    sqrt(<a,Ha><b,Hb>), 1e-5: the product is symmetric up to FP32
+    rounding)."""
     from oracle.band import inner, symbol_L
     p = case["p"]
-    _, _, cache = exact.gradient(0.6 * case["vstar"], case["I0"], case["I1"], p)
+    cache = case["cache"]
     prob = dataclasses.replace(case["prob"], hessian=L().GN_EXACT)
     ws = L().Workspace(prob)
     L().gradient(prob, *case["args"], ws)
     Lsym = symbol_L(p.band, p.alpha, p.s)
     dirs = [synth.random_direction(500 + k, p.band, s=p.s) for k in range(4)]
     H = [host(L().hessvec(prob, dev(d, torch.complex64), ws)) for d in dirs]
-    ref = exact.gauss_newton_hessvec(cache, dirs[0], p)
-    e = rel(H[0], ref)
+    e = rel(H[0], exact.gauss_newton_hessvec(cache, dirs[0], p))
+    e32 = rel(H[0], exact.gauss_newton_hessvec(cache, dirs[0], p, decisions="fp32"))
     sym = []
     for i, j in ((0, 1), (2, 3), (0, 3)):
         ab, ba = inner(Lsym * dirs[i], H[j]), inner(Lsym * dirs[j], H[i])
         sym.append(abs(ab - ba) / np.sqrt(inner(Lsym * dirs[i], H[i]) * inner(Lsym * dirs[j], H[j])))
-    print(f"{case['name']}: exact Gauss-Newton product rel {e:.2e}, symmetry {['%.1e' % x for x in sym]}")
-    assert e < 1e-4 and max(sym) < 1e-5
+    print(f"{case['name']}: exact Gauss-Newton product rel {e32:.2e} (single-precision cell decisions), "
+          f"{e:.2e} (FP64), symmetry {['%.1e' % x for x in sym]}")
+    assert e32 < 1e-5 and e < 5e-4 and max(sym) < 1e-5
 
 
 def test_exact_registration_loop_matches_oracle():

@@ -131,3 +131,28 @@ def test_exact_gauss_newton_loop_decreases_energy():
     assert status == 0
     assert not any(s["pcg_guard"] for s in stats)
     assert all(stats[k + 1]["E"] < stats[k]["E"] for k in range(len(stats) - 1))
+
+
+def test_single_precision_departure_points():
+    """departure_points_fp32 rounds v, dt v and the departure point to single
+    precision (within half an ulp of X plus 2^-23 of the displacement of the
+    FP64 point) and leaves every
+    derivative of the oracle a derivative of its energy: at FP64 departure
+    points everything above holds; with FP32 ones only the cell decisions of
+    a few points move (the gradient by 1e-5-1e-4 here)."""
+    from oracle.transport import departure_points
+    p, I0, I1, v0, rng = problem("3d")
+    vg = forward(v0, I0, p)[1][0]
+    X64 = departure_points(vg, p.dt)
+    X32 = exact.departure_points_fp32(vg, p.dt)
+    nodes = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in p.grid], indexing="ij"))
+    ulp = np.spacing(np.abs(X64).astype(np.float32)).astype(np.float64)
+    bound = 0.5 * ulp + 2.0 ** -23 * np.abs(X64 - nodes) * 1.01
+    assert np.all(np.abs(X32 - X64) <= bound)
+    assert np.any(X32 != X64)
+    assert np.all(X32 == X32.astype(np.float32))
+    g64, _, _ = exact.gradient(v0, I0, I1, p)
+    g32, _, _ = exact.gradient(v0, I0, I1, p, decisions="fp32")
+    gap = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    print(f"FP32 cell decisions move the exact gradient by {gap:.1e}")
+    assert gap < 1e-3
