@@ -13,7 +13,11 @@ the timed region.
 ``--state deformation`` registers the same images subject to the deformation
 state equation (paper §3.3) instead of the image state (paper §3.2).
 ``--batch N`` measures instead the atlas-serving batch: N independent pairs of
-different sizes in one lddmm_register_batch call (aggregate HVP/s).
+different sizes in one lddmm_register_batch call (aggregate HVP/s), all
+driven from one host thread; ``--graphs`` replays each pair's captured
+sequences.  Before the timed region the tile autotuner (lddmm_autotune)
+picks the launch shapes of each problem shape, or ``--tiles FILE`` loads a
+table (``--no-autotune``: the built-in rule); the choice is in the JSON line.
 
 Prints one JSON line on stdout (everything else goes to stderr).
 """
@@ -52,6 +56,11 @@ def parse():
     ap.add_argument("--batch", type=int, default=0,
                     help="measure the atlas-serving batch of this many pairs (lddmm_register_batch) instead")
     ap.add_argument("--concurrency", type=int, default=0, help="pairs running at a time in --batch (0: default)")
+    ap.add_argument("--graphs", action="store_true", help="graph replay of the registration loops' sequences")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the tile autotuner before the timed region (built-in launch shapes)")
+    ap.add_argument("--tiles", default=None, help="load this tile table (JSON) instead of autotuning")
+    ap.add_argument("--tiles-out", default=None, help="write the tile table used to this JSON file")
     ap.add_argument("--band", type=int, default=0,
                     help="register with this band size instead of 32 (the band sweep of the paper's experiment; "
                          "the target stays the one made with band 32)")
@@ -288,6 +297,33 @@ def dominant_family(L, run):
     return max(fam_ms, key=fam_ms.get)
 
 
+def select_tiles(args, L, jobs):
+    """The launch shapes of the timed region: the tile table loaded from
+    --tiles, else the autotuner's choice for each problem shape (one untimed
+    tuning run per shape, on its first job: (problem, I0, I1, v0, ws)), else
+    the built-in rule.  Returns what was chosen, per shape."""
+    out = {}
+    if args.tiles:
+        L.tiles_load(args.tiles)
+        for prob, *_ in jobs:
+            out["x".join(map(str, prob.grid)) + f"/{prob.band[0]}"] = {"chosen": L.tiles_get(prob),
+                                                                       "from": args.tiles}
+    elif not args.no_autotune:
+        seen = set()
+        for prob, I0, I1, v0, ws in jobs:
+            key = (prob.grid, prob.band, prob.precision)
+            if key in seen:
+                continue
+            seen.add(key)
+            best, ms_b, ms_d = L.autotune(prob, I0, I1, v0, ws, reps=10)
+            name = "x".join(map(str, prob.grid)) + f"/{prob.band[0]}"
+            log(f"autotune {name}: {best}, {ms_b:.3f} ms per product (built-in rule {ms_d:.3f} ms)")
+            out[name] = {"chosen": best, "ms_per_hvp": ms_b, "built_in_ms_per_hvp": ms_d}
+    if args.tiles_out:
+        L.tiles_save(args.tiles_out)
+    return out or None
+
+
 def batch_main(args):
     """The atlas-serving batch: independent registrations of different sizes
     in one lddmm_register_batch call."""
@@ -308,9 +344,18 @@ def batch_main(args):
         I0s.append(I0)
         I1s.append(I1)
     gn, pcg = synth.BATCH["gn"], synth.BATCH["pcg"]
+    tune = []
+    for w, prob, I0, I1 in zip(work, probs, I0s, I1s):
+        if any(q.grid == prob.grid and q.band == prob.band for q, *_ in tune):
+            continue
+        v0 = torch.from_numpy(0.5 * w["v_star"]).to(torch.complex64).to(dev)
+        tune.append((prob, I0, I1, v0, L.Workspace(prob, dev)))
+    tiles = select_tiles(args, L, tune)
+    del tune
     ws = L.BatchWorkspace(probs, dev)
     torch.cuda.synchronize()
     log(f"batch ready: {len(probs)} pairs, workspace {ws.nbytes / 2**30:.2f} GiB")
+    L.use_graphs(bool(args.graphs))
 
     def run():
         return L.register_batch(probs, I0s, I1s, ws, gn_iters=gn, pcg_iters=pcg, concurrency=args.concurrency)
@@ -363,7 +408,9 @@ def batch_main(args):
                         f"{gn} Gauss-Newton x {pcg} CG iterations each, lddmm_register_batch",
             "pairs": [[list(q.grid), q.band[0]] for q in probs],
             "concurrency": args.concurrency or 8,
+            "driver": "one host thread resuming every pair's loop" + (", graph replay" if args.graphs else ""),
         },
+        "tiles": tiles,
         "registrations_per_min": 60.0 * args.steps * len(probs) / T,
         "value_without_timer_events": hvps_u / T_u,
         "final_mse_rel_mean": float(np.mean([s[-1]["mse_rel"] for s in stats])),
@@ -434,6 +481,8 @@ def main():
     I1 = L.shoot(prob_img, I0, vstar, L.Workspace(prob_img, dev))
     torch.cuda.synchronize()
     log(f"workload ready: grid {prob.grid} band {prob.band} ws {ws.nbytes / 2**20:.0f} MiB")
+    tiles = select_tiles(args, L, [(prob, I0, I1, 0.5 * vstar, ws)])
+    L.use_graphs(bool(args.graphs))
 
     def registration():
         return L.register(prob, I0, I1, ws, gn_iters=gn, pcg_iters=pcg)
@@ -613,6 +662,8 @@ def main():
         "final_mse_rel": stats[-1]["mse_rel"] if stats else None,
         "final_grad_inf_rel": stats[-1]["grad_inf_rel"] if stats else None,
         "workspace_mib": ws.nbytes / 2**20,
+        "tiles": tiles,
+        "graphs": bool(args.graphs),
         "roofline": roofline(dominant, name, launches, kms, kfl, kby, stored_traffic(name)),
         "cpu_baseline": cpu,
     }

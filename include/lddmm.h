@@ -326,10 +326,17 @@ int lddmm_batch_workspace_bytes(int32_t n, const lddmm_params* p, size_t* bytes)
  * (sizes, band, state and Hessian mode may differ), images I0[i], I1[i] and
  * iterate v0_inout[i], and runs exactly the loop of lddmm_register, so its
  * results equal those of lddmm_register on the same inputs.  Up to
- * `concurrency` pairs run at a time (0 selects 8), each from its own host
- * thread on one library stream of its own (a pair's grid chain follows its
- * band chain on that stream), so that the launches of different pairs share
- * the compute units; pairs start largest first (by workspace size).
+ * `concurrency` pairs run at a time (0 selects 8), each on one library stream
+ * of its own (a pair's grid chain follows its band chain on that stream), so
+ * that the launches of different pairs share the compute units; pairs start
+ * largest first (by workspace size).  The calling thread drives every pair:
+ * each pair's loop is suspended while it waits for a value from the device
+ * and resumed once that value is there, so no pair's host work waits for
+ * another's device work.  With lddmm_use_graphs(1) each pair replays its
+ * captured sequences (Gauss-Newton head, CG iteration, line-search trials);
+ * pair i takes the i-th block of pinned host words from the library's pool
+ * (allocated on first use, kept until the process ends), so a repeated call
+ * on the same workspace replays the graphs of the previous one.
  *   n          1 <= n <= 4096
  *   p, I0, I1, v0_inout   host arrays of n entries; the images and iterates are
  *              device buffers laid out as for lddmm_register
@@ -388,8 +395,8 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, 
  * Captures run one at a time across host threads (the pairs of
  * lddmm_register_batch capture their own graphs in turn).  The CG iteration's
  * graph also holds the calling thread's pinned host words (see
- * lddmm_register), so each block of words has its own; the worker threads of
- * successive batched calls reuse the blocks and therefore the graphs.  The
+ * lddmm_register), so each block of words has its own; successive batched
+ * calls give pair i the same block and therefore the same graphs.  The
  * graphs are keyed by the state and integrator too, so calls on one
  * workspace that differ only in those never share a graph.  The captured graphs hold workspace addresses: a workspace that is freed
  * and reallocated at the same address with the same problem reuses them,
@@ -397,6 +404,61 @@ int lddmm_kernel_timer_read(int64_t* launches, double* total_ms, double* flops, 
  * until the process ends.  `enable` must be 0 or 1 (else
  * LDDMM_E_INVALID_ARG).  Process-wide; host only. */
 int lddmm_use_graphs(int32_t enable);
+
+/* Launch shapes of three kernel families for one problem shape (the tile
+ * table).  They change which thread blocks compute what, never the
+ * arithmetic of an output: results are bitwise those of the built-in rule.
+ *   prod_rows   padded-grid rows per block of the pointwise Lie products
+ *               (1 .. floor(256 / M2), capped at M1; 0: the largest)
+ *   col_split   band column steps: 0 the built-in rule, 1 one block per
+ *               column tile, 2 two blocks per tile sharing its next-stage
+ *               outputs, 3 as 2 with the lean kernel for the forward
+ *               sweeps where the shape has one (bands 24^3 and 32^3)
+ *   sl_threads  threads per block of the semi-Lagrangian transport step:
+ *               64, 128 or 256 (0: 256) */
+typedef struct {
+  int32_t prod_rows;
+  int32_t col_split;
+  int32_t sl_threads;
+} lddmm_tiles;
+
+/* The tile table: one entry per (grid, band, spectral grid, precision,
+ * arch), e.g. arch "gfx950".  Every call reads the entry for its parameters
+ * on the current device, if any; else the built-in rule applies.
+ * lddmm_tiles_set: sets the entry for p's shape and precision (the other
+ * fields of p are only validated); arch NULL names the current device's.
+ * LDDMM_E_INVALID_ARG for fields out of range.
+ * lddmm_tiles_get: *found = 1 and the entry, or *found = 0 and zeros.
+ * lddmm_tiles_clear: empties the table.
+ * lddmm_tiles_save / lddmm_tiles_load: the table as a JSON file
+ *   {"format": "lddmm-tiles-1", "entries": [{"arch": "gfx950",
+ *    "grid": [N0, N1, N2], "band": [K0, K1, K2], "spectral": [M0, M1, M2],
+ *    "precision": "fp32" | "bf16x3", "prod_rows": r, "col_split": c,
+ *    "sl_threads": t, "ms_per_hvp": x}, ...]}
+ * (load merges into the table; every entry is validated before any is
+ * taken, and a malformed file changes nothing and returns
+ * LDDMM_E_INVALID_ARG).  Process-wide, thread-safe; host only. */
+int lddmm_tiles_set(const lddmm_params* p, const char* arch, const lddmm_tiles* t);
+int lddmm_tiles_get(const lddmm_params* p, const char* arch, lddmm_tiles* t, int32_t* found);
+int lddmm_tiles_clear(void);
+int lddmm_tiles_save(const char* path);
+int lddmm_tiles_load(const char* path);
+
+/* Autotuner of the tile table for one problem (the Hessian-vector product of
+ * §2.7's CG is the measure): runs the gradient at v0 with the built-in rule
+ * (leaving ws prepared for lddmm_hessvec, as lddmm_gradient does), then times
+ * `reps` products (direction v0, after one untimed product) for the built-in
+ * rule and for each candidate of one field at a time (sl_threads 64, 128;
+ * prod_rows 1 .. max - 1; col_split 1, 2, 3), keeping a candidate when it is
+ * at least 1 % faster than the choice so far.  The winner is stored in the
+ * table for p's shape on the current device and returned in *best, its time
+ * per product (ms) in *ms_best and the built-in rule's in *ms_default (each
+ * may be NULL).  Synchronous.
+ *   I0, I1  [N0][N1][N2] float32 (device, read); v0 [3][K0][K1][K2]
+ *           complex64 (device, read); 1 <= reps <= 1000 */
+int lddmm_autotune(const lddmm_params* p, const float* I0, const float* I1, const void* v0, int32_t reps,
+                   lddmm_tiles* best, double* ms_best, double* ms_default, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* Static description of a status code. */
 const char* lddmm_status_string(int code);

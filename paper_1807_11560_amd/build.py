@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "liblddmm.so")
 SOURCES = ["kernels.hip", "engine.hip", "abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++20", "-fPIC", "-shared", "--offload-arch=gfx950",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -7,13 +7,14 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <coroutine>
 #include <cstdio>
 #include <cstring>
 #include <functional>
 #include <map>
 #include <mutex>
 #include <string>
-#include <thread>
+#include <memory>
 #include <vector>
 
 #include "engine.h"
@@ -59,9 +60,236 @@ void set_prepared(const void* ws, bool prepared, const Dims& d) {
   r.dims = d;
 }
 
+// ---------------------------------------------------------------- tile table
+// Launch shapes per (grid, band, spectral grid, precision, arch): set by
+// lddmm_tiles_set / lddmm_autotune / lddmm_tiles_load, read when a call's
+// parameters are validated.
+struct TileKey {
+  int N[3], K[3], M[3], prec;
+  std::string arch;
+  bool operator<(const TileKey& o) const {
+    const int a[10] = {N[0], N[1], N[2], K[0], K[1], K[2], M[0], M[1], M[2], prec};
+    const int b[10] = {o.N[0], o.N[1], o.N[2], o.K[0], o.K[1], o.K[2], o.M[0], o.M[1], o.M[2], o.prec};
+    for (int i = 0; i < 10; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return arch < o.arch;
+  }
+};
+struct TileEntry {
+  lddmm_tiles t{};
+  double ms = 0.0;  // the autotuner's time per Hessian-vector product (0: not measured)
+};
+std::mutex g_tiles_mu;
+std::map<TileKey, TileEntry> g_tiles;
+std::atomic<bool> g_tiles_any{false};
+
+// Architecture name of the current device ("gfx950"), "" without one.
+std::string current_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "";
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string name;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    name = prop.gcnArchName;
+    name = name.substr(0, name.find(':'));
+  } else {
+    (void)hipGetLastError();
+  }
+  names[dev] = name;
+  return name;
+}
+
+TileKey tile_key(const Dims& d, const std::string& arch) {
+  TileKey k;
+  for (int j = 0; j < 3; ++j) {
+    k.N[j] = d.N[j];
+    k.K[j] = d.K[j];
+    k.M[j] = d.M[j];
+  }
+  k.prec = d.prec;
+  k.arch = arch;
+  return k;
+}
+
+int check_tiles(const Dims& d, const lddmm_tiles& t) {
+  if (t.prod_rows < 0 || t.prod_rows > prod_rows_max(d))
+    return fail(LDDMM_E_INVALID_ARG, "prod_rows must be in [0, " + std::to_string(prod_rows_max(d)) + "]");
+  if (t.col_split < 0 || t.col_split > 3) return fail(LDDMM_E_INVALID_ARG, "col_split must be in [0, 3]");
+  if (t.sl_threads != 0 && t.sl_threads != 64 && t.sl_threads != 128 && t.sl_threads != 256)
+    return fail(LDDMM_E_INVALID_ARG, "sl_threads must be 0, 64, 128 or 256");
+  return LDDMM_OK;
+}
+
+void apply_tiles(Dims& d) {
+  if (!g_tiles_any.load()) return;
+  const std::string arch = current_arch();
+  if (arch.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  auto it = g_tiles.find(tile_key(d, arch));
+  if (it == g_tiles.end()) return;
+  d.tile_prod_rows = it->second.t.prod_rows;
+  d.tile_col = it->second.t.col_split;
+  d.tile_sl = it->second.t.sl_threads;
+}
+
+// ---- the table as JSON: {"format": "lddmm-tiles-1", "entries": [{"arch":
+// "gfx950", "grid": [..], "band": [..], "spectral": [..], "precision":
+// "fp32"|"bf16x3", "prod_rows": r, "col_split": c, "sl_threads": t,
+// "ms_per_hvp": x}, ...]}.  The reader takes that form (any key order, extra
+// keys ignored) and nothing else of JSON.
+struct JsonValue {
+  enum Kind { NUL, NUM, STR, ARR, OBJ, BOOL } kind = NUL;
+  double num = 0.0;
+  std::string str;
+  std::vector<JsonValue> arr;
+  std::vector<std::pair<std::string, JsonValue>> obj;
+  const JsonValue* get(const char* key) const {
+    for (auto& kv : obj)
+      if (kv.first == key) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct JsonReader {
+  const std::string& s;
+  size_t i = 0;
+  int depth = 0;
+  explicit JsonReader(const std::string& text) : s(text) {}
+  void ws() {
+    while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r')) ++i;
+  }
+  bool str(std::string* out) {
+    if (i >= s.size() || s[i] != '"') return false;
+    ++i;
+    out->clear();
+    while (i < s.size() && s[i] != '"') {
+      if (s[i] == '\\') {
+        if (++i >= s.size()) return false;
+        const char c = s[i];
+        if (c != '"' && c != '\\' && c != '/') return false;
+        out->push_back(c);
+      } else {
+        out->push_back(s[i]);
+      }
+      ++i;
+    }
+    if (i >= s.size()) return false;
+    ++i;
+    return true;
+  }
+  bool value(JsonValue* v) {
+    ws();
+    if (i >= s.size() || ++depth > 8) return false;
+    bool ok = false;
+    const char c = s[i];
+    if (c == '{') {
+      v->kind = JsonValue::OBJ;
+      ++i;
+      ws();
+      if (i < s.size() && s[i] == '}') {
+        ++i;
+        ok = true;
+      } else {
+        for (;;) {
+          ws();
+          std::string key;
+          JsonValue val;
+          if (!str(&key)) break;
+          ws();
+          if (i >= s.size() || s[i] != ':') break;
+          ++i;
+          if (!value(&val)) break;
+          v->obj.emplace_back(key, std::move(val));
+          ws();
+          if (i < s.size() && s[i] == ',') {
+            ++i;
+            continue;
+          }
+          if (i < s.size() && s[i] == '}') {
+            ++i;
+            ok = true;
+          }
+          break;
+        }
+      }
+    } else if (c == '[') {
+      v->kind = JsonValue::ARR;
+      ++i;
+      ws();
+      if (i < s.size() && s[i] == ']') {
+        ++i;
+        ok = true;
+      } else {
+        for (;;) {
+          JsonValue val;
+          if (!value(&val)) break;
+          v->arr.push_back(std::move(val));
+          ws();
+          if (i < s.size() && s[i] == ',') {
+            ++i;
+            continue;
+          }
+          if (i < s.size() && s[i] == ']') {
+            ++i;
+            ok = true;
+          }
+          break;
+        }
+      }
+    } else if (c == '"') {
+      v->kind = JsonValue::STR;
+      ok = str(&v->str);
+    } else if (s.compare(i, 4, "null") == 0) {
+      v->kind = JsonValue::NUL;
+      i += 4;
+      ok = true;
+    } else if (s.compare(i, 4, "true") == 0 || s.compare(i, 5, "false") == 0) {
+      v->kind = JsonValue::BOOL;
+      v->num = s[i] == 't';
+      i += s[i] == 't' ? 4 : 5;
+      ok = true;
+    } else {
+      const char* b = s.c_str() + i;
+      char* e = nullptr;
+      v->kind = JsonValue::NUM;
+      v->num = std::strtod(b, &e);
+      ok = e != b && std::isfinite(v->num);
+      i += (size_t)(e - b);
+    }
+    --depth;
+    return ok;
+  }
+};
+
+bool json_int3(const JsonValue* v, int out[3]) {
+  if (!v || v->kind != JsonValue::ARR || v->arr.size() != 3) return false;
+  for (int j = 0; j < 3; ++j) {
+    const JsonValue& x = v->arr[j];
+    if (x.kind != JsonValue::NUM || x.num != (double)(int)x.num) return false;
+    out[j] = (int)x.num;
+  }
+  return true;
+}
+
+bool json_int(const JsonValue* v, int* out) {
+  if (!v || v->kind != JsonValue::NUM || v->num != (double)(int)v->num) return false;
+  *out = (int)v->num;
+  return true;
+}
+
 int validate(const lddmm_params* p, Dims* d) {
   if (!p) return fail(LDDMM_E_INVALID_ARG, "params is NULL");
-  if (p->ndim != 3) return fail(LDDMM_E_SHAPE, "only ndim == 3 is supported");
+  if (p->ndim != 3)
+    return fail(LDDMM_E_SHAPE, p->ndim == 2 ? "two-dimensional problems are taken by the single-problem entry points only"
+                                            : "ndim must be 2 or 3");
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha))
     return fail(LDDMM_E_INVALID_ARG, "alpha must be positive");
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma))
@@ -119,6 +347,7 @@ int validate(const lddmm_params* p, Dims* d) {
     return fail(LDDMM_E_SHAPE, "band/padded grid too large for the step kernel's LDS tile");
   if (gridstep_shared_bytes(o) > kMaxLds || src_shared_bytes(o) > kMaxLds)
     return fail(LDDMM_E_SHAPE, "grid rows too long for the grid kernels' LDS tile");
+  apply_tiles(o);
   return LDDMM_OK;
 }
 
@@ -305,6 +534,9 @@ std::string graph_key(const Engine& e, const void* ws, int kind, std::initialize
   put(&d.integrator, sizeof d.integrator);
   put(&d.prec, sizeof d.prec);
   put(&d.ckpt, sizeof d.ckpt);
+  put(&d.tile_prod_rows, sizeof d.tile_prod_rows);
+  put(&d.tile_col, sizeof d.tile_col);
+  put(&d.tile_sl, sizeof d.tile_sl);
   for (const void* p : ext) put(&p, sizeof p);
   return k;
 }
@@ -480,44 +712,143 @@ hipError_t wait_host_flag(double* hf, hipStream_t st) {
   }
 }
 
-// out[0 .. na + nb) = a[0 .. na), b[0 .. nb) (device memory, na + nb < 64),
-// read once the work enqueued on st so far has finished.
-hipError_t read_back(double* out, const double* a, int na, const double* b, int nb, hipStream_t st) {
-  hipError_t r;
-  double* hf = host_words();
-  if (!hf) {
-    if ((r = hipMemcpyAsync(out, a, na * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
-    if (nb && (r = hipMemcpyAsync(out + na, b, nb * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
-    return hipStreamSynchronize(st);
+// ------------------------------------------------------ resumable loop
+// The Gauss-Newton-Krylov loop is a C++ coroutine that enqueues device work
+// and suspends wherever it needs a value back from the device (the energy
+// and |g| of an iteration, the CG stop flag, the CG scalars, a trial's
+// energy).  lddmm_register resumes it by waiting for each value in turn; the
+// batch resumes many of them from one host thread, polling whichever pairs
+// have a value ready, so that no pair's host work waits for another's device
+// work.  What a suspended loop waits for: hf[0] set by the stream's last
+// kernel (hf non-null), or the stream finished (hf null).
+struct DeviceWait {
+  double* hf = nullptr;
+  hipStream_t st = nullptr;
+};
+
+struct RegTask {
+  struct promise_type {
+    int result = LDDMM_OK;
+    DeviceWait wait;
+    hipError_t wait_result = hipSuccess;
+    RegTask get_return_object() { return RegTask{std::coroutine_handle<promise_type>::from_promise(*this)}; }
+    std::suspend_always initial_suspend() noexcept { return {}; }
+    std::suspend_always final_suspend() noexcept { return {}; }
+    void return_value(int r) { result = r; }
+    void unhandled_exception() { result = LDDMM_E_HIP; }
+  };
+  using handle = std::coroutine_handle<promise_type>;
+  handle h;
+  RegTask() = default;
+  explicit RegTask(handle hh) : h(hh) {}
+  RegTask(RegTask&& o) noexcept : h(o.h) { o.h = nullptr; }
+  RegTask& operator=(RegTask&& o) noexcept {
+    if (this != &o) {
+      if (h) h.destroy();
+      h = o.h;
+      o.h = nullptr;
+    }
+    return *this;
   }
-  volatile double* f = hf;
-  f[0] = 0.0;
-  if ((r = launch_host_copy(a, na, b, nb, hf, st))) return r;
-  if ((r = wait_host_flag(hf, st))) return r;
-  for (int i = 0; i < na + nb; ++i) out[i] = f[1 + i];
-  return hipSuccess;
+  RegTask(const RegTask&) = delete;
+  ~RegTask() {
+    if (h) h.destroy();
+  }
+  bool done() const { return !h || h.done(); }
+  int result() const { return h.promise().result; }
+};
+
+// co_await DeviceReady{hf, st}: suspends the loop until the wait is over and
+// yields the wait's status.
+struct DeviceReady {
+  DeviceWait w;
+  RegTask::handle h{};
+  bool await_ready() const noexcept { return false; }
+  void await_suspend(RegTask::handle hh) noexcept {
+    h = hh;
+    hh.promise().wait = w;
+  }
+  hipError_t await_resume() const noexcept { return h.promise().wait_result; }
+};
+
+DeviceReady until(double* hf, hipStream_t st) { return DeviceReady{DeviceWait{hf, st}}; }
+
+// Non-blocking test of a wait: true when it is over (status in *r).
+bool wait_over(const DeviceWait& w, hipError_t* r, bool query_stream) {
+  if (w.hf && static_cast<volatile double*>(w.hf)[0] != 0.0) {
+    *r = hipSuccess;
+    return true;
+  }
+  if (!query_stream) return false;
+  const hipError_t q = hipStreamQuery(w.st);
+  if (q == hipErrorNotReady) return false;
+  if (q != hipSuccess) {
+    *r = q;
+    return true;
+  }
+  *r = (!w.hf || static_cast<volatile double*>(w.hf)[0] != 0.0) ? hipSuccess : hipErrorUnknown;
+  return true;
 }
 
-int run_register(Engine& e, const void* ws, const float* I0, const float* I1, void* v0_inout,
-                 int gn_iters, int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps) {
+// Resumes a loop to its end on the calling thread, waiting for each value.
+int run_to_end(RegTask& t) {
+  t.h.resume();
+  while (!t.h.done()) {
+    auto& pr = t.h.promise();
+    pr.wait_result = pr.wait.hf ? wait_host_flag(pr.wait.hf, pr.wait.st) : hipStreamSynchronize(pr.wait.st);
+    t.h.resume();
+  }
+  return t.result();
+}
+
+// Enqueues the copy of a[0 .. na), b[0 .. nb) (device) to the host: to
+// hf[1 ..] with hf[0] set last when hf is non-null (hf[0] cleared here),
+// else to fb by copy commands; then the loop awaits DeviceWait{hf, st} and
+// reads the values with read_values.
+hipError_t read_enqueue(double* hf, double* fb, const double* a, int na, const double* b, int nb, hipStream_t st) {
+  hipError_t r;
+  if (hf) {
+    static_cast<volatile double*>(hf)[0] = 0.0;
+    return launch_host_copy(a, na, b, nb, hf, st);
+  }
+  if ((r = hipMemcpyAsync(fb, a, na * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
+  if (nb && (r = hipMemcpyAsync(fb + na, b, nb * sizeof(double), hipMemcpyDeviceToHost, st))) return r;
+  return hipSuccess;
+}
+void read_values(double* out, const double* hf, const double* fb, int n) {
+  const volatile double* src = hf ? static_cast<const volatile double*>(hf + 1) : fb;
+  for (int i = 0; i < n; ++i) out[i] = src[i];
+}
+
+// The Gauss-Newton-Krylov loop (see lddmm_register).  hf: the pinned host
+// words of this loop (or null: copy commands instead).
+RegTask register_loop(Engine& e, const void* ws, const float* I0, const float* I1, void* v0_inout, int gn_iters,
+                      int pcg_iters, lddmm_stats* stats, int stats_len, int64_t* hvps, double* hf) {
   const Dims& d = e.dims();
   hipStream_t st = e.stream();
   const int n = 3 * d.nb;
   const double c1 = 1e-4;
   const int max_trials = 10;
   hipError_t err;
-#define HTRY(x)                                  \
-  do {                                           \
-    err = (x);                                   \
-    if (err != hipSuccess) return hip_fail(err, #x); \
+  double fb[kHostWords];  // values read by copy commands when hf is null
+#define HTRY(x)                                     \
+  do {                                              \
+    err = (x);                                      \
+    if (err != hipSuccess) co_return hip_fail(err, #x); \
+  } while (0)
+  // out[0 .. na + nb) = a[0 .. na), b[0 .. nb) once the work enqueued so far has finished
+#define READ_BACK(out, a, na, b, nb)                        \
+  do {                                                      \
+    HTRY(read_enqueue(hf, fb, (a), (na), (b), (nb), st));   \
+    HTRY(co_await until(hf, st));         \
+    read_values((out), hf, fb, (na) + (nb));                \
   } while (0)
   HTRY(e.init_tables());
   HTRY(e.load_band(v0_inout, e.v0h));
   // ||I0 - I1||^2 for MSE_rel
   HTRY(launch_sqdiff(I0, I1, d.nN, e.partial, e.scal + 8, 1.0, st));
   double denom = 0.0;
-  HTRY(hipMemcpyAsync(&denom, e.scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
-  HTRY(hipStreamSynchronize(st));
+  READ_BACK(&denom, e.scal + 8, 1, nullptr, 0);
   double g0_inf = -1.0;
   int status = LDDMM_OK;
   // the accepted line-search trial of the previous iteration ran the caching
@@ -539,15 +870,14 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     }));
     kept = false;
     double sc[4];
-    HTRY(read_back(sc, e.scal, 4, nullptr, 0, st));
+    READ_BACK(sc, e.scal, 4, nullptr, 0);
     if (!std::isfinite(sc[0]) || !std::isfinite(sc[3]))
-      return fail(LDDMM_E_NONFINITE, "energy or gradient is not finite");
+      co_return fail(LDDMM_E_NONFINITE, "energy or gradient is not finite");
     if (g0_inf < 0) g0_inf = sc[3];
     // CG in the V metric on H_V p = -g_V
     HTRY(launch_pcg_init(e.gh, e.ph, e.rh, e.dh, n, st));
     HTRY(launch_band_dot(e.rh, e.rh, e.Lsym, d, e.partial, e.pcg + SC_RR, 1.0, st));
     HTRY(launch_pcg_reset(e.pcg, st));
-    double* hf = host_words();
     const std::string iter_key = graph_key(e, ws, GK_PCG_ITER, {hf});
     for (int k = 0; k < pcg_iters; ++k) {
       if (hf) static_cast<volatile double*>(hf)[0] = 0.0;
@@ -568,11 +898,12 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
       ++*hvps;
       double stopped = 0.0;
       if (hf) {
-        HTRY(wait_host_flag(hf, st));
+        HTRY(co_await until(hf, st));
         stopped = static_cast<volatile double*>(hf)[1];
       } else {
-        HTRY(hipMemcpyAsync(&stopped, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
-        HTRY(hipStreamSynchronize(st));
+        HTRY(hipMemcpyAsync(fb, e.pcg + SC_STOPPED, sizeof(double), hipMemcpyDeviceToHost, st));
+        HTRY(co_await until(nullptr, st));
+        stopped = fb[0];
       }
       if (stopped != 0.0) break;
     }
@@ -580,12 +911,12 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     // descent direction
     double pc[SC_COUNT + 1];
     HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
-    HTRY(read_back(pc, e.pcg, SC_COUNT, e.scal + 4, 1, st));
+    READ_BACK(pc, e.pcg, SC_COUNT, e.scal + 4, 1);
     double slope = pc[SC_COUNT];
     if (!(slope < 0.0)) {
       HTRY(launch_axpy_band(e.tmph, e.gh, -1.f, e.ph, n, st));  // tmph is zero-filled below
       HTRY(launch_band_dot(e.gh, e.ph, e.Lsym, d, e.partial, e.scal + 4, 1.0, st));
-      HTRY(read_back(&slope, e.scal + 4, 1, nullptr, 0, st));
+      READ_BACK(&slope, e.scal + 4, 1, nullptr, 0);
     }
     // Armijo backtracking
     double eps = 1.0, Etry = 0.0;
@@ -605,7 +936,7 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
         if ((r = e.forward(I0))) return r;
         return e.energy(e.final_state(), I1);
       }));
-      HTRY(read_back(&Etry, e.scal, 1, nullptr, 0, st));
+      READ_BACK(&Etry, e.scal, 1, nullptr, 0);
       if (std::isfinite(Etry) && Etry <= sc[0] + c1 * eps * slope) {
         ok = true;
         break;
@@ -633,16 +964,92 @@ int run_register(Engine& e, const void* ws, const float* I0, const float* I1, vo
     kept = true;
   }
   HTRY(e.store_band(e.v0h, nullptr, 0.f, v0_inout));
-  HTRY(hipStreamSynchronize(st));
-  return status;
+  HTRY(co_await until(nullptr, st));
+  co_return status;
+#undef READ_BACK
 #undef HTRY
 }
+
+// ------------------------------------------------ two-dimensional problems
+// A problem on the plane (paper §3.1 with d = 2: grid N0 x N1, band K0 x K1,
+// two velocity components) runs as the three-dimensional problem on
+// kDepthN x N0 x N1 with band kDepthK x K0 x K1 whose fields do not depend on
+// the new first coordinate: images repeated over the planes, band fields in
+// components 1 and 2 at first-axis frequency 0.  That problem is the planar
+// one exactly: every product, derivative and symbol of such fields keeps them
+// independent of the first coordinate (the derivative along it and the
+// first velocity component stay zero, the symbols at k = (0, k0, k1) are the
+// planar ones), and the energy's mean over voxels and its band inner product
+// are unchanged.  In floating point the forward transforms along the first
+// axis leave rounding-level values at its nonzero frequencies, which the
+// results do not read.  The staging buffers sit after the three-dimensional
+// workspace in ws.
+constexpr int kDepthN = 8, kDepthK = 4;
+
+void lift2d(const lddmm_params* p, lddmm_params* q) {
+  *q = *p;
+  q->ndim = 3;
+  q->grid[0] = kDepthN;
+  q->grid[1] = p->grid[0];
+  q->grid[2] = p->grid[1];
+  q->band[0] = kDepthK;
+  q->band[1] = p->band[0];
+  q->band[2] = p->band[1];
+  q->spectral[0] = 0;
+  q->spectral[1] = p->spectral[0];
+  q->spectral[2] = p->spectral[1];
+}
+
+struct Stage2D {
+  lddmm_params q;
+  size_t ws3 = 0, total = 0;
+  long long plane = 0, plane2 = 0;  // N0 N1 and K0 K1
+  float *I0e = nullptr, *I1e = nullptr;  // [kDepthN][N0][N1]
+  float2 *A = nullptr, *B = nullptr;     // [3][kDepthK][K0][K1]
+};
+
+// Sizes (and, with ws, the buffers) of a planar problem's staging.
+int stage2d(const lddmm_params* p, void* ws, size_t ws_bytes, Stage2D* s) {
+  lift2d(p, &s->q);
+  Dims d;
+  int rc = validate(&s->q, &d);
+  if (rc) return rc;
+  s->ws3 = batch_slice(Engine::workspace_bytes(d));
+  s->plane = (long long)d.N[1] * d.N[2];
+  s->plane2 = (long long)d.K[1] * d.K[2];
+  const size_t img = batch_slice((size_t)kDepthN * s->plane * sizeof(float));
+  const size_t band = batch_slice((size_t)3 * kDepthK * s->plane2 * sizeof(float2));
+  s->total = s->ws3 + 2 * img + 2 * band;
+  if (!ws) return LDDMM_OK;
+  if (ws_bytes < s->total)
+    return fail(LDDMM_E_WORKSPACE, "workspace too small: need " + std::to_string(s->total) + " bytes");
+  char* b = static_cast<char*>(ws) + s->ws3;
+  s->I0e = reinterpret_cast<float*>(b);
+  s->I1e = reinterpret_cast<float*>(b + img);
+  s->A = reinterpret_cast<float2*>(b + 2 * img);
+  s->B = reinterpret_cast<float2*>(b + 2 * img + band);
+  return LDDMM_OK;
+}
+
+#define TRY2D(x)                                   \
+  do {                                             \
+    const hipError_t e2 = (x);                     \
+    if (e2 != hipSuccess) return hip_fail(e2, #x); \
+  } while (0)
 
 }  // namespace
 
 extern "C" {
 
 int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes) {
+  if (p && p->ndim == 2) {
+    Stage2D st;
+    int rc = stage2d(p, nullptr, 0, &st);
+    if (rc) return rc;
+    if (!bytes) return fail(LDDMM_E_INVALID_ARG, "bytes is NULL");
+    *bytes = st.total;
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -653,6 +1060,19 @@ int lddmm_workspace_bytes(const lddmm_params* p, size_t* bytes) {
 
 int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
                 void* ws, size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!I0 || !v0 || !m1) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_image(I0, g.I0e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0), g.A, kDepthK, g.plane2, st));
+    if ((rc = lddmm_shoot(&g.q, g.I0e, g.A, g.I1e, v1 ? g.B : nullptr, ws, g.ws3, stream))) return rc;
+    TRY2D(launch_copy(g.I1e, m1, g.plane, st));
+    if (v1) TRY2D(launch_extract_band(g.B, static_cast<float2*>(v1), kDepthK, g.plane2, st));
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -675,6 +1095,7 @@ int lddmm_shoot(const lddmm_params* p, const float* I0, const void* v0, float* m
 
 int lddmm_shoot_static(const lddmm_params* p, const float* I0, const void* v0, float* m1, void* v1,
                        void* stream) {
+  if (p && p->ndim == 2) return fail(LDDMM_E_SHAPE, "lddmm_shoot_static takes three-dimensional problems");
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -703,6 +1124,17 @@ int lddmm_shoot_static(const lddmm_params* p, const float* I0, const void* v0, f
 
 int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, void* out, void* ws,
                        size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!in || !out) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_band(static_cast<const float2*>(in), g.A, kDepthK, g.plane2, st));
+    if ((rc = lddmm_apply_symbol(&g.q, which, g.A, g.B, ws, g.ws3, stream))) return rc;
+    TRY2D(launch_extract_band(g.B, static_cast<float2*>(out), kDepthK, g.plane2, st));
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -721,6 +1153,14 @@ int lddmm_apply_symbol(const lddmm_params* p, int32_t which, const void* in, voi
 
 int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energies, void* ws,
                           size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!v0 || !energies) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0), g.A, kDepthK, g.plane2, static_cast<hipStream_t>(stream)));
+    return lddmm_geodesic_energy(&g.q, g.A, energies, ws, g.ws3, stream);
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -739,6 +1179,19 @@ int lddmm_geodesic_energy(const lddmm_params* p, const void* v0, double* energie
 
 int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
                    void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_image(I0, g.I0e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_image(I1, g.I1e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0), g.A, kDepthK, g.plane2, st));
+    if ((rc = lddmm_gradient(&g.q, g.I0e, g.I1e, g.A, g.B, energy3, ws, g.ws3, stream))) return rc;
+    TRY2D(launch_extract_band(g.B, static_cast<float2*>(grad), kDepthK, g.plane2, st));
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -764,6 +1217,17 @@ int lddmm_gradient(const lddmm_params* p, const float* I0, const float* I1, cons
 
 int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const void* v0, double* energy3,
                  void* ws, size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!I0 || !I1 || !v0 || !energy3) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_image(I0, g.I0e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_image(I1, g.I1e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0), g.A, kDepthK, g.plane2, st));
+    return lddmm_energy(&g.q, g.I0e, g.I1e, g.A, energy3, ws, g.ws3, stream);
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -791,6 +1255,19 @@ int lddmm_energy(const lddmm_params* p, const float* I0, const float* I1, const 
 
 int lddmm_gradient_exact(const lddmm_params* p, const float* I0, const float* I1, const void* v0,
                          void* grad, double* energy3, void* ws, size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!I0 || !I1 || !v0 || !grad) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_image(I0, g.I0e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_image(I1, g.I1e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0), g.A, kDepthK, g.plane2, st));
+    if ((rc = lddmm_gradient_exact(&g.q, g.I0e, g.I1e, g.A, g.B, energy3, ws, g.ws3, stream))) return rc;
+    TRY2D(launch_extract_band(g.B, static_cast<float2*>(grad), kDepthK, g.plane2, st));
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -817,6 +1294,18 @@ int lddmm_gradient_exact(const lddmm_params* p, const float* I0, const float* I1
 
 int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, size_t ws_bytes,
                   void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!dv0 || !Hdv) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    if (dv0 == Hdv) return fail(LDDMM_E_INVALID_ARG, "Hdv may not alias dv0");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_band(static_cast<const float2*>(dv0), g.A, kDepthK, g.plane2, st));
+    if ((rc = lddmm_hessvec(&g.q, g.A, g.B, ws, g.ws3, stream))) return rc;
+    TRY2D(launch_extract_band(g.B, static_cast<float2*>(Hdv), kDepthK, g.plane2, st));
+    return LDDMM_OK;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -845,6 +1334,21 @@ int lddmm_hessvec(const lddmm_params* p, const void* dv0, void* Hdv, void* ws, s
 int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void* v0_inout,
                    int32_t gn_iters, int32_t pcg_iters, lddmm_stats* stats, int32_t stats_len,
                    void* ws, size_t ws_bytes, void* stream) {
+  if (p && p->ndim == 2) {
+    Stage2D g;
+    int rc = stage2d(p, ws, ws_bytes, &g);
+    if (rc) return rc;
+    if (!I0 || !I1 || !v0_inout) return fail(LDDMM_E_INVALID_ARG, "null input or output");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TRY2D(launch_embed_image(I0, g.I0e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_image(I1, g.I1e, g.plane, kDepthN, st));
+    TRY2D(launch_embed_band(static_cast<const float2*>(v0_inout), g.A, kDepthK, g.plane2, st));
+    rc = lddmm_register(&g.q, g.I0e, g.I1e, g.A, gn_iters, pcg_iters, stats, stats_len, ws, g.ws3, stream);
+    if (rc < 0) return rc;
+    TRY2D(launch_extract_band(g.A, static_cast<float2*>(v0_inout), kDepthK, g.plane2, st));
+    TRY2D(hipStreamSynchronize(st));
+    return rc;
+  }
   Dims d;
   int rc = validate(p, &d);
   if (rc) return rc;
@@ -859,7 +1363,9 @@ int lddmm_register(const lddmm_params* p, const float* I0, const float* I1, void
   hipError_t err = launch_fill(reinterpret_cast<float*>(e.tmph), 6LL * d.nb, 0.f, e.stream());
   if (err != hipSuccess) return hip_fail(err, "fill");
   g_last_hvps = 0;
-  rc = run_register(e, ws, I0, I1, v0_inout, gn_iters, pcg_iters, stats, stats_len, &g_last_hvps);
+  RegTask t = register_loop(e, ws, I0, I1, v0_inout, gn_iters, pcg_iters, stats, stats_len, &g_last_hvps,
+                            host_words());
+  rc = run_to_end(t);
   if (rc >= 0) g_last_error.clear();
   return rc;
 }
@@ -924,46 +1430,111 @@ int lddmm_register_batch(int32_t n, const lddmm_params* p, const float* const* I
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return Engine::workspace_bytes(dims[a]) > Engine::workspace_bytes(dims[b]); });
-  std::atomic<int> next{0};
-  // each worker thread owns one stream (and its engine's auxiliary stream)
-  // and takes the next pair of that order until none is left
-  auto worker = [&]() {
-    hipStream_t s = nullptr;
-    hipError_t e = hipSetDevice(dev);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, start, 0);
-    for (int k; (k = next.fetch_add(1)) < n;) {
-      const int i = order[k];
-      if (e != hipSuccess) {
-        rcs[i] = hip_fail(e, "worker stream");
-        msgs[i] = g_last_error;
-        continue;
+  // pinned host words per pair, drawn from the pool in pair order and
+  // returned in reverse, so that a repeated call gives pair i the same block
+  // (and replays the CG graphs captured with it)
+  std::vector<double*> words(n, nullptr);
+  {
+    std::lock_guard<std::mutex> lk(g_host_words.mu);
+    for (int i = 0; i < n; ++i) {
+      if (!g_host_words.free.empty()) {
+        words[i] = g_host_words.free.back();
+        g_host_words.free.pop_back();
+      } else if (hipHostMalloc(reinterpret_cast<void**>(&words[i]), kHostWords * sizeof(double),
+                               hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        words[i] = nullptr;
       }
-      void* w = static_cast<char*>(ws) + off[i];
-      set_prepared(w, false, dims[i]);
-      Engine eng(dims[i], w, s);
-      eng.set_one_stream(true);
-      int rc = LDDMM_OK;
-      hipError_t fe = launch_fill(reinterpret_cast<float*>(eng.tmph), 6LL * dims[i].nb, 0.f, s);
-      if (fe != hipSuccess)
-        rc = hip_fail(fe, "fill");
-      else
-        rc = run_register(eng, w, I0[i], I1[i], v0_inout[i], gn_iters, pcg_iters,
-                          stats ? stats + (size_t)i * stats_len : nullptr, stats ? stats_len : 0, &counts[i]);
-      rcs[i] = rc;
-      if (rc < 0) msgs[i] = g_last_error;
     }
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
-    release_thread_streams();
+  }
+  // `concurrency` slots, each with a stream of its own; every slot runs one
+  // pair's loop at a time and takes the next pair of that order when it ends.
+  // All loops are resumed from this thread (see register_loop).
+  struct Slot {
+    hipStream_t s = nullptr;
+    int pair = -1;
+    std::unique_ptr<Engine> eng;
+    RegTask task;
   };
   const int nw = std::min<int>(n, concurrency ? concurrency : kBatchConcurrency);
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
-  for (auto& t : pool) t.join();
+  std::vector<Slot> slots(nw);
+  for (Slot& sl : slots) {
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipStreamWaitEvent(sl.s, start, 0);
+  }
+  int next = 0;
+  auto finish = [&](Slot& sl) {
+    const int i = sl.pair;
+    rcs[i] = sl.task.result();
+    if (rcs[i] < 0) msgs[i] = g_last_error;
+    sl.task = RegTask();
+    sl.eng.reset();
+    sl.pair = -1;
+  };
+  // starts the next pair in the slot; false when none is left
+  auto start_pair = [&](Slot& sl) -> bool {
+    while (next < n) {
+      const int i = order[next++];
+      void* w = static_cast<char*>(ws) + off[i];
+      set_prepared(w, false, dims[i]);
+      sl.eng = std::make_unique<Engine>(dims[i], w, sl.s);
+      sl.eng->set_one_stream(true);
+      const hipError_t fe = launch_fill(reinterpret_cast<float*>(sl.eng->tmph), 6LL * dims[i].nb, 0.f, sl.s);
+      sl.pair = i;
+      if (fe != hipSuccess) {
+        rcs[i] = hip_fail(fe, "fill");
+        msgs[i] = g_last_error;
+        sl.eng.reset();
+        sl.pair = -1;
+        continue;
+      }
+      sl.task = register_loop(*sl.eng, w, I0[i], I1[i], v0_inout[i], gn_iters, pcg_iters,
+                              stats ? stats + (size_t)i * stats_len : nullptr, stats ? stats_len : 0, &counts[i],
+                              words[i]);
+      sl.task.h.resume();
+      if (!sl.task.done()) return true;
+      finish(sl);
+    }
+    return false;
+  };
+  if (err == hipSuccess) {
+    int active = 0;
+    for (Slot& sl : slots)
+      if (start_pair(sl)) ++active;
+    // a loop waiting for a flag is resumed once the flag is set; its stream
+    // is queried (for a failure that would leave the flag unset) every 64th
+    // round, a loop waiting for its stream to finish every round
+    for (unsigned round = 1; active > 0; ++round) {
+      const bool query = round % 64 == 0;
+      for (Slot& sl : slots) {
+        if (sl.pair < 0) continue;
+        auto& pr = sl.task.h.promise();
+        hipError_t r;
+        if (!wait_over(pr.wait, &r, query || !pr.wait.hf)) continue;
+        pr.wait_result = r;
+        sl.task.h.resume();
+        if (!sl.task.done()) continue;
+        finish(sl);
+        if (!start_pair(sl)) --active;
+      }
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      rcs[i] = hip_fail(err, "batch stream");
+      msgs[i] = g_last_error;
+    }
+  }
+  for (Slot& sl : slots)
+    if (sl.s) {
+      (void)hipStreamSynchronize(sl.s);
+      (void)hipStreamDestroy(sl.s);
+    }
   (void)hipEventDestroy(start);
+  {
+    std::lock_guard<std::mutex> lk(g_host_words.mu);
+    for (int i = n - 1; i >= 0; --i)
+      if (words[i]) g_host_words.free.push_back(words[i]);
+  }
   int result = LDDMM_OK;
   int64_t sum = 0;
   for (int i = 0; i < n; ++i) {
@@ -1044,5 +1615,246 @@ const char* lddmm_status_string(int code) {
 }
 
 const char* lddmm_last_error(void) { return g_last_error.c_str(); }
+
+int lddmm_tiles_set(const lddmm_params* p, const char* arch, const lddmm_tiles* t) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!t) return fail(LDDMM_E_INVALID_ARG, "tiles is NULL");
+  if ((rc = check_tiles(d, *t))) return rc;
+  const std::string a = arch ? std::string(arch) : current_arch();
+  if (a.empty()) return fail(LDDMM_E_INVALID_ARG, "no arch given and no current device");
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  TileEntry& e = g_tiles[tile_key(d, a)];
+  e.t = *t;
+  e.ms = 0.0;
+  g_tiles_any.store(true);
+  return LDDMM_OK;
+}
+
+int lddmm_tiles_get(const lddmm_params* p, const char* arch, lddmm_tiles* t, int32_t* found) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if (!t || !found) return fail(LDDMM_E_INVALID_ARG, "tiles or found is NULL");
+  const std::string a = arch ? std::string(arch) : current_arch();
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  auto it = g_tiles.find(tile_key(d, a));
+  *found = it != g_tiles.end();
+  *t = *found ? it->second.t : lddmm_tiles{};
+  return LDDMM_OK;
+}
+
+int lddmm_tiles_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  g_tiles.clear();
+  g_tiles_any.store(false);
+  return LDDMM_OK;
+}
+
+int lddmm_tiles_save(const char* path) {
+  if (!path) return fail(LDDMM_E_INVALID_ARG, "path is NULL");
+  std::string out = "{\"format\": \"lddmm-tiles-1\", \"entries\": [";
+  {
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    bool first = true;
+    for (auto& kv : g_tiles) {
+      const TileKey& k = kv.first;
+      char buf[512];
+      std::snprintf(buf, sizeof buf,
+                    "%s\n  {\"arch\": \"%s\", \"grid\": [%d, %d, %d], \"band\": [%d, %d, %d], "
+                    "\"spectral\": [%d, %d, %d], \"precision\": \"%s\", \"prod_rows\": %d, \"col_split\": %d, "
+                    "\"sl_threads\": %d, \"ms_per_hvp\": %.6f}",
+                    first ? "" : ",", k.arch.c_str(), k.N[0], k.N[1], k.N[2], k.K[0], k.K[1], k.K[2], k.M[0],
+                    k.M[1], k.M[2], k.prec ? "bf16x3" : "fp32", kv.second.t.prod_rows, kv.second.t.col_split,
+                    kv.second.t.sl_threads, kv.second.ms);
+      out += buf;
+      first = false;
+    }
+  }
+  out += "\n]}\n";
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(LDDMM_E_INVALID_ARG, std::string("cannot write ") + path);
+  const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+  if (std::fclose(f) != 0 || !ok) return fail(LDDMM_E_INVALID_ARG, std::string("write failed: ") + path);
+  return LDDMM_OK;
+}
+
+int lddmm_tiles_load(const char* path) {
+  if (!path) return fail(LDDMM_E_INVALID_ARG, "path is NULL");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(LDDMM_E_INVALID_ARG, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 24)) text.append(buf, n);
+  std::fclose(f);
+  JsonReader r(text);
+  JsonValue root;
+  const bool parsed = r.value(&root);
+  r.ws();
+  if (!parsed || r.i != text.size() || root.kind != JsonValue::OBJ)
+    return fail(LDDMM_E_INVALID_ARG, "not a tile table (JSON object expected)");
+  const JsonValue* fmt = root.get("format");
+  const JsonValue* ents = root.get("entries");
+  if (!fmt || fmt->kind != JsonValue::STR || fmt->str != "lddmm-tiles-1" || !ents || ents->kind != JsonValue::ARR)
+    return fail(LDDMM_E_INVALID_ARG, "tile table: format \"lddmm-tiles-1\" and an entries array expected");
+  // every entry is checked before any is taken
+  std::vector<std::pair<TileKey, TileEntry>> add;
+  for (size_t k = 0; k < ents->arr.size(); ++k) {
+    const JsonValue& e = ents->arr[k];
+    const std::string where = "tile table entry " + std::to_string(k) + ": ";
+    lddmm_params p{};
+    int grid[3], band[3], spec[3];
+    const JsonValue* arch = e.get("arch");
+    const JsonValue* prec = e.get("precision");
+    lddmm_tiles t{};
+    if (e.kind != JsonValue::OBJ || !arch || arch->kind != JsonValue::STR || arch->str.empty() ||
+        !json_int3(e.get("grid"), grid) || !json_int3(e.get("band"), band) || !json_int3(e.get("spectral"), spec) ||
+        !prec || prec->kind != JsonValue::STR || (prec->str != "fp32" && prec->str != "bf16x3") ||
+        !json_int(e.get("prod_rows"), &t.prod_rows) || !json_int(e.get("col_split"), &t.col_split) ||
+        !json_int(e.get("sl_threads"), &t.sl_threads))
+      return fail(LDDMM_E_INVALID_ARG, where + "arch, grid, band, spectral, precision, prod_rows, col_split and "
+                                               "sl_threads expected");
+    p.ndim = 3;
+    for (int j = 0; j < 3; ++j) {
+      p.grid[j] = grid[j];
+      p.band[j] = band[j];
+      p.spectral[j] = spec[j];
+    }
+    p.time_steps = 1;
+    p.s = 2;
+    p.alpha = 1.0;
+    p.sigma = 1.0;
+    p.precision = prec->str == "bf16x3" ? LDDMM_FP32_BF16X3 : LDDMM_FP32;
+    Dims d;
+    int rc = validate(&p, &d);
+    if (!rc) rc = check_tiles(d, t);
+    if (rc) return fail(rc, where + g_last_error);
+    TileEntry te;
+    te.t = t;
+    const JsonValue* ms = e.get("ms_per_hvp");
+    te.ms = (ms && ms->kind == JsonValue::NUM) ? ms->num : 0.0;
+    add.emplace_back(tile_key(d, arch->str), te);
+  }
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  for (auto& kv : add) g_tiles[kv.first] = kv.second;
+  if (!g_tiles.empty()) g_tiles_any.store(true);
+  return LDDMM_OK;
+}
+
+int lddmm_autotune(const lddmm_params* p, const float* I0, const float* I1, const void* v0, int32_t reps,
+                   lddmm_tiles* best, double* ms_best, double* ms_default, void* ws, size_t ws_bytes, void* stream) {
+  Dims d;
+  int rc = validate(p, &d);
+  if (rc) return rc;
+  if ((rc = no_checkpoint(d))) return rc;
+  if ((rc = euler_only(d))) return rc;
+  if (!I0 || !I1 || !v0) return fail(LDDMM_E_INVALID_ARG, "null input");
+  if (reps < 1 || reps > 1000) return fail(LDDMM_E_INVALID_ARG, "reps must be in [1, 1000]");
+  if ((rc = check_ws(d, ws, ws_bytes))) return rc;
+  const std::string arch = current_arch();
+  if (arch.empty()) return fail(LDDMM_E_HIP, "no current device");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  // the built-in rule prepares the workspace (the layout does not depend on the tiles)
+  d.tile_prod_rows = d.tile_col = d.tile_sl = 0;
+  set_prepared(ws, false, d);
+  hipError_t err;
+  {
+    Engine e(d, ws, st);
+    if ((err = e.init_tables()) || (err = e.load_band(v0, e.V[0])) || (err = e.forward(I0)) ||
+        (err = e.energy(e.final_state(), I1)) || (err = e.backward(I1, nullptr)) ||
+        (err = launch_copy(reinterpret_cast<const float*>(e.V[0]), reinterpret_cast<float*>(e.dV[0]), 6LL * d.nb,
+                           st)))
+      return hip_fail(err, "autotune gradient");
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& x : ev)
+    if ((err = hipEventCreate(&x)) != hipSuccess) return hip_fail(err, "event");
+  // The built-in rule's product is kept (in the line search's trial buffer,
+  // unused here) and every candidate's product must equal it bit for bit; a
+  // candidate that differs is rejected.  Mismatches are counted in the
+  // reduction scratch.
+  Engine e0(d, ws, st);
+  float2* ref = e0.vtry;
+  unsigned* nbad = reinterpret_cast<unsigned*>(e0.partial);
+  const long long nfl = 6LL * d.nb;
+  // time per Hessian-vector product (direction v0) with the given tiles; 0
+  // mismatches in *bad if its product equals the reference
+  auto measure = [&](const lddmm_tiles& t, double* ms, unsigned* bad) -> hipError_t {
+    Dims dc = d;
+    dc.tile_prod_rows = t.prod_rows;
+    dc.tile_col = t.col_split;
+    dc.tile_sl = t.sl_threads;
+    Engine e(dc, ws, st);
+    hipError_t r;
+    if ((r = e.hessvec(e.dV[0], e.Hdh))) return r;  // first launches of the variant
+    if (bad) {
+      if ((r = launch_fill(reinterpret_cast<float*>(nbad), 1, 0.f, st)) ||
+          (r = launch_count_ne(reinterpret_cast<const float*>(e.Hdh), reinterpret_cast<const float*>(ref), nfl,
+                               nbad, st)) ||
+          (r = hipMemcpyAsync(bad, nbad, sizeof(unsigned), hipMemcpyDeviceToHost, st)))
+        return r;
+    }
+    if ((r = hipEventRecord(ev[0], st))) return r;
+    for (int k = 0; k < reps; ++k)
+      if ((r = e.hessvec(e.dV[0], e.Hdh))) return r;
+    if ((r = hipEventRecord(ev[1], st)) || (r = hipEventSynchronize(ev[1]))) return r;
+    float el = 0.f;
+    if ((r = hipEventElapsedTime(&el, ev[0], ev[1]))) return r;
+    *ms = el / reps;
+    return hipSuccess;
+  };
+  // one field at a time, from the built-in rule; a candidate replaces the
+  // current choice only if it is at least 1 % faster (the built-in rule is
+  // timed twice, the first time to bring clocks and caches to their state)
+  lddmm_tiles cur{};
+  double tcur = 0.0, t0 = 0.0;
+  err = measure(cur, &t0, nullptr);
+  if (err == hipSuccess)
+    err = launch_copy(reinterpret_cast<const float*>(e0.Hdh), reinterpret_cast<float*>(ref), nfl, st);
+  if (err == hipSuccess) err = measure(cur, &t0, nullptr);
+  tcur = t0;
+  auto trial = [&](lddmm_tiles t) {
+    double tt = 0.0;
+    unsigned bad = 1;
+    if (err == hipSuccess) err = measure(t, &tt, &bad);
+    if (err == hipSuccess && bad == 0 && tt < 0.99 * tcur) {
+      cur = t;
+      tcur = tt;
+    }
+  };
+  for (int th : {64, 128}) {
+    lddmm_tiles t = cur;
+    t.sl_threads = th;
+    trial(t);
+  }
+  for (int r = 1; r < prod_rows_max(d); ++r) {
+    lddmm_tiles t = cur;
+    t.prod_rows = r;
+    trial(t);
+  }
+  for (int c = 1; c <= 3; ++c) {
+    lddmm_tiles t = cur;
+    t.col_split = c;
+    trial(t);
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (err != hipSuccess) return hip_fail(err, "autotune");
+  // the workspace stays prepared for lddmm_hessvec with these parameters
+  set_prepared(ws, true, d);
+  {
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    TileEntry& e = g_tiles[tile_key(d, arch)];
+    e.t = cur;
+    e.ms = tcur;
+    g_tiles_any.store(true);
+  }
+  if (best) *best = cur;
+  if (ms_best) *ms_best = tcur;
+  if (ms_default) *ms_default = t0;
+  g_last_error.clear();
+  return LDDMM_OK;
+}
 
 }  // extern "C"

@@ -29,7 +29,15 @@ struct Dims {
   int integrator;   // 0: Euler; 1: RK4 shooting with midpoint transport (shooting only)
   int prec;         // 0: FP32 matrix-core products; 1: compensated BF16 (three products)
   int ckpt;         // 0: every state kept; c > 0: states every c steps (exact gradient only)
+  // launch shapes from the tile table (0: the built-in rule); they change
+  // which blocks do what, never the arithmetic of an output
+  int tile_prod_rows;  // padded-grid rows per block of k_prods
+  int tile_col;        // column step: 1 one block per column tile, 2 two (general kernel), 3 two (lean kernel where it applies)
+  int tile_sl;         // threads per block of k_sl (64, 128 or 256)
 };
+
+// Valid range of the tile fields for a shape (host only).
+int prod_rows_max(const Dims& d);
 
 // ---------------------------------------------------------------- tables
 // Twiddle tables for one transform direction set (grid G = M or N).
@@ -222,6 +230,14 @@ hipError_t launch_image_derivs(const float* I0, float* G, float* H, const Dims& 
 hipError_t launch_rho_fwd2(const RhoArgs& a, float2* s1, const Dims& d, const Twiddles& tw, hipStream_t st);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, long long n, hipStream_t st);
+// Two-dimensional problems on the three-dimensional path: out [depth][plane] =
+// in [plane] per plane; band out [3][kd][plane2] = in [2][plane2] placed in
+// components 1, 2 at first-axis slot 0, zero elsewhere; and back.
+hipError_t launch_embed_image(const float* in, float* out, long long plane, int depth, hipStream_t st);
+// *out += number of i < n with a[i] and b[i] different bit for bit
+hipError_t launch_count_ne(const float* a, const float* b, long long n, unsigned* out, hipStream_t st);
+hipError_t launch_embed_band(const float2* in, float2* out, int kd, long long plane2, hipStream_t st);
+hipError_t launch_extract_band(const float2* in, float2* out, int kd, long long plane2, hipStream_t st);
 hipError_t launch_diff(const float* a, const float* b, float* out, long long n, hipStream_t st);  // a - b
 hipError_t launch_axpy_band(const float2* x, const float2* y, float a, float2* out, int n,
                             hipStream_t st);   // out = x + a*y

@@ -629,10 +629,10 @@ __global__ void k_synth_tables(const float2* inv1, const float2* inv2, float* w1
 // matrix cores when M2 % 4 == 0 (rows (o, r) x columns (kh re | kh im), depth
 // x2), else one thread per output.
 template <class S, bool BF3>
-__global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
+__global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh, int R) {
+  // R: padded-grid rows of this block (R M2 <= blockDim.x rounded to waves)
   extern __shared__ float smp[];
   const int M0 = sh.M0(), M1 = sh.M1(), M2 = sh.M2(), Kh = sh.Kh();
-  const int R = (256 / M2 < 1) ? 1 : (256 / M2 > M1 ? M1 : 256 / M2);
   const int x0 = blockIdx.y;
   const int x1b = blockIdx.x * R;
   const int rv = min(R, M1 - x1b);
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(256) k_prods(ProdArgs a, Twiddles tw, S sh) {
   float* outv = (float*)(wfx + M2 * Kh);       // [nout][R][LV]
   // the stage-2 table goes to LDS after the products (its loads overlap theirs)
   const int nw = M2 * Kh;
-  const bool wreg = nw <= 256 * 4;
+  const bool wreg = nw <= 256 * 4 && blockDim.x == 256;  // the register stage covers 256 threads
   RegStage<4, float2> rw;
   if (wreg) rw.load(nw, [&](int i) { return tw.fwd2[(size_t)(i % Kh) * M2 + i / Kh]; });
   for (int p = threadIdx.x; p < P; p += blockDim.x) {
@@ -991,13 +991,18 @@ __device__ __forceinline__ void zero_acc(floatx4* acc, int n) {
 // Logical block index (x, y, z) of a launch whose workgroups the command
 // processor hands round-robin to the eight XCDs (workgroup p to XCD p % 8):
 // with the block count a multiple of 8, XCD x takes the contiguous logical
-// range [x T/8, (x + 1) T/8), so blocks that are neighbours in x (here the
-// kh of one band column and its neighbours, which share 32-byte granules of
-// the band) run on one XCD and meet in its L2.
+// range [x T/8, (x + 1) T/8), so blocks that are neighbours in the logical
+// order run on one XCD and meet in its L2.  The logical order runs x fastest,
+// or with ZFirst z fastest, then x, then y (for launches whose z blocks of
+// one (x, y) read the same input: the column steps' k1 tiles and parts of one
+// kh read the same stage-1 input, and neighbouring kh share 32-byte granules
+// of the band).
+template <bool ZFirst>
 __device__ __forceinline__ uint3 xcd_block3() {
-  const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z, total = gx * gy * gz;
   unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
   if (total % 8u == 0) p = (p % 8u) * (total / 8u) + p / 8u;
+  if constexpr (ZFirst) return make_uint3((p / gz) % gx, p / (gz * gx), p % gz);
   return make_uint3(p % gx, (p / gx) % gy, p / (gx * gy));
 }
 
@@ -1077,7 +1082,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   __shared__ __align__(16) float2 w0fs[Kp][LW0F];     // w0f
   __shared__ __align__(16) float2 w0is[2][Mp][LW0I];  // w0i
   float2* g0s = &s1[0][0][0];           // [N0][LG] image-grid stage-0 table, after stage 1'
-  const uint3 lb = xcd_block3();
+  const uint3 lb = xcd_block3<true>();
   const ColJob& job = jobs.j[lb.y];
   const int kh = lb.x;
   constexpr int T0 = Kp / 16;
@@ -1284,7 +1289,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   float2(*w0fs)[LW0F] = reinterpret_cast<float2(*)[LW0F]>(ra);
   float2(*w0is)[Mp][LW0I] = reinterpret_cast<float2(*)[Mp][LW0I]>(ra);
   float2* g0s = ra;
-  const uint3 lb = xcd_block3();
+  const uint3 lb = xcd_block3<true>();
   const ColJob& job = jobs.j[lb.y];
   const int kh = lb.x;
   const int kc = (lb.z % T0) * 16;
@@ -1646,8 +1651,10 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
   constexpr int LM = N2 + 4;
   __shared__ __align__(16) float mrow[R + 2][LM];
   static_assert(N1 % R == 0, "whole row tiles");
-  const int x0 = blockIdx.y;
-  const int x1b = blockIdx.x * R;
+  // the row tiles of one plane read the same stage-0 input: one XCD each
+  const uint3 lb = xcd_block3<false>();
+  const int x0 = lb.y;
+  const int x1b = lb.x * R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
   // ---- all global loads of the block at once: the stage-0 input of this
@@ -2860,11 +2867,16 @@ hipError_t launch_synth(const float2* t1g0, const float2* t1g1, float* dst0, flo
   return e;
 }
 
-static int prod_rows(const Dims& d) {
+int prod_rows_max(const Dims& d) {
   int R = 256 / d.M[2];
   if (R < 1) R = 1;
   if (R > d.M[1]) R = d.M[1];
   return R;
+}
+
+static int prod_rows(const Dims& d) {
+  const int R = prod_rows_max(d);
+  return (d.tile_prod_rows > 0 && d.tile_prod_rows < R) ? d.tile_prod_rows : R;
 }
 
 size_t prods_shared_bytes(const Dims& d, int nout) {
@@ -2888,9 +2900,9 @@ hipError_t launch_prods(const ProdArgs& a, const Dims& d, const Twiddles& tw, hi
   hipError_t e = with_band(d, [&](auto sh) {
     do {
       if (d.prec)
-        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), true>), grid, dim3(threads), shm, st, a, tw, sh);
+        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), true>), grid, dim3(threads), shm, st, a, tw, sh, R);
       else
-        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), false>), grid, dim3(threads), shm, st, a, tw, sh);
+        LAUNCH_TIMED(KF_PRODS, (k_prods<decltype(sh), false>), grid, dim3(threads), shm, st, a, tw, sh, R);
     } while (0);
     return hipGetLastError();
   });
@@ -2988,11 +3000,15 @@ hipError_t launch_colstep(const ColJobs& jobs, int njobs, const Dims& d, const T
     const int t = j.nt1 * 2 * (round_up(d.M[0], 16) / 16) + (j.t1n ? d.N[0] / 16 : 0);
     min_tiles = t < min_tiles ? t : min_tiles;
   }
-  const int nparts = (d.Kh * njobs * ktiles <= 128 && min_tiles >= 8) ? 2 : 1;
+  // (or as the tile table says: tile_col 1 / 2 / 3 = one part, two parts, two
+  // parts with the lean kernel where it applies)
+  const int nparts = d.tile_col == 1 ? 1
+                     : d.tile_col >= 2 ? 2
+                                       : ((d.Kh * njobs * ktiles <= 128 && min_tiles >= 8) ? 2 : 1);
   const dim3 cgrid(d.Kh, njobs, ktiles * nparts);
   // the forward sweeps' launches (one product field per job, image-grid stage
   // 0 fused, two parts) take the lean kernel
-  bool lean = nparts == 2 && (band_iso(d, 32, 48) || band_iso(d, 24, 36));
+  bool lean = nparts == 2 && d.tile_col != 2 && (band_iso(d, 32, 48) || band_iso(d, 24, 36));
   for (int i = 0; i < njobs && lean; ++i) lean = jobs.j[i].b == nullptr && jobs.j[i].t1n != nullptr;
   if (lean) {
     if (band_iso(d, 32, 48))
@@ -3149,8 +3165,9 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
 hipError_t launch_sl(const float* src, const float* vel, float* dst, float dt, const Dims& d,
                      hipStream_t st) {
   timer_work(KF_SL, 40.0 * (double)d.nN, 20.0 * (double)d.nN);
+  const int T = (d.tile_sl == 64 || d.tile_sl == 128) ? d.tile_sl : 256;
   hipError_t e = with_grid(d, [&](auto gs) {
-    LAUNCH_TIMED(KF_SL, (k_sl<decltype(gs)>), dim3(nblk(d.nN, 256)), dim3(256), 0, st, src, vel, dst, dt, gs);
+    LAUNCH_TIMED(KF_SL, (k_sl<decltype(gs)>), dim3(nblk(d.nN, T)), dim3(T), 0, st, src, vel, dst, dt, gs);
     return hipGetLastError();
   });
   return e;
@@ -3337,6 +3354,57 @@ hipError_t launch_diff(const float* a, const float* b, float* out, long long n, 
 
 hipError_t launch_copy(const float* s, float* dd, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(nblk(n, 256)), dim3(256), 0, st, s, dd, n);
+  return hipGetLastError();
+}
+
+// Two-dimensional problems as three-dimensional ones independent of the
+// first coordinate: images repeated over `depth` planes, band fields placed
+// in components 1.. at first-axis frequency slot 0 (component 0 and the other
+// slots zero), and the inverse of the band placement.
+__global__ void k_embed_image(const float* __restrict__ in, float* __restrict__ out, long long plane, int depth) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= plane * depth) return;
+  out[i] = in[i % plane];
+}
+
+__global__ void k_embed_band(const float2* __restrict__ in, float2* __restrict__ out, int kd, long long plane2) {
+  // out [3][kd][plane2], in [2][plane2]
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * kd * plane2) return;
+  const long long c = i / (kd * plane2), slot = (i / plane2) % kd, r = i % plane2;
+  out[i] = (c > 0 && slot == 0) ? in[(c - 1) * plane2 + r] : make_float2(0.f, 0.f);
+}
+
+__global__ void k_extract_band(const float2* __restrict__ in, float2* __restrict__ out, int kd, long long plane2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * plane2) return;
+  const long long c = i / plane2, r = i % plane2;
+  out[i] = in[((c + 1) * kd) * plane2 + r];
+}
+
+// Number of positions where a and b differ bit for bit (NaN never equals).
+__global__ void k_count_ne(const float* __restrict__ a, const float* __restrict__ b, long long n, unsigned* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && __float_as_uint(a[i]) != __float_as_uint(b[i])) atomicAdd(out, 1u);
+}
+
+hipError_t launch_count_ne(const float* a, const float* b, long long n, unsigned* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_ne, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed_image(const float* in, float* out, long long plane, int depth, hipStream_t st) {
+  hipLaunchKernelGGL(k_embed_image, dim3(nblk(plane * depth, 256)), dim3(256), 0, st, in, out, plane, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed_band(const float2* in, float2* out, int kd, long long plane2, hipStream_t st) {
+  hipLaunchKernelGGL(k_embed_band, dim3(nblk(3 * kd * plane2, 256)), dim3(256), 0, st, in, out, kd, plane2);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_band(const float2* in, float2* out, int kd, long long plane2, hipStream_t st) {
+  hipLaunchKernelGGL(k_extract_band, dim3(nblk(2 * plane2, 256)), dim3(256), 0, st, in, out, kd, plane2);
   return hipGetLastError();
 }
 

@@ -84,8 +84,17 @@ class LddmmStats(ctypes.Structure):
     ]
 
 
+class LddmmTiles(ctypes.Structure):
+    _fields_ = [
+        ("prod_rows", ctypes.c_int32),
+        ("col_split", ctypes.c_int32),
+        ("sl_threads", ctypes.c_int32),
+    ]
+
+
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER(LddmmParams)
+_T = ctypes.POINTER(LddmmTiles)
 _SIGS = {
     "lddmm_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "lddmm_shoot": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -111,6 +120,13 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double)]),
     "lddmm_use_graphs": (ctypes.c_int, [ctypes.c_int32]),
+    "lddmm_tiles_set": (ctypes.c_int, [_P, ctypes.c_char_p, _T]),
+    "lddmm_tiles_get": (ctypes.c_int, [_P, ctypes.c_char_p, _T, ctypes.POINTER(ctypes.c_int32)]),
+    "lddmm_tiles_clear": (ctypes.c_int, []),
+    "lddmm_tiles_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "lddmm_tiles_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "lddmm_autotune": (ctypes.c_int, [_P, _vp, _vp, _vp, ctypes.c_int32, _T, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp]),
     "lddmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, []),
 }
@@ -177,7 +193,8 @@ class Problem:
 
     @property
     def band_shape(self):
-        return (3,) + tuple(self.band)
+        # one component per axis: [3][K0][K1][K2], or [2][K0][K1] in the plane
+        return (len(self.grid),) + tuple(self.band)
 
 
 def _torch():
@@ -435,3 +452,53 @@ def use_graphs(enable: bool):
 def raw():
     """The loaded ctypes library (for tests of the C-ABI itself)."""
     return _lib
+
+
+TILE_FIELDS = ("prod_rows", "col_split", "sl_threads")
+
+
+def _arch(arch):
+    return arch.encode() if arch is not None else None
+
+
+def tiles_set(problem: Problem, tiles: dict, arch: Optional[str] = None):
+    """Sets the tile-table entry of the problem's shape (lddmm_tiles_set)."""
+    t = LddmmTiles(*(int(tiles.get(k, 0)) for k in TILE_FIELDS))
+    _check(_lib.lddmm_tiles_set(ctypes.byref(problem.c_params()), _arch(arch), ctypes.byref(t)), "lddmm_tiles_set")
+
+
+def tiles_get(problem: Problem, arch: Optional[str] = None):
+    """The tile-table entry of the problem's shape, or None (lddmm_tiles_get)."""
+    t = LddmmTiles()
+    found = ctypes.c_int32(0)
+    _check(_lib.lddmm_tiles_get(ctypes.byref(problem.c_params()), _arch(arch), ctypes.byref(t),
+                                ctypes.byref(found)), "lddmm_tiles_get")
+    return {k: getattr(t, k) for k in TILE_FIELDS} if found.value else None
+
+
+def tiles_clear():
+    _check(_lib.lddmm_tiles_clear(), "lddmm_tiles_clear")
+
+
+def tiles_save(path: str):
+    _check(_lib.lddmm_tiles_save(os.fsencode(path)), "lddmm_tiles_save")
+
+
+def tiles_load(path: str):
+    _check(_lib.lddmm_tiles_load(os.fsencode(path)), "lddmm_tiles_load")
+
+
+def autotune(problem: Problem, I0, I1, v0, ws: Workspace, reps: int = 10, stream=None):
+    """Tunes the tile table for this problem (lddmm_autotune): returns the
+    chosen tiles, their ms per Hessian-vector product and the built-in
+    rule's.  Leaves ws prepared for hessvec at v0."""
+    torch = _torch()
+    _need(I0, torch.float32, problem.grid, "I0")
+    _need(I1, torch.float32, problem.grid, "I1")
+    _need(v0, torch.complex64, problem.band_shape, "v0")
+    t = LddmmTiles()
+    mb, md = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(_lib.lddmm_autotune(ctypes.byref(problem.c_params()), _ptr(I0), _ptr(I1), _ptr(v0), int(reps),
+                               ctypes.byref(t), ctypes.byref(mb), ctypes.byref(md), ws.ptr, ws.nbytes,
+                               _stream(stream)), "lddmm_autotune")
+    return {k: getattr(t, k) for k in TILE_FIELDS}, mb.value, md.value

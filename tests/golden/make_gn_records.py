@@ -19,12 +19,14 @@ the FP64 oracle and the seeded input generators:
       iterate.
 
   gn_band64.json
-      The first Gauss-Newton iteration from v0 = 0 of the 128^3 workload
+      The first Gauss-Newton iterations from v0 = 0 of the 128^3 workload
       registered with band 64^3 (padded grid 96^3) to the band-32 target, the
-      paper's band sweep: the record and its decision margins.
+      paper's band sweep: the records and their decision margins
+      (band64x3: three iterations).
 
-Usage: python tests/golden/make_gn_records.py [config3|config2|all|band64]
-(the config-3 records take minutes, band 64 about an hour, on eight cores).
+Usage: python tests/golden/make_gn_records.py [config3|config2|all|band64|band64x3]
+(the config-3 records take minutes, band 64 about 20 minutes per iteration,
+on eight cores).
 """
 
 import json
@@ -143,19 +145,21 @@ def config2():
                   default=float)
 
 
-def band_sweep(band):
-    """The first Gauss-Newton iteration (from v0 = 0) of the 128^3 registration
-    of the band-32 target with another band (the paper's band sweep): the
-    record and its decision margins, no iterate."""
+def band_sweep(band, iters):
+    """The first `iters` Gauss-Newton iterations (from v0 = 0) of the 128^3
+    registration of the band-32 target with another band (the paper's band
+    sweep): the records and their decision margins, no iterate."""
     t0 = time.time()
     p32, pp, I0, I1 = problem(3)
     p = Params(grid=p32.grid, band=(band,) * 3, nt=p32.nt, alpha=p32.alpha, s=p32.s, sigma=p32.sigma)
     with DecisionLog(p) as cl:
-        v, st, status = GN.register(I0, I1, p, gn_iters=1, pcg_iters=pp["pcg"], mode="R1")
-    print(f"band {band}: {st[0]}  {time.time() - t0:.0f} s", flush=True)
+        v, st, status = GN.register(I0, I1, p, gn_iters=iters, pcg_iters=pp["pcg"], mode="R1")
+    for i, r in enumerate(st):
+        print(f"band {band} iteration {i}: {r}", flush=True)
+    print(f"status {status}, {time.time() - t0:.0f} s", flush=True)
     with open(os.path.join(HERE, f"gn_band{band}.json"), "w") as f:
         json.dump({"workload": f"128^3 tissue phantom registered with band {band}^3 to the band-32 target, s = 3, "
-                               "nt = 10, mode R1, 20 CG; iteration 0 from v0 = 0",
+                               f"nt = 10, mode R1, 20 CG; iterations 0..{len(st) - 1} from v0 = 0",
                    "status": status, "records": st, "curvature": cl.log, "armijo": cl.armijo}, f, indent=1,
                   default=float)
 
@@ -167,4 +171,6 @@ if __name__ == "__main__":
     if which in ("config3", "all"):
         config3()
     if which.startswith("band"):
-        band_sweep(int(which[4:]))
+        # bandK: the first iteration; bandKxI: the first I iterations
+        k, _, it = which[4:].partition("x")
+        band_sweep(int(k), int(it) if it else 1)

@@ -78,11 +78,35 @@ def test_validation_rejects(kw, code):
     assert e.value.code == code
 
 
-def test_two_dimensional_problems_are_rejected_by_the_gpu_library():
+def test_planar_problems_size_their_workspace_and_validate():
+    """A planar problem runs as the volume problem of depth 8 with band depth
+    4 plus staging for two images of that depth and two band fields: its
+    workspace is at least that volume problem's; the planar bounds are the
+    volume ones; the batch, the static entry and the tile table take volumes
+    only; ndim other than 2 or 3 is rejected."""
+    planar = L.Problem(grid=(64, 64), band=(16, 16))
+    assert planar.band_shape == (2, 16, 16)
+    vol = L.Problem(grid=(8, 64, 64), band=(4, 16, 16))
+    stage = 2 * 8 * 64 * 64 * 4 + 2 * 3 * 4 * 16 * 16 * 8
+    assert planar.workspace_bytes() >= vol.workspace_bytes() + stage
+    assert planar.workspace_bytes() < vol.workspace_bytes() + stage + 4096
+    with pytest.raises(L.LddmmError) as ei:
+        L.Problem(grid=(64, 64), band=(15, 16)).workspace_bytes()
+    assert ei.value.code == L.E_SHAPE
+    with pytest.raises(L.LddmmError) as ei:
+        L.Problem(grid=(64, 300), band=(16, 16)).workspace_bytes()
+    assert ei.value.code == L.E_SHAPE
+    with pytest.raises(L.LddmmError) as ei:
+        L.batch_workspace_bytes([planar])
+    assert ei.value.code == L.E_SHAPE
+    with pytest.raises(L.LddmmError) as ei:
+        L.tiles_set(planar, {"sl_threads": 64}, arch="gfx950")
+    assert ei.value.code == L.E_SHAPE
     p = L.Problem(grid=(64, 64, 64), band=(16, 16, 16)).c_params()
-    p.ndim = 2
     n = ctypes.c_size_t(0)
-    assert L.raw().lddmm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == L.E_SHAPE
+    for nd in (1, 4):
+        p.ndim = nd
+        assert L.raw().lddmm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == L.E_SHAPE
 
 
 def test_entry_points_validate_before_touching_the_device():
@@ -178,3 +202,63 @@ def test_rk4_is_for_shooting_only():
     assert lib.lddmm_register_batch(1, arr, ptrs, ptrs, ptrs, 1, 1, 0, None, 0, None, None, fake, big,
                                     null) == L.E_INVALID_ARG
     assert lib.lddmm_geodesic_energy(ctypes.byref(p), null, fake, fake, big, null) == L.E_INVALID_ARG
+
+
+def test_tile_table_set_get_save_load_round_trip(tmp_path):
+    """Host-only: entries keyed by (grid, band, spectral grid, precision,
+    arch), JSON written and read back exactly, and a malformed or invalid
+    file rejected without changing the table."""
+    import json
+    L.tiles_clear()
+    try:
+        a = L.Problem(grid=(128, 128, 128), band=(32, 32, 32), s=3)
+        b = L.Problem(grid=(96, 96, 96), band=(24, 24, 24), s=3, precision=L.FP32_BF16X3)
+        assert L.tiles_get(a, arch="gfx950") is None
+        L.tiles_set(a, {"prod_rows": 2, "col_split": 3, "sl_threads": 128}, arch="gfx950")
+        L.tiles_set(b, {"prod_rows": 1, "col_split": 1, "sl_threads": 64}, arch="gfx950")
+        assert L.tiles_get(a, arch="gfx950") == {"prod_rows": 2, "col_split": 3, "sl_threads": 128}
+        assert L.tiles_get(a, arch="gfx942") is None
+        # the key is the shape and precision, not the other parameters
+        a2 = L.Problem(grid=(128, 128, 128), band=(32, 32, 32), s=2, time_steps=20, alpha=0.01)
+        assert L.tiles_get(a2, arch="gfx950") == L.tiles_get(a, arch="gfx950")
+        assert L.tiles_get(L.Problem(grid=(96, 96, 96), band=(24, 24, 24), s=3), arch="gfx950") is None
+        path = tmp_path / "tiles.json"
+        L.tiles_save(str(path))
+        doc = json.loads(path.read_text())
+        assert doc["format"] == "lddmm-tiles-1" and len(doc["entries"]) == 2
+        e = [x for x in doc["entries"] if x["grid"] == [128, 128, 128]][0]
+        assert e == {"arch": "gfx950", "grid": [128, 128, 128], "band": [32, 32, 32], "spectral": [48, 48, 48],
+                     "precision": "fp32", "prod_rows": 2, "col_split": 3, "sl_threads": 128, "ms_per_hvp": 0.0}
+        L.tiles_clear()
+        assert L.tiles_get(a, arch="gfx950") is None
+        L.tiles_load(str(path))
+        assert L.tiles_get(a, arch="gfx950") == {"prod_rows": 2, "col_split": 3, "sl_threads": 128}
+        assert L.tiles_get(b, arch="gfx950") == {"prod_rows": 1, "col_split": 1, "sl_threads": 64}
+        # every entry is checked before any is taken
+        bad = dict(doc)
+        bad["entries"] = [dict(e, grid=[64, 64, 64], band=[16, 16, 16], spectral=[24, 24, 24]),
+                          dict(e, sl_threads=100)]
+        (tmp_path / "bad.json").write_text(json.dumps(bad))
+        with pytest.raises(L.LddmmError) as ei:
+            L.tiles_load(str(tmp_path / "bad.json"))
+        assert ei.value.code == L.E_INVALID_ARG and "entry 1" in str(ei.value)
+        assert L.tiles_get(L.Problem(grid=(64, 64, 64), band=(16, 16, 16)), arch="gfx950") is None
+        for text in ["", "{", "[]", '{"format": "other", "entries": []}', '{"format": "lddmm-tiles-1"}',
+                     path.read_text()[:-5], path.read_text() + "x"]:
+            (tmp_path / "m.json").write_text(text)
+            with pytest.raises(L.LddmmError):
+                L.tiles_load(str(tmp_path / "m.json"))
+        with pytest.raises(L.LddmmError):
+            L.tiles_load(str(tmp_path / "missing.json"))
+    finally:
+        L.tiles_clear()
+
+
+@pytest.mark.parametrize("tiles", [dict(prod_rows=6), dict(prod_rows=-1), dict(col_split=4), dict(sl_threads=32),
+                                   dict(sl_threads=512)])
+def test_tile_fields_out_of_range_are_rejected(tiles):
+    a = L.Problem(grid=(128, 128, 128), band=(32, 32, 32), s=3)  # M2 = 48: at most 5 rows
+    with pytest.raises(L.LddmmError) as ei:
+        L.tiles_set(a, tiles, arch="gfx950")
+    assert ei.value.code == L.E_INVALID_ARG
+    assert L.tiles_get(a, arch="gfx950") is None

@@ -2,7 +2,8 @@
 state and Hessian mode in one call give, pair by pair, exactly the results of
 lddmm_register on the same inputs (the single-pair loop is itself compared
 with the oracle in test_gpu_register.py), for any number of pairs running at
-a time; and the atlas-serving shapes run."""
+a time (all driven from the calling thread); and the atlas-serving shapes
+run."""
 
 import numpy as np
 import pytest
@@ -100,8 +101,8 @@ def test_atlas_serving_shapes_run():
 
 
 def test_batch_with_graph_replay():
-    """With graph replay on, the pairs' host threads capture their sequences
-    one at a time and then replay them: two batches in a row give, pair by
+    """With graph replay on, the pairs capture their sequences on the first
+    batch and replay them on the second: two batches in a row give, pair by
     pair, exactly the results of the batch without graphs."""
     pairs = small_pairs()
     probs = [q for q, _, _ in pairs]
