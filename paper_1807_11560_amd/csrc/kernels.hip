@@ -112,15 +112,17 @@ struct GridDyn {
   __device__ __forceinline__ int K1() const { return k1; }
   __device__ __forceinline__ int Kh() const { return kh; }
 };
-template <int N, int K>
-struct GridIso {
+template <int A, int B, int C, int K>
+struct GridShape {
   static constexpr bool kStatic = true;
-  __device__ static constexpr int N0() { return N; }
-  __device__ static constexpr int N1() { return N; }
-  __device__ static constexpr int N2() { return N; }
+  __device__ static constexpr int N0() { return A; }
+  __device__ static constexpr int N1() { return B; }
+  __device__ static constexpr int N2() { return C; }
   __device__ static constexpr int K1() { return K; }
   __device__ static constexpr int Kh() { return K / 2; }
 };
+template <int N, int K>
+using GridIso = GridShape<N, N, N, K>;
 
 // ------------------------------------------------------------- tables
 // mode 0: inverse, full axis  [2][G][K]
@@ -2726,6 +2728,9 @@ static bool band_iso(const Dims& d, int K, int M) {
 static bool grid_iso(const Dims& d, int N, int K) {
   return d.N[0] == N && d.N[1] == N && d.N[2] == N && d.K[1] == K && d.K[2] == K;
 }
+static bool grid_is(const Dims& d, int A, int B, int C, int K) {
+  return d.N[0] == A && d.N[1] == B && d.N[2] == C && d.K[1] == K && d.K[2] == K;
+}
 // Calls f with the band shape type for these sizes.
 template <class F>
 static hipError_t with_band(const Dims& d, F&& f) {
@@ -2736,8 +2741,17 @@ static hipError_t with_band(const Dims& d, F&& f) {
 }
 template <class F>
 static hipError_t with_grid(const Dims& d, F&& f) {
+  // the measured volume, the 64^3 problem and the grids of the atlas
+  // batch and of the differentiation volume, with bands 24^3 and 32^3
   if (grid_iso(d, 128, 32)) return f(GridIso<128, 32>{});
   if (grid_iso(d, 64, 16)) return f(GridIso<64, 16>{});
+  if (grid_iso(d, 128, 24)) return f(GridIso<128, 24>{});
+  if (grid_iso(d, 96, 24)) return f(GridIso<96, 24>{});
+  if (grid_iso(d, 96, 32)) return f(GridIso<96, 32>{});
+  if (grid_is(d, 144, 176, 144, 24)) return f(GridShape<144, 176, 144, 24>{});
+  if (grid_is(d, 144, 176, 144, 32)) return f(GridShape<144, 176, 144, 32>{});
+  if (grid_is(d, 160, 192, 160, 24)) return f(GridShape<160, 192, 160, 24>{});
+  if (grid_is(d, 160, 192, 160, 32)) return f(GridShape<160, 192, 160, 32>{});
   return f(GridDyn{d.N[0], d.N[1], d.N[2], d.K[1], d.Kh});
 }
 
@@ -3130,23 +3144,22 @@ hipError_t launch_gridstep(const GridStepArgs& a, const Dims& d, const Twiddles&
     timer_work(KF_GRID, fl, by);
   }
   hipError_t e;
-  if (grid_iso(d, 128, 32)) {
-    do {
+  // the compile-time grid shapes take the matrix-core kernel
+  bool done = false;
+  e = with_grid(d, [&](auto gs) -> hipError_t {
+    using G = decltype(gs);
+    if constexpr (G::kStatic) {
+      static_assert(G::N1() % kGridRows == 0 && G::N2() % 16 == 0 && G::K1() % 4 == 0, "matrix-core grid shape");
+      done = true;
       if (d.prec)
-        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>, true>), grid, dim3(256), 0, st, a, tw);
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<G, true>), grid, dim3(256), 0, st, a, tw);
       else
-        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<128, 32>, false>), grid, dim3(256), 0, st, a, tw);
-    } while (0);
-    e = hipGetLastError();
-  } else if (grid_iso(d, 64, 16)) {
-    do {
-      if (d.prec)
-        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>, true>), grid, dim3(256), 0, st, a, tw);
-      else
-        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<GridIso<64, 16>, false>), grid, dim3(256), 0, st, a, tw);
-    } while (0);
-    e = hipGetLastError();
-  } else {
+        LAUNCH_TIMED(KF_GRID, (k_gridstep_mfma<G, false>), grid, dim3(256), 0, st, a, tw);
+      return hipGetLastError();
+    }
+    return hipSuccess;
+  });
+  if (!done) {
     const int jn = (d.N[2] + 15) / 16;
     GridDyn gs{d.N[0], d.N[1], d.N[2], d.K[1], d.Kh};
     if (jn <= 2)

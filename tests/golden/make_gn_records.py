@@ -23,6 +23,9 @@ the FP64 oracle and the seeded input generators:
       registered with band 64^3 (padded grid 96^3) to the band-32 target, the
       paper's band sweep: the records and their decision margins
       (band64x3: three iterations).
+  gn_band48_deformation.json
+      The same at band 48^3 subject to the deformation state, ten iterations
+      (band48x10:deformation).
 
 Usage: python tests/golden/make_gn_records.py [config3|config2|all|band64|band64x3]
 (the config-3 records take minutes, band 64 about 20 minutes per iteration,
@@ -145,21 +148,23 @@ def config2():
                   default=float)
 
 
-def band_sweep(band, iters):
+def band_sweep(band, iters, state="image"):
     """The first `iters` Gauss-Newton iterations (from v0 = 0) of the 128^3
     registration of the band-32 target with another band (the paper's band
-    sweep): the records and their decision margins, no iterate."""
+    sweep), subject to the image or the deformation state: the records and
+    their decision margins, no iterate."""
     t0 = time.time()
     p32, pp, I0, I1 = problem(3)
     p = Params(grid=p32.grid, band=(band,) * 3, nt=p32.nt, alpha=p32.alpha, s=p32.s, sigma=p32.sigma)
     with DecisionLog(p) as cl:
-        v, st, status = GN.register(I0, I1, p, gn_iters=iters, pcg_iters=pp["pcg"], mode="R1")
+        v, st, status = GN.register(I0, I1, p, gn_iters=iters, pcg_iters=pp["pcg"], mode="R1", state=state)
     for i, r in enumerate(st):
         print(f"band {band} iteration {i}: {r}", flush=True)
     print(f"status {status}, {time.time() - t0:.0f} s", flush=True)
-    with open(os.path.join(HERE, f"gn_band{band}.json"), "w") as f:
+    name = f"gn_band{band}" + ("" if state == "image" else "_deformation")
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
         json.dump({"workload": f"128^3 tissue phantom registered with band {band}^3 to the band-32 target, s = 3, "
-                               f"nt = 10, mode R1, 20 CG; iterations 0..{len(st) - 1} from v0 = 0",
+                               f"nt = 10, mode R1, 20 CG, {state} state; iterations 0..{len(st) - 1} from v0 = 0",
                    "status": status, "records": st, "curvature": cl.log, "armijo": cl.armijo}, f, indent=1,
                   default=float)
 
@@ -171,6 +176,8 @@ if __name__ == "__main__":
     if which in ("config3", "all"):
         config3()
     if which.startswith("band"):
-        # bandK: the first iteration; bandKxI: the first I iterations
-        k, _, it = which[4:].partition("x")
-        band_sweep(int(k), int(it) if it else 1)
+        # bandK: the first iteration; bandKxI: the first I iterations;
+        # a suffix ":deformation" for the deformation state
+        spec, _, state = which[4:].partition(":")
+        k, _, it = spec.partition("x")
+        band_sweep(int(k), int(it) if it else 1, state or "image")

@@ -148,3 +148,29 @@ def test_config2_registration_end_to_end():
         mse_ref = 100.0 * np.sum((m_ref - I1) ** 2) / np.sum((I0 - I1) ** 2)
         print(f"final iterate rel {ev:.2e}; final MSE_rel {mse:.4f} % (oracle {mse_ref:.4f} %)", flush=True)
         assert ev < 1e-2 and abs(mse - mse_ref) <= 1e-2 * mse_ref
+
+
+def test_band64_registration_stops_where_the_oracle_stops():
+    """The paper's band sweep at band 64^3 (padded grid 96^3, the generic
+    kernels) on the 128^3 workload of band 32^3: the oracle's own registration
+    (gn_band64.json) takes a guarded CG of 10 iterations and eps = 1/8 after
+    three overflowing trials, then meets negative curvature at the first CG
+    iteration (p = -g) and no trial with a finite energy, stopping at
+    MSE_rel 41.76 %.  The library's record is the same, decision by decision
+    (energies of iteration 0 to 1e-4, of iteration 1 to 1e-3: its start is
+    the end of a guarded FP32 CG solve)."""
+    import dataclasses
+    print("\n[GN records 128^3 band 64^3]", flush=True)
+    with open(os.path.join(GOLDEN, "gn_band64.json")) as f:
+        meta = json.load(f)
+    pp, prob32, I0, I1 = workload(3)
+    prob = dataclasses.replace(prob32, band=(64, 64, 64))
+    ws = L().Workspace(prob)
+    v, st, rc, hv = L().register(prob, torch.from_numpy(I0).float().cuda(), torch.from_numpy(I1).float().cuda(),
+                                 ws, gn_iters=3, pcg_iters=pp["pcg"])
+    for k, (a, b) in enumerate(zip(st, meta["records"])):
+        print(f"iteration {k}: library {a}\n  oracle {b}", flush=True)
+    assert rc == L().W_LINESEARCH and meta["status"] == 1
+    assert len(st) == len(meta["records"]) == 2
+    same_record(st[0], meta["records"][0], "iteration 0")
+    same_record(st[1], meta["records"][1], "iteration 1", tol=1e-3)
