@@ -414,6 +414,8 @@ def batch_main(args):
         "registrations_per_min": 60.0 * args.steps * len(probs) / T,
         "value_without_timer_events": hvps_u / T_u,
         "final_mse_rel_mean": float(np.mean([s[-1]["mse_rel"] for s in stats])),
+        "pair_status": [int(x) for x in status],
+        "pair_hvps": [int(x) for x in hv],
         "workspace_mib": ws.nbytes / 2**20,
         "roofline": roofline(dominant, name, launches, kms, kfl, kby, None),
         "cpu_baseline": cpu,
@@ -529,7 +531,7 @@ def main():
     T_u = time.perf_counter() - t0
 
     # pure Hessian-vector product rate (same problem, last iterate)
-    hvp_only = hvp_med = cold_ms = work = None
+    hvp_only = hvp_med = cold_ms = work = hvp_enqueue_ms = None
     if args.hvp_loop > 0:
         L.gradient(prob, I0, I1, v, ws)
         d = torch.from_numpy(synth.random_direction(1, prob.band, s=pp["s"])).to(torch.complex64).to(dev)
@@ -540,8 +542,11 @@ def main():
         t1 = time.perf_counter()
         for _ in range(args.hvp_loop):
             L.hessvec(prob, d, ws, out=out)
+        t_enq = time.perf_counter()
         torch.cuda.synchronize()
         hvp_only = args.hvp_loop / (time.perf_counter() - t1)
+        # host time to enqueue one product (its launches, event records and waits)
+        hvp_enqueue_ms = 1e3 * (t_enq - t1) / args.hvp_loop
         # per-call durations (events on the stream the library runs on) and the cold product
         # (gradient with its trajectories recomputed, then the product)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
@@ -654,6 +659,7 @@ def main():
         "value_without_timer_events": hvps_u / T_u,
         "hvp_only_per_s": hvp_only,
         "hvp_ms_median": hvp_med,
+        "hvp_enqueue_ms": hvp_enqueue_ms,
         "cold_hvp_ms": cold_ms,
         "hvp_roofline": hvp_ceiling(prob, work, res_value=hvps / T, hvp_only=hvp_only) if work else None,
         "gn_classical": classical,
