@@ -85,8 +85,16 @@ enum { LDDMM_STATE_IMAGE = 0, LDDMM_STATE_DEFORMATION = 1 };
 enum { LDDMM_EULER = 0, LDDMM_RK4 = 1 };
 
 typedef struct lddmm_params {
-  int32_t ndim;         /* spatial dimension; this library computes ndim == 3 */
-  int32_t grid[3];      /* N_j >= 8, C order */
+  int32_t ndim;         /* spatial dimension, 3 or 2.  With ndim == 2 only grid[0..1],
+                           band[0..1] and spectral[0..1] are read; images are [N0][N1],
+                           band fields [2][K0][K1] (same slot convention), the domain the
+                           periodic unit square.  The single-problem entry points take
+                           planar problems (run as the volume problem of depth 8, band
+                           depth 4, whose fields do not depend on the new first coordinate;
+                           lddmm_workspace_bytes adds staging for two images of that depth
+                           and two band fields); lddmm_shoot_static, the batch, the tile
+                           table and the autotuner take volumes only (LDDMM_E_SHAPE). */
+  int32_t grid[3];      /* N_j >= 8, C order; the last axis at most 256 */
   int32_t band[3];      /* K_j even, 4 <= K_j <= min(N_j, 64) */
   int32_t spectral[3];  /* M_j, padded grid of the truncated convolution; 0 selects 3*K_j/2.
                            Must satisfy 3*K_j/2 - 2 <= M_j <= 256 so that the product of two
