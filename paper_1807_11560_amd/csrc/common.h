@@ -13,8 +13,9 @@ constexpr size_t kMaxLds = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int kMaxJobs = 32;   // jobs per batched launch
 
 // Problem sizes.  Band fields are kept internally as the half spectrum
-// [3][K0][K1][Kh] (k2 = 0..K2/2-1), complex float; the negative-k2 half
-// follows from Hermitian symmetry.
+// [3][Kh][K0][K1] (k2 = 0..K2/2-1 slowest, k1 fastest), complex float; the
+// negative-k2 half follows from Hermitian symmetry.  A column step owns one
+// k2 and 16 k1, so its band reads and writes are rows of 16 consecutive k1.
 struct Dims {
   int N[3], K[3], M[3];
   int Kh;           // K[2] / 2
@@ -53,7 +54,7 @@ struct Twiddles {
 
 // ---------------------------------------------------------------- jobs
 struct Inv0Job {
-  const float2* in;   // band half spectrum of one component [K0][K1*Kh]
+  const float2* in;   // band half spectrum of one component [Kh][K0][K1]
   float2* out;        // [nvar][G0][Kh][K1]
   int lflag;          // multiply the input by L~ on load
 };
@@ -120,7 +121,7 @@ struct ColJobs {
   int N0;
 };
 
-struct Fwd1Job { const float2* in; float2* out; };   // [G0][G1][Kh] -> [G0][K1][Kh]
+struct Fwd1Job { const float2* in; float2* out; };   // [G0][G1][Kh] -> [G0][Kh][K1]
 struct Fwd1Jobs { Fwd1Job j[kMaxJobs]; };
 
 // out = base + ca*(K~ if syma)*F(a) + cb*(K~ if symb)*F(b) + ce*extra, per

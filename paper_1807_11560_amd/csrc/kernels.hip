@@ -178,13 +178,14 @@ __device__ __forceinline__ float2 band_symbols(int q0, int q1, int k2, int K0, i
 __global__ void k_symbols(float* Lsym, float* Ksym, int K0, int K1, int Kh, int s, double alpha) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K0 * K1 * Kh) return;
-  const float2 lk = band_symbols(i / (K1 * Kh), (i / Kh) % K1, i % Kh, K0, K1, s, alpha);
+  // band layout [Kh][K0][K1]
+  const float2 lk = band_symbols((i / K1) % K0, i % K1, i / (K0 * K1), K0, K1, s, alpha);
   Lsym[i] = lk.x;
   Ksym[i] = lk.y;
 }
 
 // ------------------------------------------------------- layout changes
-// full [3][K0][K1][K2] -> half [3][K0][K1][Kh], projecting onto Hermitian
+// full [3][K0][K1][K2] -> half [3][Kh][K0][K1], projecting onto Hermitian
 // fields on the effective band.
 __global__ void k_full_to_half(const float2* __restrict__ full, float2* __restrict__ half, int K0,
                                int K1, int K2) {
@@ -192,7 +193,7 @@ __global__ void k_full_to_half(const float2* __restrict__ full, float2* __restri
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * K0 * K1 * Kh) return;
   int c = i / (K0 * K1 * Kh);
-  int q0 = (i / (K1 * Kh)) % K0, q1 = (i / Kh) % K1, q2 = i % Kh;
+  int q2 = (i / (K0 * K1)) % Kh, q0 = (i / K1) % K0, q1 = i % K1;
   if (q0 == K0 / 2 || q1 == K1 / 2) { half[i] = make_float2(0.f, 0.f); return; }
   const float2* f = full + (size_t)c * K0 * K1 * K2;
   float2 a = f[((size_t)q0 * K1 + q1) * K2 + q2];
@@ -214,11 +215,12 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
   bool conj = q2 > Kh;
   int s0 = conj ? (K0 - q0) % K0 : q0, s1 = conj ? (K1 - q1) % K1 : q1, s2 = conj ? K2 - q2 : q2;
   auto value = [&](int t0, int t1, int t2) {
-    const size_t j = (size_t)c * K0 * K1 * Kh + ((size_t)t0 * K1 + t1) * Kh + t2;
+    const size_t jb = ((size_t)t2 * K0 + t0) * K1 + t1;  // band layout [Kh][K0][K1]
+    const size_t j = (size_t)c * K0 * K1 * Kh + jb;
     float2 v = a[j];
     if (b) { v.x += cb * b[j].x; v.y += cb * b[j].y; }
     if (sym) {
-      const float w = sym[((size_t)t0 * K1 + t1) * Kh + t2];
+      const float w = sym[jb];
       v.x *= w;
       v.y *= w;
     }
@@ -236,7 +238,8 @@ __global__ void k_half_to_full(const float2* __restrict__ a, const float2* __res
 }
 
 // ------------------------------------------------- inverse stage 0 (k0)
-// out[v][x0][kh][k1] = sum_k0 tw[v][x0][k0] * in[k0][k1][kh] (optionally in * L~).
+// out[v][x0][kh][k1] = sum_k0 tw[v][x0][k0] * in[kh][k0][k1] (optionally in * L~):
+// column c = kh K1 + k1 of the output reads in[c / K1][k0][c % K1].
 // KC > 0: compile-time K0 = KC (all loads of a column issued before use).
 template <int NV, int XT, int KC>
 __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __restrict__ tw,
@@ -254,6 +257,8 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
   __syncthreads();
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
+  const int K1 = C / Kh;
+  const size_t cin = (size_t)(c / K1) * K0 * K1 + c % K1;  // (kh, k1) of column c, k0 = 0
   float2 acc[NV][XT];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -264,11 +269,11 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
   for (int k0 = 0; k0 < K0; k0 += 8) {
     float2 col[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) col[u] = (k0 + u < K0) ? job.in[(size_t)(k0 + u) * C + c] : make_float2(0.f, 0.f);
+    for (int u = 0; u < 8; ++u) col[u] = (k0 + u < K0) ? job.in[cin + (size_t)(k0 + u) * K1] : make_float2(0.f, 0.f);
     if (job.lflag) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        float l = (k0 + u < K0) ? Lsym[(size_t)(k0 + u) * C + c] : 0.f;
+        float l = (k0 + u < K0) ? Lsym[cin + (size_t)(k0 + u) * K1] : 0.f;
         col[u].x *= l;
         col[u].y *= l;
       }
@@ -287,10 +292,7 @@ __global__ void __launch_bounds__(128) k_inv0(Inv0Jobs jobs, const float2* __res
 #pragma unroll
     for (int t = 0; t < XT; ++t) {
       int x = xb + t;
-      if (x < G0) {
-        const int co = (c % Kh) * (C / Kh) + c / Kh;  // column c = k1 * Kh + kh
-        job.out[((size_t)v * G0 + x) * C + co] = acc[v][t];
-      }
+      if (x < G0) job.out[((size_t)v * G0 + x) * C + c] = acc[v][t];
     }
 }
 
@@ -881,7 +883,7 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
     int k1 = kb + kk;
     float2 res = make_float2(0.f, 0.f);
     if (k1 < K1 && k0 != K0 / 2 && k1 != K1 / 2) {
-      const size_t idx = ((size_t)k0 * K1 + k1) * Kh + kh;
+      const size_t idx = ((size_t)kh * K0 + k0) * K1 + k1;
       float2 fa = make_float2(0.f, 0.f), fb = make_float2(0.f, 0.f);
       const float2* w = wf0 + (size_t)k0 * M0;
       for (int x0 = 0; x0 < M0; ++x0) cmac(fa, w[x0], s2[(size_t)x0 * KG + kk]);
@@ -903,9 +905,9 @@ __global__ void __launch_bounds__(256) k_colstep(ColJobs jobs, Twiddles tw, cons
         res.y = fmaf(job.ce, e.y, res.y);
       }
     }
-    if (k1 < K1) job.out[((size_t)k0 * K1 + k1) * Kh + kh] = res;
+    if (k1 < K1) job.out[((size_t)kh * K0 + k0) * K1 + k1] = res;
     bnd[i] = res;
-    float l = (k1 < K1) ? Lsym[((size_t)k0 * K1 + k1) * Kh + kh] : 0.f;
+    float l = (k1 < K1) ? Lsym[((size_t)kh * K0 + k0) * K1 + k1] : 0.f;
     bnd[K0 * KG + i] = make_float2(l * res.x, l * res.y);
   }
   if (job.nt1 == 0 && !job.t1n) return;
@@ -1049,7 +1051,7 @@ __device__ __forceinline__ void update_values(const ColJob& job, int tile, int l
   for (int r = 0; r < 4; ++r) {
     const int k0 = tile * 16 + 4 * lk + r;
     const bool ok = k0 < K && k1 < K;
-    const size_t idx = ((size_t)(ok ? k0 : 0) * K + (ok ? k1 : 0)) * Kh + kh;
+    const size_t idx = ((size_t)kh * K + (ok ? k0 : 0)) * K + (ok ? k1 : 0);
     pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
     pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
   }
@@ -1197,7 +1199,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     for (int r = 0; r < 4; ++r) {
       const int k0 = ti * 16 + 4 * lk + r;
       if (k0 >= K || k1 >= K) continue;
-      const size_t idx = ((size_t)k0 * K + k1) * Kh + kh;
+      const size_t idx = ((size_t)kh * K + k0) * K + k1;
       float2 res = make_float2(0.f, 0.f);
       if (k0 != K / 2 && k1 != K / 2) {
         res = pbase[r];
@@ -1370,7 +1372,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     for (int r = 0; r < 4; ++r) {
       const int k0 = ti * 16 + 4 * lk + r;
       if (k0 >= K || k1 >= K) continue;
-      const size_t idx = ((size_t)k0 * K + k1) * Kh + kh;
+      const size_t idx = ((size_t)kh * K + k0) * K + k1;
       float2 res = make_float2(0.f, 0.f);
       if (k0 != K / 2 && k1 != K / 2) {
         res = pbase[r];
@@ -1456,7 +1458,7 @@ __global__ void __launch_bounds__(128) k_fwd1(Fwd1Jobs jobs, const float2* __res
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     int q = qb + t;
-    if (q < K1) job.out[((size_t)x0 * K1 + q) * Kh + kh] = acc[t];
+    if (q < K1) job.out[((size_t)x0 * Kh + kh) * K1 + q] = acc[t];
   }
 }
 
@@ -1492,12 +1494,12 @@ __global__ void __launch_bounds__(128) k_fwd0(Fwd0Jobs jobs, const float2* __res
       for (int t = 0; t < QT; ++t) cmac(bb[t], sh[t * G0 + x], vb);
     }
   }
-  const int q1 = c / Kh;
+  const int q1 = c % K1, kh = c / K1;  // input column c = kh K1 + q1
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     int q0 = qb + t;
     if (q0 >= K0) continue;
-    size_t idx = (size_t)q0 * C + c;
+    size_t idx = ((size_t)kh * K0 + q0) * K1 + q1;
     float2 r = make_float2(0.f, 0.f);
     if (q0 != K0 / 2 && q1 != K1 / 2) {
       if (job.base) r = job.base[idx];
@@ -2377,7 +2379,7 @@ __global__ void __launch_bounds__(256) k_srcfwd(const float* __restrict__ a, con
 // group-0 stage-0 buffer and zero into the group-1 buffer.
 struct TailJobs {
   const float2* P;
-  float2* out;       // band field [3][K0][K1][Kh]
+  float2* out;       // band field [3][Kh][K0][K1]
   float2* t1u[3];    // [2][M0][Kh][K1] per component
   float2* t1z[3];
   float ca;
@@ -2459,7 +2461,7 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
         const float sc = tj.ca * invG * pks[r];
         res = make_float2(sc * (acc[0][r] - acc[1][r]), sc * (acc[2][r] + acc[3][r]));
       }
-      tj.out[(size_t)c * K * C + ((size_t)k0 * K + k1) * Kh + kh] = res;
+      tj.out[(size_t)c * K * C + ((size_t)kh * K + k0) * K + k1] = res;
       ob[0][k0][li] = res;
       ob[1][k0][li] = make_float2(pls[r] * res.x, pls[r] * res.y);
     }
@@ -2533,7 +2535,7 @@ __global__ void __launch_bounds__(kRedThreads) k_sqdiff(const float* a, const fl
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// sum_c sum_k w(k2) (L~ if given) Re(conj a b), w = 1 at k2 = 0 else 2
+// sum_c sum_k w(k2) (L~ if given) Re(conj a b), w = 1 at k2 = 0 else 2 (band layout [3][Kh][K0][K1])
 __global__ void __launch_bounds__(kRedThreads) k_band_dot(const float2* a, const float2* b,
                                                           const float* Lsym, int nb, int Kh,
                                                           double* partial) {
@@ -2541,7 +2543,7 @@ __global__ void __launch_bounds__(kRedThreads) k_band_dot(const float2* a, const
   double s = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nb; i += gridDim.x * blockDim.x) {
     int e = i % nb;
-    double w = (e % Kh == 0) ? 1.0 : 2.0;
+    double w = (e < nb / Kh) ? 1.0 : 2.0;  // layout [Kh][K0][K1]: k2 = 0 first
     if (Lsym) w *= (double)Lsym[e];
     s += w * ((double)a[i].x * b[i].x + (double)a[i].y * b[i].y);
   }
@@ -2566,7 +2568,7 @@ __global__ void __launch_bounds__(kRedThreads) k_band_dot_once(const float2* a, 
   double s = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nb; i += gridDim.x * blockDim.x) {
     int e = i % nb;
-    double w = (e % Kh == 0) ? 1.0 : 2.0;
+    double w = (e < nb / Kh) ? 1.0 : 2.0;  // layout [Kh][K0][K1]: k2 = 0 first
     if (Lsym) w *= (double)Lsym[e];
     s += w * ((double)a[i].x * b[i].x + (double)a[i].y * b[i].y);
   }
