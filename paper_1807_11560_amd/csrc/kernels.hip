@@ -163,7 +163,7 @@ __global__ void k_twiddles(float2* dst, int K, int G, int mode) {
 
 // L~ and K~ = 1 / L~ at the band slot (q0, q1, k2) (FP64, rounded once);
 // kernels that need a few symbols per thread form them here instead of
-// loading them from the tables at a stride of Kh.
+// loading them from the tables.
 __device__ __forceinline__ float2 band_symbols(int q0, int q1, int k2, int K0, int K1, int s, double alpha) {
   const int k0 = q0 < K0 / 2 ? q0 : q0 - K0;
   const int k1 = q1 < K1 / 2 ? q1 : q1 - K1;
@@ -1041,8 +1041,9 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
 // the start, two complex values per load; the image-grid table waits in
 // registers until the LDS of the stage-1 input is free.
 // Band values of the column step's update at (k0 = 16 tile + 4 lk + r, k1):
-// the base and extra terms (read at a stride of Kh) and the L~ / K~ symbols
-// (formed in FP64); zero outside the band.
+// the base and extra terms (the block's 16 k1 of one k2 are a 128-byte row
+// of the band layout [Kh][K0][K1]) and the L~ / K~ symbols (formed in FP64);
+// zero outside the band.
 template <int K, int Kh>
 __device__ __forceinline__ void update_values(const ColJob& job, int tile, int lk, int k1, int kh, int spow,
                                               double alpha, float2 (&pbase)[4], float2 (&pextra)[4],

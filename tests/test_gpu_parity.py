@@ -41,6 +41,9 @@ def host(t):
 
 
 CASES = {
+    # the smallest problem the library takes: grid 8^3, band 4^3 (effective
+    # band |k| <= 1), padded grid 6^3
+    "tiny": dict(grid=(8, 8, 8), band=(4, 4, 4), nt=2, s=2, dmax=1.0, cfg=2),
     # anisotropic, odd padded axis (M2 = 9), ragged grid rows
     "small": dict(grid=(24, 20, 18), band=(8, 8, 6), nt=4, s=2, dmax=1.5, cfg=2),
     # ragged padded-grid rows (M1 = 18 with 21-row tiles -> one tile; M = 24 with 10-row tiles)
