@@ -1043,18 +1043,24 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
 // Band values of the column step's update at (k0 = 16 tile + 4 lk + r, k1):
 // the base and extra terms (the block's 16 k1 of one k2 are a 128-byte row
 // of the band layout [Kh][K0][K1]) and the L~ / K~ symbols (formed in FP64);
-// zero outside the band.
+// zero outside the band.  The loads are unconditional (a job without a base
+// or extra term reads its stage-1 input, which is longer than a band field,
+// at a clamped index): a load under a branch makes the merge wait for every
+// load in flight, so base_or_zero / extra_or_zero drop the missing terms
+// where the values are used.
 template <int K, int Kh>
 __device__ __forceinline__ void update_values(const ColJob& job, int tile, int lk, int k1, int kh, int spow,
                                               double alpha, float2 (&pbase)[4], float2 (&pextra)[4],
                                               float (&pks)[4], float (&pls)[4]) {
+  const float2* pb = job.base ? job.base : job.a;
+  const float2* pe = job.extra ? job.extra : job.a;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int k0 = tile * 16 + 4 * lk + r;
     const bool ok = k0 < K && k1 < K;
     const size_t idx = ((size_t)kh * K + (ok ? k0 : 0)) * K + (ok ? k1 : 0);
-    pbase[r] = (ok && job.base) ? job.base[idx] : make_float2(0.f, 0.f);
-    pextra[r] = (ok && job.extra) ? job.extra[idx] : make_float2(0.f, 0.f);
+    pbase[r] = pb[idx];
+    pextra[r] = pe[idx];
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -1064,6 +1070,13 @@ __device__ __forceinline__ void update_values(const ColJob& job, int tile, int l
     pks[r] = ok ? sym.y : 0.f;
     pls[r] = ok ? sym.x : 0.f;
   }
+}
+
+__device__ __forceinline__ float2 base_or_zero(const ColJob& job, float2 v) {
+  return job.base ? v : make_float2(0.f, 0.f);
+}
+__device__ __forceinline__ float2 extra_or_zero(const ColJob& job, float2 v) {
+  return job.extra ? v : make_float2(0.f, 0.f);
 }
 
 constexpr int kGrid0Pre = 16;  // image-grid stage-0 table: complex values per thread
@@ -1122,25 +1135,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     return (x0 < M) ? ld4((t ? sb : sa) + x0 * M + x1) : z4;
   });
   rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
-  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
-  rw0i.load(2 * Mp * KH2, [&](int i) { return ld4(w0i + 2 * i); });
-  const int ng = my_grid0 ? N0 * KH2 : 0;
-  rg.load(ng, [&](int i) { return ld4(jobs.w0n + 2 * i); });
   // band values of the update at (k0 = 16 wave + 4 lk + r, k1)
   float2 pbase[4], pextra[4];
   float pks[4], pls[4];
   if (wave < T0) update_values<K, Kh>(job, wave, lk, k1, kh, spow, alpha, pbase, pextra, pks, pls);
-  // ---- stores
+  // ---- stores of what stage 1' reads
   rs1.store(ns1, [&](int i, float4 v) {
     const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
     st22(&s1[t][x0][x1], v);
   });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
-  rw0f.store(Kp * H, [&](int i, float4 v) { st22(&w0fs[i / H][2 * (i % H)], v); });
-  rw0i.store(2 * Mp * KH2, [&](int i, float4 v) {
-    st22(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
-  });
   __syncthreads();
+  // the stage-0 tables arrive during stage 1' (issued after the first
+  // barrier, which then waits for the stage-1 input alone), waiting in
+  // registers until its products are done
+  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
+  rw0i.load(2 * Mp * KH2, [&](int i) { return ld4(w0i + 2 * i); });
+  const int ng = my_grid0 ? N0 * KH2 : 0;
+  rg.load(ng, [&](int i) { return ld4(jobs.w0n + 2 * i); });
   // stage 1': s2[t][x0][j] = sum_x1 s1[t][x0][x1] w1t[x1][kc + j]
   constexpr int T1R = Mp / 16;
   for (int jb = wave; jb < nterm * T1R; jb += 4) {
@@ -1154,6 +1166,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       if (x0 < M) s2[t][x0][li] = make_float2(acc[0][r] - acc[1][r], acc[2][r] + acc[3][r]);
     }
   }
+  rw0f.store(Kp * H, [&](int i, float4 v) { st22(&w0fs[i / H][2 * (i % H)], v); });
+  rw0i.store(2 * Mp * KH2, [&](int i, float4 v) {
+    st22(&w0is[i / (Mp * KH2)][(i / KH2) % Mp][2 * (i % KH2)], v);
+  });
   __syncthreads();
   rg.store(ng, [&](int i, float4 v) { st22(g0s + (2 * i / K) * LG + (2 * i) % K, v); });
   // stage 0' and the band update (one k0 tile per wave).  With two k0 tiles
@@ -1203,7 +1219,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const size_t idx = ((size_t)kh * K + k0) * K + k1;
       float2 res = make_float2(0.f, 0.f);
       if (k0 != K / 2 && k1 != K / 2) {
-        res = pbase[r];
+        res = base_or_zero(job, pbase[r]);
         const float sa_ = job.ca * invG * (job.syma ? pks[r] : 1.f);
         if constexpr (kSplit0) {
           const float2 ta = (nterm == 2) ? own[r] : make_float2(own[r].x + other[r].x, own[r].y + other[r].y);
@@ -1223,8 +1239,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
             res.y = fmaf(sb_, bb[2][r] + bb[3][r], res.y);
           }
         }
-        res.x = fmaf(job.ce, pextra[r].x, res.x);
-        res.y = fmaf(job.ce, pextra[r].y, res.y);
+        const float2 ex = extra_or_zero(job, pextra[r]);
+        res.x = fmaf(job.ce, ex.x, res.x);
+        res.y = fmaf(job.ce, ex.y, res.y);
       }
       if (part == 0) job.out[idx] = res;
       ob[0][k0][li] = res;
@@ -1315,18 +1332,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     return (x0 < M) ? ld4(sa + x0 * M + x1) : z4;
   });
   rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
-  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
-  const int nt_tab = part == 0 ? NT_I : N0 * KH2;
-  if (part == 0)
-    rt.load(nt_tab, [&](int i) { return ld4(w0i + 2 * i); });
-  else
-    rt.load(nt_tab, [&](int i) { return ld4(jobs.w0n + 2 * i); });
   float2 pbase[4], pextra[4];
   float pks[4], pls[4];
   if (wave < T0) update_values<K, Kh>(job, wave, lk, k1, kh, spow, alpha, pbase, pextra, pks, pls);
   rs1.store(Mp * H, [&](int i, float4 v) { st22(&s1[i / H][2 * (i % H)], v); });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
   __syncthreads();
+  // the tables are issued after the first barrier (which then waits for the
+  // stage-1 input alone) and arrive during stage 1'; one load path for both
+  // parts' next-stage tables
+  rw0f.load(Kp * H, [&](int i) { return ld4(w0f + 2 * i); });
+  const int nt_tab = part == 0 ? NT_I : N0 * KH2;
+  const float2* tsrc = part == 0 ? w0i : jobs.w0n;
+  rt.load(nt_tab, [&](int i) { return ld4(tsrc + 2 * i); });
   // stage 1': s2[x0][j] = sum_x1 s1[x0][x1] w1t[x1][kc + j]
   for (int ti = wave; ti < TIR; ti += 4) {
     floatx4 acc[4];
@@ -1376,12 +1394,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const size_t idx = ((size_t)kh * K + k0) * K + k1;
       float2 res = make_float2(0.f, 0.f);
       if (k0 != K / 2 && k1 != K / 2) {
-        res = pbase[r];
+        res = base_or_zero(job, pbase[r]);
         const float sa_ = job.ca * invG * (job.syma ? pks[r] : 1.f);
         res.x = fmaf(sa_, own[r].x + other[r].x, res.x);
         res.y = fmaf(sa_, own[r].y + other[r].y, res.y);
-        res.x = fmaf(job.ce, pextra[r].x, res.x);
-        res.y = fmaf(job.ce, pextra[r].y, res.y);
+        const float2 ex = extra_or_zero(job, pextra[r]);
+        res.x = fmaf(job.ce, ex.x, res.x);
+        res.y = fmaf(job.ce, ex.y, res.y);
       }
       if (part == 0) job.out[idx] = res;
       ob[0][k0][li] = res;
