@@ -50,15 +50,19 @@ __device__ __forceinline__ void batched_fill(int n, Load load, Store store) {
 // Two-phase copy for 256-thread blocks with every load of a thread in
 // flight at once: load() fills r[u] for element i = threadIdx.x + 256 u
 // (u < CAP, i < n), store() puts them.  The caller guarantees n <= 256 CAP.
+// Every lane loads (a lane past the end reads element n - 1 again): loads
+// under a per-lane branch would make the branch's merge wait for every load
+// in flight, which serialises the caller's later loads behind them.
 template <int CAP, class T>
 struct RegStage {
   T r[CAP];
   template <class Load>
   __device__ __forceinline__ void load(int n, Load f) {
+    if (n <= 0) return;
 #pragma unroll
     for (int u = 0; u < CAP; ++u) {
       const int i = threadIdx.x + 256 * u;
-      if (i < n) r[u] = f(i);
+      r[u] = f(i < n ? i : n - 1);
     }
   }
   template <class Store>
@@ -424,13 +428,13 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   (void)M1p;
-  // The stage-2 table w2b [2][N1][M2p] is loaded into registers now and put
-  // into the LDS of bt1 once GEMM1 has consumed it (when it fits; else GEMM2
-  // reads it from global memory).
+  // The stage-2 table w2b [2][N1][M2p] is loaded into registers during GEMM1
+  // (issued after the first barrier, which then waits for GEMM1's operands
+  // alone) and put into the LDS of bt1 once GEMM1 has consumed it (when it
+  // fits; else GEMM2 reads it from global memory).
   const int nw2 = 2 * N1 * M2p;
   const bool w2_lds = nw2 <= 256 * kSynthW2Pre;
   RegStage<kSynthW2Pre / 4, float4> rw2;
-  if (w2_lds) rw2.load(nw2 / 4, [&](int i) { return reinterpret_cast<const float4*>(a.w2b)[i]; });
   const float2* src = a.t1[g] + (size_t)c * 2 * M0 * C;
   auto put_t1 = [&](int vs, int k1, int kh, float2 t) {  // B[k][col] kept as bT[col][k]
     float* b = bt1 + (size_t)vs * N1 * ldbT;
@@ -489,6 +493,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     });
   }
   __syncthreads();
+  if (w2_lds) rw2.load(nw2 / 4, [&](int i) { return reinterpret_cast<const float4*>(a.w2b)[i]; });
   // GEMM1 on this tile's 16 rows: var 0 = pp (plain stage 0, plain stage 1),
   // 1 = p1 (d1), 2 = 0p (d0 input).  Wave w takes tiles w, w + 4, w + 8, ...
   // and runs up to kSynthT of them at once, their matrix instructions
@@ -1043,17 +1048,18 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
 // Band values of the column step's update at (k0 = 16 tile + 4 lk + r, k1):
 // the base and extra terms (the block's 16 k1 of one k2 are a 128-byte row
 // of the band layout [Kh][K0][K1]) and the L~ / K~ symbols (formed in FP64);
-// zero outside the band.  The loads are unconditional (a job without a base
-// or extra term reads its stage-1 input, which is longer than a band field,
-// at a clamped index): a load under a branch makes the merge wait for every
-// load in flight, so base_or_zero / extra_or_zero drop the missing terms
-// where the values are used.
+// zero outside the band.  The loads are unconditional (a job without an
+// extra term reads its base again, the same cache lines; one without a base
+// reads its stage-1 input, which is longer than a band field, at a clamped
+// index): a load under a branch makes the merge wait for every load in
+// flight, so base_or_zero / extra_or_zero drop the missing terms where the
+// values are used.
 template <int K, int Kh>
 __device__ __forceinline__ void update_values(const ColJob& job, int tile, int lk, int k1, int kh, int spow,
                                               double alpha, float2 (&pbase)[4], float2 (&pextra)[4],
                                               float (&pks)[4], float (&pls)[4]) {
   const float2* pb = job.base ? job.base : job.a;
-  const float2* pe = job.extra ? job.extra : job.a;
+  const float2* pe = job.extra ? job.extra : pb;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int k0 = tile * 16 + 4 * lk + r;
