@@ -50,17 +50,19 @@ __device__ __forceinline__ void batched_fill(int n, Load load, Store store) {
 // Two-phase copy for 256-thread blocks with every load of a thread in
 // flight at once: load() fills r[u] for element i = threadIdx.x + 256 u
 // (u < CAP, i < n), store() puts them.  The caller guarantees n <= 256 CAP.
-// Every lane loads (a lane past the end reads element n - 1 again): loads
-// under a per-lane branch would make the branch's merge wait for every load
-// in flight, which serialises the caller's later loads behind them.
+// Every lane of a slot with any element loads (a lane past the end reads
+// element n - 1 again): loads under a per-lane branch would make the
+// branch's merge wait for every load in flight, which serialises the
+// caller's later loads behind them.  Slots past the end are skipped (a
+// condition that is the same for the whole block).
 template <int CAP, class T>
 struct RegStage {
   T r[CAP];
   template <class Load>
   __device__ __forceinline__ void load(int n, Load f) {
-    if (n <= 0) return;
 #pragma unroll
     for (int u = 0; u < CAP; ++u) {
+      if (256 * u >= n) break;
       const int i = threadIdx.x + 256 * u;
       r[u] = f(i < n ? i : n - 1);
     }
@@ -458,10 +460,11 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
       const int vv = i / (16 * R4), row = (i / R4) % 16, k = 4 * (i % R4);
       return *reinterpret_cast<const float4*>(w1rows + vv * (size_t)sM1p * sK2r + (size_t)row * sK2r + k);
     });
+    // the padding columns kh >= Kh load a valid row and are zeroed when stored
+    // (a load under a per-lane condition would wait for every load in flight)
     rt1.load(NT1, [&](int i) {
       const int vs = i / (sKhp * KP), kh = (i / KP) % sKhp, k1 = 2 * (i % KP);
-      return (kh < sKh) ? ld4(src + ((size_t)vs * M0 + x0) * C + (size_t)kh * sK1 + k1)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      return ld4(src + ((size_t)vs * M0 + x0) * C + (size_t)(kh < sKh ? kh : sKh - 1) * sK1 + k1);
     });
     rw1.store(NW1, [&](int i, float4 v) {
       const int vv = i / (16 * R4), row = (i / R4) % 16, k = 4 * (i % R4);
@@ -473,6 +476,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
     });
     rt1.store(NT1, [&](int i, float4 v) {
       const int vs = i / (sKhp * KP), kh = (i / KP) % sKhp, k1 = 2 * (i % KP);
+      if (kh >= sKh) v = make_float4(0.f, 0.f, 0.f, 0.f);
       put_t1(vs, k1, kh, make_float2(v.x, v.y));
       put_t1(vs, k1 + 1, kh, make_float2(v.z, v.w));
     });
@@ -1136,9 +1140,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   RegStage<(2 * Mp * KH2 + 255) / 256, float4> rw0i;
   RegStage<kGrid0Pre / 2, float4> rg;
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // padding rows x0 >= M load a valid row and are zeroed when stored
   rs1.load(ns1, [&](int i) {
     const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
-    return (x0 < M) ? ld4((t ? sb : sa) + x0 * M + x1) : z4;
+    return ld4((t ? sb : sa) + (x0 < M ? x0 : M - 1) * M + x1);
   });
   rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
   // band values of the update at (k0 = 16 wave + 4 lk + r, k1)
@@ -1148,7 +1153,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   // ---- stores of what stage 1' reads
   rs1.store(ns1, [&](int i, float4 v) {
     const int t = i / (Mp * H), x0 = (i / H) % Mp, x1 = 2 * (i % H);
-    st22(&s1[t][x0][x1], v);
+    st22(&s1[t][x0][x1], x0 < M ? v : z4);
   });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
   __syncthreads();
@@ -1333,15 +1338,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   constexpr int NT_I = 2 * Mp * KH2, NT_G = NG0MAX * KH2;
   RegStage<((NT_I > NT_G ? NT_I : NT_G) + 255) / 256, float4> rt;
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // padding rows x0 >= M load a valid row and are zeroed when stored
   rs1.load(Mp * H, [&](int i) {
     const int x0 = i / H, x1 = 2 * (i % H);
-    return (x0 < M) ? ld4(sa + x0 * M + x1) : z4;
+    return ld4(sa + (x0 < M ? x0 : M - 1) * M + x1);
   });
   rw1.load(M * 8, [&](int i) { return ld4(w1t + (i / 8) * Kp + kc + 2 * (i % 8)); });
   float2 pbase[4], pextra[4];
   float pks[4], pls[4];
   if (wave < T0) update_values<K, Kh>(job, wave, lk, k1, kh, spow, alpha, pbase, pextra, pks, pls);
-  rs1.store(Mp * H, [&](int i, float4 v) { st22(&s1[i / H][2 * (i % H)], v); });
+  rs1.store(Mp * H, [&](int i, float4 v) { st22(&s1[i / H][2 * (i % H)], i / H < M ? v : z4); });
   rw1.store(M * 8, [&](int i, float4 v) { st4(&w1s[i / 8][2 * (i % 8)], v); });
   __syncthreads();
   // the tables are issued after the first barrier (which then waits for the
@@ -1697,9 +1703,9 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     const int c = i / (Kh * KP), kh = (i / KP) % Kh, k1 = 2 * (i % KP);
     return ld4(a.t1 + (((size_t)c * N0 + x0) * Kh + kh) * K1 + k1);
   });
-  rw1.load(R * KP, [&](int i) {
+  rw1.load(R * KP, [&](int i) {  // rows past N1 load a valid row and are zeroed when stored
     const int x1 = x1b + i / KP;
-    return (x1 < N1) ? ld4(tw.inv1 + (size_t)x1 * K1 + 2 * (i % KP)) : z4;
+    return ld4(tw.inv1 + (size_t)(x1 < N1 ? x1 : N1 - 1) * K1 + 2 * (i % KP));
   });
   rw2.load(N2 * KHP, [&](int i) { return ld4(tw.inv2 + (size_t)(i / KHP) * Kh + 2 * (i % KHP)); });
   constexpr int NTJ = N2 / 16, TPW = (NTJ + 3) / 4, NM4 = (R + 2) * N2 / 4;
@@ -1731,7 +1737,7 @@ __global__ void __launch_bounds__(256) k_gridstep_mfma(GridStepArgs a, Twiddles 
     t1s[c][k1][kh] = make_float2(v.x, v.y);
     t1s[c][k1 + 1][kh] = make_float2(v.z, v.w);
   });
-  rw1.store(R * KP, [&](int i, float4 v) { st22(&w1s[i / KP][2 * (i % KP)], v); });
+  rw1.store(R * KP, [&](int i, float4 v) { st22(&w1s[i / KP][2 * (i % KP)], x1b + i / KP < N1 ? v : z4); });
   rw2.store(N2 * KHP, [&](int i, float4 v) {
     const int x2 = i / KHP, kh = 2 * (i % KHP);
     w2t[kh][x2] = make_float2(v.x, v.y);
@@ -2438,9 +2444,9 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     const int row = i / 8, p = row / NG0, x0 = row % NG0;
     return ld4(tj.P + ((((size_t)p * 3 + c) * Kh + kh) * NG0 + x0) * K + kc + 2 * (i % 8));
   });
-  ra.load(Kp * NG0 / 2, [&](int i) {
+  ra.load(Kp * NG0 / 2, [&](int i) {  // rows past K load a valid row and are zeroed when stored
     const int k0 = i / (NG0 / 2);
-    return (k0 < K) ? ld4(w0n + (size_t)k0 * NG0 + 2 * (i % (NG0 / 2))) : z4;
+    return ld4(w0n + (size_t)(k0 < K ? k0 : K - 1) * NG0 + 2 * (i % (NG0 / 2)));
   });
   rw.load(2 * Mp * K / 2, [&](int i) { return ld4(w0i + 2 * i); });
   float pks[4], pls[4];
@@ -2455,7 +2461,9 @@ __global__ void __launch_bounds__(256) k_fwd0_mfma(TailJobs tj, const float2* __
     }
   }
   rb.store(DEPTH * 8, [&](int i, float4 v) { st4(&bs[i / 8][2 * (i % 8)], v); });
-  ra.store(Kp * NG0 / 2, [&](int i, float4 v) { st22(&as[i / (NG0 / 2)][2 * (i % (NG0 / 2))], v); });
+  ra.store(Kp * NG0 / 2, [&](int i, float4 v) {
+    st22(&as[i / (NG0 / 2)][2 * (i % (NG0 / 2))], i / (NG0 / 2) < K ? v : z4);
+  });
   rw.store(2 * Mp * K / 2, [&](int i, float4 v) {
     st22(&w0is[i / (Mp * K / 2)][(i / (K / 2)) % Mp][2 * (i % (K / 2))], v);
   });
