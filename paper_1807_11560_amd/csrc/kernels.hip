@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256) k_synth(SynthArgs a, S sh) {
   const float* w1rows = a.w1a + (size_t)rt * 16 * K2r;
   const size_t w1var = (size_t)M1p * K2r;
   if constexpr (S::kStatic) {
-    // all loads of the block in flight at once, four floats per load
+    // the loads of GEMM1's operands in flight at once, four floats per load
     constexpr int sM1p = (S::M1() + 15) & ~15, sK1 = S::K1(), sKh = S::Kh(), sKhp = (sKh + 7) & ~7;
     constexpr int sK2r = 2 * sK1, KP = sK1 / 2, R4 = sK2r / 4;
     constexpr int NW1 = 2 * 16 * R4, NT1 = 2 * sKhp * KP;
@@ -1044,11 +1044,11 @@ __global__ void k_col_tables(const float2* fwd1, const float2* fwd0, const float
 // With nparts > 1 the blocks of one tile all form the band update (only part
 // 0 stores it) and split the output tiles of the next inverse stage 0 between
 // them in contiguous ranges, which multiplies the blocks of launches that
-// would leave most compute units idle.  All
-// global loads of the block (the stage-1 input, the twiddle tables, the
-// image-grid stage-0 table and the band values of the update) are issued at
-// the start, two complex values per load; the image-grid table waits in
-// registers until the LDS of the stage-1 input is free.
+// would leave most compute units idle.  The loads that stage 1' needs (the
+// stage-1 input, its table, the band values of the update) are issued at the
+// start, two complex values per load; the stage-0 tables and the image-grid
+// table after the first barrier, arriving during stage 1' and waiting in
+// registers until their LDS is free.
 // Band values of the column step's update at (k0 = 16 tile + 4 lk + r, k1):
 // the base and extra terms (the block's 16 k1 of one k2 are a 128-byte row
 // of the band layout [Kh][K0][K1]) and the L~ / K~ symbols (formed in FP64);
@@ -1297,8 +1297,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 // stage 0 and stores the band update, part 1 the image-grid stage 0.  One LDS
 // region holds in turn the stage-1 input, the stage-0 table and the part's
 // next-stage table, so the block needs about half the LDS of k_colstep_mfma
-// and can share a compute unit with grid-step blocks.  The tables wait in
-// registers until their turn.
+// and can share a compute unit with grid-step blocks.  The tables are issued
+// after the first barrier and wait in registers until their turn.
 template <class S, bool BF3>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_colstep_lean(
     ColJobs jobs, const float2* __restrict__ w1t, const float2* __restrict__ w0f, const float2* __restrict__ w0i,
